@@ -1,0 +1,503 @@
+/*
+ * FP64 CPU oracle for the BiCGSafe family of Huynh & Suito,
+ * "Communication-hiding pipelined BiCGSafe methods for solving large linear
+ * systems" (arXiv 2108.10591).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it; the product path never
+ * does.  It shares no code, header or constant with the GPU library.
+ *
+ * Conventions (kept deliberately simple so the code can be checked against
+ * the paper by eye):
+ *   - every vector statement is one plain loop over all n entries;
+ *   - an inner product is a sequential sum in index order;
+ *   - a sparse product y = A x is, per row, a sequential sum over the row's
+ *     entries in storage order;
+ *   - compiled with -ffp-contract=off, so no fused multiply-adds.
+ *
+ * Variants:
+ *   0  ssBiCGSafe2            Algorithm 3 (Section 2)
+ *   1  p-BiCGSafe             Algorithm 4 (Section 3)
+ *   2  p-BiCGSafe-rr          Algorithm 5 (Section 4)
+ *   3  p-BiCGStab             pipelined BiCGStab of Cools & Vanroose, cited in
+ *                             the introduction and Table 1 but not printed;
+ *                             derived here from BiCGStab (Algorithm 1) by the
+ *                             auxiliary definitions given below
+ *   4  BiCGStab               Algorithm 1 (Section 2), with omega written for
+ *                             the coefficient the listing calls zeta
+ *
+ * Readings of points the paper leaves open (each is used below):
+ *   R1  the shadow residual is r0* = r0, fixed for the whole solve.
+ *   R2  Algorithms 4/5 use s_0 without computing it; s_0 = A r_0 by its
+ *       definition s_i := A r_i (Section 3), one extra product at setup.
+ *   R3  vectors with index -1 (and y_0, g_0) start at zero.
+ *   R4  the i = 0 branch is special-cased as printed.
+ *   R5  the stop test is taken before the coefficients are formed (the
+ *       listings form them first); this changes nothing on iterations that
+ *       continue and avoids 0/0 when r_i is exactly zero.
+ *   R6  iters = the number of x updates made; hist[i] = sqrt(rho_i)/sqrt(rho_ref),
+ *       rho_i = (r_i, r_i) of the recursively updated residual.
+ *   R7  Algorithm 5 computes "A t_{i+1}" but assigns l_i = A t_i; t_{i+1}
+ *       does not exist yet, so l_i = A t_i.
+ *   R9  the replacement cut-off M defaults to maxit.
+ *   R10 a zero or non-finite denominator in alpha, beta, zeta, eta (or
+ *       omega's successor) stops the solve with status BREAKDOWN and x_i.
+ *
+ * Status codes: 0 converged, 1 maxit, 2 breakdown, 3 non-finite inner product.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* vector slots in the caller-provided state array V[NV][n] */
+enum {
+  VX = 0, VR, VRS, VS, VY, VT, VP, VU, VZ, VW, VL, VG, VQ, VO, VAS, VAW, VV, VTMP,
+  NV
+};
+/* scalar slots in the caller-provided array S[NS] */
+enum {
+  S_ALPHA = 0, S_BETA, S_ZETA, S_ETA, S_OMEGA, S_F, S_RHOREF, S_RHO,
+  S_NSPMV, S_NDOT, S_NPHASE, S_PENDING_BREAKDOWN,
+  S_GS, S_GW, S_GZ, /* p-BiCGStab: (r*, s), (r*, w), (r*, z) of the last phase */
+  NS
+};
+enum { ST_CONVERGED = 0, ST_MAXIT = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3, ST_RUNNING = -1 };
+enum { V_SSBICGSAFE2 = 0, V_PBICGSAFE = 1, V_PBICGSAFE_RR = 2, V_PBICGSTAB = 3, V_BICGSTAB = 4 };
+
+typedef struct {
+  int64_t n;
+  const int64_t *rowptr;
+  const int32_t *col;
+  const double *val;
+} csr_t;
+
+/* ---------------------------------------------------------------- kernels */
+
+/* y = A x (the "matrix-vector product" of every listing) */
+static void spmv(const csr_t *A, const double *x, double *y, double *S) {
+  for (int64_t i = 0; i < A->n; ++i) {
+    double acc = 0.0;
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) acc += A->val[k] * x[A->col[k]];
+    y[i] = acc;
+  }
+  S[S_NSPMV] += 1.0;
+}
+
+/* (u, v) = sum_k u_k v_k, in index order */
+static double dot(int64_t n, const double *u, const double *v, double *S) {
+  double acc = 0.0;
+  for (int64_t k = 0; k < n; ++k) acc += u[k] * v[k];
+  S[S_NDOT] += 1.0;
+  return acc;
+}
+
+static int bad(double d) { return d == 0.0 || !isfinite(d); }
+
+/* ----------------------------------------------------------- entry points */
+
+/*
+ * Initialise the state for `variant` (the steps before each listing's loop).
+ * V holds NV vectors of length n (zeroed here); S holds NS scalars.
+ * x0 may be NULL (zero initial guess).  norm_ref selects the stop-test scale:
+ * 0 = ||r_0|| (the paper's criterion, Section 5), 1 = ||b||.
+ */
+int orc_setup(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const double *b, const double *x0, int norm_ref, double *V, double *S) {
+  csr_t A = {n, rowptr, col, val};
+  double *v[NV];
+  for (int k = 0; k < NV; ++k) v[k] = V + (size_t)k * (size_t)n;
+  memset(V, 0, sizeof(double) * (size_t)NV * (size_t)n);   /* R3: everything starts at zero */
+  memset(S, 0, sizeof(double) * NS);
+  double *x = v[VX], *r = v[VR], *rs = v[VRS], *tmp = v[VTMP];
+
+  /* x_0 and r_0 = b - A x_0 */
+  for (int64_t k = 0; k < n; ++k) x[k] = x0 ? x0[k] : 0.0;
+  spmv(&A, x, tmp, S);
+  for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];
+  /* R1: r0* = r0 */
+  for (int64_t k = 0; k < n; ++k) rs[k] = r[k];
+
+  if (variant == V_PBICGSAFE || variant == V_PBICGSAFE_RR) {
+    spmv(&A, r, v[VS], S);                       /* R2: s_0 = A r_0 */
+  }
+  if (variant == V_PBICGSTAB) {
+    /* w_0 = A r_0, t_0 = A w_0, alpha_0 = (r0*, r_0)/(r0*, w_0), rho_0 = (r_0, r_0) */
+    spmv(&A, r, v[VW], S);
+    spmv(&A, v[VW], v[VT], S);
+    double f = dot(n, rs, r, S);
+    double rsw = dot(n, rs, v[VW], S);
+    double rho = dot(n, r, r, S);
+    S[S_NPHASE] += 1.0;
+    S[S_F] = f;
+    S[S_RHO] = rho;
+    S[S_GW] = rsw;
+    if (bad(rsw) || !isfinite(f / rsw)) S[S_PENDING_BREAKDOWN] = 1.0;
+    else S[S_ALPHA] = f / rsw;
+    S[S_BETA] = 0.0;
+    S[S_OMEGA] = 0.0;
+  }
+  if (variant == V_BICGSTAB) {
+    S[S_BETA] = 0.0;
+  }
+  /* reference norm for the stop test */
+  if (norm_ref == 1) S[S_RHOREF] = dot(n, b, b, S), S[S_NDOT] -= 1.0;
+  else S[S_RHOREF] = dot(n, r, r, S), S[S_NDOT] -= 1.0;
+  return 0;
+}
+
+/* hist[i] and the stop test shared by every variant: returns a status or ST_RUNNING */
+static int stop_test(double rho, double *S, int64_t i, int64_t maxit, double tol, double *hist) {
+  double ref = sqrt(S[S_RHOREF]);
+  double nr = sqrt(rho);
+  if (hist) hist[i] = ref > 0.0 ? nr / ref : 0.0;
+  if (nr <= tol * ref) return ST_CONVERGED;                 /* R14: "<=" */
+  if (i >= maxit) return ST_MAXIT;
+  return ST_RUNNING;
+}
+
+/* coefficient record per iteration: alpha, beta, zeta, eta, omega, rho, f, spare */
+#define NCOEF 8
+static void record(double *coef, int64_t i, double al, double be, double ze, double et, double om,
+                   double rho, double f) {
+  if (!coef) return;
+  double *c = coef + (size_t)i * NCOEF;
+  c[0] = al; c[1] = be; c[2] = ze; c[3] = et; c[4] = om; c[5] = rho; c[6] = f; c[7] = 0.0;
+}
+
+/*
+ * The nine inner products of the single reduction phase (Algorithms 3-5):
+ *   a = (s,s), b = (y,y), c = (s,y), d = (s,r), e = (y,r),
+ *   f = (r0*,r), g^ = (r0*,s), h = (r0*,t_{i-1}), rho = (r,r).
+ * At i = 0 only a, d, f, g^ and rho are formed.
+ * Then the stop test and the coefficients beta, alpha, zeta, eta.
+ * Returns a status, or ST_RUNNING to continue with the updates.
+ */
+static int safe_phase(int64_t n, double **v, double *S, int64_t i, int64_t maxit, double tol,
+                      double *hist, double *coef) {
+  const double *s = v[VS], *y = v[VY], *r = v[VR], *rs = v[VRS], *t = v[VT];
+  double a, bb = 0, c = 0, d, e = 0, f, gh, h = 0, rho;
+  if (i == 0) {
+    a = dot(n, s, s, S);
+    d = dot(n, s, r, S);
+    f = dot(n, rs, r, S);
+    gh = dot(n, rs, s, S);
+    rho = dot(n, r, r, S);
+  } else {
+    a = dot(n, s, s, S);
+    bb = dot(n, y, y, S);
+    c = dot(n, s, y, S);
+    d = dot(n, s, r, S);
+    e = dot(n, y, r, S);
+    f = dot(n, rs, r, S);
+    gh = dot(n, rs, s, S);
+    h = dot(n, rs, t, S);
+    rho = dot(n, r, r, S);
+  }
+  S[S_NPHASE] += 1.0;
+  S[S_RHO] = rho;
+  if (!(isfinite(a) && isfinite(bb) && isfinite(c) && isfinite(d) && isfinite(e) && isfinite(f) &&
+        isfinite(gh) && isfinite(h) && isfinite(rho))) {
+    if (hist) hist[i] = NAN;
+    return ST_NONFINITE;
+  }
+  int st = stop_test(rho, S, i, maxit, tol, hist);
+  if (st != ST_RUNNING) return st;
+
+  double beta, alpha, zeta, eta;
+  if (i == 0) {
+    if (bad(gh) || bad(a)) return ST_BREAKDOWN;
+    beta = 0.0;
+    alpha = f / gh;
+    zeta = d / a;
+    eta = 0.0;
+  } else {
+    /* previous iteration's alpha, zeta, f are still in S */
+    double den_beta = S[S_ZETA] * S[S_F];
+    if (bad(den_beta)) return ST_BREAKDOWN;
+    beta = (S[S_ALPHA] * f) / den_beta;
+    double den_alpha = gh + beta * h;
+    double den_ze = a * bb - c * c;
+    if (bad(den_alpha) || bad(den_ze)) return ST_BREAKDOWN;
+    alpha = f / den_alpha;
+    zeta = (bb * d - c * e) / den_ze;
+    eta = (a * e - c * d) / den_ze;
+  }
+  if (!isfinite(beta) || !isfinite(alpha) || !isfinite(zeta) || !isfinite(eta)) return ST_BREAKDOWN;
+  S[S_ALPHA] = alpha;
+  S[S_BETA] = beta;
+  S[S_ZETA] = zeta;
+  S[S_ETA] = eta;
+  S[S_F] = f;
+  record(coef, i, alpha, beta, zeta, eta, 0.0, rho, f);
+  return ST_RUNNING;
+}
+
+/* ssBiCGSafe2, Algorithm 3: one iteration i */
+static int iter_ssbicgsafe2(const csr_t *A, double **v, double *S, int64_t i, int64_t maxit,
+                            double tol, double *hist, double *coef) {
+  int64_t n = A->n;
+  double *x = v[VX], *r = v[VR], *s = v[VS], *y = v[VY], *t = v[VT], *p = v[VP], *u = v[VU];
+  double *z = v[VZ], *w = v[VW], *o = v[VO];
+  spmv(A, r, s, S);                                        /* s_i = A r_i */
+  int st = safe_phase(n, v, S, i, maxit, tol, hist, coef);
+  if (st != ST_RUNNING) return st;
+  const double al = S[S_ALPHA], be = S[S_BETA], ze = S[S_ZETA], et = S[S_ETA];
+  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - u[k]);          /* p_i */
+  for (int64_t k = 0; k < n; ++k) o[k] = s[k] + be * t[k];                   /* o_i */
+  for (int64_t k = 0; k < n; ++k) u[k] = ze * o[k] + et * (y[k] + be * u[k]); /* u_i */
+  spmv(A, u, w, S);                                        /* w_i = A u_i */
+  for (int64_t k = 0; k < n; ++k) t[k] = o[k] - w[k];                        /* t_i */
+  for (int64_t k = 0; k < n; ++k) z[k] = ze * r[k] + et * z[k] - al * u[k];  /* z_i */
+  for (int64_t k = 0; k < n; ++k) y[k] = ze * s[k] + et * y[k] - al * w[k];  /* y_{i+1} */
+  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + z[k];            /* x_{i+1} */
+  for (int64_t k = 0; k < n; ++k) r[k] = r[k] - al * o[k] - y[k];            /* r_{i+1} */
+  return ST_RUNNING;
+}
+
+/* p-BiCGSafe, Algorithm 4, and p-BiCGSafe-rr, Algorithm 5: one iteration i */
+static int iter_pbicgsafe(const csr_t *A, const double *b, double **v, double *S, int64_t i,
+                          int64_t maxit, double tol, int rr, int64_t m, int64_t M, double *hist,
+                          double *coef) {
+  int64_t n = A->n;
+  double *x = v[VX], *r = v[VR], *s = v[VS], *y = v[VY], *t = v[VT], *p = v[VP], *u = v[VU];
+  double *z = v[VZ], *w = v[VW], *l = v[VL], *g = v[VG], *q = v[VQ], *o = v[VO];
+  double *As = v[VAS], *Aw = v[VAW], *tmp = v[VTMP];
+  spmv(A, s, As, S);                                       /* As_i (overlapped in the paper) */
+  int st = safe_phase(n, v, S, i, maxit, tol, hist, coef);
+  if (st != ST_RUNNING) return st;
+  const double al = S[S_ALPHA], be = S[S_BETA], ze = S[S_ZETA], et = S[S_ETA];
+  const int replace = rr && m > 0 && (i % m == 0) && i > 0 && i < M;
+
+  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - u[k]);          /* p_i */
+  for (int64_t k = 0; k < n; ++k) o[k] = s[k] + be * t[k];                   /* o_i */
+  for (int64_t k = 0; k < n; ++k) u[k] = ze * o[k] + et * (y[k] + be * u[k]); /* u_i */
+  if (replace) {
+    spmv(A, o, q, S);                                      /* q_i = A o_i */
+    spmv(A, u, w, S);                                      /* w_i = A u_i */
+  } else {
+    for (int64_t k = 0; k < n; ++k) q[k] = As[k] + be * l[k];                /* q_i, Eq. (q) */
+    for (int64_t k = 0; k < n; ++k) w[k] = ze * q[k] + et * (g[k] + be * w[k]); /* w_i, Eq. (w) */
+  }
+  for (int64_t k = 0; k < n; ++k) t[k] = o[k] - w[k];                        /* t_i */
+  for (int64_t k = 0; k < n; ++k) z[k] = ze * r[k] + et * z[k] - al * u[k];  /* z_i */
+  for (int64_t k = 0; k < n; ++k) y[k] = ze * s[k] + et * y[k] - al * w[k];  /* y_{i+1} */
+  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + z[k];            /* x_{i+1} */
+  if (replace) {
+    spmv(A, x, tmp, S);                                    /* A x_{i+1} */
+    for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];                    /* r_{i+1} = b - A x_{i+1} */
+    spmv(A, t, l, S);                                      /* R7: l_i = A t_i */
+    spmv(A, y, g, S);                                      /* g_{i+1} = A y_{i+1} */
+    spmv(A, r, s, S);                                      /* s_{i+1} = A r_{i+1} */
+  } else {
+    for (int64_t k = 0; k < n; ++k) r[k] = r[k] - al * o[k] - y[k];          /* r_{i+1} */
+    spmv(A, w, Aw, S);                                     /* Aw_i */
+    for (int64_t k = 0; k < n; ++k) l[k] = q[k] - Aw[k];                     /* l_i, Eq. (l) */
+    for (int64_t k = 0; k < n; ++k) g[k] = ze * As[k] + et * g[k] - al * Aw[k]; /* g_{i+1}, Eq. (g) */
+    for (int64_t k = 0; k < n; ++k) s[k] = s[k] - al * q[k] - g[k];          /* s_{i+1}, Eq. (sip1) */
+  }
+  return ST_RUNNING;
+}
+
+/*
+ * p-BiCGStab: one iteration i.  Derived from BiCGStab (Algorithm 1, omega in
+ * place of the listing's zeta) by carrying the products
+ *     s_i = A p_i,  z_i = A s_i,  w_i = A r_i,  t_i = A w_i,  v_i = A z_i,
+ *     q_i = r_i - alpha_i s_i,  y_i = A q_i = w_i - alpha_i z_i
+ * as recurrences, so each iteration does two products (v_i = A z_i and
+ * t_{i+1} = A w_{i+1}) and two reduction phases of 2 and 5 inner products,
+ * each independent of the product next to it (Table 1: 2 products, 7 inner
+ * products).  Substituting the definitions:
+ *     p_i = r_i + beta_{i-1} (p_{i-1} - omega_{i-1} s_{i-1})
+ *     s_i = w_i + beta_{i-1} (s_{i-1} - omega_{i-1} z_{i-1})
+ *     z_i = t_i + beta_{i-1} (z_{i-1} - omega_{i-1} v_{i-1})
+ *     omega_i = (q_i, y_i) / (y_i, y_i)
+ *     x_{i+1} = x_i + alpha_i p_i + omega_i q_i,   r_{i+1} = q_i - omega_i y_i
+ *     w_{i+1} = A r_{i+1} = y_i - omega_i (t_i - alpha_i v_i)
+ *     beta_i = (alpha_i/omega_i) (r0*, r_{i+1}) / (r0*, r_i)
+ *     alpha_{i+1} = (r0*, r_{i+1}) / ((r0*, w_{i+1}) + beta_i (r0*, s_i) - beta_i omega_i (r0*, z_i))
+ * where the last denominator is (r0*, A p_{i+1}) expanded by the p recurrence.
+ * (y_i, y_i) = 0 means y_i = 0, hence q_i = 0 for nonsingular A: then
+ * omega_i = 0, x_{i+1} = x_i + alpha_i p_i and r_{i+1} = q_i; the next stop
+ * test decides, and beta_i (which divides by omega_i) is flagged as a
+ * breakdown only if the solve has to continue.
+ */
+static int iter_pbicgstab(const csr_t *A, double **v, double *S, int64_t i, int64_t maxit,
+                          double tol, double *hist, double *coef) {
+  int64_t n = A->n;
+  double *x = v[VX], *r = v[VR], *rs = v[VRS], *s = v[VS], *y = v[VY], *t = v[VT], *p = v[VP];
+  double *z = v[VZ], *w = v[VW], *q = v[VQ], *vv = v[VV];
+  /* rho_i and the phase that formed alpha_i were computed by the previous iteration (or setup) */
+  double rho = S[S_RHO];
+  if (!isfinite(rho) || !isfinite(S[S_F]) || !isfinite(S[S_GW]) || !isfinite(S[S_GS]) ||
+      !isfinite(S[S_GZ])) {
+    if (hist) hist[i] = NAN;
+    return ST_NONFINITE;
+  }
+  int st = stop_test(rho, S, i, maxit, tol, hist);
+  if (st != ST_RUNNING) return st;
+  if (S[S_PENDING_BREAKDOWN] != 0.0) return ST_BREAKDOWN;
+  const double al = S[S_ALPHA], be = S[S_BETA], omp = S[S_OMEGA];
+
+  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - omp * s[k]);   /* p_i */
+  for (int64_t k = 0; k < n; ++k) s[k] = w[k] + be * (s[k] - omp * z[k]);   /* s_i = A p_i */
+  for (int64_t k = 0; k < n; ++k) z[k] = t[k] + be * (z[k] - omp * vv[k]);  /* z_i = A s_i */
+  for (int64_t k = 0; k < n; ++k) q[k] = r[k] - al * s[k];                  /* q_i */
+  for (int64_t k = 0; k < n; ++k) y[k] = w[k] - al * z[k];                  /* y_i = A q_i */
+  /* phase 1: (q, y), (y, y), overlapped with v_i = A z_i */
+  double qy = dot(n, q, y, S);
+  double yy = dot(n, y, y, S);
+  S[S_NPHASE] += 1.0;
+  spmv(A, z, vv, S);                                                       /* v_i = A z_i */
+  if (!isfinite(qy) || !isfinite(yy)) return ST_NONFINITE;
+  double om = (yy == 0.0) ? 0.0 : qy / yy;
+  if (!isfinite(om)) return ST_BREAKDOWN;
+  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + om * q[k];     /* x_{i+1} */
+  for (int64_t k = 0; k < n; ++k) r[k] = q[k] - om * y[k];                 /* r_{i+1} */
+  for (int64_t k = 0; k < n; ++k) w[k] = y[k] - om * (t[k] - al * vv[k]);  /* w_{i+1} = A r_{i+1} */
+  /* phase 2: (r0*, r), (r0*, w), (r0*, s), (r0*, z), (r, r), overlapped with t_{i+1} = A w_{i+1} */
+  double f = dot(n, rs, r, S);
+  double gw = dot(n, rs, w, S);
+  double gs = dot(n, rs, s, S);
+  double gz = dot(n, rs, z, S);
+  double rho1 = dot(n, r, r, S);
+  S[S_NPHASE] += 1.0;
+  spmv(A, w, t, S);                                                        /* t_{i+1} = A w_{i+1} */
+  double beta = 0.0, alpha = 0.0;
+  int pend = 0;
+  double den_beta = om * S[S_F];
+  if (bad(den_beta)) pend = 1;
+  else {
+    beta = (al * f) / den_beta;
+    double den_alpha = gw + beta * gs - beta * om * gz;
+    if (bad(den_alpha)) pend = 1;
+    else alpha = f / den_alpha;
+    if (!isfinite(beta) || !isfinite(alpha)) pend = 1;
+  }
+  record(coef, i, al, be, 0.0, 0.0, om, rho, S[S_F]);
+  S[S_ALPHA] = alpha;
+  S[S_BETA] = beta;
+  S[S_OMEGA] = om;
+  S[S_F] = f;
+  S[S_GW] = gw;
+  S[S_GS] = gs;
+  S[S_GZ] = gz;
+  S[S_RHO] = rho1;
+  S[S_PENDING_BREAKDOWN] = pend ? 1.0 : 0.0;
+  return ST_RUNNING;
+}
+
+/* BiCGStab, Algorithm 1 (omega for the listing's zeta): one iteration i.
+   Slots: p = VP, Ap = VS, t = VQ (the listing's t_i), At = VY. */
+static int iter_bicgstab(const csr_t *A, double **v, double *S, int64_t i, int64_t maxit,
+                         double tol, double *hist, double *coef) {
+  int64_t n = A->n;
+  double *x = v[VX], *r = v[VR], *rs = v[VRS], *p = v[VP], *Ap = v[VS], *t = v[VQ], *At = v[VY];
+  double rho = dot(n, r, r, S);
+  S[S_NDOT] -= 1.0; /* the norm is not one of the method's counted inner products */
+  S[S_RHO] = rho;
+  if (!isfinite(rho)) { if (hist) hist[i] = NAN; return ST_NONFINITE; }
+  int st = stop_test(rho, S, i, maxit, tol, hist);
+  if (st != ST_RUNNING) return st;
+  const double be = S[S_BETA], omp = S[S_OMEGA];
+  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - omp * Ap[k]);  /* p_i */
+  spmv(A, p, Ap, S);                                                        /* A p_i */
+  double f = dot(n, rs, r, S);
+  double rsap = dot(n, rs, Ap, S);
+  S[S_NPHASE] += 1.0;
+  if (!isfinite(f) || !isfinite(rsap)) return ST_NONFINITE;
+  if (bad(rsap)) return ST_BREAKDOWN;
+  double al = f / rsap;                                                      /* alpha_i */
+  for (int64_t k = 0; k < n; ++k) t[k] = r[k] - al * Ap[k];                  /* t_i */
+  spmv(A, t, At, S);                                                        /* A t_i */
+  double att = dot(n, At, t, S);
+  double atat = dot(n, At, At, S);
+  S[S_NPHASE] += 1.0;
+  if (!isfinite(att) || !isfinite(atat)) return ST_NONFINITE;
+  double om = (atat == 0.0) ? 0.0 : att / atat;                             /* omega_i */
+  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + om * t[k];       /* x_{i+1} */
+  for (int64_t k = 0; k < n; ++k) r[k] = t[k] - om * At[k];                  /* r_{i+1} */
+  double f1 = dot(n, rs, r, S);
+  S[S_NPHASE] += 1.0;
+  record(coef, i, al, be, 0.0, 0.0, om, rho, f);
+  double beta = 0.0;
+  if (om != 0.0 && f != 0.0) beta = (al / om) * (f1 / f);                   /* beta_i */
+  S[S_BETA] = beta;
+  S[S_OMEGA] = om;
+  S[S_ALPHA] = al;
+  S[S_F] = f1;
+  if ((om == 0.0 || f == 0.0 || !isfinite(beta))) S[S_PENDING_BREAKDOWN] = 1.0;
+  return ST_RUNNING;
+}
+
+/*
+ * Run iterations i = i_begin, i_begin+1, ... from the state (V, S) until a
+ * stop.  hist (length >= maxit+1, indexed by i) and coef (NCOEF doubles per
+ * iteration) may be NULL.  rr_m / rr_M are the replacement period and cut-off
+ * of Algorithm 5 (ignored by the other variants).  On return *iters is the
+ * index i at which the solve stopped (= the number of x updates from 0) and
+ * V holds the state at the start of that iteration.
+ */
+int orc_run(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+            const double *b, double *V, double *S, int64_t i_begin, int64_t maxit, double tol,
+            int64_t rr_m, int64_t rr_M, int64_t *iters, double *hist, double *coef, int32_t *status) {
+  csr_t A = {n, rowptr, col, val};
+  double *v[NV];
+  for (int k = 0; k < NV; ++k) v[k] = V + (size_t)k * (size_t)n;
+  int st = ST_RUNNING;
+  int64_t i = i_begin;
+  for (;; ++i) {
+    if (variant == V_BICGSTAB && i > i_begin && S[S_PENDING_BREAKDOWN] != 0.0) {
+      /* the previous beta was not finite: only a converged stop may follow */
+      double rho = dot(n, v[VR], v[VR], S);
+      S[S_NDOT] -= 1.0;
+      st = stop_test(rho, S, i, maxit, tol, hist);
+      if (st == ST_RUNNING) st = ST_BREAKDOWN;
+      break;
+    }
+    switch (variant) {
+      case V_SSBICGSAFE2: st = iter_ssbicgsafe2(&A, v, S, i, maxit, tol, hist, coef); break;
+      case V_PBICGSAFE: st = iter_pbicgsafe(&A, b, v, S, i, maxit, tol, 0, 0, 0, hist, coef); break;
+      case V_PBICGSAFE_RR:
+        st = iter_pbicgsafe(&A, b, v, S, i, maxit, tol, 1, rr_m, rr_M, hist, coef);
+        break;
+      case V_PBICGSTAB: st = iter_pbicgstab(&A, v, S, i, maxit, tol, hist, coef); break;
+      case V_BICGSTAB: st = iter_bicgstab(&A, v, S, i, maxit, tol, hist, coef); break;
+      default: return -1;
+    }
+    if (st != ST_RUNNING) break;
+  }
+  *iters = i;
+  *status = st;
+  return 0;
+}
+
+/* setup + run from i = 0; x (length n) receives the final iterate. */
+int orc_solve(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const double *b, const double *x0, double tol, int64_t maxit, int64_t rr_m,
+              int64_t rr_M, int norm_ref, double *x, int64_t *iters, double *hist, double *coef,
+              int32_t *status, double *counters) {
+  if (n < 1 || variant < 0 || variant > 4) return -1;
+  double *V = (double *)malloc(sizeof(double) * (size_t)NV * (size_t)n);
+  double S[NS];
+  if (!V) return -2;
+  orc_setup(variant, n, rowptr, col, val, b, x0, norm_ref, V, S);
+  orc_run(variant, n, rowptr, col, val, b, V, S, 0, maxit, tol, rr_m, rr_M, iters, hist, coef, status);
+  memcpy(x, V + (size_t)VX * (size_t)n, sizeof(double) * (size_t)n);
+  if (counters) { counters[0] = S[S_NSPMV]; counters[1] = S[S_NDOT]; counters[2] = S[S_NPHASE]; }
+  free(V);
+  return 0;
+}
+
+/* y = A x, exposed for checks of the sparse product alone */
+void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+              const double *x, double *y) {
+  csr_t A = {n, rowptr, col, val};
+  double S[NS];
+  spmv(&A, x, y, S);
+}
+
+int orc_nv(void) { return NV; }
+int orc_ns(void) { return NS; }

@@ -1,0 +1,291 @@
+"""Seeded synthetic inputs for the pipelined BiCGSafe solvers.
+
+This module builds sparse matrices (CSR, FP64 values, int32 column indices,
+int64 row pointers) and right-hand sides.  It holds none of the solver's
+arithmetic: it is shared by the CPU oracle's tests and by the GPU path so
+that both see bit-identical inputs.
+
+The paper's experiments (Section 5) use SuiteSparse matrices that are not
+available here; the generators below produce synthetic matrices of the same
+classes (3D fluid-dynamics stencils with ~7 nonzeros per row, and uneven
+rows with ~27 nonzeros per row) and keep the paper's protocol: the exact
+solution is the all-ones vector (``b = A * 1``), ``x0 = 0``, FP64.
+
+Discretisation used for the convection-diffusion families (the paper has no
+PDE of its own): vertex-centred finite differences on the unit square/cube
+with ``N`` interior nodes per dimension, ``h = 1/(N+1)``, homogeneous
+Dirichlet boundaries (neighbours outside the domain are dropped), rows scaled
+by ``h^2``.  Diffusion uses the harmonic mean of the two node coefficients on
+each face (the node's own coefficient on a boundary face); convection is
+first-order upwind.  Node order is lexicographic with x fastest, and columns
+are ascending within each row.
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+
+import numpy as np
+
+__all__ = [
+    "CSR", "convection_diffusion", "cd2d", "cd3d", "rand_band", "rhs_ones",
+    "identity", "diag_distinct", "skew_blocks", "small_nonsym", "random_csr",
+    "workload", "WORKLOADS",
+]
+
+
+@dataclasses.dataclass
+class CSR:
+    """A square sparse matrix in CSR form plus its right-hand side."""
+    n: int
+    rowptr: np.ndarray  # int64[n+1]
+    col: np.ndarray     # int32[nnz]
+    val: np.ndarray     # float64[nnz]
+    b: np.ndarray | None = None  # float64[n]
+    name: str = ""
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=(self.n, self.n))
+
+    def to_dense(self) -> np.ndarray:
+        d = np.zeros((self.n, self.n))
+        rows = np.repeat(np.arange(self.n), np.diff(self.rowptr))
+        np.add.at(d, (rows, self.col.astype(np.int64)), self.val)
+        return d
+
+
+def rhs_ones(rowptr: np.ndarray, val: np.ndarray) -> np.ndarray:
+    """``b = A * 1``: the FP64 row sums of ``A`` (so the exact solution is all ones)."""
+    n = len(rowptr) - 1
+    b = np.zeros(n)
+    nz = np.diff(rowptr) > 0
+    if val.size:
+        b[nz] = np.add.reduceat(val, rowptr[:-1][nz])
+    return b
+
+
+def _from_dense_rows(cols: np.ndarray, vals: np.ndarray, mask: np.ndarray, name: str) -> CSR:
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(cols.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    col = cols[mask].astype(np.int32)
+    val = vals[mask].astype(np.float64)
+    return CSR(cols.shape[0], rowptr, col, val, rhs_ones(rowptr, val), name)
+
+
+def convection_diffusion(N: int, velocity, kfield: np.ndarray | None = None, name: str = "") -> CSR:
+    """Upwind convection-diffusion operator on an ``N^d`` grid (d = len(velocity)).
+
+    ``kfield`` holds the diffusion coefficient per node, shaped ``(N,)*d``
+    with the x axis last (fastest); ``None`` means constant 1.
+    """
+    d = len(velocity)
+    n = N ** d
+    h = 1.0 / (N + 1)
+    shape = (N,) * d
+    k = np.ones(shape) if kfield is None else np.asarray(kfield, dtype=np.float64).reshape(shape)
+    # axis a of the numpy array holds grid direction (d-1-a); direction 0 (x) is fastest
+    idx = np.arange(n, dtype=np.int64).reshape(shape)
+    # slots: -e_{d-1} .. -e_0, diag, +e_0 .. +e_{d-1}: ascending column offsets
+    nslot = 2 * d + 1
+    cols = np.zeros((n, nslot), dtype=np.int64)
+    vals = np.zeros((n, nslot))
+    mask = np.zeros((n, nslot), dtype=bool)
+    diag = np.zeros(shape)
+    cols[:, d] = idx.ravel()
+    mask[:, d] = True
+    for direction in range(d):
+        ax = d - 1 - direction
+        stride = N ** direction
+        vd = float(velocity[direction])
+        for sgn in (-1, +1):
+            slot = d + sgn * (direction + 1)
+            # neighbour Q = P + sgn * e_direction, and whether it is inside
+            kq = np.roll(k, -sgn, axis=ax)
+            pos = np.arange(N).reshape([-1 if a == ax else 1 for a in range(d)])
+            inside = (pos + sgn >= 0) & (pos + sgn < N)
+            inside = np.broadcast_to(inside, shape)
+            kf = np.where(inside, 2.0 * k * kq / (k + kq), k)
+            diag += kf
+            off = -kf
+            upstream = (vd > 0 and sgn < 0) or (vd < 0 and sgn > 0)
+            if upstream:
+                off = off - h * abs(vd)
+            cols[:, slot] = (idx + sgn * stride).ravel()
+            vals[:, slot] = np.where(inside, off, 0.0).ravel()
+            mask[:, slot] = inside.ravel()
+        diag += h * abs(vd)
+    vals[:, d] = diag.ravel()
+    return _from_dense_rows(cols, vals, mask, name or f"cd{d}d_{N}")
+
+
+def cd2d(N: int = 64, beta: float = 10.0, kfield=None) -> CSR:
+    """2D 5-point upwind convection-diffusion, convection (beta, beta)."""
+    return convection_diffusion(N, (beta, beta), kfield, name=f"cd2d_{N}")
+
+
+def cd3d(N: int = 128, beta: float = 20.0, seed: int = 2108) -> CSR:
+    """3D 7-point upwind convection-diffusion, convection (1,1,1)*beta, diffusion exp(N(0,1)) per node."""
+    rng = np.random.default_rng(seed)
+    k = np.exp(rng.standard_normal((N, N, N)))
+    return convection_diffusion(N, (beta, beta, beta), k, name=f"cd3d_{N}")
+
+
+def rand_band(n: int = 1_000_000, seed: int = 10591, gamma: float = 1.37629, lmin: int = 3,
+              lmax: int = 200, band: int = 5000, diag_factor: float = 1.1) -> CSR:
+    """Random nonsymmetric CSR with uneven rows.
+
+    Row lengths (diagonal included) follow p(L) ~ L^-gamma on [lmin, lmax]
+    (gamma = 1.37629 gives mean 27 on [3, 200]); off-diagonal columns are drawn
+    uniformly without replacement within +-band of the diagonal; off-diagonal
+    values are U(-1, 1) and the diagonal is diag_factor times the row's
+    absolute off-diagonal sum.
+    """
+    rng = np.random.default_rng(seed)
+    lengths = np.arange(lmin, lmax + 1)
+    p = lengths.astype(np.float64) ** -gamma
+    p /= p.sum()
+    L = rng.choice(lengths, size=n, p=p)
+    m = (L - 1).astype(np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), m)
+    lo = np.maximum(0, rows - band)
+    hi = np.minimum(n - 1, rows + band)
+    width = hi - lo  # candidates excluding the diagonal
+    c = lo + rng.integers(0, width)
+    c += c >= rows
+    # redraw duplicated (row, col) pairs until every row's columns are distinct
+    while True:
+        key = rows * n + c
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        dup = np.zeros(ks.size, dtype=bool)
+        dup[1:] = ks[1:] == ks[:-1]
+        if not dup.any():
+            break
+        redo = order[dup]
+        cr = lo[redo] + rng.integers(0, width[redo])
+        cr += cr >= rows[redo]
+        c[redo] = cr
+    rows = rows[order]
+    c = c[order]
+    off = rng.uniform(-1.0, 1.0, size=c.size)
+    absum = np.zeros(n)
+    np.add.at(absum, rows, np.abs(off))
+    allrows = np.concatenate([rows, np.arange(n, dtype=np.int64)])
+    allcols = np.concatenate([c, np.arange(n, dtype=np.int64)])
+    allvals = np.concatenate([off, diag_factor * absum])
+    order = np.argsort(allrows * n + allcols, kind="stable")
+    col = allcols[order].astype(np.int32)
+    val = allvals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(L, out=rowptr[1:])
+    return CSR(n, rowptr, col, val, rhs_ones(rowptr, val), f"rand_band_{n}")
+
+
+# ----------------------------------------------------------------------------
+# Small matrices with known structure (for closed-form and special-case checks)
+# ----------------------------------------------------------------------------
+
+def _from_dense(a: np.ndarray, name: str, b: np.ndarray | None = None) -> CSR:
+    n = a.shape[0]
+    mask = a != 0.0
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    cols = np.nonzero(mask)[1].astype(np.int32)
+    val = a[mask].astype(np.float64)
+    bb = rhs_ones(rowptr, val) if b is None else np.asarray(b, dtype=np.float64)
+    return CSR(n, rowptr, cols, val, bb, name)
+
+
+def identity(n: int, seed: int = 0) -> CSR:
+    """A = I with a random right-hand side."""
+    rng = np.random.default_rng(seed)
+    return _from_dense(np.eye(n), f"eye_{n}", rng.uniform(0.5, 1.5, n))
+
+
+def diag_distinct(n: int, eigs, seed: int = 0) -> CSR:
+    """Diagonal A whose entries take exactly the distinct values ``eigs``, each at least once."""
+    rng = np.random.default_rng(seed)
+    eigs = np.asarray(eigs, dtype=np.float64)
+    lam = np.concatenate([eigs, rng.choice(eigs, size=n - len(eigs))])
+    lam = lam[rng.permutation(n)]
+    return _from_dense(np.diag(lam), f"diag{len(eigs)}_{n}", lam * rng.uniform(0.5, 1.5, n))
+
+
+def skew_blocks(n: int, seed: int = 0) -> CSR:
+    """Block-diagonal skew-symmetric matrix of 2x2 blocks [[0, c], [-c, 0]] with integer c and b.
+
+    With integer entries every product is exact, so ``(r, A r)`` is exactly zero.
+    """
+    assert n % 2 == 0
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n, n))
+    for k in range(0, n, 2):
+        c = float(rng.integers(1, 5))
+        a[k, k + 1] = c
+        a[k + 1, k] = -c
+    return _from_dense(a, f"skew_{n}", rng.integers(1, 5, n).astype(np.float64))
+
+
+def small_nonsym(n: int, seed: int, density: float = 0.3, dominance: float = 1.5) -> CSR:
+    """Random sparse nonsymmetric matrix, diagonally dominant by ``dominance``; b = A*1."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, (n, n)) * (rng.random((n, n)) < density)
+    np.fill_diagonal(a, 0.0)
+    np.fill_diagonal(a, dominance * np.abs(a).sum(axis=1) + 1.0)
+    return _from_dense(a, f"nonsym_{n}_{seed}")
+
+
+def random_csr(n: int, seed: int, lengths=None, unsorted: bool = False, duplicates: bool = False) -> CSR:
+    """Random CSR with a given row-length multiset, for SpMV checks.
+
+    ``lengths`` may contain zeros (empty rows) and long rows.  Columns are
+    uniform over [0, n); with ``unsorted`` the columns of each row are
+    shuffled, and with ``duplicates`` some (row, col) pairs repeat.
+    """
+    rng = np.random.default_rng(seed)
+    if lengths is None:
+        lengths = rng.integers(0, 40, n)
+    lengths = np.asarray(lengths, dtype=np.int64)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lengths, out=rowptr[1:])
+    nnz = int(rowptr[-1])
+    col = rng.integers(0, n, nnz).astype(np.int32)
+    if not duplicates:
+        # distinct sorted columns per row (a row longer than n necessarily repeats some)
+        for i in np.nonzero(lengths)[0]:
+            s, e = rowptr[i], rowptr[i + 1]
+            m = int(e - s)
+            col[s:e] = np.sort(rng.choice(n, size=m, replace=m > n))
+    if unsorted:
+        for i in np.nonzero(lengths)[0]:
+            s, e = rowptr[i], rowptr[i + 1]
+            col[s:e] = col[s:e][rng.permutation(int(e - s))]
+    val = rng.uniform(-1.0, 1.0, nnz)
+    return CSR(n, rowptr, col, val, rhs_ones(rowptr, val), f"random_{n}_{seed}")
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+
+WORKLOADS = {
+    # 2D 64x64, convection (10, 10), diffusion 1, tol 1e-10
+    "cd2d_64": dict(tol=1e-10, make=lambda: cd2d(64, 10.0)),
+    # 3D 128^3, convection (20, 20, 20), diffusion exp(N(0,1)) seed 2108, tol 1e-8
+    "cd3d_128": dict(tol=1e-8, make=lambda: cd3d(128, 20.0, 2108)),
+    # random power-law rows in [3, 200] (mean 27), band +-5000, n = 1M, seed 10591, tol 1e-10
+    "rand_band_1m": dict(tol=1e-10, make=lambda: rand_band(1_000_000, 10591)),
+}
+
+
+@functools.lru_cache(maxsize=4)
+def workload(name: str) -> CSR:
+    """Build (and cache per process) one of the named workloads."""
+    return WORKLOADS[name]["make"]()
