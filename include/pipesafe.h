@@ -1,0 +1,203 @@
+/*
+ * pipesafe.h -- C ABI of the MI355X (gfx950) solver library libpipesafe.so.
+ *
+ * The library solves a nonsymmetric sparse system A x = b (Huynh & Suito,
+ * "Communication-hiding pipelined BiCGSafe methods for solving large linear
+ * systems", arXiv 2108.10591, Section 2) with one of four Krylov iterations:
+ *
+ *   PS_SSBICGSAFE2   ssBiCGSafe2, Algorithm 3: one reduction phase of nine
+ *                    inner products per iteration, two sparse products.
+ *   PS_PBICGSAFE     p-BiCGSafe, Algorithm 4: the products A r and A u of
+ *                    Algorithm 3 are replaced by the recurrences of Section 3
+ *                    (Eqs. (s), (q), (w), (l), (g)); the nine inner products
+ *                    are independent of the product A s_i and are reduced
+ *                    concurrently with it.
+ *   PS_PBICGSAFE_RR  p-BiCGSafe-rr, Algorithm 5: p-BiCGSafe with the
+ *                    recursively updated vectors reset to their true values
+ *                    every m iterations while i < M (Section 4).
+ *   PS_PBICGSTAB     pipelined BiCGStab (Cools & Vanroose), cited in the
+ *                    paper's introduction and Table 1: two reduction phases,
+ *                    each concurrent with one sparse product.
+ *
+ * All arithmetic is IEEE binary64 (the paper's experiments are in double
+ * precision, Section 5).  Matrices are CSR with int32 column indices.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: PS_OK (0) or a negative ps_error.  On error, outputs are
+ *     left untouched unless stated otherwise.  Not converging is NOT an error:
+ *     the call returns PS_OK and reports it in *status.
+ *   - The caller owns every pointer it passes; the library never frees or
+ *     retains caller memory past the call.
+ *   - A handle is not thread-safe: a call that finds the handle in use by
+ *     another thread returns PS_EBUSY.
+ *   - "host" pointers point to ordinary CPU memory, "device" pointers to GPU
+ *     memory of the device the handle was created on.
+ */
+#ifndef PIPESAFE_H
+#define PIPESAFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_matrix ps_matrix; /* opaque: device CSR, workspace, streams */
+
+enum ps_variant {
+  PS_SSBICGSAFE2 = 0,
+  PS_PBICGSAFE = 1,
+  PS_PBICGSAFE_RR = 2,
+  PS_PBICGSTAB = 3
+};
+
+/* outcome of a solve (Section 5: converged, or stopped at the iteration limit) */
+enum ps_status {
+  PS_CONVERGED = 0, /* ||r_i|| <= tol * ||r_ref||                                     */
+  PS_MAXIT = 1,     /* reached i = maxit without converging                           */
+  PS_BREAKDOWN = 2, /* a coefficient denominator was exactly zero or not finite       */
+  PS_NONFINITE = 3  /* an inner product was NaN or infinite (e.g. NaN in b)           */
+};
+
+enum ps_error {
+  PS_OK = 0,
+  PS_EINVAL = -1, /* invalid argument (sizes, CSR structure, variant, options)        */
+  PS_ENOMEM = -2, /* device or host allocation failed                                 */
+  PS_EHIP = -3,   /* a HIP runtime call failed                                        */
+  PS_EBUSY = -4,  /* the handle is in use by another thread                           */
+  PS_ENODEV = -5  /* no usable gfx950 device                                          */
+};
+
+typedef struct {
+  int32_t rr_m;        /* replacement period m of Algorithm 5 (default 100; Section 5.2).
+                          <= 0 disables replacement. Ignored by other variants.          */
+  int32_t rr_M;        /* no replacement at i >= M (Algorithm 5); <= 0 means maxit.     */
+  int32_t norm_ref;    /* stop-test scale: 0 = ||r_0|| (the paper's criterion, default),
+                          1 = ||b||.                                                     */
+  int32_t batch_iters; /* iterations enqueued between host checks of the device stop
+                          flag; 0 = automatic.  Iterations enqueued after the stop are
+                          no-ops, so the result does not depend on this value.           */
+  int32_t overlap;     /* 1 (default): the reduction phase runs on a second stream
+                          concurrently with the sparse product it is independent of;
+                          0: everything on one stream (results are bit-identical).      */
+  int32_t profile;     /* bit mask of ps_kernel classes to time with HIP events on the
+                          stream each kernel runs on; 0 (default) = none.               */
+  int32_t resume;      /* 0 (default): initialise from b and x0.  1: skip initialisation
+                          and continue from the state loaded by ps_set_state /
+                          ps_set_scalars, starting at iteration resume_iter.            */
+  int32_t resume_iter;
+  void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
+                          caller's current stream).  NULL: ps_solve_dev uses the null
+                          stream, ps_solve the library's own stream.                   */
+} ps_options;
+
+/* classes of kernels, for ps_options.profile and ps_kernel_stats */
+enum ps_kernel {
+  PS_K_SPMV = 0,       /* sparse product with no fused work (A s_i, A z_i, ...)         */
+  PS_K_DOTS = 1,       /* multi-inner-product kernel with its last-block finish         */
+  PS_K_UPDATE = 2,     /* fused vector-update pass                                       */
+  PS_K_SPMV_FUSED = 3, /* sparse product with a fused update epilogue                    */
+  PS_K_OTHER = 4,      /* set-up, replacement and bookkeeping kernels                    */
+  PS_K_COUNT = 5
+};
+
+/* state vectors, for ps_get_state / ps_set_state (names follow Algorithms 3-5;
+   for PS_PBICGSTAB: s = A p, z = A s, w = A r, t = A w, v = A z, q = r - alpha s,
+   y = A q).  Each is double[n]. */
+enum ps_vec {
+  PS_V_X = 0, PS_V_R, PS_V_RS /* r0* */, PS_V_S, PS_V_Y, PS_V_T, PS_V_P, PS_V_U, PS_V_Z,
+  PS_V_W, PS_V_L, PS_V_G, PS_V_Q, PS_V_O, PS_V_AS, PS_V_V, PS_V_B, PS_V_COUNT
+};
+
+/* scalar state, for ps_get_scalars / ps_set_scalars (double[PS_S_COUNT]) */
+enum ps_scalar {
+  PS_S_ALPHA = 0,  /* alpha of the last coefficient update (p-BiCGStab: alpha_i)         */
+  PS_S_BETA,       /* beta used in p_i                                                   */
+  PS_S_ZETA,
+  PS_S_ETA,
+  PS_S_OMEGA,      /* p-BiCGStab: omega_{i-1}                                            */
+  PS_S_F,          /* (r0*, r) of the last coefficient update                           */
+  PS_S_RHOREF,     /* squared stop-test scale (||r_0||^2 or ||b||^2)                      */
+  PS_S_RHO,        /* (r_i, r_i) of the last reduction phase                             */
+  PS_S_PENDING,    /* p-BiCGStab: 1 if alpha_i/beta_{i-1} could not be formed            */
+  PS_S_GS,         /* p-BiCGStab: (r0*, s), (r0*, w), (r0*, z) of the last phase          */
+  PS_S_GW,
+  PS_S_GZ,
+  PS_S_COUNT
+};
+
+/* Fill *opt with the defaults documented above. */
+void ps_default_options(ps_options *opt);
+
+/*
+ * Create a solver handle for the n x n CSR matrix (rowptr, col, val), all HOST
+ * pointers: rowptr int64[n+1], col int32[nnz], val double[nnz].  The matrix is
+ * copied to the current HIP device; the caller may free its arrays on return.
+ * Validation: n >= 1, nnz = rowptr[n] < 2^31, rowptr[0] = 0, rowptr
+ * non-decreasing, 0 <= col < n, val finite; otherwise PS_EINVAL.  Columns need
+ * not be sorted; duplicate (row, col) entries are summed; empty rows are
+ * allowed (they make A singular).
+ */
+int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+              const double *val);
+
+/*
+ * Solve A x = b from HOST buffers.  b: double[n]; x0: double[n] or NULL (zero,
+ * the paper's x_0); x: double[n] output, x_{iters}.  tol: the run stops when
+ * ||r_i|| <= tol * ||r_ref|| (Section 5 uses 1e-8 and ||r_0||).  maxit >= 0: at
+ * i = maxit the run stops with PS_MAXIT.  variant: ps_variant.  opt: NULL for
+ * defaults.  hist: NULL or double[maxit+1]; receives hist[k] = ||r_k||/||r_ref||
+ * for k = 0..iters from the recursively updated residual (the quantity
+ * Algorithms 3-5 test).  iters: the number of x updates made.  status:
+ * ps_status.  PS_EINVAL for a bad variant, negative maxit, negative or NaN tol.
+ */
+int ps_solve(ps_matrix *A, const double *b, const double *x0, double tol, int32_t maxit,
+             int32_t variant, const ps_options *opt, double *x, int32_t *iters, double *hist,
+             int32_t *status);
+
+/*
+ * As ps_solve, with b, x0 (or NULL) and x in DEVICE memory; hist, iters and
+ * status are HOST pointers.  Work is ordered on opt->stream (or the library's
+ * stream); the call returns after the solve has finished on the device.
+ */
+int ps_solve_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol, int32_t maxit,
+                 int32_t variant, const ps_options *opt, double *x_dev, int32_t *iters,
+                 double *hist, int32_t *status);
+
+/* y = A x with x, y DEVICE double[n] (x and y must not overlap), ordered on
+   `stream` (hipStream_t, NULL = the null stream); returns after completion. */
+int ps_spmv_dev(ps_matrix *A, const double *x_dev, double *y_dev, void *stream);
+
+/* Copy state vector `which` (ps_vec) of the last solve into HOST double[n]. */
+int ps_get_state(ps_matrix *A, int32_t which, double *host_out);
+/* Load state vector `which` from HOST double[n] (for opt.resume). */
+int ps_set_state(ps_matrix *A, int32_t which, const double *host_in);
+/* Copy / load the scalar state, HOST double[PS_S_COUNT]. */
+int ps_get_scalars(ps_matrix *A, double *host_out);
+int ps_set_scalars(ps_matrix *A, const double *host_in);
+
+/* Kernel timing of the last solve run with opt.profile != 0: total milliseconds
+   and launch count of class `cls` (ps_kernel), measured with HIP events around
+   each launch on its own stream. */
+int ps_kernel_stats(ps_matrix *A, int32_t cls, double *total_ms, int64_t *launches);
+
+/* Device copy dst = src of `bytes` bytes (DEVICE pointers, 16-byte aligned,
+   bytes a multiple of 16) with a plain streaming kernel of the library's own;
+   used to calibrate bandwidth counters and the copy ceiling.  Ordered on
+   `stream`; returns after completion. */
+int ps_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
+/* Release the handle and all device memory it owns.  NULL is accepted. */
+int ps_destroy(ps_matrix *A);
+
+/* Static description of a ps_error or ps_status code. */
+const char *ps_strerror(int code);
+
+/* Library version string. */
+const char *ps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIPESAFE_H */

@@ -1,0 +1,321 @@
+// Multi-inner-product kernels with a last-block finish.
+//
+// One pass over the input vectors forms every inner product of a reduction
+// phase at once: each thread keeps one accumulator per product over a fixed
+// grid-stride set of entries, the block combines them with wavefront
+// shuffles and LDS, and each block writes its partial sums.  The block that
+// arrives last (atomic ticket) adds the partials in block order -- so the
+// result is bit-for-bit reproducible -- and then computes the phase's scalar
+// coefficients and the stop test on the device.  No host round trip.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace ps {
+
+struct DotArgs {
+  const double *v[5];  // input vectors
+  int64_t n;
+  double *partials;    // [ND][gridDim.x]
+  int *ctl;
+  double *sc;
+  double *hist;
+  int iter, maxit;
+  double tol;
+  int flags;           // finish-specific flags
+};
+
+enum DotFlags : int {
+  DF_SET_REF = 1,      // take rho of this phase as the stop-test reference (||r_0||^2)
+};
+
+// ---------------------------------------------------------------- products
+
+// the nine inner products of Algorithms 3-5 over (s, y, r, r0*, t_{i-1}):
+// a=(s,s) b=(y,y) c=(s,y) d=(s,r) e=(y,r) f=(r0*,r) g=(r0*,s) h=(r0*,t) rho=(r,r).
+// FIRST: i = 0, where only a, d, f, g, rho are formed (y_0 = t_{-1} = 0).
+template <bool FIRST>
+struct ProdSafe9 {
+  static constexpr int NIN = FIRST ? 3 : 5;
+  static constexpr int ND = 9;
+  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
+    in[0] = A.v[0][k];  // s
+    in[2] = A.v[2][k];  // r
+    in[3] = A.v[3][k];  // r0*
+    if (!FIRST) {
+      in[1] = A.v[1][k];  // y
+      in[4] = A.v[4][k];  // t
+    }
+  }
+  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+    const double s = in[0], r = in[2], rs = in[3];
+    a[0] += s * s;
+    a[3] += s * r;
+    a[5] += rs * r;
+    a[6] += rs * s;
+    a[8] += r * r;
+    if (!FIRST) {
+      const double y = in[1], t = in[4];
+      a[1] += y * y;
+      a[2] += s * y;
+      a[4] += y * r;
+      a[7] += rs * t;
+    }
+  }
+};
+
+// p-BiCGStab phase 1: (q, y), (y, y)
+struct ProdStab2 {
+  static constexpr int ND = 2;
+  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
+    in[0] = A.v[0][k];
+    in[1] = A.v[1][k];
+  }
+  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+    a[0] += in[0] * in[1];
+    a[1] += in[1] * in[1];
+  }
+};
+
+// p-BiCGStab phase 2: (r0*, r), (r0*, w), (r0*, s), (r0*, z), (r, r)
+// inputs: v = {r0*, r, w, s, z}
+struct ProdStab5 {
+  static constexpr int ND = 5;
+  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) in[j] = A.v[j][k];
+  }
+  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+    const double rs = in[0], r = in[1];
+    a[0] += rs * r;
+    a[1] += rs * in[2];
+    a[2] += rs * in[3];
+    a[3] += rs * in[4];
+    a[4] += r * r;
+  }
+};
+
+// p-BiCGStab set-up: (r0*, r0), (r0*, w0), (r0, r0); inputs v = {r0*, r, w}
+struct ProdStab3 {
+  static constexpr int ND = 3;
+  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) in[j] = A.v[j][k];
+  }
+  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+    a[0] += in[0] * in[1];
+    a[1] += in[0] * in[2];
+    a[2] += in[1] * in[1];
+  }
+};
+
+// (v, v): the squared norm of b for the ||b|| stop-test scale
+struct ProdNorm {
+  static constexpr int ND = 1;
+  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
+    in[0] = A.v[0][k];
+  }
+  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+    a[0] += in[0] * in[0];
+  }
+};
+
+// ---------------------------------------------------------------- finishes
+// Run by one thread with the phase's final inner products.
+
+// Algorithms 3-5: stop test first, then beta, alpha, zeta, eta.
+struct FinSafe {
+  __device__ static void run(const DotArgs &A, const double (&d)[9]) {
+    double *sc = A.sc;
+    const double a = d[0], b = d[1], c = d[2], dd = d[3], e = d[4], f = d[5], g = d[6], h = d[7],
+                 rho = d[8];
+    for (int j = 0; j < 9; ++j) sc[SC_DOTS + j] = d[j];
+    sc[PS_S_RHO] = rho;
+    bool finite = true;
+    for (int j = 0; j < 9; ++j) finite = finite && isfinite(d[j]);
+    if (!finite) {
+      A.hist[A.iter] = NAN;
+      set_stop(A.ctl, PS_NONFINITE, A.iter);
+      return;
+    }
+    if (A.flags & DF_SET_REF) sc[PS_S_RHOREF] = rho;
+    if (stop_test(rho, sc, A.ctl, A.hist, A.iter, A.maxit, A.tol)) return;
+    double beta, alpha, zeta, eta;
+    if (A.iter == 0) {
+      if (bad_den(g) || bad_den(a)) {
+        set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+        return;
+      }
+      beta = 0.0;
+      alpha = f / g;
+      zeta = dd / a;
+      eta = 0.0;
+    } else {
+      const double den_beta = sc[PS_S_ZETA] * sc[PS_S_F];
+      if (bad_den(den_beta)) {
+        set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+        return;
+      }
+      beta = (sc[PS_S_ALPHA] * f) / den_beta;
+      const double den_alpha = g + beta * h;
+      const double den_ze = a * b - c * c;
+      if (bad_den(den_alpha) || bad_den(den_ze)) {
+        set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+        return;
+      }
+      alpha = f / den_alpha;
+      zeta = (b * dd - c * e) / den_ze;
+      eta = (a * e - c * dd) / den_ze;
+    }
+    if (!isfinite(beta) || !isfinite(alpha) || !isfinite(zeta) || !isfinite(eta)) {
+      set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+      return;
+    }
+    sc[PS_S_ALPHA] = alpha;
+    sc[PS_S_BETA] = beta;
+    sc[PS_S_ZETA] = zeta;
+    sc[PS_S_ETA] = eta;
+    sc[PS_S_F] = f;
+  }
+};
+
+// p-BiCGStab phase 1: omega_i = (q, y)/(y, y); (y, y) = 0 gives omega = 0.
+struct FinStabOmega {
+  __device__ static void run(const DotArgs &A, const double (&d)[2]) {
+    double *sc = A.sc;
+    sc[SC_DOTS + 0] = d[0];
+    sc[SC_DOTS + 1] = d[1];
+    if (!isfinite(d[0]) || !isfinite(d[1])) {
+      set_stop(A.ctl, PS_NONFINITE, A.iter);
+      return;
+    }
+    const double om = d[1] == 0.0 ? 0.0 : d[0] / d[1];
+    if (!isfinite(om)) {
+      set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+      return;
+    }
+    sc[PS_S_OMEGA] = om;
+  }
+};
+
+// p-BiCGStab phase 2 of iteration i: beta_i and alpha_{i+1}, then the stop
+// test of iteration i+1 on rho_{i+1}.  A coefficient that cannot be formed is
+// a breakdown only if the solve does not stop there.
+struct FinStabBetaAlpha {
+  __device__ static void run(const DotArgs &A, const double (&d)[5]) {
+    double *sc = A.sc;
+    const double f = d[0], gw = d[1], gs = d[2], gz = d[3], rho = d[4];
+    for (int j = 0; j < 5; ++j) sc[SC_DOTS + j] = d[j];
+    const int i1 = A.iter + 1;
+    const double al = sc[PS_S_ALPHA], om = sc[PS_S_OMEGA];
+    double beta = 0.0, alpha = 0.0;
+    bool pend = false;
+    const double den_beta = om * sc[PS_S_F];
+    if (bad_den(den_beta)) {
+      pend = true;
+    } else {
+      beta = (al * f) / den_beta;
+      const double den_alpha = gw + beta * gs - beta * om * gz;
+      if (bad_den(den_alpha)) pend = true;
+      else alpha = f / den_alpha;
+      if (!isfinite(beta) || !isfinite(alpha)) pend = true;
+    }
+    sc[PS_S_ALPHA] = alpha;
+    sc[PS_S_BETA] = beta;
+    sc[PS_S_F] = f;
+    sc[PS_S_GW] = gw;
+    sc[PS_S_GS] = gs;
+    sc[PS_S_GZ] = gz;
+    sc[PS_S_RHO] = rho;
+    sc[PS_S_PENDING] = pend ? 1.0 : 0.0;
+    if (!isfinite(f) || !isfinite(gw) || !isfinite(gs) || !isfinite(gz) || !isfinite(rho)) {
+      A.hist[i1] = NAN;
+      set_stop(A.ctl, PS_NONFINITE, i1);
+      return;
+    }
+    if (stop_test(rho, sc, A.ctl, A.hist, i1, A.maxit, A.tol)) return;
+    if (pend) set_stop(A.ctl, PS_BREAKDOWN, i1);
+  }
+};
+
+// p-BiCGStab set-up: alpha_0 = (r0*, r0)/(r0*, w0), then the stop test at i = 0.
+struct FinStabSetup {
+  __device__ static void run(const DotArgs &A, const double (&d)[3]) {
+    double *sc = A.sc;
+    const double f = d[0], gw = d[1], rho = d[2];
+    for (int j = 0; j < 3; ++j) sc[SC_DOTS + j] = d[j];
+    const bool pend = bad_den(gw) || !isfinite(f / gw);
+    sc[PS_S_ALPHA] = pend ? 0.0 : f / gw;
+    sc[PS_S_BETA] = 0.0;
+    sc[PS_S_OMEGA] = 0.0;
+    sc[PS_S_F] = f;
+    sc[PS_S_GW] = gw;
+    sc[PS_S_GS] = 0.0;
+    sc[PS_S_GZ] = 0.0;
+    sc[PS_S_RHO] = rho;
+    sc[PS_S_PENDING] = pend ? 1.0 : 0.0;
+    if (A.flags & DF_SET_REF) sc[PS_S_RHOREF] = rho;
+    if (!isfinite(f) || !isfinite(gw) || !isfinite(rho)) {
+      A.hist[0] = NAN;
+      set_stop(A.ctl, PS_NONFINITE, 0);
+      return;
+    }
+    if (stop_test(rho, sc, A.ctl, A.hist, 0, A.maxit, A.tol)) return;
+    if (pend) set_stop(A.ctl, PS_BREAKDOWN, 0);
+  }
+};
+
+// ||b||^2 as the stop-test reference
+struct FinNormRef {
+  __device__ static void run(const DotArgs &A, const double (&d)[1]) { A.sc[PS_S_RHOREF] = d[0]; }
+};
+
+// ---------------------------------------------------------------- the kernel
+
+template <class Prod, class Fin>
+__global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
+  constexpr int ND = Prod::ND;
+  __shared__ double lds[kWavesPerBlock * 9 + 16];
+  __shared__ int last;
+  if (A.ctl[C_DONE]) return;
+  double acc[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  double in[5];
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < A.n; k += stride) {
+    Prod::load(A, k, in);
+    Prod::acc(in, acc);
+  }
+  double s = block_sum_k<ND>(acc, lds);
+  const int G = gridDim.x;
+  if (threadIdx.x < ND) {
+    A.partials[threadIdx.x * G + blockIdx.x] = s;
+    __threadfence();  // publish the partial device-wide before taking a ticket
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&A.ctl[C_TICKET], 1) == G - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // acquire: see every block's partials
+  double tot[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) tot[j] = 0.0;
+  for (int b = threadIdx.x; b < G; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) tot[j] += __builtin_nontemporal_load(&A.partials[j * G + b]);
+  }
+  s = block_sum_k<ND>(tot, lds);
+  __shared__ double fin[9];
+  if (threadIdx.x < ND) fin[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) d[j] = fin[j];
+    A.ctl[C_TICKET] = 0;
+    Fin::run(A, d);
+  }
+}
+
+}  // namespace ps

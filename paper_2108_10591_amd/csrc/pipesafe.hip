@@ -1,0 +1,677 @@
+// libpipesafe: host driver and C ABI of the gfx950 BiCGSafe-family solvers.
+//
+// Iteration schedules (one enqueue per iteration; every kernel reads the
+// device stop flag, so iterations enqueued past the stop are no-ops and the
+// host only polls the flag once per batch of iterations):
+//
+//   p-BiCGSafe (Algorithm 4), iteration i:
+//     stream A:  As_i = A s_i                      (sparse product)
+//     stream B:  9 inner products + finish        (concurrent with A s_i: the
+//                                                  one-GPU form of hiding the
+//                                                  global reduction, Section 3)
+//     stream A:  join; pass A (ten updates); A w_i + pass B (l, g, s) epilogue
+//   ssBiCGSafe2 (Algorithm 3): s_i = A r_i; 9 inner products + finish;
+//     p, u; w_i = A u_i + epilogue (t, z, y, x, r).  One stream: the inner
+//     products need s_i.
+//   p-BiCGSafe-rr (Algorithm 5): p-BiCGSafe, except every m-th iteration
+//     (0 < i < M) runs the replacement step with products A o, A u, A x,
+//     A t, A y, A r (A s_i, unused there, is skipped).
+//   p-BiCGStab: pass 1; [A z_i || (q,y),(y,y) + omega]; pass 2;
+//     [A w_{i+1} || 5 inner products + stop test + beta, alpha].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "pipesafe.h"
+#include "device_common.hpp"
+#include "dots.hpp"
+#include "spmv.hpp"
+#include "updates.hpp"
+
+using namespace ps;
+
+namespace {
+
+constexpr int kSlotTmp = PS_V_COUNT;  // internal scratch vector
+constexpr int kNumSlots = PS_V_COUNT + 1;
+constexpr int kMaxDotGrid = 1024;
+
+struct Timer {
+  hipEvent_t a, b;
+  int cls;
+};
+
+}  // namespace
+
+struct ps_matrix {
+  int device = -1;
+  int64_t n = 0, nnz = 0;
+  int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
+  double *val = nullptr;
+  int nblk = 0, budget = 0;
+  size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
+  double *vec = nullptr;    // kNumSlots * ld doubles
+  double *sc = nullptr;     // SC_COUNT doubles
+  int *ctl = nullptr;       // C_COUNT ints
+  double *partials = nullptr;
+  int dot_grid = 0;
+  double *hist = nullptr;
+  int64_t hist_cap = 0;
+  int *pinned = nullptr;    // 2 * C_COUNT ints of pinned host memory
+  hipStream_t own = nullptr, aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_batch[2] = {nullptr, nullptr};
+  std::atomic<int> busy{0};
+  // kernel timing
+  int prof_mask = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<Timer> timers;
+  double prof_ms[PS_K_COUNT] = {};
+  int64_t prof_cnt[PS_K_COUNT] = {};
+
+  double *slot(int s) const { return vec + (size_t)s * ld; }
+  CsrDev csr() const { return CsrDev{rowptr, col, val, blk, nblk, budget}; }
+};
+
+namespace {
+
+#define PS_HIP(...)                                                                   \
+  do {                                                                                \
+    hipError_t e_ = (__VA_ARGS__);                                                    \
+    if (e_ != hipSuccess) {                                                           \
+      std::fprintf(stderr, "pipesafe: %s failed: %s\n", #__VA_ARGS__, hipGetErrorString(e_)); \
+      return PS_EHIP;                                                                 \
+    }                                                                                 \
+  } while (0)
+
+struct BusyGuard {
+  std::atomic<int> &flag;
+  bool ok;
+  explicit BusyGuard(std::atomic<int> &f) : flag(f) {
+    int expect = 0;
+    ok = flag.compare_exchange_strong(expect, 1);
+  }
+  ~BusyGuard() {
+    if (ok) flag.store(0);
+  }
+};
+
+int next_event(ps_matrix *M, hipEvent_t *ev) {
+  if (M->ev_used == M->ev_pool.size()) {
+    hipEvent_t e;
+    PS_HIP(hipEventCreate(&e));
+    M->ev_pool.push_back(e);
+  }
+  *ev = M->ev_pool[M->ev_used++];
+  return PS_OK;
+}
+
+// Launch `kernel` on `s`, bracketed by timing events when class `cls` is profiled.
+template <typename Kernel, typename... Args>
+int launch(ps_matrix *M, hipStream_t s, int cls, Kernel kernel, dim3 grid, size_t shmem,
+           Args... args) {
+  if (grid.x == 0) return PS_OK;
+  const bool prof = (M->prof_mask >> cls) & 1;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (prof) {
+    if (next_event(M, &a) || next_event(M, &b)) return PS_EHIP;
+    PS_HIP(hipEventRecord(a, s));
+  }
+  hipLaunchKernelGGL(kernel, grid, dim3(kBlock), shmem, s, args...);
+  if (prof) {
+    PS_HIP(hipEventRecord(b, s));
+    M->timers.push_back(Timer{a, b, cls});
+  }
+  return PS_OK;
+}
+
+#define PS_TRY(...)                 \
+  do {                              \
+    int rc_ = (__VA_ARGS__);        \
+    if (rc_ != PS_OK) return rc_;   \
+  } while (0)
+
+dim3 pair_grid(int64_t n) { return dim3((unsigned)((n + 2 * kBlock - 1) / (2 * kBlock))); }
+dim3 elem_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
+
+template <class Epi>
+int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop) {
+  return launch(M, s, cls, k_spmv<Epi>, dim3(M->nblk), (size_t)M->budget * sizeof(double),
+                M->csr(), x, epi, stop);
+}
+
+template <class Prod, class Fin>
+int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, int iter,
+         int maxit, double tol, int flags, double *hist) {
+  DotArgs A{};
+  int j = 0;
+  for (const double *p : in) A.v[j++] = p;
+  A.n = M->n;
+  A.partials = M->partials;
+  A.ctl = M->ctl;
+  A.sc = M->sc;
+  A.hist = hist;
+  A.iter = iter;
+  A.maxit = maxit;
+  A.tol = tol;
+  A.flags = flags;
+  return launch(M, s, PS_K_DOTS, k_dots<Prod, Fin>, dim3(M->dot_grid), 0, A);
+}
+
+// ------------------------------------------------------------------ set-up
+
+int zero_slots(ps_matrix *M, hipStream_t s, std::initializer_list<int> slots) {
+  for (int sl : slots)
+    PS_TRY(launch(M, s, PS_K_OTHER, k_zero, elem_grid(M->n), 0, M->slot(sl), (int64_t)M->ld, 1,
+                  M->n));
+  return PS_OK;
+}
+
+struct Plan {
+  int variant;
+  int maxit;
+  double tol;
+  int rr_m, rr_M;
+  int norm_ref;
+  bool resume;
+  int i0;
+  hipStream_t A, B;
+  bool overlap;
+};
+
+// r_0 = b - A x_0, r0* = r_0 and the zero vectors of each algorithm (x_0 and b
+// are already in their slots).
+int enqueue_setup(ps_matrix *M, const Plan &P) {
+  hipStream_t s = P.A;
+  double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *RS = M->slot(PS_V_RS),
+         *Bv = M->slot(PS_V_B);
+  if (P.variant == PS_PBICGSTAB) {
+    PS_TRY(zero_slots(M, s, {PS_V_P, PS_V_S, PS_V_Z, PS_V_V, PS_V_Q, PS_V_Y, PS_V_U, PS_V_L,
+                             PS_V_G, PS_V_O, PS_V_AS}));
+  } else {
+    PS_TRY(zero_slots(M, s, {PS_V_Y, PS_V_T, PS_V_P, PS_V_U, PS_V_Z, PS_V_W, PS_V_L, PS_V_G,
+                             PS_V_Q, PS_V_O, PS_V_AS, PS_V_V}));
+  }
+  PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, nullptr));
+  if (P.variant == PS_PBICGSAFE || P.variant == PS_PBICGSAFE_RR) {
+    // s_0 = A r_0 (its definition s_i := A r_i; Algorithm 4 uses s_0 without forming it)
+    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, nullptr));
+  }
+  if (P.norm_ref == 1) {
+    PS_TRY(dots<ProdNorm, FinNormRef>(M, s, {Bv}, 0, P.maxit, P.tol, 0, M->hist));
+  }
+  if (P.variant == PS_PBICGSTAB) {
+    double *W = M->slot(PS_V_W), *T = M->slot(PS_V_T);
+    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{W}, nullptr));  // w_0 = A r_0
+    PS_TRY(spmv(M, s, PS_K_OTHER, W, EpiStore{T}, nullptr));  // t_0 = A w_0
+    PS_TRY(dots<ProdStab3, FinStabSetup>(M, s, {RS, R, W}, 0, P.maxit, P.tol,
+                                         P.norm_ref == 0 ? DF_SET_REF : 0, M->hist));
+  }
+  return PS_OK;
+}
+
+// fork: stream B waits for everything enqueued on A so far
+int fork(ps_matrix *M, const Plan &P) {
+  if (!P.overlap) return PS_OK;
+  PS_HIP(hipEventRecord(M->ev_fork, P.A));
+  PS_HIP(hipStreamWaitEvent(P.B, M->ev_fork, 0));
+  return PS_OK;
+}
+// join: stream A waits for everything enqueued on B so far
+int join(ps_matrix *M, const Plan &P) {
+  if (!P.overlap) return PS_OK;
+  PS_HIP(hipEventRecord(M->ev_join, P.B));
+  PS_HIP(hipStreamWaitEvent(P.A, M->ev_join, 0));
+  return PS_OK;
+}
+
+// ------------------------------------------------------------ iterations
+
+int iter_safe_dots(ps_matrix *M, const Plan &P, hipStream_t s, int i) {
+  const int flags = (i == 0 && !P.resume && P.norm_ref == 0) ? DF_SET_REF : 0;
+  double *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y), *R = M->slot(PS_V_R),
+         *RS = M->slot(PS_V_RS), *T = M->slot(PS_V_T);
+  if (i == 0)
+    return dots<ProdSafe9<true>, FinSafe>(M, s, {S, Y, R, RS, T}, i, P.maxit, P.tol, flags, M->hist);
+  return dots<ProdSafe9<false>, FinSafe>(M, s, {S, Y, R, RS, T}, i, P.maxit, P.tol, flags, M->hist);
+}
+
+int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
+  hipStream_t A = P.A;
+  double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y),
+         *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P), *U = M->slot(PS_V_U), *Z = M->slot(PS_V_Z),
+         *W = M->slot(PS_V_W), *L = M->slot(PS_V_L), *G = M->slot(PS_V_G), *Q = M->slot(PS_V_Q),
+         *O = M->slot(PS_V_O), *As = M->slot(PS_V_AS), *Bv = M->slot(PS_V_B);
+  const bool replace = P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && (i % P.rr_m) == 0 && i > 0 &&
+                       i < P.rr_M;
+  int *done = M->ctl + C_DONE;
+  if (!replace) {
+    PS_TRY(fork(M, P));
+    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, M->ctl + C_HALT));  // As_i
+    PS_TRY(iter_safe_dots(M, P, P.B, i));                              // concurrently
+    PS_TRY(join(M, P));
+    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n};
+    PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe, pair_grid(M->n), 0, pa));
+    PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, done));
+    return PS_OK;
+  }
+  // replacement step (Algorithm 5): true values of q, w, r, l, g, s
+  PS_TRY(iter_safe_dots(M, P, A, i));
+  PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n};
+  PS_TRY(launch(M, A, PS_K_OTHER, k_pou, pair_grid(M->n), 0, po));
+  PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, done));  // q_i = A o_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, done));  // w_i = A u_i
+  TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n};
+  PS_TRY(launch(M, A, PS_K_OTHER, k_tzyx, pair_grid(M->n), 0, tz));
+  PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, done));  // r_{i+1} = b - A x_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, done));                  // l_i = A t_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, Y, EpiStore{G}, done));                  // g_{i+1} = A y_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, R, EpiStore{S}, done));                  // s_{i+1} = A r_{i+1}
+  return PS_OK;
+}
+
+int iter_ssbicgsafe2(ps_matrix *M, const Plan &P, int i) {
+  hipStream_t A = P.A;
+  double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y),
+         *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P), *U = M->slot(PS_V_U), *Z = M->slot(PS_V_Z);
+  int *done = M->ctl + C_DONE;
+  PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, done));  // s_i = A r_i
+  PS_TRY(iter_safe_dots(M, P, A, i));
+  PouArgs po{R, S, T, Y, Pp, U, nullptr, M->sc, M->ctl, M->n};
+  PS_TRY(launch(M, A, PS_K_UPDATE, k_pu, pair_grid(M->n), 0, po));
+  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, done));
+  return PS_OK;
+}
+
+int iter_pbicgstab(ps_matrix *M, const Plan &P, int i) {
+  hipStream_t A = P.A;
+  double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *RS = M->slot(PS_V_RS),
+         *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y), *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P),
+         *Z = M->slot(PS_V_Z), *W = M->slot(PS_V_W), *Q = M->slot(PS_V_Q), *V = M->slot(PS_V_V);
+  Stab1Args s1{R, W, T, V, Pp, S, Z, Q, Y, M->sc, M->ctl, M->n};
+  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1, pair_grid(M->n), 0, s1));
+  PS_TRY(fork(M, P));
+  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, M->ctl + C_HALT));  // v_i = A z_i
+  PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, i, P.maxit, P.tol, 0, M->hist));
+  PS_TRY(join(M, P));
+  Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n};
+  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2, pair_grid(M->n), 0, s2));
+  PS_TRY(fork(M, P));
+  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, M->ctl + C_HALT));  // t_{i+1} = A w_{i+1}
+  PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, i, P.maxit, P.tol, 0,
+                                           M->hist));
+  PS_TRY(join(M, P));
+  return PS_OK;
+}
+
+// Iterations past this index are never needed: the finish at the last one stops.
+int last_iteration(const Plan &P) { return P.variant == PS_PBICGSTAB ? P.maxit - 1 : P.maxit; }
+
+int auto_batch(const ps_matrix *M) {
+  // keep a batch around 1.5 ms of device time
+  const double bytes = 24.0 * (double)M->nnz + 300.0 * (double)M->n;
+  const double us = bytes / 4.0e6 + 30.0;
+  int k = (int)(1500.0 / us);
+  return std::max(2, std::min(64, k));
+}
+
+int ensure_hist(ps_matrix *M, int64_t need) {
+  if (need <= M->hist_cap) return PS_OK;
+  if (M->hist) {
+    PS_HIP(hipDeviceSynchronize());
+    PS_HIP(hipFree(M->hist));
+    M->hist = nullptr;
+  }
+  int64_t cap = std::max<int64_t>(need, 1024);
+  PS_HIP(hipMalloc(&M->hist, cap * sizeof(double)));
+  M->hist_cap = cap;
+  return PS_OK;
+}
+
+int collect_profile(ps_matrix *M) {
+  for (int c = 0; c < PS_K_COUNT; ++c) {
+    M->prof_ms[c] = 0.0;
+    M->prof_cnt[c] = 0;
+  }
+  for (const Timer &t : M->timers) {
+    float ms = 0.f;
+    PS_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+    M->prof_ms[t.cls] += ms;
+    M->prof_cnt[t.cls] += 1;
+  }
+  M->timers.clear();
+  M->ev_used = 0;
+  return PS_OK;
+}
+
+int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, double tol,
+               int32_t maxit, int32_t variant, const ps_options *opt, double *x, int32_t *iters,
+               double *hist, int32_t *status) {
+  if (!M) return PS_EINVAL;
+  if (variant < PS_SSBICGSAFE2 || variant > PS_PBICGSTAB) return PS_EINVAL;
+  if (maxit < 0 || !(tol >= 0.0) || !iters || !status || !x) return PS_EINVAL;
+  ps_options o;
+  ps_default_options(&o);
+  if (opt) o = *opt;
+  if (!o.resume && !b) return PS_EINVAL;
+  if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
+  if (o.resume && (o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
+  BusyGuard guard(M->busy);
+  if (!guard.ok) return PS_EBUSY;
+  PS_HIP(hipSetDevice(M->device));
+
+  Plan P;
+  P.variant = variant;
+  P.maxit = maxit;
+  P.tol = tol;
+  P.rr_m = o.rr_m;
+  P.rr_M = o.rr_M > 0 ? o.rr_M : maxit;
+  P.norm_ref = o.norm_ref;
+  P.resume = o.resume != 0;
+  P.i0 = P.resume ? o.resume_iter : 0;
+  // device-buffer solves follow the caller's stream (NULL = the null stream, which
+  // orders them after the caller's pending work); host-buffer solves default to
+  // the library's own stream
+  P.A = (on_device || o.stream) ? (hipStream_t)o.stream : M->own;
+  P.overlap = o.overlap != 0 && variant != PS_SSBICGSAFE2;
+  P.B = P.overlap ? M->aux : P.A;
+  M->prof_mask = o.profile;
+  M->timers.clear();
+  M->ev_used = 0;
+  PS_TRY(ensure_hist(M, (int64_t)maxit + 2));
+
+  const size_t vbytes = (size_t)M->n * sizeof(double);
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  PS_TRY(launch(M, P.A, PS_K_OTHER, k_init_ctl, dim3(1), 0, M->ctl));
+  if (!P.resume) {
+    PS_HIP(hipMemcpyAsync(M->slot(PS_V_B), b, vbytes, kind, P.A));
+    if (x0) PS_HIP(hipMemcpyAsync(M->slot(PS_V_X), x0, vbytes, kind, P.A));
+    else PS_TRY(zero_slots(M, P.A, {PS_V_X}));
+    PS_TRY(enqueue_setup(M, P));
+  }
+
+  const int last = last_iteration(P);
+  const int K = o.batch_iters > 0 ? o.batch_iters : auto_batch(M);
+  int batch = 0;
+  bool stopped = false;
+  for (int i = P.i0; i <= last && !stopped;) {
+    const int end = std::min(last, i + K - 1);
+    for (; i <= end; ++i) {
+      int rc;
+      switch (variant) {
+        case PS_SSBICGSAFE2: rc = iter_ssbicgsafe2(M, P, i); break;
+        case PS_PBICGSTAB: rc = iter_pbicgstab(M, P, i); break;
+        default: rc = iter_pbicgsafe(M, P, i); break;
+      }
+      if (rc != PS_OK) return rc;
+    }
+    PS_HIP(hipGetLastError());
+    const int cur = batch & 1;
+    PS_HIP(hipMemcpyAsync(M->pinned + cur * C_COUNT, M->ctl, C_COUNT * sizeof(int),
+                          hipMemcpyDeviceToHost, P.A));
+    PS_HIP(hipEventRecord(M->ev_batch[cur], P.A));
+    if (batch > 0) {
+      PS_HIP(hipEventSynchronize(M->ev_batch[cur ^ 1]));
+      if (M->pinned[(cur ^ 1) * C_COUNT + C_DONE]) stopped = true;
+    }
+    ++batch;
+  }
+  PS_HIP(hipStreamSynchronize(P.A));
+  if (P.overlap) PS_HIP(hipStreamSynchronize(P.B));
+
+  int c[C_COUNT];
+  PS_HIP(hipMemcpy(c, M->ctl, sizeof(c), hipMemcpyDeviceToHost));
+  int st = c[C_STATUS], it = c[C_ITERS];
+  if (!c[C_DONE]) {  // cannot happen: the finish at the last iteration always stops
+    st = PS_MAXIT;
+    it = maxit;
+  }
+  *iters = it;
+  *status = st;
+  if (hist) PS_HIP(hipMemcpy(hist, M->hist, (size_t)(it + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost));
+  PS_HIP(hipMemcpy(x, M->slot(PS_V_X), vbytes,
+                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  if (M->prof_mask) PS_TRY(collect_profile(M));
+  return PS_OK;
+}
+
+void free_matrix(ps_matrix *M) {
+  if (!M) return;
+  if (M->device >= 0) (void)hipSetDevice(M->device);
+  (void)hipDeviceSynchronize();
+  hipFree(M->rowptr);
+  hipFree(M->col);
+  hipFree(M->val);
+  hipFree(M->blk);
+  hipFree(M->vec);
+  hipFree(M->sc);
+  hipFree(M->ctl);
+  hipFree(M->partials);
+  hipFree(M->hist);
+  if (M->pinned) hipHostFree(M->pinned);
+  for (hipEvent_t e : M->ev_pool) hipEventDestroy(e);
+  if (M->ev_fork) hipEventDestroy(M->ev_fork);
+  if (M->ev_join) hipEventDestroy(M->ev_join);
+  for (hipEvent_t e : M->ev_batch)
+    if (e) hipEventDestroy(e);
+  if (M->own) hipStreamDestroy(M->own);
+  if (M->aux) hipStreamDestroy(M->aux);
+  delete M;
+}
+
+// Cut rows into blocks of <= kBlock rows whose nonzeros fit `budget`; a row
+// longer than the budget forms a block of its own.
+std::vector<int> row_blocks(int64_t n, const int64_t *rowptr, int budget) {
+  std::vector<int> blk;
+  blk.push_back(0);
+  int64_t r = 0;
+  while (r < n) {
+    const int64_t start = r;
+    int64_t nz = 0;
+    while (r < n && r - start < kBlock) {
+      const int64_t len = rowptr[r + 1] - rowptr[r];
+      if (nz + len > budget) break;
+      nz += len;
+      ++r;
+    }
+    if (r == start) ++r;
+    blk.push_back((int)r);
+  }
+  return blk;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+
+extern "C" {
+
+void ps_default_options(ps_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->rr_m = 100;
+  opt->rr_M = 0;
+  opt->norm_ref = 0;
+  opt->batch_iters = 0;
+  opt->overlap = 1;
+  opt->profile = 0;
+  opt->resume = 0;
+  opt->resume_iter = 0;
+  opt->stream = nullptr;
+}
+
+int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+              const double *val) {
+  if (!out) return PS_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n >= INT32_MAX - 1 || nnz < 0 || nnz >= INT32_MAX || !rowptr) return PS_EINVAL;
+  if (nnz > 0 && (!col || !val)) return PS_EINVAL;
+  if (rowptr[0] != 0 || rowptr[n] != nnz) return PS_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return PS_EINVAL;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (col[k] < 0 || col[k] >= n || !std::isfinite(val[k])) return PS_EINVAL;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PS_ENODEV;
+  int dev = 0;
+  PS_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  PS_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PS_ENODEV;
+
+  ps_matrix *M = new ps_matrix();
+  M->device = dev;
+  M->n = n;
+  M->nnz = nnz;
+  const double mean = (double)nnz / (double)n;
+  int budget = (int)std::ceil(kBlock * mean * 1.25 / 256.0) * 256;
+  M->budget = std::max(1024, std::min(8192, budget));
+  std::vector<int> blk = row_blocks(n, rowptr, M->budget);
+  M->nblk = (int)blk.size() - 1;
+  std::vector<int> rp32(n + 1);
+  for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
+  M->ld = ((size_t)n + 31) / 32 * 32;
+  M->dot_grid = (int)std::min<int64_t>(kMaxDotGrid, (n + kBlock - 1) / kBlock);
+
+  auto fail = [&](int code) {
+    free_matrix(M);
+    return code;
+  };
+#define PS_CREATE_HIP(call)                 \
+  do {                                      \
+    if ((call) != hipSuccess) return fail(PS_ENOMEM); \
+  } while (0)
+  PS_CREATE_HIP(hipMalloc(&M->rowptr, (n + 1) * sizeof(int)));
+  PS_CREATE_HIP(hipMalloc(&M->col, std::max<int64_t>(nnz, 1) * sizeof(int)));
+  PS_CREATE_HIP(hipMalloc(&M->val, std::max<int64_t>(nnz, 1) * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->blk, blk.size() * sizeof(int)));
+  PS_CREATE_HIP(hipMalloc(&M->vec, (size_t)kNumSlots * M->ld * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->sc, SC_COUNT * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->ctl, C_COUNT * sizeof(int)));
+  PS_CREATE_HIP(hipMalloc(&M->partials, 9 * (size_t)M->dot_grid * sizeof(double)));
+  PS_CREATE_HIP(hipHostMalloc(&M->pinned, 2 * C_COUNT * sizeof(int), hipHostMallocDefault));
+#undef PS_CREATE_HIP
+  auto chk = [&](hipError_t e) { return e == hipSuccess; };
+  if (!chk(hipMemcpy(M->rowptr, rp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice)) ||
+      (nnz > 0 && !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
+      (nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
+      !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice)) ||
+      !chk(hipMemset(M->vec, 0, (size_t)kNumSlots * M->ld * sizeof(double))) ||
+      !chk(hipMemset(M->sc, 0, SC_COUNT * sizeof(double))) ||
+      !chk(hipMemset(M->ctl, 0, C_COUNT * sizeof(int))) ||
+      !chk(hipStreamCreateWithFlags(&M->own, hipStreamNonBlocking)) ||
+      !chk(hipStreamCreateWithFlags(&M->aux, hipStreamNonBlocking)) ||
+      !chk(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming)) ||
+      !chk(hipEventCreateWithFlags(&M->ev_join, hipEventDisableTiming)) ||
+      !chk(hipEventCreateWithFlags(&M->ev_batch[0], hipEventDisableTiming)) ||
+      !chk(hipEventCreateWithFlags(&M->ev_batch[1], hipEventDisableTiming)))
+    return fail(PS_EHIP);
+  if (ensure_hist(M, 10002) != PS_OK) return fail(PS_ENOMEM);
+  *out = M;
+  return PS_OK;
+}
+
+int ps_solve(ps_matrix *A, const double *b, const double *x0, double tol, int32_t maxit,
+             int32_t variant, const ps_options *opt, double *x, int32_t *iters, double *hist,
+             int32_t *status) {
+  return solve_impl(A, b, x0, false, tol, maxit, variant, opt, x, iters, hist, status);
+}
+
+int ps_solve_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol, int32_t maxit,
+                 int32_t variant, const ps_options *opt, double *x_dev, int32_t *iters,
+                 double *hist, int32_t *status) {
+  return solve_impl(A, b_dev, x0_dev, true, tol, maxit, variant, opt, x_dev, iters, hist, status);
+}
+
+int ps_spmv_dev(ps_matrix *A, const double *x_dev, double *y_dev, void *stream) {
+  if (!A || !x_dev || !y_dev) return PS_EINVAL;
+  BusyGuard guard(A->busy);
+  if (!guard.ok) return PS_EBUSY;
+  PS_HIP(hipSetDevice(A->device));
+  hipStream_t s = (hipStream_t)stream;
+  A->prof_mask = 0;
+  PS_TRY(spmv(A, s, PS_K_SPMV, x_dev, EpiStore{y_dev}, nullptr));
+  PS_HIP(hipGetLastError());
+  PS_HIP(hipStreamSynchronize(s));
+  return PS_OK;
+}
+
+int ps_get_state(ps_matrix *A, int32_t which, double *host_out) {
+  if (!A || !host_out || which < 0 || which >= PS_V_COUNT) return PS_EINVAL;
+  PS_HIP(hipSetDevice(A->device));
+  PS_HIP(hipMemcpy(host_out, A->slot(which), A->n * sizeof(double), hipMemcpyDeviceToHost));
+  return PS_OK;
+}
+
+int ps_set_state(ps_matrix *A, int32_t which, const double *host_in) {
+  if (!A || !host_in || which < 0 || which >= PS_V_COUNT) return PS_EINVAL;
+  PS_HIP(hipSetDevice(A->device));
+  PS_HIP(hipMemcpy(A->slot(which), host_in, A->n * sizeof(double), hipMemcpyHostToDevice));
+  return PS_OK;
+}
+
+int ps_get_scalars(ps_matrix *A, double *host_out) {
+  if (!A || !host_out) return PS_EINVAL;
+  PS_HIP(hipSetDevice(A->device));
+  PS_HIP(hipMemcpy(host_out, A->sc, PS_S_COUNT * sizeof(double), hipMemcpyDeviceToHost));
+  return PS_OK;
+}
+
+int ps_set_scalars(ps_matrix *A, const double *host_in) {
+  if (!A || !host_in) return PS_EINVAL;
+  PS_HIP(hipSetDevice(A->device));
+  PS_HIP(hipMemcpy(A->sc, host_in, PS_S_COUNT * sizeof(double), hipMemcpyHostToDevice));
+  return PS_OK;
+}
+
+int ps_kernel_stats(ps_matrix *A, int32_t cls, double *total_ms, int64_t *launches) {
+  if (!A || cls < 0 || cls >= PS_K_COUNT || !total_ms || !launches) return PS_EINVAL;
+  *total_ms = A->prof_ms[cls];
+  *launches = A->prof_cnt[cls];
+  return PS_OK;
+}
+
+int ps_stream_copy(void *dst, const void *src, int64_t bytes, void *stream) {
+  if (!dst || !src || bytes < 0 || (bytes % 16) != 0) return PS_EINVAL;
+  if (((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return PS_EINVAL;
+  const int64_t n16 = bytes / 16;
+  if (n16 == 0) return PS_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned grid = (unsigned)std::min<int64_t>((n16 + kBlock - 1) / kBlock, 8192);
+  hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(kBlock), 0, s, (double2 *)dst,
+                     (const double2 *)src, n16);
+  PS_HIP(hipGetLastError());
+  PS_HIP(hipStreamSynchronize(s));
+  return PS_OK;
+}
+
+int ps_destroy(ps_matrix *A) {
+  free_matrix(A);
+  return PS_OK;
+}
+
+const char *ps_strerror(int code) {
+  switch (code) {
+    case PS_OK: return "ok / converged";
+    case PS_MAXIT: return "stopped at the iteration limit";
+    case PS_BREAKDOWN: return "breakdown: a coefficient denominator was zero or not finite";
+    case PS_NONFINITE: return "an inner product was not finite";
+    case PS_EINVAL: return "invalid argument";
+    case PS_ENOMEM: return "out of memory";
+    case PS_EHIP: return "HIP runtime error";
+    case PS_EBUSY: return "handle in use by another thread";
+    case PS_ENODEV: return "no usable gfx950 device";
+    default: return "unknown code";
+  }
+}
+
+const char *ps_version(void) { return "pipesafe 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,322 @@
+// Fused, row-local vector-update passes.  Each kernel streams every vector it
+// needs once (two entries per thread, 16-byte loads and stores) and applies a
+// whole block of the algorithm's update statements per entry, in the
+// algorithm's order, so no intermediate vector makes an HBM round trip.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace ps {
+
+template <int W>
+__device__ __forceinline__ void ldv(const double *__restrict__ p, int64_t k, double (&o)[W]) {
+  if constexpr (W == 2) {
+    const double2 v = *reinterpret_cast<const double2 *>(p + k);
+    o[0] = v.x;
+    o[1] = v.y;
+  } else {
+    o[0] = p[k];
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void stv(double *__restrict__ p, int64_t k, const double (&o)[W]) {
+  if constexpr (W == 2) {
+    *reinterpret_cast<double2 *>(p + k) = make_double2(o[0], o[1]);
+  } else {
+    p[k] = o[0];
+  }
+}
+
+// A kernel that follows a reduction phase: if that phase stopped the solve,
+// note it in C_HALT (read by the sparse products of later iterations, which
+// may run concurrently with a finish and so must not read C_DONE) and return.
+__device__ __forceinline__ bool halted_after_finish(int *ctl) {
+  if (ctl[C_DONE]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[C_HALT] = 1;
+    return true;
+  }
+  return false;
+}
+
+// Launch helper: entry index of this thread (two entries per thread).
+__device__ __forceinline__ int64_t pair_index() {
+  return 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+#define PS_DISPATCH_PAIRS(n, body)            \
+  do {                                        \
+    const int64_t k_ = pair_index();          \
+    if (k_ + 1 < (n)) {                       \
+      body<2>(P, k_);                         \
+    } else if (k_ < (n)) {                    \
+      body<1>(P, k_);                         \
+    }                                         \
+  } while (0)
+
+// ------------------------------------------------ p-BiCGSafe, Algorithm 4
+// The ten updates between the reduction phase and the product A w_i:
+//   p_i = r_i + beta (p_{i-1} - u_{i-1})         o_i = s_i + beta t_{i-1}
+//   u_i = zeta o_i + eta (y_i + beta u_{i-1})    q_i = As_i + beta l_{i-1}       (Eq. (q))
+//   w_i = zeta q_i + eta (g_i + beta w_{i-1})    (Eq. (w))
+//   t_i = o_i - w_i                              z_i = zeta r_i + eta z_{i-1} - alpha u_i
+//   y_{i+1} = zeta s_i + eta y_i - alpha w_i     x_{i+1} = x_i + alpha p_i + z_i
+//   r_{i+1} = r_i - alpha o_i - y_{i+1}
+// o_i stays in registers.
+struct PassAArgs {
+  double *x, *r, *p, *u, *t, *y, *z, *w, *q;
+  const double *s, *As, *l, *g;
+  const double *sc;
+  int *ctl;
+  int64_t n;
+};
+
+template <int W>
+__device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k) {
+  const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA],
+               et = P.sc[PS_S_ETA];
+  double r[W], p[W], u[W], s[W], t[W], y[W], As[W], l[W], g[W], w[W], z[W], x[W], q[W];
+  ldv<W>(P.r, k, r);
+  ldv<W>(P.p, k, p);
+  ldv<W>(P.u, k, u);
+  ldv<W>(P.s, k, s);
+  ldv<W>(P.t, k, t);
+  ldv<W>(P.y, k, y);
+  ldv<W>(P.As, k, As);
+  ldv<W>(P.l, k, l);
+  ldv<W>(P.g, k, g);
+  ldv<W>(P.w, k, w);
+  ldv<W>(P.z, k, z);
+  ldv<W>(P.x, k, x);
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    p[j] = r[j] + be * (p[j] - u[j]);
+    const double o = s[j] + be * t[j];
+    u[j] = ze * o + et * (y[j] + be * u[j]);
+    q[j] = As[j] + be * l[j];
+    w[j] = ze * q[j] + et * (g[j] + be * w[j]);
+    t[j] = o - w[j];
+    z[j] = ze * r[j] + et * z[j] - al * u[j];
+    y[j] = ze * s[j] + et * y[j] - al * w[j];
+    x[j] = x[j] + al * p[j] + z[j];
+    r[j] = r[j] - al * o - y[j];
+  }
+  stv<W>(P.p, k, p);
+  stv<W>(P.u, k, u);
+  stv<W>(P.q, k, q);
+  stv<W>(P.w, k, w);
+  stv<W>(P.t, k, t);
+  stv<W>(P.z, k, z);
+  stv<W>(P.y, k, y);
+  stv<W>(P.x, k, x);
+  stv<W>(P.r, k, r);
+}
+
+__global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P) {
+  if (halted_after_finish(P.ctl)) return;
+  PS_DISPATCH_PAIRS(P.n, passA_body);
+}
+
+// ---------------------------------- ssBiCGSafe2 (Algorithm 3) and the
+// replacement step of Algorithm 5: p_i, o_i, u_i before the product A u_i.
+struct PouArgs {
+  const double *r, *s, *t, *y;
+  double *p, *u;
+  double *o;  // stored only when a later kernel needs A o_i (replacement step)
+  const double *sc;
+  int *ctl;
+  int64_t n;
+};
+
+template <int W, bool STORE_O>
+__device__ __forceinline__ void pou_body(const PouArgs &P, int64_t k) {
+  const double be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA], et = P.sc[PS_S_ETA];
+  double r[W], p[W], u[W], s[W], t[W], y[W], o[W];
+  ldv<W>(P.r, k, r);
+  ldv<W>(P.p, k, p);
+  ldv<W>(P.u, k, u);
+  ldv<W>(P.s, k, s);
+  ldv<W>(P.t, k, t);
+  ldv<W>(P.y, k, y);
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    p[j] = r[j] + be * (p[j] - u[j]);
+    o[j] = s[j] + be * t[j];
+    u[j] = ze * o[j] + et * (y[j] + be * u[j]);
+  }
+  stv<W>(P.p, k, p);
+  stv<W>(P.u, k, u);
+  if (STORE_O) stv<W>(P.o, k, o);
+}
+
+template <int W>
+__device__ __forceinline__ void pou_body_noo(const PouArgs &P, int64_t k) {
+  pou_body<W, false>(P, k);
+}
+template <int W>
+__device__ __forceinline__ void pou_body_o(const PouArgs &P, int64_t k) {
+  pou_body<W, true>(P, k);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pu(PouArgs P) {
+  if (halted_after_finish(P.ctl)) return;
+  PS_DISPATCH_PAIRS(P.n, pou_body_noo);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pou(PouArgs P) {
+  if (halted_after_finish(P.ctl)) return;
+  PS_DISPATCH_PAIRS(P.n, pou_body_o);
+}
+
+// replacement step of Algorithm 5, after q_i = A o_i and w_i = A u_i:
+//   t_i = o_i - w_i, z_i = zeta r_i + eta z_{i-1} - alpha u_i,
+//   y_{i+1} = zeta s_i + eta y_i - alpha w_i, x_{i+1} = x_i + alpha p_i + z_i
+struct TzyxArgs {
+  const double *o, *w, *r, *u, *s, *p;
+  double *t, *z, *y, *x;
+  const double *sc;
+  int *ctl;
+  int64_t n;
+};
+
+template <int W>
+__device__ __forceinline__ void tzyx_body(const TzyxArgs &P, int64_t k) {
+  const double al = P.sc[PS_S_ALPHA], ze = P.sc[PS_S_ZETA], et = P.sc[PS_S_ETA];
+  double o[W], w[W], r[W], u[W], s[W], p[W], t[W], z[W], y[W], x[W];
+  ldv<W>(P.o, k, o);
+  ldv<W>(P.w, k, w);
+  ldv<W>(P.r, k, r);
+  ldv<W>(P.u, k, u);
+  ldv<W>(P.s, k, s);
+  ldv<W>(P.p, k, p);
+  ldv<W>(P.z, k, z);
+  ldv<W>(P.y, k, y);
+  ldv<W>(P.x, k, x);
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    t[j] = o[j] - w[j];
+    z[j] = ze * r[j] + et * z[j] - al * u[j];
+    y[j] = ze * s[j] + et * y[j] - al * w[j];
+    x[j] = x[j] + al * p[j] + z[j];
+  }
+  stv<W>(P.t, k, t);
+  stv<W>(P.z, k, z);
+  stv<W>(P.y, k, y);
+  stv<W>(P.x, k, x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tzyx(TzyxArgs P) {
+  if (P.ctl[C_DONE]) return;
+  PS_DISPATCH_PAIRS(P.n, tzyx_body);
+}
+
+// --------------------------------------------------- pipelined BiCGStab
+// pass 1 of iteration i (after the stop test on rho_i):
+//   p_i = r_i + beta (p - omega s),  s_i = w_i + beta (s - omega z),
+//   z_i = t_i + beta (z - omega v),  q_i = r_i - alpha s_i,  y_i = w_i - alpha z_i
+struct Stab1Args {
+  const double *r, *w, *t, *v;
+  double *p, *s, *z, *q, *y;
+  const double *sc;
+  int *ctl;
+  int64_t n;
+};
+
+template <int W>
+__device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k) {
+  const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], om = P.sc[PS_S_OMEGA];
+  double r[W], w[W], t[W], v[W], p[W], s[W], z[W], q[W], y[W];
+  ldv<W>(P.r, k, r);
+  ldv<W>(P.w, k, w);
+  ldv<W>(P.t, k, t);
+  ldv<W>(P.v, k, v);
+  ldv<W>(P.p, k, p);
+  ldv<W>(P.s, k, s);
+  ldv<W>(P.z, k, z);
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    p[j] = r[j] + be * (p[j] - om * s[j]);
+    s[j] = w[j] + be * (s[j] - om * z[j]);
+    z[j] = t[j] + be * (z[j] - om * v[j]);
+    q[j] = r[j] - al * s[j];
+    y[j] = w[j] - al * z[j];
+  }
+  stv<W>(P.p, k, p);
+  stv<W>(P.s, k, s);
+  stv<W>(P.z, k, z);
+  stv<W>(P.q, k, q);
+  stv<W>(P.y, k, y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_stab_pass1(Stab1Args P) {
+  if (halted_after_finish(P.ctl)) return;
+  PS_DISPATCH_PAIRS(P.n, stab1_body);
+}
+
+// pass 2 of iteration i (after omega_i):
+//   x_{i+1} = x_i + alpha p_i + omega q_i,  r_{i+1} = q_i - omega y_i,
+//   w_{i+1} = y_i - omega (t_i - alpha v_i)
+struct Stab2Args {
+  const double *p, *q, *y, *t, *v;
+  double *x, *r, *w;
+  const double *sc;
+  int *ctl;
+  int64_t n;
+};
+
+template <int W>
+__device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k) {
+  const double al = P.sc[PS_S_ALPHA], om = P.sc[PS_S_OMEGA];
+  double p[W], q[W], y[W], t[W], v[W], x[W], r[W], w[W];
+  ldv<W>(P.p, k, p);
+  ldv<W>(P.q, k, q);
+  ldv<W>(P.y, k, y);
+  ldv<W>(P.t, k, t);
+  ldv<W>(P.v, k, v);
+  ldv<W>(P.x, k, x);
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    x[j] = x[j] + al * p[j] + om * q[j];
+    r[j] = q[j] - om * y[j];
+    w[j] = y[j] - om * (t[j] - al * v[j]);
+  }
+  stv<W>(P.x, k, x);
+  stv<W>(P.r, k, r);
+  stv<W>(P.w, k, w);
+}
+
+__global__ __launch_bounds__(kBlock) void k_stab_pass2(Stab2Args P) {
+  if (halted_after_finish(P.ctl)) return;
+  PS_DISPATCH_PAIRS(P.n, stab2_body);
+}
+
+// ------------------------------------------------------------ bookkeeping
+
+// zero-fill of `count` vectors of length n laid out `ld` doubles apart
+__global__ __launch_bounds__(kBlock) void k_zero(double *base, int64_t ld, int count, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  for (int c = 0; c < count; ++c) base[c * ld + k] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(double *__restrict__ dst,
+                                                 const double *__restrict__ src, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) dst[k] = src[k];
+}
+
+// plain streaming copy, 16 bytes per thread per step (bandwidth calibration)
+__global__ __launch_bounds__(kBlock) void k_stream_copy(double2 *__restrict__ dst,
+                                                        const double2 *__restrict__ src,
+                                                        int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n16; k += stride)
+    dst[k] = src[k];
+}
+
+__global__ void k_init_ctl(int *ctl) {
+  const int k = threadIdx.x;
+  if (k < C_COUNT) ctl[k] = (k == C_STATUS) ? -1 : 0;
+}
+
+}  // namespace ps

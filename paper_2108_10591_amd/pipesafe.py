@@ -1,0 +1,244 @@
+"""Python binding of libpipesafe (ctypes; argument marshalling only).
+
+Every step of a solve runs in the library's HIP kernels.  PyTorch is used,
+where the caller wants device buffers, only to provide device memory and the
+current stream (``solve_dev`` / ``spmv_dev`` take torch CUDA tensors).  There
+is no CPU fallback: if the library is missing or no gfx950 GPU is present,
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpipesafe.so")
+
+VARIANTS = {"ssbicgsafe2": 0, "pbicgsafe": 1, "pbicgsafe_rr": 2, "pbicgstab": 3}
+CONVERGED, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+STATUS_NAMES = {0: "converged", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
+VEC = ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o", "As", "v", "b"]
+SCAL = ["alpha", "beta", "zeta", "eta", "omega", "f", "rhoref", "rho", "pending", "gs", "gw", "gz"]
+KERNEL_CLASSES = {"spmv": 0, "dots": 1, "update": 2, "spmv_fused": 3, "other": 4}
+
+
+class PipesafeError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_lib().ps_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("rr_m", ctypes.c_int32), ("rr_M", ctypes.c_int32), ("norm_ref", ctypes.c_int32),
+                ("batch_iters", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("resume", ctypes.c_int32),
+                ("resume_iter", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        Pi32, Pi64, Pf64 = ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(f64)
+        L.ps_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.ps_default_options.restype = None
+        L.ps_create.argtypes = [ctypes.POINTER(P), i64, i64, P, P, P]
+        L.ps_solve.argtypes = [P, P, P, f64, i32, i32, ctypes.POINTER(Options), P, Pi32, P, Pi32]
+        L.ps_solve_dev.argtypes = L.ps_solve.argtypes
+        L.ps_spmv_dev.argtypes = [P, P, P, P]
+        L.ps_get_state.argtypes = [P, i32, P]
+        L.ps_set_state.argtypes = [P, i32, P]
+        L.ps_get_scalars.argtypes = [P, P]
+        L.ps_set_scalars.argtypes = [P, P]
+        L.ps_kernel_stats.argtypes = [P, i32, Pf64, Pi64]
+        L.ps_stream_copy.argtypes = [P, P, i64, P]
+        L.ps_destroy.argtypes = [P]
+        L.ps_strerror.argtypes = [ctypes.c_int]
+        L.ps_strerror.restype = ctypes.c_char_p
+        L.ps_version.restype = ctypes.c_char_p
+        for name in ("ps_create", "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
+                     "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats",
+                     "ps_stream_copy", "ps_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        _L = L
+    return _L
+
+
+def library():
+    """The loaded ctypes library (raises ImportError if it is not built)."""
+    return _lib()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise PipesafeError(rc, what)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _vid(variant) -> int:
+    return VARIANTS[variant] if isinstance(variant, str) else int(variant)
+
+
+def options(**kw) -> Options:
+    o = Options()
+    _lib().ps_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "profile" and isinstance(v, (list, tuple, set)):
+            v = sum(1 << KERNEL_CLASSES[c] for c in v)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class SolveResult:
+    x: object
+    iters: int
+    status: int
+    hist: np.ndarray
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+class Matrix:
+    """A CSR matrix resident on the current HIP device, with its solver workspace."""
+
+    def __init__(self, n: int, rowptr, col, val):
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        self.n = int(n)
+        self.nnz = int(rowptr[-1]) if rowptr.size else 0
+        h = ctypes.c_void_p()
+        _check(_lib().ps_create(ctypes.byref(h), self.n, self.nnz, _ptr(rowptr), _ptr(col), _ptr(val)),
+               "ps_create")
+        self._h = h
+
+    @classmethod
+    def from_csr(cls, A) -> "Matrix":
+        return cls(A.n, A.rowptr, A.col, A.val)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().ps_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -------------------------------------------------------------- solves
+    def solve(self, b, x0=None, tol=1e-8, maxit=10_000, variant="pbicgsafe", hist=True, **opt):
+        """Solve from host (numpy) buffers; returns SolveResult with a numpy x."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        x = np.empty(self.n)
+        h = np.empty(maxit + 1) if hist else None
+        iters, status = ctypes.c_int32(), ctypes.c_int32()
+        o = options(**opt)
+        _check(_lib().ps_solve(self._h, _ptr(b), None if x0a is None else _ptr(x0a), float(tol),
+                               int(maxit), _vid(variant), ctypes.byref(o), _ptr(x),
+                               ctypes.byref(iters), None if h is None else _ptr(h),
+                               ctypes.byref(status)), "ps_solve")
+        it = iters.value
+        return SolveResult(x, it, status.value, h[: it + 1] if h is not None else None)
+
+    def solve_dev(self, b, x0=None, x=None, tol=1e-8, maxit=10_000, variant="pbicgsafe",
+                  hist=True, stream=None, **opt):
+        """Solve with torch CUDA tensors b, x0 (or None), x (allocated if None), float64.
+
+        Work is ordered on ``stream`` (default: torch's current stream)."""
+        import torch
+        for t in (b, x0, x):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != self.n):
+                raise ValueError("expected contiguous float64 CUDA tensors of length n")
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=b.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(b.device).cuda_stream
+        h = np.empty(maxit + 1) if hist else None
+        iters, status = ctypes.c_int32(), ctypes.c_int32()
+        o = options(stream=stream, **opt)
+        _check(_lib().ps_solve_dev(self._h, ctypes.c_void_p(b.data_ptr()),
+                                   None if x0 is None else ctypes.c_void_p(x0.data_ptr()),
+                                   float(tol), int(maxit), _vid(variant), ctypes.byref(o),
+                                   ctypes.c_void_p(x.data_ptr()), ctypes.byref(iters),
+                                   None if h is None else _ptr(h), ctypes.byref(status)),
+               "ps_solve_dev")
+        it = iters.value
+        return SolveResult(x, it, status.value, h[: it + 1] if h is not None else None)
+
+    def spmv_dev(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device).cuda_stream
+        _check(_lib().ps_spmv_dev(self._h, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(stream)),
+               "ps_spmv_dev")
+        return y
+
+    # --------------------------------------------------------------- state
+    def get_state(self, name: str) -> np.ndarray:
+        out = np.empty(self.n)
+        _check(_lib().ps_get_state(self._h, VEC.index(name), _ptr(out)), "ps_get_state")
+        return out
+
+    def set_state(self, name: str, values):
+        a = np.ascontiguousarray(values, dtype=np.float64)
+        assert a.size == self.n
+        _check(_lib().ps_set_state(self._h, VEC.index(name), _ptr(a)), "ps_set_state")
+
+    def get_scalars(self) -> dict:
+        out = np.empty(len(SCAL))
+        _check(_lib().ps_get_scalars(self._h, _ptr(out)), "ps_get_scalars")
+        return dict(zip(SCAL, out.tolist()))
+
+    def set_scalars(self, values: dict):
+        cur = np.empty(len(SCAL))
+        _check(_lib().ps_get_scalars(self._h, _ptr(cur)), "ps_get_scalars")
+        for k, v in values.items():
+            cur[SCAL.index(k)] = v
+        _check(_lib().ps_set_scalars(self._h, _ptr(cur)), "ps_set_scalars")
+
+    def kernel_stats(self) -> dict:
+        """{class: (total_ms, launches)} of the last profiled solve."""
+        out = {}
+        for name, c in KERNEL_CLASSES.items():
+            ms, cnt = ctypes.c_double(), ctypes.c_int64()
+            _check(_lib().ps_kernel_stats(self._h, c, ctypes.byref(ms), ctypes.byref(cnt)),
+                   "ps_kernel_stats")
+            out[name] = (ms.value, cnt.value)
+        return out
+
+
+def stream_copy(dst, src, stream=None):
+    """dst[:] = src[:] for torch CUDA tensors with the library's streaming copy kernel."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device).cuda_stream
+    nbytes = src.numel() * src.element_size()
+    _check(_lib().ps_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                 nbytes, ctypes.c_void_p(stream)), "ps_stream_copy")

@@ -1,0 +1,277 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Bars (derivations are in the design notes):
+  * sparse product: bit-identical to the oracle for rows that fit a row block
+    (same products, same summation order, no fused multiply-add); long rows
+    within 4 * len * u * sum|a_ij x_j|.
+  * one iteration from an identical state: every state vector within
+    tol_step * ||v||_inf elementwise, coefficients within tol_step relative,
+    tol_step = 64 * n * u * kappa, kappa the conditioning of that iteration's
+    coefficient formulas (>= 1), computed from the oracle's own inner products.
+  * full solve: iteration count within max(1, ceil(0.02 * iters_oracle)) of the
+    oracle's, same status, solution within 1e-8 relative infinity-norm.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2108_10591_amd import pipesafe, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["ssbicgsafe2", "pbicgsafe", "pbicgsafe_rr", "pbicgstab"]
+U = np.finfo(np.float64).eps / 2
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    pipesafe.library()
+
+
+def iters_ok(g, o):
+    return abs(g - o) <= max(1, math.ceil(0.02 * o))
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# ------------------------------------------------------------------ sparse product
+
+SPMV_CASES = {
+    "random_mixed": dict(n=3001, seed=1),
+    "empty_and_single": dict(n=777, seed=2, lengths="sparse"),
+    "long_rows": dict(n=600, seed=3, lengths="long"),
+    "unsorted_dups": dict(n=1000, seed=4, unsorted=True, duplicates=True),
+    "one_row": dict(n=1, seed=5, lengths=[1]),
+    "single_empty_row": dict(n=1, seed=6, lengths=[0]),
+}
+
+
+def _spmv_matrix(case):
+    kw = dict(SPMV_CASES[case])
+    n, seed = kw.pop("n"), kw.pop("seed")
+    rng = np.random.default_rng(seed)
+    lens = kw.pop("lengths", None)
+    if lens == "sparse":
+        lens = rng.choice([0, 0, 1, 1, 2, 7], size=n)
+    elif lens == "long":
+        lens = rng.integers(0, 20, n)
+        lens[[5, 100, 101, 599]] = [300, 1500, 9000, 20000]
+    return W.random_csr(n, seed, lengths=lens, **kw)
+
+
+@pytest.mark.parametrize("case", sorted(SPMV_CASES))
+def test_spmv_matches_oracle(case):
+    import torch
+    say(f"spmv case {case}")
+    A = _spmv_matrix(case)
+    x = np.random.default_rng(7).standard_normal(A.n)
+    ref = O.spmv(A, x)
+    with pipesafe.Matrix.from_csr(A) as M:
+        y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
+    lens = np.diff(A.rowptr)
+    short = lens <= 1024
+    assert np.array_equal(y[short], ref[short])
+    if (~short).any():
+        rows = np.nonzero(~short)[0]
+        for r in rows:
+            s, e = A.rowptr[r], A.rowptr[r + 1]
+            bound = 4 * (e - s) * U * np.abs(A.val[s:e] * x[A.col[s:e]]).sum()
+            assert abs(y[r] - ref[r]) <= bound
+
+
+# ----------------------------------------------------------------- full solves
+
+def _solve_both(A, variant, tol, maxit=5000, **opt):
+    ref = O.solve(A, tol=tol, maxit=maxit, variant=variant, rr_m=opt.get("rr_m", 100))
+    with pipesafe.Matrix.from_csr(A) as M:
+        res = M.solve(A.b, tol=tol, maxit=maxit, variant=variant, **opt)
+    return ref, res
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_solve_cd2d_64(variant):
+    say(f"full solve cd2d_64 {variant}")
+    A = W.workload("cd2d_64")
+    ref, res = _solve_both(A, variant, 1e-10)
+    assert res.status == ref.status == O.CONVERGED
+    assert iters_ok(res.iters, ref.iters), (res.iters, ref.iters)
+    assert rel_inf(res.x, ref.x) <= 1e-8
+    assert res.hist[0] == 1.0 and res.hist[-1] <= 1e-10
+    # the history follows the oracle's until rounding differences build up
+    k = min(8, res.iters, ref.iters)
+    assert np.allclose(res.hist[:k], ref.hist[:k], rtol=1e-6)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_solve_small_cases(variant):
+    for name, A, tol in [
+        ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), 1e-10),
+        ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), 1e-10),
+        ("cd3d_12", W.cd3d(12, 20.0, seed=1), 1e-10),
+        ("cd2d_5", W.cd2d(5, 10.0), 1e-12),
+    ]:
+        say(f"full solve {name} {variant}")
+        ref, res = _solve_both(A, variant, tol)
+        assert res.status == ref.status == O.CONVERGED, (name, res.status, ref.status)
+        assert iters_ok(res.iters, ref.iters), (name, res.iters, ref.iters)
+        assert rel_inf(res.x, ref.x) <= 1e-8, name
+
+
+def test_rr_replaces_every_m():
+    A = W.workload("cd2d_64")
+    for m in (5, 17):
+        say(f"rr m={m}")
+        ref, res = _solve_both(A, "pbicgsafe_rr", 1e-10, rr_m=m)
+        assert res.status == ref.status == O.CONVERGED
+        assert iters_ok(res.iters, ref.iters), (res.iters, ref.iters)
+        assert rel_inf(res.x, ref.x) <= 1e-8
+
+
+def test_norm_ref_b_and_x0():
+    A = W.workload("cd2d_64")
+    x0 = np.linspace(0.0, 2.0, A.n)
+    for variant in VARIANTS:
+        say(f"norm_ref=1 x0 {variant}")
+        ref = O.solve(A, x0=x0, tol=1e-9, maxit=3000, variant=variant, norm_ref=1)
+        with pipesafe.Matrix.from_csr(A) as M:
+            res = M.solve(A.b, x0=x0, tol=1e-9, maxit=3000, variant=variant, norm_ref=1)
+        assert res.status == ref.status == O.CONVERGED
+        assert iters_ok(res.iters, ref.iters)
+        assert rel_inf(res.x, ref.x) <= 1e-8
+
+
+# --------------------------------------------------------------- one iteration
+
+STATE = {
+    "pbicgsafe": ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q"],
+    "pbicgsafe_rr": ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q"],
+    "ssbicgsafe2": ["x", "r", "s", "y", "t", "p", "u", "z"],
+    "pbicgstab": ["x", "r", "p", "s", "z", "w", "t", "v", "q", "y"],
+}
+LOAD = {
+    "pbicgsafe": ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o"],
+    "ssbicgsafe2": ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w"],
+    "pbicgstab": ["x", "r", "rs", "p", "s", "z", "w", "t", "v", "q", "y"],
+}
+LOAD["pbicgsafe_rr"] = LOAD["pbicgsafe"]
+SCAL_SAFE = ["alpha", "beta", "zeta", "eta", "f"]
+SCAL_STAB = ["alpha", "beta", "omega", "f", "rho", "gs", "gw", "gz"]
+
+
+def coefficient_conditioning(st, variant):
+    """Amplification of relative inner-product errors into the coefficients of the
+    next iteration, from the oracle's own state (>= 1)."""
+    s, y, r = st.vec("s"), st.vec("y"), st.vec("r")
+    if variant == "pbicgstab":
+        return 4.0
+    a, b, c = s @ s, y @ y, s @ y
+    den = abs(a * b - c * c)
+    return max(1.0, (a * b + c * c) / den) if den > 0 else 1e6
+
+
+def one_step(A, variant, k, rr_m=100):
+    st, r0 = O.state_at(A, k, variant=variant, rr_m=rr_m)
+    assert r0.status == O.MAXIT
+    st1, r1 = O.state_at(A, k + 1, variant=variant, rr_m=rr_m)
+    assert r1.status == O.MAXIT
+    with pipesafe.Matrix.from_csr(A) as M:
+        for name in LOAD[variant]:
+            M.set_state(name, st.vec(name))
+        M.set_state("b", A.b)
+        M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "omega", "f",
+                                                  "rhoref", "rho", "gs", "gw", "gz"]}
+                      | {"pending": st.scal("pending_breakdown")})
+        res = M.solve(A.b, tol=0.0, maxit=k + 1, variant=variant, resume=1, resume_iter=k,
+                      rr_m=rr_m)
+        assert res.status == O.MAXIT and res.iters == k + 1, (res.status, res.iters)
+        got = {name: M.get_state(name) for name in STATE[variant]}
+        sc = M.get_scalars()
+    kappa = coefficient_conditioning(st, variant)
+    tol = 64 * A.n * U * kappa
+    for name in STATE[variant]:
+        ref = st1.vec(name)
+        scale = max(np.abs(ref).max(), 1e-300)
+        err = np.abs(got[name] - ref).max() / scale
+        assert err <= tol, f"{variant} k={k} vector {name}: {err:.2e} > {tol:.2e}"
+    for name in (SCAL_STAB if variant == "pbicgstab" else SCAL_SAFE):
+        ref = st1.scal(name)
+        g = sc[name]
+        assert abs(g - ref) <= tol * max(abs(ref), 1e-300), f"{variant} k={k} {name}: {g!r} vs {ref!r}"
+    return res
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_one_iteration_from_oracle_state(variant):
+    A = W.workload("cd2d_64")
+    for k in (0, 1, 5, 30, 100):
+        say(f"one step {variant} k={k}")
+        one_step(A, variant, k, rr_m=10)
+    B = W.rand_band(50_001, seed=9, band=2000)
+    for k in (0, 3, 10):
+        say(f"one step rand_band_50001 {variant} k={k}")
+        one_step(B, variant, k, rr_m=10)
+
+
+# ------------------------------------------------------------- determinism
+
+def test_bitwise_reproducible_and_overlap_invariant():
+    A = W.rand_band(100_000, seed=21, band=3000)
+    for variant in VARIANTS:
+        say(f"determinism {variant}")
+        with pipesafe.Matrix.from_csr(A) as M:
+            a = M.solve(A.b, tol=1e-10, maxit=500, variant=variant)
+            b = M.solve(A.b, tol=1e-10, maxit=500, variant=variant)
+            c = M.solve(A.b, tol=1e-10, maxit=500, variant=variant, overlap=0)
+            d = M.solve(A.b, tol=1e-10, maxit=500, variant=variant, batch_iters=1)
+        for other in (b, c, d):
+            assert other.iters == a.iters and other.status == a.status
+            assert np.array_equal(other.x, a.x) and np.array_equal(other.hist, a.hist)
+
+
+# ------------------------------------------------------------ edge cases
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_statuses_and_degenerate_cases(variant):
+    say(f"statuses {variant}")
+    # A = I: one iteration, x = b exactly
+    for n in (1, 2, 63, 1000):
+        E = W.identity(n, seed=n)
+        with pipesafe.Matrix.from_csr(E) as M:
+            res = M.solve(E.b, tol=1e-12, maxit=50, variant=variant)
+        assert res.status == O.CONVERGED and res.iters == 1 and np.array_equal(res.x, E.b)
+    # exact skew-symmetric: (r0*, A r0) = 0 -> breakdown at i = 0
+    S = W.skew_blocks(64, seed=1)
+    ref = O.solve(S, tol=1e-10, maxit=100, variant=variant)
+    with pipesafe.Matrix.from_csr(S) as M:
+        res = M.solve(S.b, tol=1e-10, maxit=100, variant=variant)
+    assert res.status == ref.status == O.BREAKDOWN and res.iters == ref.iters == 0
+    # NaN in b -> non-finite inner products at i = 0
+    B = W.small_nonsym(40, 0)
+    b = B.b.copy()
+    b[7] = np.nan
+    with pipesafe.Matrix.from_csr(B) as M:
+        res = M.solve(b, tol=1e-10, maxit=100, variant=variant)
+        assert res.status == O.NONFINITE and res.iters == 0
+        # maxit = 0 and maxit = 3
+        r0 = M.solve(B.b, tol=1e-10, maxit=0, variant=variant)
+        assert r0.status == O.MAXIT and r0.iters == 0 and np.all(r0.x == 0)
+        r3 = M.solve(B.b, tol=1e-30, maxit=3, variant=variant)
+        o3 = O.solve(B, tol=1e-30, maxit=3, variant=variant)
+        assert r3.status == o3.status == O.MAXIT and r3.iters == 3
+        assert rel_inf(r3.x, o3.x) <= 1e-10
+        # b = 0 -> converged at i = 0
+        rz = M.solve(np.zeros(40), tol=1e-10, maxit=10, variant=variant)
+        assert rz.status == O.CONVERGED and rz.iters == 0 and np.all(rz.x == 0)
