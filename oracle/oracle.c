@@ -11,7 +11,9 @@
  * Conventions (kept deliberately simple so the code can be checked against
  * the paper by eye):
  *   - every vector statement is one plain loop over all n entries;
- *   - an inner product is a sequential sum in index order;
+ *   - an inner product is a sequential sum in index order, carried with
+ *     compensated summation (see dot() below) so that its value does not
+ *     depend on the summation order;
  *   - a sparse product y = A x is, per row, a sequential sum over the row's
  *     entries in storage order;
  *   - compiled with -ffp-contract=off, so no fused multiply-adds.
@@ -86,12 +88,29 @@ static void spmv(const csr_t *A, const double *x, double *y, double *S) {
   S[S_NSPMV] += 1.0;
 }
 
-/* (u, v) = sum_k u_k v_k, in index order */
+/*
+ * (u, v) = sum_k u_k v_k in index order, with compensated summation (the
+ * algorithm Dot2 of Ogita, Rump & Oishi, "Accurate sum and dot product",
+ * SIAM J. Sci. Comput. 26(6), 2005): every product and every partial sum is
+ * split into its rounded value and its exact rounding error, the errors are
+ * summed alongside, and the total is rounded once at the end.  The result is
+ * as accurate as a sum carried in twice the working precision, so it does not
+ * depend on the order of summation (except when the exact value lies within
+ * about n^2 u^2 sum|u_k v_k| of a rounding boundary).
+ */
 static double dot(int64_t n, const double *u, const double *v, double *S) {
-  double acc = 0.0;
-  for (int64_t k = 0; k < n; ++k) acc += u[k] * v[k];
+  double s = 0.0, c = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    const double p = u[k] * v[k];
+    const double ep = fma(u[k], v[k], -p);      /* u_k v_k = p + ep exactly */
+    const double t = s + p;
+    const double z = t - s;
+    const double es = (s - (t - z)) + (p - z);  /* s + p = t + es exactly */
+    s = t;
+    c = c + (ep + es);
+  }
   S[S_NDOT] += 1.0;
-  return acc;
+  return s + c;
 }
 
 static int bad(double d) { return d == 0.0 || !isfinite(d); }
