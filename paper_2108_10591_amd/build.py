@@ -19,6 +19,10 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    # every arithmetic statement rounds as written (no fused multiply-add
+    # contraction), in the same order as the CPU reference, so that the
+    # iteration is reproducible across implementations
+    "-ffp-contract=off",
     # no packed-FP32 instructions anywhere (host pass warns that it does not know the feature)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -7,6 +7,12 @@
 // arrives last (atomic ticket) adds the partials in block order -- so the
 // result is bit-for-bit reproducible -- and then computes the phase's scalar
 // coefficients and the stop test on the device.  No host round trip.
+//
+// Accumulators are unevaluated pairs (hi, lo): each product is split exactly
+// into its rounded value and rounding error (one FMA), each addition into its
+// rounded sum and exact error (Knuth's two-sum), and the errors are carried in
+// lo (compensated dot product, Ogita-Rump-Oishi).  hi + lo is rounded once at
+// the end, so the value does not depend on how the grid splits the sum.
 #pragma once
 
 #include "device_common.hpp"
@@ -16,7 +22,7 @@ namespace ps {
 struct DotArgs {
   const double *v[5];  // input vectors
   int64_t n;
-  double *partials;    // [ND][gridDim.x]
+  double *partials;    // [ND][gridDim.x] (hi, lo) pairs
   int *ctl;
   double *sc;
   double *hist;
@@ -30,6 +36,31 @@ enum DotFlags : int {
 };
 
 // ---------------------------------------------------------------- products
+
+// pair accumulator: hi + lo carries a sum to about twice double precision
+struct DD {
+  double hi, lo;
+};
+
+// (hi, lo) += x*y
+__device__ __forceinline__ void dd_fma(DD &a, double x, double y) {
+  const double p = x * y;
+  const double ep = __builtin_fma(x, y, -p);  // x*y = p + ep exactly
+  const double t = a.hi + p;
+  const double z = t - a.hi;
+  const double es = (a.hi - (t - z)) + (p - z);  // a.hi + p = t + es exactly
+  a.hi = t;
+  a.lo = a.lo + (ep + es);
+}
+
+// a += b for two pairs
+__device__ __forceinline__ void dd_add(DD &a, double bhi, double blo) {
+  const double t = a.hi + bhi;
+  const double z = t - a.hi;
+  const double es = (a.hi - (t - z)) + (bhi - z);
+  a.hi = t;
+  a.lo = a.lo + (blo + es);
+}
 
 // the nine inner products of Algorithms 3-5 over (s, y, r, r0*, t_{i-1}):
 // a=(s,s) b=(y,y) c=(s,y) d=(s,r) e=(y,r) f=(r0*,r) g=(r0*,s) h=(r0*,t) rho=(r,r).
@@ -47,19 +78,19 @@ struct ProdSafe9 {
       in[4] = A.v[4][k];  // t
     }
   }
-  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     const double s = in[0], r = in[2], rs = in[3];
-    a[0] += s * s;
-    a[3] += s * r;
-    a[5] += rs * r;
-    a[6] += rs * s;
-    a[8] += r * r;
+    dd_fma(a[0], s, s);
+    dd_fma(a[3], s, r);
+    dd_fma(a[5], rs, r);
+    dd_fma(a[6], rs, s);
+    dd_fma(a[8], r, r);
     if (!FIRST) {
       const double y = in[1], t = in[4];
-      a[1] += y * y;
-      a[2] += s * y;
-      a[4] += y * r;
-      a[7] += rs * t;
+      dd_fma(a[1], y, y);
+      dd_fma(a[2], s, y);
+      dd_fma(a[4], y, r);
+      dd_fma(a[7], rs, t);
     }
   }
 };
@@ -71,9 +102,9 @@ struct ProdStab2 {
     in[0] = A.v[0][k];
     in[1] = A.v[1][k];
   }
-  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
-    a[0] += in[0] * in[1];
-    a[1] += in[1] * in[1];
+  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
+    dd_fma(a[0], in[0], in[1]);
+    dd_fma(a[1], in[1], in[1]);
   }
 };
 
@@ -85,13 +116,13 @@ struct ProdStab5 {
 #pragma unroll
     for (int j = 0; j < 5; ++j) in[j] = A.v[j][k];
   }
-  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
+  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     const double rs = in[0], r = in[1];
-    a[0] += rs * r;
-    a[1] += rs * in[2];
-    a[2] += rs * in[3];
-    a[3] += rs * in[4];
-    a[4] += r * r;
+    dd_fma(a[0], rs, r);
+    dd_fma(a[1], rs, in[2]);
+    dd_fma(a[2], rs, in[3]);
+    dd_fma(a[3], rs, in[4]);
+    dd_fma(a[4], r, r);
   }
 };
 
@@ -102,10 +133,10 @@ struct ProdStab3 {
 #pragma unroll
     for (int j = 0; j < 3; ++j) in[j] = A.v[j][k];
   }
-  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
-    a[0] += in[0] * in[1];
-    a[1] += in[0] * in[2];
-    a[2] += in[1] * in[1];
+  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
+    dd_fma(a[0], in[0], in[1]);
+    dd_fma(a[1], in[0], in[2]);
+    dd_fma(a[2], in[1], in[1]);
   }
 };
 
@@ -115,8 +146,8 @@ struct ProdNorm {
   __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
     in[0] = A.v[0][k];
   }
-  __device__ __forceinline__ static void acc(const double (&in)[5], double (&a)[ND]) {
-    a[0] += in[0] * in[0];
+  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
+    dd_fma(a[0], in[0], in[0]);
   }
 };
 
@@ -272,25 +303,60 @@ struct FinNormRef {
 
 // ---------------------------------------------------------------- the kernel
 
+// Block-wide pair sums: on return thread k (< K) holds the block total of a[k].
+template <int K>
+__device__ __forceinline__ DD block_sum_dd(DD (&a)[K], double *lds) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const double h = __shfl_xor(a[k].hi, off, kWave);
+      const double l = __shfl_xor(a[k].lo, off, kWave);
+      dd_add(a[k], h, l);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      lds[(wid * K + k) * 2] = a[k].hi;
+      lds[(wid * K + k) * 2 + 1] = a[k].lo;
+    }
+  }
+  __syncthreads();
+  DD r{0.0, 0.0};
+  if (threadIdx.x < K) {
+    r.hi = lds[threadIdx.x * 2];
+    r.lo = lds[threadIdx.x * 2 + 1];
+    for (int w = 1; w < kWavesPerBlock; ++w)
+      dd_add(r, lds[(w * K + threadIdx.x) * 2], lds[(w * K + threadIdx.x) * 2 + 1]);
+  }
+  __syncthreads();
+  return r;
+}
+
 template <class Prod, class Fin>
 __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
   constexpr int ND = Prod::ND;
-  __shared__ double lds[kWavesPerBlock * 9 + 16];
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double fin[9];
   __shared__ int last;
   if (A.ctl[C_DONE]) return;
-  double acc[ND];
+  DD acc[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+  for (int j = 0; j < ND; ++j) acc[j] = DD{0.0, 0.0};
   double in[5];
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < A.n; k += stride) {
     Prod::load(A, k, in);
     Prod::acc(in, acc);
   }
-  double s = block_sum_k<ND>(acc, lds);
+  DD s = block_sum_dd<ND>(acc, lds);
   const int G = gridDim.x;
   if (threadIdx.x < ND) {
-    A.partials[threadIdx.x * G + blockIdx.x] = s;
+    A.partials[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
+    A.partials[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
     __threadfence();  // publish the partial device-wide before taking a ticket
   }
   __syncthreads();
@@ -298,16 +364,16 @@ __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
   __syncthreads();
   if (!last) return;
   __threadfence();  // acquire: see every block's partials
-  double tot[ND];
+  DD tot[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) tot[j] = 0.0;
+  for (int j = 0; j < ND; ++j) tot[j] = DD{0.0, 0.0};
   for (int b = threadIdx.x; b < G; b += kBlock) {
 #pragma unroll
-    for (int j = 0; j < ND; ++j) tot[j] += __builtin_nontemporal_load(&A.partials[j * G + b]);
+    for (int j = 0; j < ND; ++j)
+      dd_add(tot[j], A.partials[(j * G + b) * 2], A.partials[(j * G + b) * 2 + 1]);
   }
-  s = block_sum_k<ND>(tot, lds);
-  __shared__ double fin[9];
-  if (threadIdx.x < ND) fin[threadIdx.x] = s;
+  s = block_sum_dd<ND>(tot, lds);
+  if (threadIdx.x < ND) fin[threadIdx.x] = s.hi + s.lo;  // the one final rounding
   __syncthreads();
   if (threadIdx.x == 0) {
     double d[ND];

@@ -445,23 +445,23 @@ void free_matrix(ps_matrix *M) {
   if (!M) return;
   if (M->device >= 0) (void)hipSetDevice(M->device);
   (void)hipDeviceSynchronize();
-  hipFree(M->rowptr);
-  hipFree(M->col);
-  hipFree(M->val);
-  hipFree(M->blk);
-  hipFree(M->vec);
-  hipFree(M->sc);
-  hipFree(M->ctl);
-  hipFree(M->partials);
-  hipFree(M->hist);
-  if (M->pinned) hipHostFree(M->pinned);
-  for (hipEvent_t e : M->ev_pool) hipEventDestroy(e);
-  if (M->ev_fork) hipEventDestroy(M->ev_fork);
-  if (M->ev_join) hipEventDestroy(M->ev_join);
+  (void)hipFree(M->rowptr);
+  (void)hipFree(M->col);
+  (void)hipFree(M->val);
+  (void)hipFree(M->blk);
+  (void)hipFree(M->vec);
+  (void)hipFree(M->sc);
+  (void)hipFree(M->ctl);
+  (void)hipFree(M->partials);
+  (void)hipFree(M->hist);
+  if (M->pinned) (void)hipHostFree(M->pinned);
+  for (hipEvent_t e : M->ev_pool) (void)hipEventDestroy(e);
+  if (M->ev_fork) (void)hipEventDestroy(M->ev_fork);
+  if (M->ev_join) (void)hipEventDestroy(M->ev_join);
   for (hipEvent_t e : M->ev_batch)
-    if (e) hipEventDestroy(e);
-  if (M->own) hipStreamDestroy(M->own);
-  if (M->aux) hipStreamDestroy(M->aux);
+    if (e) (void)hipEventDestroy(e);
+  if (M->own) (void)hipStreamDestroy(M->own);
+  if (M->aux) (void)hipStreamDestroy(M->aux);
   delete M;
 }
 
@@ -555,7 +555,7 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   PS_CREATE_HIP(hipMalloc(&M->vec, (size_t)kNumSlots * M->ld * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->sc, SC_COUNT * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->ctl, C_COUNT * sizeof(int)));
-  PS_CREATE_HIP(hipMalloc(&M->partials, 9 * (size_t)M->dot_grid * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->partials, 2 * 9 * (size_t)M->dot_grid * sizeof(double)));
   PS_CREATE_HIP(hipHostMalloc(&M->pinned, 2 * C_COUNT * sizeof(int), hipHostMallocDefault));
 #undef PS_CREATE_HIP
   auto chk = [&](hipError_t e) { return e == hipSuccess; };
