@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark: p-BiCGSafe (Algorithm 4) on the 128^3 convection-diffusion system.
+
+One step = one full solve of A x = b to ||r_i|| <= 1e-8 ||r_0|| from x0 = 0
+(set-up included), FP64, with the matrix and b already resident on the GPU.
+
+Prints ONE JSON line on stdout:
+  value      achieved HBM GB/s of the iteration = algorithmic bytes per
+             iteration x iterations / solve time (set-up time counted, its
+             bytes not)
+  roofline   the dominant kernel: algorithmic bytes per launch / average
+             launch time measured with HIP events on its own stream during
+             the timed steps, against the 8 TB/s HBM3E peak; `traffic` is the
+             counter-measured HBM bytes per launch from the committed
+             rocprofv3 summary when it still matches the kernel sources
+  cpu_baseline  the FP64 CPU oracle, single-threaded, on a bounded sample of
+             the same solve (set-up + a fixed number of iterations)
+
+Everything else (progress, per-variant numbers) goes to stderr or to extra
+JSON fields.  Only one GPU is used: --gpus N with N > 1 exits with a message.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HBM GB/s per pipelined iteration; time-to-1e-8 residual vs plain FP64"
+PEAK_GBPS = 8000.0
+CLASSES = ["spmv", "dots", "update", "spmv_fused", "other"]
+KERNEL_NAMES = {"spmv": "k_spmv<EpiStore> (A s_i)", "dots": "k_dots<ProdSafe9, FinSafe>",
+                "update": "k_passA_pbicgsafe", "spmv_fused": "k_spmv<EpiPBiCGSafeB> (A w_i + l, g, s)"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cd3d_128.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def matrix_bytes(n, nnz):
+    """CSR bytes: int32 column index + FP64 value per nonzero, int32 row pointer."""
+    return 12 * nnz + 4 * (n + 1)
+
+
+def bytes_per_iteration(variant, n, nnz):
+    """Algorithmic HBM bytes of one iteration of the implemented schedule (FP64 vectors,
+    each vector entry read or written once per kernel that needs it, x-gather once).
+
+    p-BiCGSafe:  A s (M+16n) + 9 dots (40n) + pass A (168n) + A w with l, g, s (M+64n)
+    ssBiCGSafe2: A r (M+16n) + 9 dots (40n) + p, u (64n) + A u with t, z, y, x, r (M+104n)
+    p-BiCGStab:  pass 1 (96n) + A z (M+16n) + 2 dots (16n) + pass 2 (72n) + A w (M+16n)
+                 + 5 dots (40n)
+    (p-BiCGSafe-rr is counted as p-BiCGSafe; its replacement steps add ~1% at m = 100.)
+    """
+    M = matrix_bytes(n, nnz)
+    return {"pbicgsafe": 2 * M + 288 * n, "pbicgsafe_rr": 2 * M + 288 * n,
+            "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
+
+
+def bytes_per_launch(cls, n, nnz):
+    M = matrix_bytes(n, nnz)
+    return {"spmv": M + 16 * n, "dots": 40 * n, "update": 168 * n, "spmv_fused": M + 64 * n}[cls]
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2108_10591_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(cls):
+    """Counter-measured bytes per launch of class `cls`, or None if absent or stale."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    k = t.get("kernels", {}).get(cls)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(A, iters, variant="pbicgsafe"):
+    import oracle
+    t0 = time.perf_counter()
+    res = oracle.solve(A, tol=1e-8, maxit=iters, variant=variant)
+    dt = time.perf_counter() - t0
+    gb = bytes_per_iteration(variant, A.n, A.nnz) * res.iters / 1e9
+    return {"value": round(gb / dt, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{A.name} {variant}: set-up + {res.iters} iterations (maxit={iters}) in "
+                      f"{dt:.2f} s, single-threaded C, FP64; {res.iters / dt:.2f} iterations/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cd3d_128")
+    ap.add_argument("--variant", default="pbicgsafe")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--overlap", type=int, default=1)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run the library's streaming copy on MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the solver is a single-GPU implementation "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2108_10591_amd import pipesafe, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.calibrate_copy:
+        nb = args.calibrate_copy * (1 << 20)
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            pipesafe.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            pipesafe.stream_copy(dst, src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        log(f"copy {args.calibrate_copy} MiB: {2 * nb / dt / 1e9:.1f} GB/s (read + write)")
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb,
+                          "copy_GBps": round(2 * nb / dt / 1e9, 1)}))
+        return
+
+    log(f"building workload {args.workload} ...")
+    t0 = time.perf_counter()
+    A = workloads.workload(args.workload)
+    tol = workloads.WORKLOADS[args.workload]["tol"]
+    log(f"  n={A.n} nnz={A.nnz} ({time.perf_counter() - t0:.1f} s)")
+    M = pipesafe.Matrix.from_csr(A)
+    b = torch.from_numpy(A.b).to(dev)
+    x = torch.empty(A.n, dtype=torch.float64, device=dev)
+    maxit = 10_000
+    variant = args.variant
+
+    # one profiled solve to find the dominant kernel class
+    res = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, overlap=args.overlap,
+                      profile=CLASSES[:4])
+    stats = M.kernel_stats()
+    dominant = max(CLASSES[:4], key=lambda c: stats[c][0])
+    log(f"profiled solve: iters={res.iters} status={res.status_name}; per-class ms: "
+        + ", ".join(f"{c}={stats[c][0]:.2f}/{stats[c][1]}" for c in CLASSES[:4])
+        + f"; dominant: {dominant}")
+
+    for _ in range(args.warmup):
+        M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, overlap=args.overlap)
+    torch.cuda.synchronize()
+    iters = []
+    kms, kcnt = 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, overlap=args.overlap,
+                        profile=[dominant], hist=False)
+        iters.append(r.iters)
+        st = M.kernel_stats()[dominant]
+        kms += st[0]
+        kcnt += st[1]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert r.status == pipesafe.CONVERGED, r.status_name
+    it = iters[-1]
+    assert all(i == it for i in iters), iters
+    ms_per_step = 1e3 * elapsed / args.steps
+    bpi = bytes_per_iteration(variant, A.n, A.nnz)
+    value = bpi * it / (ms_per_step * 1e-3) / 1e9
+    xh = x.cpu().numpy()
+    err1 = float(np.abs(xh - 1.0).max())
+    log(f"{variant}: {it} iterations, {ms_per_step:.2f} ms/solve, {1e3 * ms_per_step / it:.1f} us/iter,"
+        f" {value:.0f} GB/s, ||x-1||_inf={err1:.2e}")
+
+    avg_us = 1e3 * kms / max(kcnt, 1)
+    bpl = bytes_per_launch(dominant, A.n, A.nnz)
+    achieved = bpl / (avg_us * 1e-6) / 1e9
+    traffic = load_traffic(dominant)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": KERNEL_NAMES[dominant], "bytes_per_launch": bpl,
+                "avg_launch_us": round(avg_us, 3), "launches": kcnt}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "n": A.n, "nnz": A.nnz, "variant": variant,
+                      "tol": tol, "x0": "zero", "rhs": "A*ones", "iterations": it,
+                      "bytes_per_iteration": bpi, "overlap": bool(args.overlap)},
+           "time_to_tol_ms": round(ms_per_step, 3), "iters_per_s": round(it / (ms_per_step * 1e-3), 1),
+           "us_per_iter": round(1e3 * ms_per_step / it, 2),
+           "iteration_hbm_frac": round(value / PEAK_GBPS, 4), "x_minus_1_inf": err1,
+           "roofline": roofline}
+
+    if not args.no_variants:
+        var = {}
+        for v in ["ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"]:
+            M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                rv = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, hist=False)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t1) / reps
+            gbps = bytes_per_iteration(v, A.n, A.nnz) * rv.iters / (ms * 1e-3) / 1e9
+            var[v] = {"iterations": rv.iters, "status": rv.status_name, "time_to_tol_ms": round(ms, 3),
+                      "us_per_iter": round(1e3 * ms / max(rv.iters, 1), 2), "GBps": round(gbps, 1)}
+            log(f"{v}: {var[v]}")
+        out["variants"] = var
+
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_iters} iterations ...")
+        out["cpu_baseline"] = cpu_baseline(A, args.cpu_iters, variant)
+        log(f"  {out['cpu_baseline']}")
+    M.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -93,12 +93,13 @@ typedef struct {
 
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */
 enum ps_kernel {
-  PS_K_SPMV = 0,       /* sparse product with no fused work (A s_i, A z_i, ...)         */
-  PS_K_DOTS = 1,       /* multi-inner-product kernel with its last-block finish         */
-  PS_K_UPDATE = 2,     /* fused vector-update pass                                       */
-  PS_K_SPMV_FUSED = 3, /* sparse product with a fused update epilogue                    */
-  PS_K_OTHER = 4,      /* set-up, replacement and bookkeeping kernels                    */
-  PS_K_COUNT = 5
+  PS_K_SPMV = 0,        /* sparse product with no fused work (A s_i, A z_i, ...)        */
+  PS_K_DOTS = 1,        /* multi-inner-product kernel (per-block partial sums)          */
+  PS_K_UPDATE = 2,      /* fused vector-update pass                                      */
+  PS_K_SPMV_FUSED = 3,  /* sparse product with a fused update epilogue                   */
+  PS_K_OTHER = 4,       /* set-up, replacement and bookkeeping kernels                   */
+  PS_K_DOTS_FINISH = 5, /* one-block finish: final sums, coefficients, stop test         */
+  PS_K_COUNT = 6
 };
 
 /* state vectors, for ps_get_state / ps_set_state (names follow Algorithms 3-5;
@@ -178,7 +179,8 @@ int ps_set_scalars(ps_matrix *A, const double *host_in);
 
 /* Kernel timing of the last solve run with opt.profile != 0: total milliseconds
    and launch count of class `cls` (ps_kernel), measured with HIP events around
-   each launch on its own stream. */
+   each launch on its own stream.  Only launches of iterations before the
+   stopping one are counted (later launches may be no-ops). */
 int ps_kernel_stats(ps_matrix *A, int32_t cls, double *total_ms, int64_t *launches);
 
 /* Device copy dst = src of `bytes` bytes (DEVICE pointers, 16-byte aligned,

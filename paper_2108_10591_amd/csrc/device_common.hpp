@@ -17,7 +17,6 @@ enum Ctl : int {
   C_DONE = 0,     // nonzero once the solve has stopped; every later kernel is a no-op
   C_STATUS = 1,   // ps_status once done
   C_ITERS = 2,    // iteration index at the stop
-  C_TICKET = 3,   // arrival counter of the multi-dot kernels (reset by the last block)
   C_HALT = 4,     // set by the first main-stream kernel that sees C_DONE; read by the
                   // sparse products that may run concurrently with a finish
   C_COUNT = 16

@@ -1,12 +1,19 @@
-// Multi-inner-product kernels with a last-block finish.
+// Multi-inner-product kernels and their finish.
 //
 // One pass over the input vectors forms every inner product of a reduction
 // phase at once: each thread keeps one accumulator per product over a fixed
 // grid-stride set of entries, the block combines them with wavefront
-// shuffles and LDS, and each block writes its partial sums.  The block that
-// arrives last (atomic ticket) adds the partials in block order -- so the
-// result is bit-for-bit reproducible -- and then computes the phase's scalar
+// shuffles and LDS, and each block writes its partial sums.  A one-block
+// finish kernel, next in the same stream, adds the partials in block order --
+// so the result is bit-for-bit reproducible -- and computes the phase's scalar
 // coefficients and the stop test on the device.  No host round trip.
+//
+// Why two kernels rather than a last-arriving-block finish: on this part each
+// XCD has its own write-back L2, so a block that publishes partials to a block
+// on another XCD needs a device-scope release (a full L2 write-back) per
+// block; one kernel boundary gives the same visibility once.  The finish is a
+// small launch on the reduction's own stream, hidden behind the concurrent
+// sparse product.
 //
 // Accumulators are unevaluated pairs (hi, lo): each product is split exactly
 // into its rounded value and rounding error (one FMA), each addition into its
@@ -67,17 +74,8 @@ __device__ __forceinline__ void dd_add(DD &a, double bhi, double blo) {
 // FIRST: i = 0, where only a, d, f, g, rho are formed (y_0 = t_{-1} = 0).
 template <bool FIRST>
 struct ProdSafe9 {
-  static constexpr int NIN = FIRST ? 3 : 5;
+  static constexpr unsigned MASK = FIRST ? 0b01101u : 0b11111u;  // s, (y), r, r0*, (t)
   static constexpr int ND = 9;
-  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
-    in[0] = A.v[0][k];  // s
-    in[2] = A.v[2][k];  // r
-    in[3] = A.v[3][k];  // r0*
-    if (!FIRST) {
-      in[1] = A.v[1][k];  // y
-      in[4] = A.v[4][k];  // t
-    }
-  }
   __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     const double s = in[0], r = in[2], rs = in[3];
     dd_fma(a[0], s, s);
@@ -97,11 +95,8 @@ struct ProdSafe9 {
 
 // p-BiCGStab phase 1: (q, y), (y, y)
 struct ProdStab2 {
+  static constexpr unsigned MASK = 0b11u;  // q, y
   static constexpr int ND = 2;
-  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
-    in[0] = A.v[0][k];
-    in[1] = A.v[1][k];
-  }
   __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     dd_fma(a[0], in[0], in[1]);
     dd_fma(a[1], in[1], in[1]);
@@ -111,11 +106,8 @@ struct ProdStab2 {
 // p-BiCGStab phase 2: (r0*, r), (r0*, w), (r0*, s), (r0*, z), (r, r)
 // inputs: v = {r0*, r, w, s, z}
 struct ProdStab5 {
+  static constexpr unsigned MASK = 0b11111u;
   static constexpr int ND = 5;
-  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
-#pragma unroll
-    for (int j = 0; j < 5; ++j) in[j] = A.v[j][k];
-  }
   __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     const double rs = in[0], r = in[1];
     dd_fma(a[0], rs, r);
@@ -128,11 +120,8 @@ struct ProdStab5 {
 
 // p-BiCGStab set-up: (r0*, r0), (r0*, w0), (r0, r0); inputs v = {r0*, r, w}
 struct ProdStab3 {
+  static constexpr unsigned MASK = 0b111u;
   static constexpr int ND = 3;
-  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) in[j] = A.v[j][k];
-  }
   __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     dd_fma(a[0], in[0], in[1]);
     dd_fma(a[1], in[0], in[2]);
@@ -142,14 +131,31 @@ struct ProdStab3 {
 
 // (v, v): the squared norm of b for the ||b|| stop-test scale
 struct ProdNorm {
+  static constexpr unsigned MASK = 0b1u;
   static constexpr int ND = 1;
-  __device__ __forceinline__ static void load(const DotArgs &A, int64_t k, double (&in)[5]) {
-    in[0] = A.v[0][k];
-  }
   __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
     dd_fma(a[0], in[0], in[0]);
   }
 };
+
+// load entry k (or the pair k, k+1, 16-byte aligned) of the inputs in MASK
+template <unsigned MASK>
+__device__ __forceinline__ void load_in(const DotArgs &A, int64_t k, double (&a)[5]) {
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+    if ((MASK >> j) & 1u) a[j] = A.v[j][k];
+}
+template <unsigned MASK>
+__device__ __forceinline__ void load_in2(const DotArgs &A, int64_t k, double (&a)[5],
+                                         double (&b)[5]) {
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+    if ((MASK >> j) & 1u) {
+      const double2 v = *reinterpret_cast<const double2 *>(A.v[j] + k);
+      a[j] = v.x;
+      b[j] = v.y;
+    }
+}
 
 // ---------------------------------------------------------------- finishes
 // Run by one thread with the phase's final inner products.
@@ -336,34 +342,41 @@ __device__ __forceinline__ DD block_sum_dd(DD (&a)[K], double *lds) {
   return r;
 }
 
-template <class Prod, class Fin>
+template <class Prod>
 __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
   constexpr int ND = Prod::ND;
   __shared__ double lds[kWavesPerBlock * 9 * 2];
-  __shared__ double fin[9];
-  __shared__ int last;
   if (A.ctl[C_DONE]) return;
   DD acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = DD{0.0, 0.0};
-  double in[5];
+  double in0[5], in1[5];
+  const int64_t npair = A.n / 2;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < A.n; k += stride) {
-    Prod::load(A, k, in);
-    Prod::acc(in, acc);
+  for (int64_t k2 = (int64_t)blockIdx.x * kBlock + threadIdx.x; k2 < npair; k2 += stride) {
+    load_in2<Prod::MASK>(A, 2 * k2, in0, in1);
+    Prod::acc(in0, acc);
+    Prod::acc(in1, acc);
   }
-  DD s = block_sum_dd<ND>(acc, lds);
+  if ((A.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    load_in<Prod::MASK>(A, A.n - 1, in0);
+    Prod::acc(in0, acc);
+  }
+  const DD s = block_sum_dd<ND>(acc, lds);
   const int G = gridDim.x;
   if (threadIdx.x < ND) {
     A.partials[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
     A.partials[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
-    __threadfence();  // publish the partial device-wide before taking a ticket
   }
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&A.ctl[C_TICKET], 1) == G - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();  // acquire: see every block's partials
+}
+
+// One block: add the G partial pairs of each product in block order, round
+// once, and run the phase's finish.
+template <int ND, class Fin>
+__global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double fin[9];
+  if (A.ctl[C_DONE]) return;
   DD tot[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) tot[j] = DD{0.0, 0.0};
@@ -372,14 +385,13 @@ __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
     for (int j = 0; j < ND; ++j)
       dd_add(tot[j], A.partials[(j * G + b) * 2], A.partials[(j * G + b) * 2 + 1]);
   }
-  s = block_sum_dd<ND>(tot, lds);
+  const DD s = block_sum_dd<ND>(tot, lds);
   if (threadIdx.x < ND) fin[threadIdx.x] = s.hi + s.lo;  // the one final rounding
   __syncthreads();
   if (threadIdx.x == 0) {
     double d[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) d[j] = fin[j];
-    A.ctl[C_TICKET] = 0;
     Fin::run(A, d);
   }
 }

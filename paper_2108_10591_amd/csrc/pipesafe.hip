@@ -44,6 +44,7 @@ constexpr int kMaxDotGrid = 1024;
 struct Timer {
   hipEvent_t a, b;
   int cls;
+  int iter;  // iteration the launch belongs to (-1: set-up)
 };
 
 }  // namespace
@@ -68,6 +69,7 @@ struct ps_matrix {
   std::atomic<int> busy{0};
   // kernel timing
   int prof_mask = 0;
+  int cur_iter = -1;        // iteration being enqueued (for kernel timing)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<Timer> timers;
@@ -125,7 +127,7 @@ int launch(ps_matrix *M, hipStream_t s, int cls, Kernel kernel, dim3 grid, size_
   hipLaunchKernelGGL(kernel, grid, dim3(kBlock), shmem, s, args...);
   if (prof) {
     PS_HIP(hipEventRecord(b, s));
-    M->timers.push_back(Timer{a, b, cls});
+    M->timers.push_back(Timer{a, b, cls, M->cur_iter});
   }
   return PS_OK;
 }
@@ -160,7 +162,8 @@ int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, 
   A.maxit = maxit;
   A.tol = tol;
   A.flags = flags;
-  return launch(M, s, PS_K_DOTS, k_dots<Prod, Fin>, dim3(M->dot_grid), 0, A);
+  PS_TRY(launch(M, s, PS_K_DOTS, k_dots<Prod>, dim3(M->dot_grid), 0, A));
+  return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<Prod::ND, Fin>, dim3(1), 0, A, M->dot_grid);
 }
 
 // ------------------------------------------------------------------ set-up
@@ -333,12 +336,16 @@ int ensure_hist(ps_matrix *M, int64_t need) {
   return PS_OK;
 }
 
-int collect_profile(ps_matrix *M) {
+// Sum the timed launches of iterations before the stop; launches of the
+// stopping iteration and of iterations enqueued after it may be no-ops and are
+// left out.
+int collect_profile(ps_matrix *M, int stop_iter) {
   for (int c = 0; c < PS_K_COUNT; ++c) {
     M->prof_ms[c] = 0.0;
     M->prof_cnt[c] = 0;
   }
   for (const Timer &t : M->timers) {
+    if (t.iter < 0 || t.iter >= stop_iter) continue;
     float ms = 0.f;
     PS_HIP(hipEventElapsedTime(&ms, t.a, t.b));
     M->prof_ms[t.cls] += ms;
@@ -381,6 +388,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.overlap = o.overlap != 0 && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
   M->prof_mask = o.profile;
+  M->cur_iter = -1;
   M->timers.clear();
   M->ev_used = 0;
   PS_TRY(ensure_hist(M, (int64_t)maxit + 2));
@@ -402,6 +410,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   for (int i = P.i0; i <= last && !stopped;) {
     const int end = std::min(last, i + K - 1);
     for (; i <= end; ++i) {
+      M->cur_iter = i;
       int rc;
       switch (variant) {
         case PS_SSBICGSAFE2: rc = iter_ssbicgsafe2(M, P, i); break;
@@ -437,7 +446,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
                              hipMemcpyDeviceToHost));
   PS_HIP(hipMemcpy(x, M->slot(PS_V_X), vbytes,
                    on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
-  if (M->prof_mask) PS_TRY(collect_profile(M));
+  if (M->prof_mask) PS_TRY(collect_profile(M, it));
   return PS_OK;
 }
 
@@ -538,7 +547,7 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   std::vector<int> rp32(n + 1);
   for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
   M->ld = ((size_t)n + 31) / 32 * 32;
-  M->dot_grid = (int)std::min<int64_t>(kMaxDotGrid, (n + kBlock - 1) / kBlock);
+  M->dot_grid = (int)std::min<int64_t>(kMaxDotGrid, (n / 2 + kBlock - 1) / kBlock + 1);
 
   auto fail = [&](int code) {
     free_matrix(M);

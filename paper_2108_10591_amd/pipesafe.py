@@ -21,7 +21,7 @@ CONVERGED, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 STATUS_NAMES = {0: "converged", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
 VEC = ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o", "As", "v", "b"]
 SCAL = ["alpha", "beta", "zeta", "eta", "omega", "f", "rhoref", "rho", "pending", "gs", "gw", "gz"]
-KERNEL_CLASSES = {"spmv": 0, "dots": 1, "update": 2, "spmv_fused": 3, "other": 4}
+KERNEL_CLASSES = {"spmv": 0, "dots": 1, "update": 2, "spmv_fused": 3, "other": 4, "dots_finish": 5}
 
 
 class PipesafeError(RuntimeError):
