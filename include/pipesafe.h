@@ -86,6 +86,10 @@ typedef struct {
                           and continue from the state loaded by ps_set_state /
                           ps_set_scalars, starting at iteration resume_iter.            */
   int32_t resume_iter;
+  int32_t graph;       /* 1 (default): replay batches of identical iterations as cached
+                          HIP graphs; 0: launch every kernel directly.  Results are
+                          bit-identical either way.  Ignored while profiling.          */
+  int32_t reserved;    /* set to 0 */
   void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
                           caller's current stream).  NULL: ps_solve_dev uses the null
                           stream, ps_solve the library's own stream.                   */

@@ -19,6 +19,8 @@ enum Ctl : int {
   C_ITERS = 2,    // iteration index at the stop
   C_HALT = 4,     // set by the first main-stream kernel that sees C_DONE; read by the
                   // sparse products that may run concurrently with a finish
+  C_ITER = 5,     // index of the iteration whose reduction phase runs next; advanced
+                  // by the finish, so replayed launches need no per-iteration argument
   C_COUNT = 16
 };
 
@@ -70,6 +72,13 @@ __device__ __forceinline__ double block_sum_1(double v, double *lds) {
 }
 
 __device__ __forceinline__ bool bad_den(double d) { return d == 0.0 || !isfinite(d); }
+
+// Sweep direction.  Consecutive streaming kernels of an iteration walk the
+// rows in alternating directions, so each one starts on the rows the previous
+// one touched last -- the lines most likely still held in the 256 MB
+// memory-side Infinity Cache (MALL) -- instead of the ones it evicted first.
+// Per-row arithmetic is unchanged, so results do not depend on the direction.
+__device__ __forceinline__ int sweep_block(int b, int nb, int rev) { return rev ? nb - 1 - b : b; }
 
 // Stop the solve: record status and iteration index.
 __device__ __forceinline__ void set_stop(int *ctl, int status, int iters) {

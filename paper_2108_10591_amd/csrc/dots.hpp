@@ -33,7 +33,7 @@ struct DotArgs {
   int *ctl;
   double *sc;
   double *hist;
-  int iter, maxit;
+  int maxit;
   double tol;
   int flags;           // finish-specific flags
 };
@@ -164,6 +164,7 @@ __device__ __forceinline__ void load_in2(const DotArgs &A, int64_t k, double (&a
 struct FinSafe {
   __device__ static void run(const DotArgs &A, const double (&d)[9]) {
     double *sc = A.sc;
+    const int i = A.ctl[C_ITER];
     const double a = d[0], b = d[1], c = d[2], dd = d[3], e = d[4], f = d[5], g = d[6], h = d[7],
                  rho = d[8];
     for (int j = 0; j < 9; ++j) sc[SC_DOTS + j] = d[j];
@@ -171,16 +172,16 @@ struct FinSafe {
     bool finite = true;
     for (int j = 0; j < 9; ++j) finite = finite && isfinite(d[j]);
     if (!finite) {
-      A.hist[A.iter] = NAN;
-      set_stop(A.ctl, PS_NONFINITE, A.iter);
+      A.hist[i] = NAN;
+      set_stop(A.ctl, PS_NONFINITE, i);
       return;
     }
     if (A.flags & DF_SET_REF) sc[PS_S_RHOREF] = rho;
-    if (stop_test(rho, sc, A.ctl, A.hist, A.iter, A.maxit, A.tol)) return;
+    if (stop_test(rho, sc, A.ctl, A.hist, i, A.maxit, A.tol)) return;
     double beta, alpha, zeta, eta;
-    if (A.iter == 0) {
+    if (i == 0) {
       if (bad_den(g) || bad_den(a)) {
-        set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+        set_stop(A.ctl, PS_BREAKDOWN, i);
         return;
       }
       beta = 0.0;
@@ -190,14 +191,14 @@ struct FinSafe {
     } else {
       const double den_beta = sc[PS_S_ZETA] * sc[PS_S_F];
       if (bad_den(den_beta)) {
-        set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+        set_stop(A.ctl, PS_BREAKDOWN, i);
         return;
       }
       beta = (sc[PS_S_ALPHA] * f) / den_beta;
       const double den_alpha = g + beta * h;
       const double den_ze = a * b - c * c;
       if (bad_den(den_alpha) || bad_den(den_ze)) {
-        set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+        set_stop(A.ctl, PS_BREAKDOWN, i);
         return;
       }
       alpha = f / den_alpha;
@@ -205,7 +206,7 @@ struct FinSafe {
       eta = (a * e - c * dd) / den_ze;
     }
     if (!isfinite(beta) || !isfinite(alpha) || !isfinite(zeta) || !isfinite(eta)) {
-      set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+      set_stop(A.ctl, PS_BREAKDOWN, i);
       return;
     }
     sc[PS_S_ALPHA] = alpha;
@@ -213,6 +214,7 @@ struct FinSafe {
     sc[PS_S_ZETA] = zeta;
     sc[PS_S_ETA] = eta;
     sc[PS_S_F] = f;
+    A.ctl[C_ITER] = i + 1;
   }
 };
 
@@ -220,15 +222,16 @@ struct FinSafe {
 struct FinStabOmega {
   __device__ static void run(const DotArgs &A, const double (&d)[2]) {
     double *sc = A.sc;
+    const int i = A.ctl[C_ITER];
     sc[SC_DOTS + 0] = d[0];
     sc[SC_DOTS + 1] = d[1];
     if (!isfinite(d[0]) || !isfinite(d[1])) {
-      set_stop(A.ctl, PS_NONFINITE, A.iter);
+      set_stop(A.ctl, PS_NONFINITE, i);
       return;
     }
     const double om = d[1] == 0.0 ? 0.0 : d[0] / d[1];
     if (!isfinite(om)) {
-      set_stop(A.ctl, PS_BREAKDOWN, A.iter);
+      set_stop(A.ctl, PS_BREAKDOWN, i);
       return;
     }
     sc[PS_S_OMEGA] = om;
@@ -243,7 +246,7 @@ struct FinStabBetaAlpha {
     double *sc = A.sc;
     const double f = d[0], gw = d[1], gs = d[2], gz = d[3], rho = d[4];
     for (int j = 0; j < 5; ++j) sc[SC_DOTS + j] = d[j];
-    const int i1 = A.iter + 1;
+    const int i1 = A.ctl[C_ITER] + 1;
     const double al = sc[PS_S_ALPHA], om = sc[PS_S_OMEGA];
     double beta = 0.0, alpha = 0.0;
     bool pend = false;
@@ -271,7 +274,11 @@ struct FinStabBetaAlpha {
       return;
     }
     if (stop_test(rho, sc, A.ctl, A.hist, i1, A.maxit, A.tol)) return;
-    if (pend) set_stop(A.ctl, PS_BREAKDOWN, i1);
+    if (pend) {
+      set_stop(A.ctl, PS_BREAKDOWN, i1);
+      return;
+    }
+    A.ctl[C_ITER] = i1;
   }
 };
 
@@ -309,20 +316,50 @@ struct FinNormRef {
 
 // ---------------------------------------------------------------- the kernel
 
+// Lane permutations of a double within rows of 16 lanes (DPP), and a lane read.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dd_step(DD &a) {
+  const double h = dpp_f64<CTRL>(a.hi);
+  const double l = dpp_f64<CTRL>(a.lo);
+  dd_add(a, h, l);
+}
+
+// Pair sum over a wavefront, the same value in every lane.  Within each row of
+// 16 lanes: partner at lane^1 and lane^2 (quad permutes), then the other quad
+// of the half-row and the other half of the row (mirrors); then the four row
+// totals (lanes 0, 16, 32, 48) in row order.
+__device__ __forceinline__ DD wave_sum_dd(DD a) {
+  dd_step<0xB1>(a);   // quad_perm [1,0,3,2]
+  dd_step<0x4E>(a);   // quad_perm [2,3,0,1]
+  dd_step<0x141>(a);  // row_half_mirror
+  dd_step<0x140>(a);  // row_mirror
+  DD t{readlane_f64(a.hi, 0), readlane_f64(a.lo, 0)};
+#pragma unroll
+  for (int r = 1; r < 4; ++r) dd_add(t, readlane_f64(a.hi, 16 * r), readlane_f64(a.lo, 16 * r));
+  return t;
+}
+
 // Block-wide pair sums: on return thread k (< K) holds the block total of a[k].
 template <int K>
 __device__ __forceinline__ DD block_sum_dd(DD (&a)[K], double *lds) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-      const double h = __shfl_xor(a[k].hi, off, kWave);
-      const double l = __shfl_xor(a[k].lo, off, kWave);
-      dd_add(a[k], h, l);
-    }
-  }
+  for (int k = 0; k < K; ++k) a[k] = wave_sum_dd(a[k]);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -350,17 +387,18 @@ __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
   DD acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) acc[j] = DD{0.0, 0.0};
-  double in0[5], in1[5];
+  // a pair of entries (16-byte loads) per thread per grid-stride step
+  double a0[5], a1[5];
   const int64_t npair = A.n / 2;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t k2 = (int64_t)blockIdx.x * kBlock + threadIdx.x; k2 < npair; k2 += stride) {
-    load_in2<Prod::MASK>(A, 2 * k2, in0, in1);
-    Prod::acc(in0, acc);
-    Prod::acc(in1, acc);
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < npair; p += stride) {
+    load_in2<Prod::MASK>(A, 2 * p, a0, a1);
+    Prod::acc(a0, acc);
+    Prod::acc(a1, acc);
   }
   if ((A.n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    load_in<Prod::MASK>(A, A.n - 1, in0);
-    Prod::acc(in0, acc);
+    load_in<Prod::MASK>(A, A.n - 1, a0);
+    Prod::acc(a0, acc);
   }
   const DD s = block_sum_dd<ND>(acc, lds);
   const int G = gridDim.x;

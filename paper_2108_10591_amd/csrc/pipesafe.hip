@@ -39,12 +39,30 @@ namespace {
 
 constexpr int kSlotTmp = PS_V_COUNT;  // internal scratch vector
 constexpr int kNumSlots = PS_V_COUNT + 1;
-constexpr int kMaxDotGrid = 1024;
+constexpr int kMaxDotGrid = 512;  // partial-sum blocks: about two per CU
 
 struct Timer {
   hipEvent_t a, b;
   int cls;
   int iter;  // iteration the launch belongs to (-1: set-up)
+};
+
+// Everything a captured batch of iterations depends on.
+struct GraphKey {
+  int variant, maxit, rr_m, rr_M, overlap, count, phase;
+  double tol;
+  hipStream_t stream;
+  bool operator==(const GraphKey &o) const {
+    return variant == o.variant && maxit == o.maxit && rr_m == o.rr_m && rr_M == o.rr_M &&
+           overlap == o.overlap && count == o.count && phase == o.phase && tol == o.tol &&
+           stream == o.stream;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec;
+  int sweep_flip;  // parity of the full sweeps the batch performs
 };
 
 }  // namespace
@@ -54,7 +72,8 @@ struct ps_matrix {
   int64_t n = 0, nnz = 0;
   int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
   double *val = nullptr;
-  int nblk = 0, budget = 0;
+  int nblk = 0;
+  int ipt = 8;              // nonzeros per thread of a short-row block (4, 8 or 16)
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -70,6 +89,8 @@ struct ps_matrix {
   // kernel timing
   int prof_mask = 0;
   int cur_iter = -1;        // iteration being enqueued (for kernel timing)
+  int sweep = 0;            // direction of the next full-sweep kernel (0 forward, 1 backward)
+  std::vector<GraphEntry> graphs;  // instantiated batches of iterations
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<Timer> timers;
@@ -77,7 +98,7 @@ struct ps_matrix {
   int64_t prof_cnt[PS_K_COUNT] = {};
 
   double *slot(int s) const { return vec + (size_t)s * ld; }
-  CsrDev csr() const { return CsrDev{rowptr, col, val, blk, nblk, budget}; }
+  CsrDev csr() const { return CsrDev{rowptr, col, val, blk, nblk}; }
 };
 
 namespace {
@@ -141,15 +162,31 @@ int launch(ps_matrix *M, hipStream_t s, int cls, Kernel kernel, dim3 grid, size_
 dim3 pair_grid(int64_t n) { return dim3((unsigned)((n + 2 * kBlock - 1) / (2 * kBlock))); }
 dim3 elem_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
 
+// Direction of the next full sweep over the rows: consecutive sweeps alternate
+// (see sweep_block).
+int next_rev(ps_matrix *M) {
+  const int r = M->sweep;
+  M->sweep ^= 1;
+  return r;
+}
+
 template <class Epi>
 int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop) {
-  return launch(M, s, cls, k_spmv<Epi>, dim3(M->nblk), (size_t)M->budget * sizeof(double),
-                M->csr(), x, epi, stop);
+  const size_t lds = (size_t)M->ipt * kBlock * sizeof(double);
+  const int rev = next_rev(M);
+  switch (M->ipt) {
+    case 4:
+      return launch(M, s, cls, k_spmv<4, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
+    case 8:
+      return launch(M, s, cls, k_spmv<8, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
+    default:
+      return launch(M, s, cls, k_spmv<16, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
+  }
 }
 
 template <class Prod, class Fin>
-int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, int iter,
-         int maxit, double tol, int flags, double *hist) {
+int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, int maxit,
+         double tol, int flags, double *hist) {
   DotArgs A{};
   int j = 0;
   for (const double *p : in) A.v[j++] = p;
@@ -158,7 +195,6 @@ int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, 
   A.ctl = M->ctl;
   A.sc = M->sc;
   A.hist = hist;
-  A.iter = iter;
   A.maxit = maxit;
   A.tol = tol;
   A.flags = flags;
@@ -206,13 +242,13 @@ int enqueue_setup(ps_matrix *M, const Plan &P) {
     PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, nullptr));
   }
   if (P.norm_ref == 1) {
-    PS_TRY(dots<ProdNorm, FinNormRef>(M, s, {Bv}, 0, P.maxit, P.tol, 0, M->hist));
+    PS_TRY(dots<ProdNorm, FinNormRef>(M, s, {Bv}, P.maxit, P.tol, 0, M->hist));
   }
   if (P.variant == PS_PBICGSTAB) {
     double *W = M->slot(PS_V_W), *T = M->slot(PS_V_T);
     PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{W}, nullptr));  // w_0 = A r_0
     PS_TRY(spmv(M, s, PS_K_OTHER, W, EpiStore{T}, nullptr));  // t_0 = A w_0
-    PS_TRY(dots<ProdStab3, FinStabSetup>(M, s, {RS, R, W}, 0, P.maxit, P.tol,
+    PS_TRY(dots<ProdStab3, FinStabSetup>(M, s, {RS, R, W}, P.maxit, P.tol,
                                          P.norm_ref == 0 ? DF_SET_REF : 0, M->hist));
   }
   return PS_OK;
@@ -240,8 +276,8 @@ int iter_safe_dots(ps_matrix *M, const Plan &P, hipStream_t s, int i) {
   double *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y), *R = M->slot(PS_V_R),
          *RS = M->slot(PS_V_RS), *T = M->slot(PS_V_T);
   if (i == 0)
-    return dots<ProdSafe9<true>, FinSafe>(M, s, {S, Y, R, RS, T}, i, P.maxit, P.tol, flags, M->hist);
-  return dots<ProdSafe9<false>, FinSafe>(M, s, {S, Y, R, RS, T}, i, P.maxit, P.tol, flags, M->hist);
+    return dots<ProdSafe9<true>, FinSafe>(M, s, {S, Y, R, RS, T}, P.maxit, P.tol, flags, M->hist);
+  return dots<ProdSafe9<false>, FinSafe>(M, s, {S, Y, R, RS, T}, P.maxit, P.tol, flags, M->hist);
 }
 
 int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
@@ -258,18 +294,18 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
     PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, M->ctl + C_HALT));  // As_i
     PS_TRY(iter_safe_dots(M, P, P.B, i));                              // concurrently
     PS_TRY(join(M, P));
-    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n};
+    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M)};
     PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe, pair_grid(M->n), 0, pa));
     PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, done));
     return PS_OK;
   }
   // replacement step (Algorithm 5): true values of q, w, r, l, g, s
   PS_TRY(iter_safe_dots(M, P, A, i));
-  PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n};
+  PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n, next_rev(M)};
   PS_TRY(launch(M, A, PS_K_OTHER, k_pou, pair_grid(M->n), 0, po));
   PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, done));  // q_i = A o_i
   PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, done));  // w_i = A u_i
-  TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n};
+  TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n, next_rev(M)};
   PS_TRY(launch(M, A, PS_K_OTHER, k_tzyx, pair_grid(M->n), 0, tz));
   PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, done));  // r_{i+1} = b - A x_{i+1}
   PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, done));                  // l_i = A t_i
@@ -285,30 +321,92 @@ int iter_ssbicgsafe2(ps_matrix *M, const Plan &P, int i) {
   int *done = M->ctl + C_DONE;
   PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, done));  // s_i = A r_i
   PS_TRY(iter_safe_dots(M, P, A, i));
-  PouArgs po{R, S, T, Y, Pp, U, nullptr, M->sc, M->ctl, M->n};
+  PouArgs po{R, S, T, Y, Pp, U, nullptr, M->sc, M->ctl, M->n, next_rev(M)};
   PS_TRY(launch(M, A, PS_K_UPDATE, k_pu, pair_grid(M->n), 0, po));
   PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, done));
   return PS_OK;
 }
 
-int iter_pbicgstab(ps_matrix *M, const Plan &P, int i) {
+int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
   hipStream_t A = P.A;
   double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *RS = M->slot(PS_V_RS),
          *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y), *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P),
          *Z = M->slot(PS_V_Z), *W = M->slot(PS_V_W), *Q = M->slot(PS_V_Q), *V = M->slot(PS_V_V);
-  Stab1Args s1{R, W, T, V, Pp, S, Z, Q, Y, M->sc, M->ctl, M->n};
+  Stab1Args s1{R, W, T, V, Pp, S, Z, Q, Y, M->sc, M->ctl, M->n, next_rev(M)};
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1, pair_grid(M->n), 0, s1));
   PS_TRY(fork(M, P));
   PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, M->ctl + C_HALT));  // v_i = A z_i
-  PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, i, P.maxit, P.tol, 0, M->hist));
+  PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, P.maxit, P.tol, 0, M->hist));
   PS_TRY(join(M, P));
-  Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n};
+  Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2, pair_grid(M->n), 0, s2));
   PS_TRY(fork(M, P));
   PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, M->ctl + C_HALT));  // t_{i+1} = A w_{i+1}
-  PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, i, P.maxit, P.tol, 0,
+  PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, P.maxit, P.tol, 0,
                                            M->hist));
   PS_TRY(join(M, P));
+  return PS_OK;
+}
+
+int enqueue_iteration(ps_matrix *M, const Plan &P, int i) {
+  switch (P.variant) {
+    case PS_SSBICGSAFE2: return iter_ssbicgsafe2(M, P, i);
+    case PS_PBICGSTAB: return iter_pbicgstab(M, P, i);
+    default: return iter_pbicgsafe(M, P, i);
+  }
+}
+
+// An iteration whose launches are the same as every other such iteration's
+// (all arguments fixed; the iteration index lives on the device): not the
+// first iteration of the BiCGSafe forms and not a replacement step.
+bool is_standard(const Plan &P, int i) {
+  if (P.variant == PS_PBICGSTAB) return true;
+  if (i == 0) return false;
+  if (P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && i % P.rr_m == 0 && i < P.rr_M) return false;
+  return true;
+}
+
+void clear_graphs(ps_matrix *M) {
+  for (GraphEntry &g : M->graphs) (void)hipGraphExecDestroy(g.exec);
+  M->graphs.clear();
+}
+
+// The instantiated graph of `count` standard iterations that starts in the
+// current sweep phase, captured from the launch sequence on first use.
+int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **out) {
+  const GraphKey key{P.variant, P.maxit, P.rr_m, P.rr_M, P.overlap ? 1 : 0, count, M->sweep,
+                     P.tol, P.A};
+  for (GraphEntry &g : M->graphs)
+    if (g.key == key) {
+      *out = &g;
+      return PS_OK;
+    }
+  const int phase = M->sweep;
+  hipGraph_t graph = nullptr;
+  PS_HIP(hipStreamBeginCapture(P.A, hipStreamCaptureModeThreadLocal));
+  int rc = PS_OK;
+  for (int k = 0; k < count && rc == PS_OK; ++k) rc = enqueue_iteration(M, P, probe_i);
+  const hipError_t e = hipStreamEndCapture(P.A, &graph);
+  const int flip = M->sweep ^ phase;
+  M->sweep = phase;  // nothing ran yet
+  if (rc != PS_OK || e != hipSuccess || graph == nullptr) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return PS_EHIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    (void)hipGetLastError();
+    return PS_EHIP;
+  }
+  if (M->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(M->graphs.front().exec);
+    M->graphs.erase(M->graphs.begin());
+  }
+  M->graphs.push_back(GraphEntry{key, exec, flip});
+  *out = &M->graphs.back();
   return PS_OK;
 }
 
@@ -327,6 +425,7 @@ int ensure_hist(ps_matrix *M, int64_t need) {
   if (need <= M->hist_cap) return PS_OK;
   if (M->hist) {
     PS_HIP(hipDeviceSynchronize());
+    clear_graphs(M);  // captured launches hold the old history pointer
     PS_HIP(hipFree(M->hist));
     M->hist = nullptr;
   }
@@ -385,17 +484,26 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   // orders them after the caller's pending work); host-buffer solves default to
   // the library's own stream
   P.A = (on_device || o.stream) ? (hipStream_t)o.stream : M->own;
+  bool use_graph = o.graph != 0 && o.profile == 0;
+  if (use_graph && P.A == nullptr) {
+    // the null stream cannot be captured: run on the library's stream, after
+    // the work already queued on the null stream
+    PS_HIP(hipEventRecord(M->ev_fork, nullptr));
+    PS_HIP(hipStreamWaitEvent(M->own, M->ev_fork, 0));
+    P.A = M->own;
+  }
   P.overlap = o.overlap != 0 && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
   M->prof_mask = o.profile;
   M->cur_iter = -1;
+  M->sweep = 0;
   M->timers.clear();
   M->ev_used = 0;
   PS_TRY(ensure_hist(M, (int64_t)maxit + 2));
 
   const size_t vbytes = (size_t)M->n * sizeof(double);
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  PS_TRY(launch(M, P.A, PS_K_OTHER, k_init_ctl, dim3(1), 0, M->ctl));
+  PS_TRY(launch(M, P.A, PS_K_OTHER, k_init_ctl, dim3(1), 0, M->ctl, P.i0));
   if (!P.resume) {
     PS_HIP(hipMemcpyAsync(M->slot(PS_V_B), b, vbytes, kind, P.A));
     if (x0) PS_HIP(hipMemcpyAsync(M->slot(PS_V_X), x0, vbytes, kind, P.A));
@@ -409,15 +517,25 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   bool stopped = false;
   for (int i = P.i0; i <= last && !stopped;) {
     const int end = std::min(last, i + K - 1);
-    for (; i <= end; ++i) {
-      M->cur_iter = i;
-      int rc;
-      switch (variant) {
-        case PS_SSBICGSAFE2: rc = iter_ssbicgsafe2(M, P, i); break;
-        case PS_PBICGSTAB: rc = iter_pbicgstab(M, P, i); break;
-        default: rc = iter_pbicgsafe(M, P, i); break;
+    bool launched = false;
+    if (use_graph && end - i + 1 == K) {
+      bool uniform = true;
+      for (int j = i; j <= end; ++j) uniform = uniform && is_standard(P, j);
+      GraphEntry *g = nullptr;
+      if (uniform && get_graph(M, P, K, i, &g) == PS_OK) {
+        PS_HIP(hipGraphLaunch(g->exec, P.A));
+        M->sweep ^= g->sweep_flip;
+        i = end + 1;
+        launched = true;
+      } else if (uniform) {
+        use_graph = false;  // capture not possible here: launch directly from now on
       }
-      if (rc != PS_OK) return rc;
+    }
+    if (!launched) {
+      for (; i <= end; ++i) {
+        M->cur_iter = i;
+        PS_TRY(enqueue_iteration(M, P, i));
+      }
     }
     PS_HIP(hipGetLastError());
     const int cur = batch & 1;
@@ -454,6 +572,7 @@ void free_matrix(ps_matrix *M) {
   if (!M) return;
   if (M->device >= 0) (void)hipSetDevice(M->device);
   (void)hipDeviceSynchronize();
+  clear_graphs(M);
   (void)hipFree(M->rowptr);
   (void)hipFree(M->col);
   (void)hipFree(M->val);
@@ -512,6 +631,8 @@ void ps_default_options(ps_options *opt) {
   opt->profile = 0;
   opt->resume = 0;
   opt->resume_iter = 0;
+  opt->graph = 1;
+  opt->reserved = 0;
   opt->stream = nullptr;
 }
 
@@ -539,15 +660,15 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   M->device = dev;
   M->n = n;
   M->nnz = nnz;
+  // smallest per-thread nonzero count whose block budget holds kBlock average rows
   const double mean = (double)nnz / (double)n;
-  int budget = (int)std::ceil(kBlock * mean * 1.25 / 256.0) * 256;
-  M->budget = std::max(1024, std::min(8192, budget));
-  std::vector<int> blk = row_blocks(n, rowptr, M->budget);
+  M->ipt = mean * 1.1 <= 4.0 ? 4 : (mean * 1.1 <= 8.0 ? 8 : 16);
+  std::vector<int> blk = row_blocks(n, rowptr, M->ipt * kBlock);
   M->nblk = (int)blk.size() - 1;
   std::vector<int> rp32(n + 1);
   for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
   M->ld = ((size_t)n + 31) / 32 * 32;
-  M->dot_grid = (int)std::min<int64_t>(kMaxDotGrid, (n / 2 + kBlock - 1) / kBlock + 1);
+  M->dot_grid = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxDotGrid, (n / 2 + kBlock - 1) / kBlock));
 
   auto fail = [&](int code) {
     free_matrix(M);

@@ -20,7 +20,6 @@ struct CsrDev {
   const double *val;   // double[nnz]
   const int *blk;      // int32[nblk+1] first row of each row block
   int nblk;
-  int budget;          // max nonzeros of a short-row block (LDS doubles)
 };
 
 // Row-block index for workgroup `b`: consecutive workgroups are dispatched
@@ -35,43 +34,77 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return start + k;
 }
 
+// IPT: nonzeros per thread of a short-row block (the block's LDS budget is
+// IPT * kBlock products).  Every load a thread needs -- its row bounds, the
+// epilogue's operands, and all IPT (col, val) pairs -- is issued before the
+// first dependent gather, so a block waits for about three memory latencies
+// in total instead of two per nonzero.
+//
 // `stop` (may be null) points at the control word that turns the launch into a
 // no-op: C_DONE for products that follow a finish in stream order, C_HALT for
 // products that may run concurrently with one.
-template <class Epi>
+//
+// `rev` = 1 walks the row blocks from the last to the first (see sweep_block).
+template <int IPT, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restrict__ x, Epi epi,
-                                                 const int *__restrict__ stop) {
+                                                 const int *__restrict__ stop, int rev) {
   if (stop != nullptr && *stop) return;
   extern __shared__ double prod[];
-  const int b = xcd_block(blockIdx.x, A.nblk);
+  const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
   const int r0 = A.blk[b], r1 = A.blk[b + 1];
+  const int r = r0 + threadIdx.x;
+  const bool has_row = r < r1;
+  int ra = 0, re = 0;
+  typename Epi::In ein{};
+  if (has_row) {
+    ra = A.rowptr[r];
+    re = A.rowptr[r + 1];
+    ein = epi.load(r);
+  }
   const int k0 = A.rowptr[r0], k1 = A.rowptr[r1];
   const int nz = k1 - k0;
-  if (nz <= A.budget) {
-    for (int k = threadIdx.x; k < nz; k += kBlock) prod[k] = A.val[k0 + k] * x[A.col[k0 + k]];
+  if (nz <= IPT * kBlock) {
+    int c[IPT];
+    double v[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const int k = threadIdx.x + i * kBlock;
+      if (k < nz) {
+        c[i] = A.col[k0 + k];
+        v[i] = A.val[k0 + k];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const int k = threadIdx.x + i * kBlock;
+      if (k < nz) prod[k] = v[i] * x[c[i]];
+    }
     __syncthreads();
-    const int r = r0 + threadIdx.x;
-    if (r < r1) {
-      const int a = A.rowptr[r] - k0, e = A.rowptr[r + 1] - k0;
+    if (has_row) {
+      // the row's products added in storage order
       double acc = 0.0;
-      for (int k = a; k < e; ++k) acc += prod[k];
-      epi(r, acc);
+      for (int k = ra - k0; k < re - k0; ++k) acc += prod[k];
+      epi.store(r, acc, ein);
     }
   } else {
     // one long row: strided partial sums, then a fixed-order block reduction
     double acc = 0.0;
     for (int k = k0 + threadIdx.x; k < k1; k += kBlock) acc += A.val[k] * x[A.col[k]];
     acc = block_sum_1(acc, prod);
-    if (threadIdx.x == 0) epi(r0, acc);
+    if (threadIdx.x == 0) epi.store(r0, acc, ein);
   }
 }
 
 // ------------------------------------------------------------------ epilogues
+// load(r) fetches the row's operands before the products; store(r, ax, in)
+// finishes the row once its sum A x is known.
 
 // y = A x
 struct EpiStore {
   double *y;
-  __device__ __forceinline__ void operator()(int r, double ax) const { y[r] = ax; }
+  struct In {};
+  __device__ __forceinline__ In load(int) const { return In{}; }
+  __device__ __forceinline__ void store(int r, double ax, const In &) const { y[r] = ax; }
 };
 
 // r = b - A x (and optionally r0* = r): the initial residual of every
@@ -80,8 +113,12 @@ struct EpiResidual {
   const double *b;
   double *r;
   double *rs;  // may be null
-  __device__ __forceinline__ void operator()(int row, double ax) const {
-    const double v = b[row] - ax;
+  struct In {
+    double b;
+  };
+  __device__ __forceinline__ In load(int row) const { return In{b[row]}; }
+  __device__ __forceinline__ void store(int row, double ax, const In &in) const {
+    const double v = in.b - ax;
     r[row] = v;
     if (rs) rs[row] = v;
   }
@@ -95,13 +132,16 @@ struct EpiPBiCGSafeB {
   const double *q, *As;
   double *l, *g, *s;
   const double *sc;
-  __device__ __forceinline__ void operator()(int r, double aw) const {
+  struct In {
+    double q, As, g, s;
+  };
+  __device__ __forceinline__ In load(int r) const { return In{q[r], As[r], g[r], s[r]}; }
+  __device__ __forceinline__ void store(int r, double aw, const In &in) const {
     const double al = sc[PS_S_ALPHA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
-    const double qr = q[r];
-    l[r] = qr - aw;
-    const double gn = ze * As[r] + et * g[r] - al * aw;
+    l[r] = in.q - aw;
+    const double gn = ze * in.As + et * in.g - al * aw;
     g[r] = gn;
-    s[r] = s[r] - al * qr - gn;
+    s[r] = in.s - al * in.q - gn;
   }
 };
 
@@ -113,17 +153,22 @@ struct EpiSsBiCGSafe2B {
   const double *s, *u, *p;
   double *t, *z, *y, *x, *r;
   const double *sc;
-  __device__ __forceinline__ void operator()(int row, double wv) const {
+  struct In {
+    double s, t, r, z, u, y, x, p;
+  };
+  __device__ __forceinline__ In load(int row) const {
+    return In{s[row], t[row], r[row], z[row], u[row], y[row], x[row], p[row]};
+  }
+  __device__ __forceinline__ void store(int row, double wv, const In &in) const {
     const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
-    const double sr = s[row], rr = r[row];
-    const double o = sr + be * t[row];
+    const double o = in.s + be * in.t;
     t[row] = o - wv;
-    const double zn = ze * rr + et * z[row] - al * u[row];
+    const double zn = ze * in.r + et * in.z - al * in.u;
     z[row] = zn;
-    const double yn = ze * sr + et * y[row] - al * wv;
+    const double yn = ze * in.s + et * in.y - al * wv;
     y[row] = yn;
-    x[row] = x[row] + al * p[row] + zn;
-    r[row] = rr - al * o - yn;
+    x[row] = in.x + al * in.p + zn;
+    r[row] = in.r - al * o - yn;
   }
 };
 

@@ -39,14 +39,16 @@ __device__ __forceinline__ bool halted_after_finish(int *ctl) {
   return false;
 }
 
-// Launch helper: entry index of this thread (two entries per thread).
-__device__ __forceinline__ int64_t pair_index() {
-  return 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+// Entry index of this thread (two entries per thread), blocks taken in the
+// sweep direction `rev`.
+__device__ __forceinline__ int64_t pair_index(int rev) {
+  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, rev);
+  return 2 * ((int64_t)b * kBlock + threadIdx.x);
 }
 
 #define PS_DISPATCH_PAIRS(n, body)            \
   do {                                        \
-    const int64_t k_ = pair_index();          \
+    const int64_t k_ = pair_index(P.rev);     \
     if (k_ + 1 < (n)) {                       \
       body<2>(P, k_);                         \
     } else if (k_ < (n)) {                    \
@@ -69,6 +71,7 @@ struct PassAArgs {
   const double *sc;
   int *ctl;
   int64_t n;
+  int rev;  // sweep direction
 };
 
 template <int W>
@@ -126,6 +129,7 @@ struct PouArgs {
   const double *sc;
   int *ctl;
   int64_t n;
+  int rev;  // sweep direction
 };
 
 template <int W, bool STORE_O>
@@ -177,6 +181,7 @@ struct TzyxArgs {
   const double *sc;
   int *ctl;
   int64_t n;
+  int rev;  // sweep direction
 };
 
 template <int W>
@@ -220,6 +225,7 @@ struct Stab1Args {
   const double *sc;
   int *ctl;
   int64_t n;
+  int rev;  // sweep direction
 };
 
 template <int W>
@@ -262,6 +268,7 @@ struct Stab2Args {
   const double *sc;
   int *ctl;
   int64_t n;
+  int rev;  // sweep direction
 };
 
 template <int W>
@@ -314,9 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_stream_copy(double2 *__restrict__ ds
     dst[k] = src[k];
 }
 
-__global__ void k_init_ctl(int *ctl) {
+__global__ void k_init_ctl(int *ctl, int first_iter) {
   const int k = threadIdx.x;
-  if (k < C_COUNT) ctl[k] = (k == C_STATUS) ? -1 : 0;
+  if (k < C_COUNT) ctl[k] = (k == C_STATUS) ? -1 : (k == C_ITER ? first_iter : 0);
 }
 
 }  // namespace ps

@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
     _fields_ = [("rr_m", ctypes.c_int32), ("rr_M", ctypes.c_int32), ("norm_ref", ctypes.c_int32),
                 ("batch_iters", ctypes.c_int32), ("overlap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("resume", ctypes.c_int32),
-                ("resume_iter", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("resume_iter", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 _L = None

@@ -253,17 +253,48 @@ def test_one_iteration_from_oracle_state(variant):
 # ------------------------------------------------------------- determinism
 
 def test_bitwise_reproducible_and_overlap_invariant():
-    A = W.rand_band(100_000, seed=21, band=3000)
-    for variant in VARIANTS:
-        say(f"determinism {variant}")
-        with pipesafe.Matrix.from_csr(A) as M:
-            a = M.solve(A.b, tol=1e-10, maxit=500, variant=variant)
-            b = M.solve(A.b, tol=1e-10, maxit=500, variant=variant)
-            c = M.solve(A.b, tol=1e-10, maxit=500, variant=variant, overlap=0)
-            d = M.solve(A.b, tol=1e-10, maxit=500, variant=variant, batch_iters=1)
-        for other in (b, c, d):
-            assert other.iters == a.iters and other.status == a.status
-            assert np.array_equal(other.x, a.x) and np.array_equal(other.hist, a.hist)
+    """Eager launches, a second stream, and cached graph replays (several replays per
+    solve, several solves per graph, eager solves in between) give identical bits."""
+    cases = [("rand_band_100k", W.rand_band(100_000, seed=21, band=3000)),
+             ("cd2d_64", W.workload("cd2d_64"))]
+    for name, A in cases:
+        for variant in VARIANTS:
+            say(f"determinism {name} {variant}")
+            with pipesafe.Matrix.from_csr(A) as M:
+                ref = M.solve(A.b, tol=1e-10, maxit=600, variant=variant, graph=0, overlap=0,
+                              rr_m=7)
+                runs = [
+                    M.solve(A.b, tol=1e-10, maxit=600, variant=variant, graph=0, rr_m=7),
+                    M.solve(A.b, tol=1e-10, maxit=600, variant=variant, graph=1, batch_iters=4,
+                            rr_m=7),
+                    M.solve(A.b, tol=1e-10, maxit=600, variant=variant, graph=0, batch_iters=1,
+                            rr_m=7),
+                    M.solve(A.b, tol=1e-10, maxit=600, variant=variant, graph=1, batch_iters=4,
+                            rr_m=7),
+                    M.solve(A.b, tol=1e-10, maxit=600, variant=variant, graph=1, batch_iters=5,
+                            overlap=0, rr_m=7),
+                    M.solve(A.b, tol=1e-10, maxit=600, variant=variant, rr_m=7),
+                ]
+            for k, other in enumerate(runs):
+                assert other.iters == ref.iters and other.status == ref.status, (name, variant, k)
+                assert np.array_equal(other.x, ref.x) and np.array_equal(other.hist, ref.hist), \
+                    (name, variant, k)
+
+
+def test_solve_dev_on_null_and_side_streams():
+    import torch
+    A = W.workload("cd2d_64")
+    ref = O.solve(A, tol=1e-10, maxit=2000, variant="pbicgsafe")
+    with pipesafe.Matrix.from_csr(A) as M:
+        b = torch.from_numpy(A.b).cuda()
+        r1 = M.solve_dev(b, tol=1e-10, maxit=2000, variant="pbicgsafe")
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            b2 = b * 1.0  # queued on the side stream before the solve
+            r2 = M.solve_dev(b2, tol=1e-10, maxit=2000, variant="pbicgsafe")
+        torch.cuda.synchronize()
+    for r in (r1, r2):
+        assert r.iters == ref.iters and np.array_equal(r.x.cpu().numpy(), ref.x)
 
 
 # ------------------------------------------------------------ edge cases
