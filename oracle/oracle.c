@@ -14,8 +14,9 @@
  *   - an inner product is a sequential sum in index order, carried with
  *     compensated summation (see dot() below) so that its value does not
  *     depend on the summation order;
- *   - a sparse product y = A x is, per row, a sequential sum over the row's
- *     entries in storage order;
+ *   - a sparse product y = A x is, per row, a sequential sum of the rounded
+ *     products over the row's entries in storage order, carried with the
+ *     same compensated summation (see spmv() below);
  *   - compiled with -ffp-contract=off, so no fused multiply-adds.
  *
  * Variants:
@@ -78,12 +79,28 @@ typedef struct {
 
 /* ---------------------------------------------------------------- kernels */
 
-/* y = A x (the "matrix-vector product" of every listing) */
+/*
+ * (s, c) += v: Knuth's two-sum splits s + v exactly into the rounded sum and its
+ * error; the error is added to c.  s + c then carries a running sum to about
+ * twice the working precision.
+ */
+static void two_sum_acc(double *s, double *c, double v) {
+  const double t = *s + v;
+  const double z = t - *s;
+  const double e = (*s - (t - z)) + (v - z);
+  *s = t;
+  *c = *c + e;
+}
+
+/* y = A x (the "matrix-vector product" of every listing): for each row, the
+   rounded products a_ij x_j in storage order, summed with two_sum_acc and
+   rounded once, so that the row's value does not depend on the order in which
+   its products are added */
 static void spmv(const csr_t *A, const double *x, double *y, double *S) {
   for (int64_t i = 0; i < A->n; ++i) {
-    double acc = 0.0;
-    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) acc += A->val[k] * x[A->col[k]];
-    y[i] = acc;
+    double s = 0.0, c = 0.0;
+    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) two_sum_acc(&s, &c, A->val[k] * x[A->col[k]]);
+    y[i] = s + c;
   }
   S[S_NSPMV] += 1.0;
 }

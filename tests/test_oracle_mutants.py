@@ -15,10 +15,9 @@ import oracle as O
 
 import test_oracle_pins as pins
 
-SPMV_BODY = ("    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) acc += A->val[k] * x[A->col[k]];\n"
-             "    y[i] = acc;\n")
-SPMV_TRANSPOSED = ("    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) acc += A->val[k] * x[A->col[k]];\n"
-                   "    y[i] = acc;\n  }\n  { double *yt = (double *)calloc((size_t)A->n, sizeof(double));\n"
+SPMV_BODY = ("    for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) two_sum_acc(&s, &c, A->val[k] * x[A->col[k]]);\n"
+             "    y[i] = s + c;\n")
+SPMV_TRANSPOSED = (SPMV_BODY + "  }\n  { double *yt = (double *)calloc((size_t)A->n, sizeof(double));\n"
                    "    for (int64_t i2 = 0; i2 < A->n; ++i2)\n"
                    "      for (int64_t k = A->rowptr[i2]; k < A->rowptr[i2 + 1]; ++k) yt[A->col[k]] += A->val[k] * x[i2];\n"
                    "    memcpy(y, yt, sizeof(double) * (size_t)A->n); free(yt);\n")
@@ -45,6 +44,8 @@ MUTANTS = {
     "e_uses_s": ("e = dot(n, y, r, S)", "e = dot(n, y, s, S)"),
     "no_initial_s": ("spmv(&A, r, v[VS], S);                       /* R2", "(void)0;                       /* R2"),
     "spmv_transposed": (SPMV_BODY, SPMV_TRANSPOSED),
+    "spmv_drops_compensation": ("    y[i] = s + c;", "    y[i] = s;"),
+    "dot_drops_compensation": ("    c = c + (ep + es);", "    c = c + 0.0 * (ep + es);"),
     "rr_l_from_y": ("spmv(A, t, l, S);", "spmv(A, y, l, S);"),
     "rr_residual_sign": ("r[k] = b[k] - tmp[k]", "r[k] = b[k] + tmp[k]"),
     "pbicgstab_w_sign": ("om * (t[k] - al * vv[k])", "om * (t[k] + al * vv[k])"),

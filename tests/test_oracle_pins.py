@@ -18,6 +18,9 @@ mathematics, not against the oracle itself.
       (Eq. (eta&zeta_ssBiCGSafe2)); omega_i minimises ||q - omega A q||.
   P12 alpha_i, beta_i equal the BiCG coefficients (Section 2: the product
       methods reuse BiCG's alpha and beta), against a textbook BiCG that uses A^T.
+  P13 inner products and sparse-product rows are the correctly rounded sums on
+      inputs with massive cancellation (closed form: e.g. 1e16 + 1 - 1e16 = 1),
+      which plain recursive summation gets wrong.
 """
 import json
 import os
@@ -270,8 +273,32 @@ def check_p8(orc, variants=ALL):
     return None
 
 
+def check_p13(orc):
+    import fractions
+    # a row with cancelling products: exact value 1 + 2^-30, plain summation gives 2^-30 or 0
+    vals = [1e16, 1.0, -1e16, 2.0 ** -30]
+    A = W.CSR(1, np.array([0, 4], dtype=np.int64), np.zeros(4, dtype=np.int32), np.array(vals),
+              np.array([0.0]))
+    y = orc.spmv(A, np.array([1.0]))
+    exact = float(sum(fractions.Fraction(v) for v in vals))
+    if y[0] != exact:
+        return f"P13 spmv row sum {y[0]!r} != {exact!r}"
+    # an inner product with cancellation: d = (s, r) with s = D r, D = diag(1, 1, -1, 1),
+    # r = b; zeta_0 = d / a (Algorithm 4, i = 0) must use the correctly rounded d and a
+    r = np.array([1.0 + 2.0 ** -30, 1e8, 1e8, 1.0])
+    D = np.array([1.0, 1.0, -1.0, 1.0])
+    B = W.CSR(4, np.arange(5, dtype=np.int64), np.arange(4, dtype=np.int32), D, r)
+    R = orc.solve(B, tol=0.0, maxit=1, variant="pbicgsafe")
+    F = fractions.Fraction
+    d = float(sum(F(x) * F(dd) * F(x) for x, dd in zip(r, D)))
+    a = float(sum((F(dd) * F(x)) ** 2 for x, dd in zip(r, D)))
+    if R.coef[0, 2] != d / a:
+        return f"P13 zeta_0 {R.coef[0, 2]!r} != {d / a!r} (inner products not correctly rounded)"
+    return None
+
+
 CHECKS = [check_p1, check_p2, check_p3, check_p4, check_p5, check_p6, check_p7, check_p8, check_p11,
-          check_p12]
+          check_p12, check_p13]
 
 
 # --------------------------------------------------------------------------- tests
