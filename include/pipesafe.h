@@ -77,9 +77,11 @@ typedef struct {
   int32_t batch_iters; /* iterations enqueued between host checks of the device stop
                           flag; 0 = automatic.  Iterations enqueued after the stop are
                           no-ops, so the result does not depend on this value.           */
-  int32_t overlap;     /* 1 (default): the reduction phase runs on a second stream
-                          concurrently with the sparse product it is independent of;
-                          0: everything on one stream (results are bit-identical).      */
+  int32_t overlap;     /* 1: the reduction phase runs on a second stream concurrently
+                          with the sparse product it is independent of; 0: everything
+                          on one stream; -1 (default): on for n >= 2^18 (below that the
+                          products are too short to hide the cross-stream waits).
+                          Results are bit-identical in every case.                     */
   int32_t profile;     /* bit mask of ps_kernel classes to time with HIP events on the
                           stream each kernel runs on; 0 (default) = none.               */
   int32_t resume;      /* 0 (default): initialise from b and x0.  1: skip initialisation

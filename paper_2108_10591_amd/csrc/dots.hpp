@@ -44,31 +44,6 @@ enum DotFlags : int {
 
 // ---------------------------------------------------------------- products
 
-// pair accumulator: hi + lo carries a sum to about twice double precision
-struct DD {
-  double hi, lo;
-};
-
-// (hi, lo) += x*y
-__device__ __forceinline__ void dd_fma(DD &a, double x, double y) {
-  const double p = x * y;
-  const double ep = __builtin_fma(x, y, -p);  // x*y = p + ep exactly
-  const double t = a.hi + p;
-  const double z = t - a.hi;
-  const double es = (a.hi - (t - z)) + (p - z);  // a.hi + p = t + es exactly
-  a.hi = t;
-  a.lo = a.lo + (ep + es);
-}
-
-// a += b for two pairs
-__device__ __forceinline__ void dd_add(DD &a, double bhi, double blo) {
-  const double t = a.hi + bhi;
-  const double z = t - a.hi;
-  const double es = (a.hi - (t - z)) + (bhi - z);
-  a.hi = t;
-  a.lo = a.lo + (blo + es);
-}
-
 // the nine inner products of Algorithms 3-5 over (s, y, r, r0*, t_{i-1}):
 // a=(s,s) b=(y,y) c=(s,y) d=(s,r) e=(y,r) f=(r0*,r) g=(r0*,s) h=(r0*,t) rho=(r,r).
 // FIRST: i = 0, where only a, d, f, g, rho are formed (y_0 = t_{-1} = 0).
@@ -315,69 +290,6 @@ struct FinNormRef {
 };
 
 // ---------------------------------------------------------------- the kernel
-
-// Lane permutations of a double within rows of 16 lanes (DPP), and a lane read.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)u, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ void dd_step(DD &a) {
-  const double h = dpp_f64<CTRL>(a.hi);
-  const double l = dpp_f64<CTRL>(a.lo);
-  dd_add(a, h, l);
-}
-
-// Pair sum over a wavefront, the same value in every lane.  Within each row of
-// 16 lanes: partner at lane^1 and lane^2 (quad permutes), then the other quad
-// of the half-row and the other half of the row (mirrors); then the four row
-// totals (lanes 0, 16, 32, 48) in row order.
-__device__ __forceinline__ DD wave_sum_dd(DD a) {
-  dd_step<0xB1>(a);   // quad_perm [1,0,3,2]
-  dd_step<0x4E>(a);   // quad_perm [2,3,0,1]
-  dd_step<0x141>(a);  // row_half_mirror
-  dd_step<0x140>(a);  // row_mirror
-  DD t{readlane_f64(a.hi, 0), readlane_f64(a.lo, 0)};
-#pragma unroll
-  for (int r = 1; r < 4; ++r) dd_add(t, readlane_f64(a.hi, 16 * r), readlane_f64(a.lo, 16 * r));
-  return t;
-}
-
-// Block-wide pair sums: on return thread k (< K) holds the block total of a[k].
-template <int K>
-__device__ __forceinline__ DD block_sum_dd(DD (&a)[K], double *lds) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int k = 0; k < K; ++k) a[k] = wave_sum_dd(a[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      lds[(wid * K + k) * 2] = a[k].hi;
-      lds[(wid * K + k) * 2 + 1] = a[k].lo;
-    }
-  }
-  __syncthreads();
-  DD r{0.0, 0.0};
-  if (threadIdx.x < K) {
-    r.hi = lds[threadIdx.x * 2];
-    r.lo = lds[threadIdx.x * 2 + 1];
-    for (int w = 1; w < kWavesPerBlock; ++w)
-      dd_add(r, lds[(w * K + threadIdx.x) * 2], lds[(w * K + threadIdx.x) * 2 + 1]);
-  }
-  __syncthreads();
-  return r;
-}
 
 template <class Prod>
 __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {

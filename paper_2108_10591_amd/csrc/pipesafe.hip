@@ -24,6 +24,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -39,7 +40,8 @@ namespace {
 
 constexpr int kSlotTmp = PS_V_COUNT;  // internal scratch vector
 constexpr int kNumSlots = PS_V_COUNT + 1;
-constexpr int kMaxDotGrid = 512;  // partial-sum blocks: about two per CU
+constexpr int kMaxDotGrid = 256;  // partial-sum blocks: one per CU
+constexpr int64_t kOverlapMinRows = 1 << 18;  // automatic second stream from this size on
 
 struct Timer {
   hipEvent_t a, b;
@@ -73,7 +75,7 @@ struct ps_matrix {
   int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
   double *val = nullptr;
   int nblk = 0;
-  int ipt = 8;              // nonzeros per thread of a short-row block (4, 8 or 16)
+  int shape = 1;            // SpMV shape: 0..4 = (IPT, LPR) (4,1) (8,1) (16,4) (16,8) (16,16)
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -170,17 +172,22 @@ int next_rev(ps_matrix *M) {
   return r;
 }
 
+template <int IPT, int LPR, class Epi>
+int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop,
+                int rev) {
+  const size_t lds = (size_t)IPT * kBlock * sizeof(double);
+  return launch(M, s, cls, k_spmv<IPT, LPR, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
+}
+
 template <class Epi>
 int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop) {
-  const size_t lds = (size_t)M->ipt * kBlock * sizeof(double);
   const int rev = next_rev(M);
-  switch (M->ipt) {
-    case 4:
-      return launch(M, s, cls, k_spmv<4, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
-    case 8:
-      return launch(M, s, cls, k_spmv<8, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
-    default:
-      return launch(M, s, cls, k_spmv<16, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
+  switch (M->shape) {
+    case 0: return spmv_launch<4, 1>(M, s, cls, x, epi, stop, rev);
+    case 1: return spmv_launch<8, 1>(M, s, cls, x, epi, stop, rev);
+    case 2: return spmv_launch<16, 4>(M, s, cls, x, epi, stop, rev);
+    case 3: return spmv_launch<16, 8>(M, s, cls, x, epi, stop, rev);
+    default: return spmv_launch<16, 16>(M, s, cls, x, epi, stop, rev);
   }
 }
 
@@ -492,7 +499,9 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
     PS_HIP(hipStreamWaitEvent(M->own, M->ev_fork, 0));
     P.A = M->own;
   }
-  P.overlap = o.overlap != 0 && variant != PS_SSBICGSAFE2;
+  // a second stream pays only when the product it hides behind is long
+  const bool want_overlap = o.overlap > 0 || (o.overlap < 0 && M->n >= kOverlapMinRows);
+  P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
   M->prof_mask = o.profile;
   M->cur_iter = -1;
@@ -627,7 +636,7 @@ void ps_default_options(ps_options *opt) {
   opt->rr_M = 0;
   opt->norm_ref = 0;
   opt->batch_iters = 0;
-  opt->overlap = 1;
+  opt->overlap = -1;
   opt->profile = 0;
   opt->resume = 0;
   opt->resume_iter = 0;
@@ -660,10 +669,17 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   M->device = dev;
   M->n = n;
   M->nnz = nnz;
-  // smallest per-thread nonzero count whose block budget holds kBlock average rows
+  // SpMV shape from the mean row length: short rows one lane each with the
+  // smallest per-thread budget that holds kBlock average rows; longer rows get
+  // 4, 8 or 16 lanes each
   const double mean = (double)nnz / (double)n;
-  M->ipt = mean * 1.1 <= 4.0 ? 4 : (mean * 1.1 <= 8.0 ? 8 : 16);
-  std::vector<int> blk = row_blocks(n, rowptr, M->ipt * kBlock);
+  M->shape = mean * 1.1 <= 4.0 ? 0 : (mean * 1.1 <= 8.0 ? 1 : (mean <= 16.0 ? 2 : (mean <= 64.0 ? 3 : 4)));
+  if (const char *e = std::getenv("PIPESAFE_SPMV_SHAPE")) {  // tuning override
+    const int v = std::atoi(e);
+    if (v >= 0 && v <= 4) M->shape = v;
+  }
+  static const int kIpt[] = {4, 8, 16, 16, 16};
+  std::vector<int> blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock);
   M->nblk = (int)blk.size() - 1;
   std::vector<int> rp32(n + 1);
   for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];

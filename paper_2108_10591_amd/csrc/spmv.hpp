@@ -2,12 +2,11 @@
 //
 // Rows are cut at creation time into row blocks of at most kBlock rows whose
 // nonzeros fit an LDS budget.  A block streams its contiguous slice of
-// (val, col) with coalesced loads, forms val*x[col] into LDS, and then one
-// thread per row adds its row's products in storage order and hands the row
-// sum to the epilogue, which updates the row's entries of other vectors (the
-// update passes that the paper's algorithms place right after each product).
-// A row longer than the budget gets a block of its own, which splits it over
-// all threads and combines the pieces with a fixed-order block reduction.
+// (val, col) with coalesced loads, forms val*x[col] into LDS, and then sums
+// each row (see LPR below) and hands the row sum to the epilogue, which
+// updates the row's entries of other vectors (the update passes that the
+// paper's algorithms place right after each product).  A row longer than the
+// budget gets a block of its own, which splits it over all threads.
 #pragma once
 
 #include "device_common.hpp"
@@ -35,17 +34,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // IPT: nonzeros per thread of a short-row block (the block's LDS budget is
-// IPT * kBlock products).  Every load a thread needs -- its row bounds, the
-// epilogue's operands, and all IPT (col, val) pairs -- is issued before the
-// first dependent gather, so a block waits for about three memory latencies
-// in total instead of two per nonzero.
+// IPT * kBlock products).  Every load a thread needs for the products -- and,
+// with one lane per row, its row bounds and the epilogue's operands -- is
+// issued before the first dependent gather, so a block waits for about three
+// memory latencies in total instead of two per nonzero.
+//
+// LPR: lanes per row when the rows are summed.  Each row's rounded products
+// are added with two-sum accumulators (hi, lo) and rounded once, so the value
+// does not depend on the order of the additions: with LPR = 1 a lane adds its
+// row in storage order; with LPR > 1 the group's lanes take every LPR-th
+// product and their pairs are combined across the group, which keeps lanes
+// busy on long, uneven rows.
 //
 // `stop` (may be null) points at the control word that turns the launch into a
 // no-op: C_DONE for products that follow a finish in stream order, C_HALT for
-// products that may run concurrently with one.
-//
-// `rev` = 1 walks the row blocks from the last to the first (see sweep_block).
-template <int IPT, class Epi>
+// products that may run concurrently with one.  `rev` = 1 walks the row blocks
+// from the last to the first (see sweep_block).
+template <int IPT, int LPR, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restrict__ x, Epi epi,
                                                  const int *__restrict__ stop, int rev) {
   if (stop != nullptr && *stop) return;
@@ -53,45 +58,58 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
   const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
   const int r0 = A.blk[b], r1 = A.blk[b + 1];
   const int r = r0 + threadIdx.x;
-  const bool has_row = r < r1;
   int ra = 0, re = 0;
   typename Epi::In ein{};
-  if (has_row) {
+  if (LPR == 1 && r < r1) {
     ra = A.rowptr[r];
     re = A.rowptr[r + 1];
     ein = epi.load(r);
   }
   const int k0 = A.rowptr[r0], k1 = A.rowptr[r1];
   const int nz = k1 - k0;
-  if (nz <= IPT * kBlock) {
-    int c[IPT];
-    double v[IPT];
+  if (nz > IPT * kBlock) {
+    // one long row: strided pair sums, then a fixed-order block combination
+    DD acc[1] = {DD{0.0, 0.0}};
+    for (int k = k0 + threadIdx.x; k < k1; k += kBlock) sum_acc(acc[0], A.val[k] * x[A.col[k]]);
+    const DD t = block_sum_dd<1>(acc, prod);
+    if (threadIdx.x == 0) epi.store(r0, t.hi + t.lo, epi.load(r0));
+    return;
+  }
+  int c[IPT];
+  double v[IPT];
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const int k = threadIdx.x + i * kBlock;
-      if (k < nz) {
-        c[i] = A.col[k0 + k];
-        v[i] = A.val[k0 + k];
-      }
+  for (int i = 0; i < IPT; ++i) {
+    const int k = threadIdx.x + i * kBlock;
+    if (k < nz) {
+      c[i] = A.col[k0 + k];
+      v[i] = A.val[k0 + k];
     }
+  }
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const int k = threadIdx.x + i * kBlock;
-      if (k < nz) prod[k] = v[i] * x[c[i]];
-    }
-    __syncthreads();
-    if (has_row) {
-      // the row's products added in storage order
-      double acc = 0.0;
-      for (int k = ra - k0; k < re - k0; ++k) acc += prod[k];
-      epi.store(r, acc, ein);
+  for (int i = 0; i < IPT; ++i) {
+    const int k = threadIdx.x + i * kBlock;
+    if (k < nz) prod[k] = v[i] * x[c[i]];
+  }
+  __syncthreads();
+  if constexpr (LPR == 1) {
+    if (r < r1) {
+      DD acc{0.0, 0.0};
+      for (int k = ra - k0; k < re - k0; ++k) sum_acc(acc, prod[k]);
+      epi.store(r, acc.hi + acc.lo, ein);
     }
   } else {
-    // one long row: strided partial sums, then a fixed-order block reduction
-    double acc = 0.0;
-    for (int k = k0 + threadIdx.x; k < k1; k += kBlock) acc += A.val[k] * x[A.col[k]];
-    acc = block_sum_1(acc, prod);
-    if (threadIdx.x == 0) epi.store(r0, acc, ein);
+    constexpr int kGroups = kBlock / LPR;
+    const int g = threadIdx.x / LPR, j = threadIdx.x % LPR;
+    for (int base = 0; base < r1 - r0; base += kGroups) {  // same trip count in every lane
+      const int rr = r0 + base + g;
+      DD acc{0.0, 0.0};
+      if (rr < r1) {
+        const int a = A.rowptr[rr] - k0, e = A.rowptr[rr + 1] - k0;
+        for (int k = a + j; k < e; k += LPR) sum_acc(acc, prod[k]);
+      }
+      group_sum_dd<LPR>(acc);
+      if (j == 0 && rr < r1) epi.store(rr, acc.hi + acc.lo, epi.load(rr));
+    }
   }
 }
 

@@ -1,0 +1,92 @@
+"""GPU parity at the benchmark's full sizes (128^3 convection-diffusion, 1M-row
+uneven band), in the launch configuration bench.py times (device buffers on the
+caller's stream, second stream, cached graphs).
+
+The oracle's full solves take minutes on one core, so their results were
+written once by tests/golden/make_full_size.py (which calls only the oracle)
+into tests/golden/full_size_oracle.json; here the GPU must reproduce them:
+same status and iteration count, the same residual history, and the same
+solution bytes (SHA-256).  Cheaper checks run the oracle live: the sparse
+product on the full matrices, and one iteration from the oracle's state.
+"""
+import hashlib
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2108_10591_amd import pipesafe, workloads as W
+
+import bounds
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "full_size_oracle.json")
+VARIANTS = ["pbicgsafe", "ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"]
+NAMES = ["cd3d_128", "rand_band_1m"]
+
+
+@pytest.fixture(scope="module")
+def golden():
+    return json.load(open(GOLDEN))["runs"]
+
+
+@pytest.fixture(scope="module", params=NAMES)
+def case(request):
+    import torch
+    assert torch.cuda.is_available()
+    A = W.workload(request.param)
+    M = pipesafe.Matrix.from_csr(A)
+    b = torch.from_numpy(A.b).cuda()
+    yield request.param, A, M, b
+    M.close()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_full_solve_reproduces_oracle(case, golden, variant):
+    name, A, M, b = case
+    g = golden[f"{name}/{variant}"]
+    print(f"full size {name} {variant}", flush=True)
+    res = M.solve_dev(b, tol=g["tol"], maxit=10_000, variant=variant, rr_m=100)
+    x = res.x.cpu().numpy()
+    # the spec bar ...
+    assert res.status == g["status"]
+    assert abs(res.iters - g["iters"]) <= max(1, math.ceil(0.02 * g["iters"]))
+    for k, v in g["x_samples"].items():
+        assert abs(x[int(k)] - v) <= 1e-8 * max(abs(v), 1.0)
+    # ... and the exact reproduction
+    assert res.iters == g["iters"]
+    assert np.array_equal(res.hist, np.array(g["hist"]))
+    assert hashlib.sha256(np.ascontiguousarray(x).tobytes()).hexdigest() == g["x_sha256"]
+
+
+def test_spmv_full_size_bit_exact(case):
+    import torch
+    name, A, M, b = case
+    x = np.random.default_rng(3).standard_normal(A.n)
+    y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.array_equal(y, O.spmv(A, x)), name
+
+
+@pytest.mark.parametrize("k", [0, 4])
+def test_one_iteration_full_size(case, k):
+    """p-BiCGSafe iteration k on the GPU from the oracle's state, against the oracle."""
+    name, A, M, b = case
+    variant = "pbicgsafe"
+    st, _ = O.state_at(A, k, variant=variant)
+    st1, _ = O.state_at(A, k + 1, variant=variant)
+    for v in ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o"]:
+        M.set_state(v, st.vec(v))
+    M.set_state("b", A.b)
+    M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "f", "rhoref"]})
+    res = M.solve(A.b, tol=0.0, maxit=k + 1, variant=variant, resume=1, resume_iter=k)
+    assert res.status == O.MAXIT and res.iters == k + 1
+    B = bounds.Bounds(A, st, st1)
+    coef, E = bounds.safe_family(B, variant, k, False)
+    for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q"]:
+        got, ref = M.get_state(v), st1.vec(v)
+        assert np.all(np.abs(got - ref) <= 4.0 * E[v]), (name, k, v)
+        assert np.array_equal(got, ref), (name, k, v)  # compensated inner products: exact
