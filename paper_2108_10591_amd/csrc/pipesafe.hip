@@ -40,7 +40,7 @@ namespace {
 
 constexpr int kSlotTmp = PS_V_COUNT;  // internal scratch vector
 constexpr int kNumSlots = PS_V_COUNT + 1;
-constexpr int kMaxDotGrid = 256;  // partial-sum blocks: one per CU
+constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 constexpr int64_t kOverlapMinRows = 1 << 18;  // automatic second stream from this size on
 
 struct Timer {
@@ -684,7 +684,12 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   std::vector<int> rp32(n + 1);
   for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
   M->ld = ((size_t)n + 31) / 32 * 32;
-  M->dot_grid = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxDotGrid, (n / 2 + kBlock - 1) / kBlock));
+  int max_dot_grid = kMaxDotGrid;
+  if (const char *e = std::getenv("PIPESAFE_DOT_GRID")) {  // tuning override
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 8192) max_dot_grid = v;
+  }
+  M->dot_grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_dot_grid, (n / 2 + kBlock - 1) / kBlock));
 
   auto fail = [&](int code) {
     free_matrix(M);
