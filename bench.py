@@ -46,7 +46,7 @@ def matrix_bytes(n, nnz):
     return 12 * nnz + 4 * (n + 1)
 
 
-def bytes_per_iteration(variant, n, nnz):
+def bytes_per_iteration(variant, n, nnz, schedule=0):
     """Algorithmic HBM bytes of one iteration of the implemented schedule (FP64 vectors,
     each vector entry read or written once per kernel that needs it, x-gather once).
 
@@ -55,14 +55,20 @@ def bytes_per_iteration(variant, n, nnz):
     p-BiCGStab:  pass 1 (96n) + A z (M+16n) + 2 dots (16n) + pass 2 (72n) + A w (M+16n)
                  + 5 dots (40n)
     (p-BiCGSafe-rr is counted as p-BiCGSafe; its replacement steps add ~1% at m = 100.)
+    p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (176n) + A w with l, g, s
+                 and y, r, r0* (M+88n)
     """
     M = matrix_bytes(n, nnz)
+    if variant == "pbicgsafe" and schedule == 1:
+        return 2 * M + 280 * n
     return {"pbicgsafe": 2 * M + 288 * n, "pbicgsafe_rr": 2 * M + 288 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
 
 
-def bytes_per_launch(cls, n, nnz):
+def bytes_per_launch(cls, n, nnz, schedule=0):
     M = matrix_bytes(n, nnz)
+    if schedule == 1:
+        return {"spmv": M + 16 * n, "update": 176 * n, "spmv_fused": M + 88 * n}[cls]
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 168 * n, "spmv_fused": M + 64 * n}[cls]
 
 
@@ -108,6 +114,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
+    ap.add_argument("--schedule", type=int, default=0,
+                    help="p-BiCGSafe: 0 separate inner-product pass, 1 fused inner products")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the library's streaming copy on MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -155,15 +163,16 @@ def main():
     variant = args.variant
 
     # one profiled solve to find the dominant kernel class
+    sched = args.schedule if variant == "pbicgsafe" else 0
     res = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, overlap=args.overlap,
-                      profile=CLASSES[:4], hist=False)
+                      schedule=sched, profile=CLASSES[:4], hist=False)
     stats = M.kernel_stats()
-    dominant = max(CLASSES[:4], key=lambda c: stats[c][0])
+    dominant = max([c for c in CLASSES[:4] if sched == 0 or c != "dots"], key=lambda c: stats[c][0])
     log(f"profiled solve: iters={res.iters} status={res.status_name}; per-class ms: "
         + ", ".join(f"{c}={stats[c][0]:.2f}/{stats[c][1]}" for c in CLASSES[:4])
         + f"; dominant: {dominant}")
 
-    opts = dict(overlap=args.overlap)
+    opts = dict(overlap=args.overlap, schedule=sched)
     for _ in range(args.warmup):
         M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, hist=False, **opts)
     # the timed steps: full solves as a caller runs them (no instrumentation)
@@ -179,7 +188,7 @@ def main():
     it = iters[-1]
     assert all(i == it for i in iters), iters
     ms_per_step = 1e3 * elapsed / args.steps
-    bpi = bytes_per_iteration(variant, A.n, A.nnz)
+    bpi = bytes_per_iteration(variant, A.n, A.nnz, sched)
     value = bpi * it / (ms_per_step * 1e-3) / 1e9
     xh = x.cpu().numpy()
     err1 = float(np.abs(xh - 1.0).max())
@@ -200,9 +209,9 @@ def main():
     torch.cuda.synchronize()
     ms_profiled = 1e3 * (time.perf_counter() - t1) / args.steps
     avg_us = 1e3 * kms / max(kcnt, 1)
-    bpl = bytes_per_launch(dominant, A.n, A.nnz)
+    bpl = bytes_per_launch(dominant, A.n, A.nnz, sched)
     achieved = bpl / (avg_us * 1e-6) / 1e9
-    traffic = load_traffic(dominant)
+    traffic = load_traffic(dominant) if sched == 0 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dominant], "bytes_per_launch": bpl,
@@ -215,7 +224,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": args.workload, "n": A.n, "nnz": A.nnz, "variant": variant,
                       "tol": tol, "x0": "zero", "rhs": "A*ones", "iterations": it,
-                      "bytes_per_iteration": bpi, "overlap": args.overlap, "graphs": True},
+                      "bytes_per_iteration": bpi, "overlap": args.overlap, "schedule": sched,
+                      "graphs": True},
            "time_to_tol_ms": round(ms_per_step, 3), "iters_per_s": round(it / (ms_per_step * 1e-3), 1),
            "us_per_iter": round(1e3 * ms_per_step / it, 2),
            "iteration_hbm_frac": round(value / PEAK_GBPS, 4), "x_minus_1_inf": err1,
@@ -223,16 +233,20 @@ def main():
 
     if not args.no_variants:
         var = {}
-        for v in ["ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"]:
-            M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v)
+        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", 0), ("pbicgstab", 0),
+                  ("pbicgsafe", 1 - sched)]
+        for v, sc in others:
+            key = v if v != "pbicgsafe" else ("pbicgsafe_fused_dots" if sc else "pbicgsafe_dot_pass")
+            M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             reps = 3
             for _ in range(reps):
-                rv = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, hist=False)
+                rv = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc, hist=False)
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t1) / reps
-            gbps = bytes_per_iteration(v, A.n, A.nnz) * rv.iters / (ms * 1e-3) / 1e9
+            gbps = bytes_per_iteration(v, A.n, A.nnz, sc) * rv.iters / (ms * 1e-3) / 1e9
+            v = key
             var[v] = {"iterations": rv.iters, "status": rv.status_name, "time_to_tol_ms": round(ms, 3),
                       "us_per_iter": round(1e3 * ms / max(rv.iters, 1), 2), "GBps": round(gbps, 1)}
             log(f"{v}: {var[v]}")

@@ -91,7 +91,16 @@ typedef struct {
   int32_t graph;       /* 1 (default): replay batches of identical iterations as cached
                           HIP graphs; 0: launch every kernel directly.  Results are
                           bit-identical either way.  Ignored while profiling.          */
-  int32_t reserved;    /* set to 0 */
+  int32_t schedule;    /* p-BiCGSafe only.  0 (default): the reduction phase of Algorithm 4
+                          as its own multi-inner-product pass, concurrent with A s_i.
+                          1: fused inner products -- pass A and the epilogue of A w_i of
+                          iteration i also form the per-block partial sums of the nine
+                          inner products of iteration i+1 (Section 4: (y,y), (y,r),
+                          (r0*,r), (r0*,t), (r,r) from pass A; (s,s), (s,y), (s,r),
+                          (r0*,s) from the epilogue), so that only their final sums and
+                          the coefficients remain, concurrent with A s_{i+1}.  Reads
+                          32n bytes more and skips the 40n-byte pass.  Results are
+                          bit-identical to schedule 0.  Other variants: must be 0.      */
   void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
                           caller's current stream).  NULL: ps_solve_dev uses the null
                           stream, ps_solve the library's own stream.                   */

@@ -346,4 +346,38 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
   }
 }
 
+// Fused-dot schedule: the nine inner products of iteration i arrive as block
+// partial sums from the two passes of iteration i-1 -- pass A: [5][ga] pairs of
+// (b, e, f, h, rho), the epilogue of A w_{i-1}: [4][gb] pairs of (a, c, d, g).
+// This kernel folds them into [9][gridDim.x] pairs in the layout k_dots
+// writes (thread t of block k takes entry k*kBlock + t of every list), so the
+// same one-block finish follows.
+__global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restrict__ pa, int ga,
+                                                          const double *__restrict__ pb, int gb,
+                                                          double *__restrict__ out,
+                                                          const int *__restrict__ ctl) {
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  if (ctl[C_DONE]) return;
+  constexpr int kA[5] = {1, 4, 5, 7, 8};
+  constexpr int kB[4] = {0, 2, 3, 6};
+  DD t[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) t[j] = DD{0.0, 0.0};
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx < ga) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) t[kA[j]] = DD{pa[(j * ga + idx) * 2], pa[(j * ga + idx) * 2 + 1]};
+  }
+  if (idx < gb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[kB[j]] = DD{pb[(j * gb + idx) * 2], pb[(j * gb + idx) * 2 + 1]};
+  }
+  const DD s = block_sum_dd<9>(t, lds);
+  const int G = gridDim.x;
+  if (threadIdx.x < 9) {
+    out[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
+    out[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
+  }
+}
+
 }  // namespace ps

@@ -10,6 +10,10 @@
 //                                                  one-GPU form of hiding the
 //                                                  global reduction, Section 3)
 //     stream A:  join; pass A (ten updates); A w_i + pass B (l, g, s) epilogue
+//   p-BiCGSafe, fused-dot schedule (option): pass A and the epilogue of A w_i
+//     also write block partial sums of the next iteration's nine inner
+//     products, so stream B only folds them and runs the finish, concurrently
+//     with A s_{i+1}; the separate inner-product pass disappears.
 //   ssBiCGSafe2 (Algorithm 3): s_i = A r_i; 9 inner products + finish;
 //     p, u; w_i = A u_i + epilogue (t, z, y, x, r).  One stream: the inner
 //     products need s_i.
@@ -51,13 +55,13 @@ struct Timer {
 
 // Everything a captured batch of iterations depends on.
 struct GraphKey {
-  int variant, maxit, rr_m, rr_M, overlap, count, phase;
+  int variant, maxit, rr_m, rr_M, overlap, count, phase, schedule;
   double tol;
   hipStream_t stream;
   bool operator==(const GraphKey &o) const {
     return variant == o.variant && maxit == o.maxit && rr_m == o.rr_m && rr_M == o.rr_M &&
-           overlap == o.overlap && count == o.count && phase == o.phase && tol == o.tol &&
-           stream == o.stream;
+           overlap == o.overlap && count == o.count && phase == o.phase &&
+           schedule == o.schedule && tol == o.tol && stream == o.stream;
   }
 };
 
@@ -82,6 +86,10 @@ struct ps_matrix {
   int *ctl = nullptr;       // C_COUNT ints
   double *partials = nullptr;
   int dot_grid = 0;
+  // fused-dot schedule: pass A partials [5][ga], epilogue partials [4][nblk],
+  // folded partials [9][gfold], all (hi, lo) pairs, in one allocation
+  double *fpart = nullptr;
+  int ga = 0, gfold = 0;
   double *hist = nullptr;
   int64_t hist_cap = 0;
   int *pinned = nullptr;    // 2 * C_COUNT ints of pinned host memory
@@ -228,6 +236,7 @@ struct Plan {
   int i0;
   hipStream_t A, B;
   bool overlap;
+  bool fused;  // fused-dot schedule (p-BiCGSafe)
 };
 
 // r_0 = b - A x_0, r0* = r_0 and the zero vectors of each algorithm (x_0 and b
@@ -287,6 +296,24 @@ int iter_safe_dots(ps_matrix *M, const Plan &P, hipStream_t s, int i) {
   return dots<ProdSafe9<false>, FinSafe>(M, s, {S, Y, R, RS, T}, P.maxit, P.tol, flags, M->hist);
 }
 
+// Fused-dot schedule: the reduction phase of iteration i from the partial sums
+// that pass A and the epilogue of A w_{i-1} wrote.
+int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
+  double *pa = M->fpart, *pb = pa + 2 * 5 * (size_t)M->ga, *pf = pb + 2 * 4 * (size_t)M->nblk;
+  PS_TRY(launch(M, s, PS_K_DOTS, k_fold_partials, dim3(M->gfold), 0, (const double *)pa, M->ga,
+                (const double *)pb, M->nblk, pf, (const int *)M->ctl));
+  DotArgs D{};
+  D.n = M->n;
+  D.partials = pf;
+  D.ctl = M->ctl;
+  D.sc = M->sc;
+  D.hist = M->hist;
+  D.maxit = P.maxit;
+  D.tol = P.tol;
+  D.flags = 0;
+  return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<9, FinSafe>, dim3(1), 0, D, M->gfold);
+}
+
 int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   hipStream_t A = P.A;
   double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y),
@@ -299,11 +326,22 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   if (!replace) {
     PS_TRY(fork(M, P));
     PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, M->ctl + C_HALT));  // As_i
-    PS_TRY(iter_safe_dots(M, P, P.B, i));                              // concurrently
+    if (P.fused && i > P.i0) PS_TRY(fused_finish(M, P, P.B));        // concurrently
+    else PS_TRY(iter_safe_dots(M, P, P.B, i));
     PS_TRY(join(M, P));
-    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M)};
-    PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe, pair_grid(M->n), 0, pa));
-    PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, done));
+    if (!P.fused) {
+      PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
+                   nullptr, nullptr};
+      PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false>, pair_grid(M->n), 0, pa));
+      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, done));
+      return PS_OK;
+    }
+    double *pa_part = M->fpart, *pb_part = pa_part + 2 * 5 * (size_t)M->ga;
+    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
+                 M->slot(PS_V_RS), pa_part};
+    PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true>, pair_grid(M->n), 0, pa));
+    PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                EpiPBiCGSafeBDots{Q, As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part}, done));
     return PS_OK;
   }
   // replacement step (Algorithm 5): true values of q, w, r, l, g, s
@@ -369,6 +407,7 @@ int enqueue_iteration(ps_matrix *M, const Plan &P, int i) {
 bool is_standard(const Plan &P, int i) {
   if (P.variant == PS_PBICGSTAB) return true;
   if (i == 0) return false;
+  if (P.fused && i == P.i0) return false;  // its inner products come from their own pass
   if (P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && i % P.rr_m == 0 && i < P.rr_M) return false;
   return true;
 }
@@ -381,8 +420,8 @@ void clear_graphs(ps_matrix *M) {
 // The instantiated graph of `count` standard iterations that starts in the
 // current sweep phase, captured from the launch sequence on first use.
 int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **out) {
-  const GraphKey key{P.variant, P.maxit, P.rr_m, P.rr_M, P.overlap ? 1 : 0, count, M->sweep,
-                     P.tol, P.A};
+  const GraphKey key{P.variant, P.maxit,   P.rr_m,           P.rr_M, P.overlap ? 1 : 0,
+                     count,     M->sweep,  P.fused ? 1 : 0, P.tol,  P.A};
   for (GraphEntry &g : M->graphs)
     if (g.key == key) {
       *out = &g;
@@ -474,6 +513,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (!o.resume && !b) return PS_EINVAL;
   if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
   if (o.resume && (o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
+  if (o.schedule != 0 && (o.schedule != 1 || variant != PS_PBICGSAFE)) return PS_EINVAL;
   BusyGuard guard(M->busy);
   if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(M->device));
@@ -503,6 +543,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool want_overlap = o.overlap > 0 || (o.overlap < 0 && M->n >= kOverlapMinRows);
   P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
+  P.fused = o.schedule == 1;
   M->prof_mask = o.profile;
   M->cur_iter = -1;
   M->sweep = 0;
@@ -590,6 +631,7 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->sc);
   (void)hipFree(M->ctl);
   (void)hipFree(M->partials);
+  (void)hipFree(M->fpart);
   (void)hipFree(M->hist);
   if (M->pinned) (void)hipHostFree(M->pinned);
   for (hipEvent_t e : M->ev_pool) (void)hipEventDestroy(e);
@@ -641,7 +683,7 @@ void ps_default_options(ps_options *opt) {
   opt->resume = 0;
   opt->resume_iter = 0;
   opt->graph = 1;
-  opt->reserved = 0;
+  opt->schedule = 0;
   opt->stream = nullptr;
 }
 
@@ -707,6 +749,10 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   PS_CREATE_HIP(hipMalloc(&M->sc, SC_COUNT * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->ctl, C_COUNT * sizeof(int)));
   PS_CREATE_HIP(hipMalloc(&M->partials, 2 * 9 * (size_t)M->dot_grid * sizeof(double)));
+  M->ga = (int)pair_grid(n).x;
+  M->gfold = (std::max(M->ga, M->nblk) + kBlock - 1) / kBlock;
+  PS_CREATE_HIP(hipMalloc(&M->fpart, 2 * (5 * (size_t)M->ga + 4 * (size_t)M->nblk +
+                                          9 * (size_t)M->gfold) * sizeof(double)));
   PS_CREATE_HIP(hipHostMalloc(&M->pinned, 2 * C_COUNT * sizeof(int), hipHostMallocDefault));
 #undef PS_CREATE_HIP
   auto chk = [&](hipError_t e) { return e == hipSuccess; };

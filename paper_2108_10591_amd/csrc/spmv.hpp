@@ -50,11 +50,23 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // no-op: C_DONE for products that follow a finish in stream order, C_HALT for
 // products that may run concurrently with one.  `rev` = 1 walks the row blocks
 // from the last to the first (see sweep_block).
+//
+// An epilogue with kDots > 0 also accumulates per-row terms of inner products
+// (compensated pairs, see dots.hpp) and writes the block's partial sums for row
+// block b; all lanes of the block take part in that reduction.
 template <int IPT, int LPR, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restrict__ x, Epi epi,
                                                  const int *__restrict__ stop, int rev) {
   if (stop != nullptr && *stop) return;
   extern __shared__ double prod[];
+  constexpr int ND = Epi::kDots;
+  DD dacc[ND > 0 ? ND : 1];
+#pragma unroll
+  for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = DD{0.0, 0.0};
+  auto put = [&](int row, double ax, const typename Epi::In &in) {
+    if constexpr (ND > 0) epi.store(row, ax, in, dacc);
+    else epi.store(row, ax, in);
+  };
   const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
   const int r0 = A.blk[b], r1 = A.blk[b + 1];
   const int r = r0 + threadIdx.x;
@@ -72,43 +84,51 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
     DD acc[1] = {DD{0.0, 0.0}};
     for (int k = k0 + threadIdx.x; k < k1; k += kBlock) sum_acc(acc[0], A.val[k] * x[A.col[k]]);
     const DD t = block_sum_dd<1>(acc, prod);
-    if (threadIdx.x == 0) epi.store(r0, t.hi + t.lo, epi.load(r0));
-    return;
-  }
-  int c[IPT];
-  double v[IPT];
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const int k = threadIdx.x + i * kBlock;
-    if (k < nz) {
-      c[i] = A.col[k0 + k];
-      v[i] = A.val[k0 + k];
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const int k = threadIdx.x + i * kBlock;
-    if (k < nz) prod[k] = v[i] * x[c[i]];
-  }
-  __syncthreads();
-  if constexpr (LPR == 1) {
-    if (r < r1) {
-      DD acc{0.0, 0.0};
-      for (int k = ra - k0; k < re - k0; ++k) sum_acc(acc, prod[k]);
-      epi.store(r, acc.hi + acc.lo, ein);
-    }
+    if (threadIdx.x == 0) put(r0, t.hi + t.lo, epi.load(r0));
   } else {
-    constexpr int kGroups = kBlock / LPR;
-    const int g = threadIdx.x / LPR, j = threadIdx.x % LPR;
-    for (int base = 0; base < r1 - r0; base += kGroups) {  // same trip count in every lane
-      const int rr = r0 + base + g;
-      DD acc{0.0, 0.0};
-      if (rr < r1) {
-        const int a = A.rowptr[rr] - k0, e = A.rowptr[rr + 1] - k0;
-        for (int k = a + j; k < e; k += LPR) sum_acc(acc, prod[k]);
+    int c[IPT];
+    double v[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const int k = threadIdx.x + i * kBlock;
+      if (k < nz) {
+        c[i] = A.col[k0 + k];
+        v[i] = A.val[k0 + k];
       }
-      group_sum_dd<LPR>(acc);
-      if (j == 0 && rr < r1) epi.store(rr, acc.hi + acc.lo, epi.load(rr));
+    }
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const int k = threadIdx.x + i * kBlock;
+      if (k < nz) prod[k] = v[i] * x[c[i]];
+    }
+    __syncthreads();
+    if constexpr (LPR == 1) {
+      if (r < r1) {
+        DD acc{0.0, 0.0};
+        for (int k = ra - k0; k < re - k0; ++k) sum_acc(acc, prod[k]);
+        put(r, acc.hi + acc.lo, ein);
+      }
+    } else {
+      constexpr int kGroups = kBlock / LPR;
+      const int g = threadIdx.x / LPR, j = threadIdx.x % LPR;
+      for (int base = 0; base < r1 - r0; base += kGroups) {  // same trip count in every lane
+        const int rr = r0 + base + g;
+        DD acc{0.0, 0.0};
+        if (rr < r1) {
+          const int a = A.rowptr[rr] - k0, e = A.rowptr[rr + 1] - k0;
+          for (int k = a + j; k < e; k += LPR) sum_acc(acc, prod[k]);
+        }
+        group_sum_dd<LPR>(acc);
+        if (j == 0 && rr < r1) put(rr, acc.hi + acc.lo, epi.load(rr));
+      }
+    }
+  }
+  if constexpr (ND > 0) {
+    __shared__ double red[kWavesPerBlock * ND * 2];
+    const DD t = block_sum_dd<ND>(dacc, red);
+    if (threadIdx.x < ND) {
+      epi.part[(threadIdx.x * A.nblk + b) * 2] = t.hi;
+      epi.part[(threadIdx.x * A.nblk + b) * 2 + 1] = t.lo;
     }
   }
 }
@@ -119,6 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
 
 // y = A x
 struct EpiStore {
+  static constexpr int kDots = 0;
   double *y;
   struct In {};
   __device__ __forceinline__ In load(int) const { return In{}; }
@@ -128,6 +149,7 @@ struct EpiStore {
 // r = b - A x (and optionally r0* = r): the initial residual of every
 // algorithm, and the true residual of a replacement step (Algorithm 5)
 struct EpiResidual {
+  static constexpr int kDots = 0;
   const double *b;
   double *r;
   double *rs;  // may be null
@@ -147,6 +169,7 @@ struct EpiResidual {
 // alpha A w_i (Eq. (g)), s_{i+1} = s_i - alpha q_i - g_{i+1} (Eq. (sip1)).
 // A w_i itself is never stored.
 struct EpiPBiCGSafeB {
+  static constexpr int kDots = 0;
   const double *q, *As;
   double *l, *g, *s;
   const double *sc;
@@ -168,6 +191,7 @@ struct EpiPBiCGSafeB {
 // z_i = zeta r_i + eta z_{i-1} - alpha u_i, y_{i+1} = zeta s_i + eta y_i - alpha w_i,
 // x_{i+1} = x_i + alpha p_i + z_i, r_{i+1} = r_i - alpha o_i - y_{i+1}.
 struct EpiSsBiCGSafe2B {
+  static constexpr int kDots = 0;
   const double *s, *u, *p;
   double *t, *z, *y, *x, *r;
   const double *sc;
@@ -187,6 +211,37 @@ struct EpiSsBiCGSafe2B {
     y[row] = yn;
     x[row] = in.x + al * in.p + zn;
     r[row] = in.r - al * o - yn;
+  }
+};
+
+// EpiPBiCGSafeB, plus the partial sums of the four inner products of the next
+// iteration that involve s_{i+1}: a = (s,s), c = (s,y), d = (s,r), g = (r0*,s),
+// with y_{i+1} and r_{i+1} from the pass A that precedes this product.
+// part: [4][nblk] (hi, lo) pairs.
+struct EpiPBiCGSafeBDots {
+  static constexpr int kDots = 4;
+  const double *q, *As;
+  double *l, *g, *s;
+  const double *y, *r, *rs;
+  const double *sc;
+  double *part;
+  struct In {
+    double q, As, g, s, y, r, rs;
+  };
+  __device__ __forceinline__ In load(int k) const {
+    return In{q[k], As[k], g[k], s[k], y[k], r[k], rs[k]};
+  }
+  __device__ __forceinline__ void store(int k, double aw, const In &in, DD (&acc)[4]) const {
+    const double al = sc[PS_S_ALPHA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
+    l[k] = in.q - aw;
+    const double gn = ze * in.As + et * in.g - al * aw;
+    g[k] = gn;
+    const double sn = in.s - al * in.q - gn;
+    s[k] = sn;
+    dd_fma(acc[0], sn, sn);
+    dd_fma(acc[1], sn, in.y);
+    dd_fma(acc[2], sn, in.r);
+    dd_fma(acc[3], in.rs, sn);
   }
 };
 

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
                 ("batch_iters", ctypes.c_int32), ("overlap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("resume", ctypes.c_int32),
                 ("resume_iter", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("schedule", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 _L = None

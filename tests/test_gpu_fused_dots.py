@@ -1,0 +1,137 @@
+"""GPU parity of the fused-dot schedule of p-BiCGSafe (option schedule = 1).
+
+The schedule changes where the nine inner products of Algorithm 4 are formed
+(per-block partial sums inside pass A and the epilogue of A w_i of the previous
+iteration, instead of a pass of their own), not what they are: the partial sums
+are compensated pairs rounded once, as in the separate pass.  So every result
+must equal the oracle's p-BiCGSafe bit for bit, like schedule 0.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2108_10591_amd import pipesafe, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    pipesafe.library()
+
+
+def _long_rows():
+    """Rows past a block's LDS budget next to short ones, made diagonally dominant so that
+    a few iterations stay finite."""
+    rng = np.random.default_rng(3)
+    lens = rng.integers(1, 20, 600)
+    lens[[5, 100, 101, 599]] = [300, 1500, 9000, 20000]
+    S = W.random_csr(600, 3, lengths=lens).to_scipy().tolil()
+    S.setdiag(1.5 * np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)
+    S = S.tocsr()
+    S.sort_indices()
+    rowptr = S.indptr.astype(np.int64)
+    return W.CSR(n=600, rowptr=rowptr, col=S.indices.astype(np.int32), val=S.data.astype(np.float64),
+                 b=W.rhs_ones(rowptr, S.data.astype(np.float64)), name="long_rows_600")
+
+
+CASES = {
+    "cd2d_64": lambda: W.workload("cd2d_64"),
+    "rand_band_20k": lambda: W.rand_band(20_000, seed=3, band=500),
+    "cd3d_16": lambda: W.cd3d(16, 20.0, seed=1),
+    "nonsym_ragged_3001": lambda: W.small_nonsym(3001, 11, density=0.003),
+    "long_rows_600": _long_rows,
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fused_schedule_trajectory_bit_identical_to_oracle(case):
+    A = CASES[case]()
+    for tol, maxit in ((1e-10, 3000), (0.0, 9)):
+        say(f"fused dots {case} tol={tol} maxit={maxit}")
+        ref = O.solve(A, tol=tol, maxit=maxit, variant="pbicgsafe")
+        with pipesafe.Matrix.from_csr(A) as M:
+            for overlap in (0, 1):
+                res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=1,
+                              overlap=overlap)
+                assert res.status == ref.status and res.iters == ref.iters, \
+                    (case, overlap, res.status, ref.status, res.iters, ref.iters)
+                assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, overlap)
+                assert np.array_equal(res.x, ref.x, equal_nan=True), (case, overlap)
+
+
+def test_fused_schedule_graphs_and_batches_bit_identical():
+    """Cached graph replays (several per solve, eager solves in between) and any batch size
+    give the same bits as eager one-stream launches; so does schedule 0."""
+    for name, A in [("rand_band_100k", W.rand_band(100_000, seed=21, band=3000)),
+                    ("cd2d_64", W.workload("cd2d_64"))]:
+        say(f"fused dots determinism {name}")
+        with pipesafe.Matrix.from_csr(A) as M:
+            ref = M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", graph=0, overlap=0)
+            runs = [M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", schedule=1, **kw)
+                    for kw in (dict(graph=0, overlap=0), dict(graph=1, batch_iters=4),
+                               dict(graph=0, batch_iters=1, overlap=1),
+                               dict(graph=1, batch_iters=4), dict(graph=1, batch_iters=7, overlap=0),
+                               dict())]
+        for k, r in enumerate(runs):
+            assert r.iters == ref.iters and r.status == ref.status, (name, k)
+            assert np.array_equal(r.x, ref.x) and np.array_equal(r.hist, ref.hist), (name, k)
+
+
+def test_fused_schedule_resume_from_oracle_state():
+    """The first iteration after a resume forms its inner products in their own pass;
+    the following ones take them from the fused partial sums."""
+    A = W.workload("cd2d_64")
+    k, extra = 6, 4
+    st, _ = O.state_at(A, k, variant="pbicgsafe")
+    st2, _ = O.state_at(A, k + extra, variant="pbicgsafe")
+    with pipesafe.Matrix.from_csr(A) as M:
+        for v in ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o"]:
+            M.set_state(v, st.vec(v))
+        M.set_state("b", A.b)
+        M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "f", "rhoref"]})
+        res = M.solve(A.b, tol=0.0, maxit=k + extra, variant="pbicgsafe", resume=1, resume_iter=k,
+                      schedule=1, graph=1, batch_iters=2)
+        assert res.status == O.MAXIT and res.iters == k + extra
+        for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q"]:
+            assert np.array_equal(M.get_state(v), st2.vec(v)), v
+
+
+def test_fused_schedule_statuses():
+    # A = I converges at i = 1, the first stop test that reads fused partial sums
+    for n in (1, 2, 63, 1000):
+        E = W.identity(n, seed=n)
+        with pipesafe.Matrix.from_csr(E) as M:
+            res = M.solve(E.b, tol=1e-12, maxit=50, variant="pbicgsafe", schedule=1)
+        assert res.status == O.CONVERGED and res.iters == 1 and np.array_equal(res.x, E.b)
+    S = W.skew_blocks(64, seed=1)
+    with pipesafe.Matrix.from_csr(S) as M:
+        res = M.solve(S.b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=1)
+    assert res.status == O.BREAKDOWN and res.iters == 0
+    B = W.small_nonsym(40, 0)
+    b = B.b.copy()
+    b[7] = np.nan
+    with pipesafe.Matrix.from_csr(B) as M:
+        assert M.solve(b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=1).status == \
+            O.NONFINITE
+        r0 = M.solve(B.b, tol=1e-10, maxit=0, variant="pbicgsafe", schedule=1)
+        assert r0.status == O.MAXIT and r0.iters == 0
+        r3 = M.solve(B.b, tol=1e-30, maxit=3, variant="pbicgsafe", schedule=1)
+        o3 = O.solve(B, tol=1e-30, maxit=3, variant="pbicgsafe")
+        assert r3.iters == 3 and np.array_equal(r3.x, o3.x)
+        # the schedule exists for p-BiCGSafe only
+        for v in ("ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"):
+            with pytest.raises(pipesafe.PipesafeError):
+                M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=1)
+        with pytest.raises(pipesafe.PipesafeError):
+            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=2)
