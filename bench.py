@@ -41,12 +41,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def matrix_bytes(n, nnz):
-    """CSR bytes: int32 column index + FP64 value per nonzero, int32 row pointer."""
+def matrix_bytes(n, nnz, info=None):
+    """Bytes one sparse product streams from the matrix: CSR int32 column index + FP64
+    value per nonzero and an int32 row pointer, or (when the library chose the sliced
+    ELLPACK layout) 12 bytes per stored slot and an int32 offset per 64-row slice."""
+    if info is not None:
+        return info["matrix_bytes"]
     return 12 * nnz + 4 * (n + 1)
 
 
-def bytes_per_iteration(variant, n, nnz, schedule=0):
+def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
     """Algorithmic HBM bytes of one iteration of the implemented schedule (FP64 vectors,
     each vector entry read or written once per kernel that needs it, x-gather once).
 
@@ -58,15 +62,15 @@ def bytes_per_iteration(variant, n, nnz, schedule=0):
     p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (176n) + A w with l, g, s
                  and y, r, r0* (M+88n)
     """
-    M = matrix_bytes(n, nnz)
+    M = matrix_bytes(n, nnz, info)
     if variant == "pbicgsafe" and schedule == 1:
         return 2 * M + 280 * n
     return {"pbicgsafe": 2 * M + 288 * n, "pbicgsafe_rr": 2 * M + 288 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
 
 
-def bytes_per_launch(cls, n, nnz, schedule=0):
-    M = matrix_bytes(n, nnz)
+def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
+    M = matrix_bytes(n, nnz, info)
     if schedule == 1:
         return {"spmv": M + 16 * n, "update": 176 * n, "spmv_fused": M + 88 * n}[cls]
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 168 * n, "spmv_fused": M + 64 * n}[cls]
@@ -92,12 +96,12 @@ def load_traffic(cls):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(A, iters, variant="pbicgsafe"):
+def cpu_baseline(A, iters, variant="pbicgsafe", info=None):
     import oracle
     t0 = time.perf_counter()
     res = oracle.solve(A, tol=1e-8, maxit=iters, variant=variant)
     dt = time.perf_counter() - t0
-    gb = bytes_per_iteration(variant, A.n, A.nnz) * res.iters / 1e9
+    gb = bytes_per_iteration(variant, A.n, A.nnz, 0, info) * res.iters / 1e9
     return {"value": round(gb / dt, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{A.name} {variant}: set-up + {res.iters} iterations (maxit={iters}) in "
                       f"{dt:.2f} s, single-threaded C, FP64; {res.iters / dt:.2f} iterations/s"}
@@ -157,6 +161,8 @@ def main():
     tol = workloads.WORKLOADS[args.workload]["tol"]
     log(f"  n={A.n} nnz={A.nnz} ({time.perf_counter() - t0:.1f} s)")
     M = pipesafe.Matrix.from_csr(A)
+    info = M.info()
+    log(f"  device layout: {info}")
     b = torch.from_numpy(A.b).to(dev)
     x = torch.empty(A.n, dtype=torch.float64, device=dev)
     maxit = 10_000
@@ -188,7 +194,7 @@ def main():
     it = iters[-1]
     assert all(i == it for i in iters), iters
     ms_per_step = 1e3 * elapsed / args.steps
-    bpi = bytes_per_iteration(variant, A.n, A.nnz, sched)
+    bpi = bytes_per_iteration(variant, A.n, A.nnz, sched, info)
     value = bpi * it / (ms_per_step * 1e-3) / 1e9
     xh = x.cpu().numpy()
     err1 = float(np.abs(xh - 1.0).max())
@@ -209,12 +215,13 @@ def main():
     torch.cuda.synchronize()
     ms_profiled = 1e3 * (time.perf_counter() - t1) / args.steps
     avg_us = 1e3 * kms / max(kcnt, 1)
-    bpl = bytes_per_launch(dominant, A.n, A.nnz, sched)
+    bpl = bytes_per_launch(dominant, A.n, A.nnz, sched, info)
     achieved = bpl / (avg_us * 1e-6) / 1e9
     traffic = load_traffic(dominant) if sched == 0 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dominant], "bytes_per_launch": bpl,
+                "kernel": KERNEL_NAMES[dominant].replace("k_spmv", "k_sell" if info["format"] == "sell"
+                                                         else "k_spmv"), "bytes_per_launch": bpl,
                 "avg_launch_us": round(avg_us, 3), "launches": kcnt,
                 "measured_over": f"{args.steps} profiled solves ({ms_profiled:.1f} ms each)"}
 
@@ -224,7 +231,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": args.workload, "n": A.n, "nnz": A.nnz, "variant": variant,
                       "tol": tol, "x0": "zero", "rhs": "A*ones", "iterations": it,
-                      "bytes_per_iteration": bpi, "overlap": args.overlap, "schedule": sched,
+                      "bytes_per_iteration": bpi, "matrix_layout": info["format"],
+                      "matrix_bytes": info["matrix_bytes"], "overlap": args.overlap, "schedule": sched,
                       "graphs": True},
            "time_to_tol_ms": round(ms_per_step, 3), "iters_per_s": round(it / (ms_per_step * 1e-3), 1),
            "us_per_iter": round(1e3 * ms_per_step / it, 2),
@@ -245,7 +253,7 @@ def main():
                 rv = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc, hist=False)
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t1) / reps
-            gbps = bytes_per_iteration(v, A.n, A.nnz, sc) * rv.iters / (ms * 1e-3) / 1e9
+            gbps = bytes_per_iteration(v, A.n, A.nnz, sc, info) * rv.iters / (ms * 1e-3) / 1e9
             v = key
             var[v] = {"iterations": rv.iters, "status": rv.status_name, "time_to_tol_ms": round(ms, 3),
                       "us_per_iter": round(1e3 * ms / max(rv.iters, 1), 2), "GBps": round(gbps, 1)}
@@ -254,7 +262,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_iters} iterations ...")
-        out["cpu_baseline"] = cpu_baseline(A, args.cpu_iters, variant)
+        out["cpu_baseline"] = cpu_baseline(A, args.cpu_iters, variant, info)
         log(f"  {out['cpu_baseline']}")
     M.close()
     print(json.dumps(out), flush=True)

@@ -106,6 +106,29 @@ typedef struct {
                           stream, ps_solve the library's own stream.                   */
 } ps_options;
 
+/* device layout of the matrix, chosen by ps_create (ps_info.format) */
+enum ps_format {
+  PS_FMT_CSR = 0,  /* the caller's CSR (int32 row pointer and columns, FP64 values),
+                      cut into row blocks whose products fit the LDS                  */
+  PS_FMT_SELL = 1  /* sliced ELLPACK: slices of 64 consecutive rows stored column by
+                      column, each row in its CSR order and padded to the slice's
+                      longest row (padding is skipped, never multiplied).  Chosen when
+                      the padded size is at most 1.10 nnz (stencil-like matrices).
+                      Same products, same summation order, same results as CSR.      */
+};
+
+/* what ps_create built, for ps_matrix_info */
+typedef struct {
+  int32_t format;        /* ps_format                                                   */
+  int32_t spmv_shape;    /* CSR product shape 0..4 (lanes per row, LDS budget); -1 SELL */
+  int64_t n, nnz;
+  int64_t slots;         /* stored matrix entries including padding (= nnz for CSR)     */
+  int32_t spmv_blocks;   /* workgroups of one sparse product                            */
+  int32_t dot_grid;      /* workgroups of the multi-inner-product kernel                */
+  int64_t matrix_bytes;  /* bytes one sparse product must stream from the matrix arrays:
+                            CSR 12 nnz + 4 (n+1); SELL 12 slots + 4 (slices+1)          */
+} ps_info;
+
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */
 enum ps_kernel {
   PS_K_SPMV = 0,        /* sparse product with no fused work (A s_i, A z_i, ...)        */
@@ -152,7 +175,11 @@ void ps_default_options(ps_options *opt);
  * Validation: n >= 1, nnz = rowptr[n] < 2^31, rowptr[0] = 0, rowptr
  * non-decreasing, 0 <= col < n, val finite; otherwise PS_EINVAL.  Columns need
  * not be sorted; duplicate (row, col) entries are summed; empty rows are
- * allowed (they make A singular).
+ * allowed (they make A singular).  The device layout (ps_format) and the
+ * product's launch shape are chosen here from the row lengths; the
+ * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SPMV_SHAPE
+ * (0..4) and PIPESAFE_DOT_GRID (1..8192 workgroups) override the choices, for
+ * tuning and tests.  Every choice gives the same results.
  */
 int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
               const double *val);
@@ -191,6 +218,9 @@ int ps_set_state(ps_matrix *A, int32_t which, const double *host_in);
 /* Copy / load the scalar state, HOST double[PS_S_COUNT]. */
 int ps_get_scalars(ps_matrix *A, double *host_out);
 int ps_set_scalars(ps_matrix *A, const double *host_in);
+
+/* Describe the handle's device layout (HOST *info).  PS_EINVAL on NULL. */
+int ps_matrix_info(ps_matrix *A, ps_info *info);
 
 /* Kernel timing of the last solve run with opt.profile != 0: total milliseconds
    and launch count of class `cls` (ps_kernel), measured with HIP events around

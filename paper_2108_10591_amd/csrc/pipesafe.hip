@@ -46,6 +46,7 @@ constexpr int kSlotTmp = PS_V_COUNT;  // internal scratch vector
 constexpr int kNumSlots = PS_V_COUNT + 1;
 constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 constexpr int64_t kOverlapMinRows = 1 << 18;  // automatic second stream from this size on
+constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 
 struct Timer {
   hipEvent_t a, b;
@@ -78,8 +79,13 @@ struct ps_matrix {
   int64_t n = 0, nnz = 0;
   int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
   double *val = nullptr;
-  int nblk = 0;
+  int nblk = 0;             // workgroups of one sparse product
   int shape = 1;            // SpMV shape: 0..4 = (IPT, LPR) (4,1) (8,1) (16,4) (16,8) (16,16)
+  int format = PS_FMT_CSR;  // device layout of the matrix
+  int *scol = nullptr, *soff = nullptr;  // sliced ELLPACK arrays (format PS_FMT_SELL)
+  double *sval = nullptr;
+  int64_t slots = 0;
+  int nslice = 0;
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -109,6 +115,7 @@ struct ps_matrix {
 
   double *slot(int s) const { return vec + (size_t)s * ld; }
   CsrDev csr() const { return CsrDev{rowptr, col, val, blk, nblk}; }
+  SellDev sell() const { return SellDev{scol, sval, soff, (int)n, nblk}; }
 };
 
 namespace {
@@ -190,6 +197,8 @@ int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, 
 template <class Epi>
 int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop) {
   const int rev = next_rev(M);
+  if (M->format == PS_FMT_SELL)
+    return launch(M, s, cls, k_sell<Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
   switch (M->shape) {
     case 0: return spmv_launch<4, 1>(M, s, cls, x, epi, stop, rev);
     case 1: return spmv_launch<8, 1>(M, s, cls, x, epi, stop, rev);
@@ -627,6 +636,9 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->col);
   (void)hipFree(M->val);
   (void)hipFree(M->blk);
+  (void)hipFree(M->scol);
+  (void)hipFree(M->sval);
+  (void)hipFree(M->soff);
   (void)hipFree(M->vec);
   (void)hipFree(M->sc);
   (void)hipFree(M->ctl);
@@ -721,10 +733,50 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
     if (v >= 0 && v <= 4) M->shape = v;
   }
   static const int kIpt[] = {4, 8, 16, 16, 16};
-  std::vector<int> blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock);
-  M->nblk = (int)blk.size() - 1;
-  std::vector<int> rp32(n + 1);
-  for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
+  // sliced ELLPACK when padding every slice to its longest row costs little
+  const int64_t nslice = (n + kWave - 1) / kWave;
+  int64_t slots = 0;
+  for (int64_t sl = 0; sl < nslice; ++sl) {
+    int64_t w = 0;
+    for (int64_t r = sl * kWave; r < std::min<int64_t>(n, (sl + 1) * kWave); ++r)
+      w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
+    slots += w * kWave;
+  }
+  M->format = (double)slots <= kSellMaxPadding * (double)nnz + kWave ? PS_FMT_SELL : PS_FMT_CSR;
+  if (const char *e = std::getenv("PIPESAFE_FORMAT")) {  // tuning override
+    const int v = std::atoi(e);
+    if (v == PS_FMT_CSR || v == PS_FMT_SELL) M->format = v;
+  }
+  if (slots >= INT32_MAX) M->format = PS_FMT_CSR;
+  std::vector<int> blk, rp32;
+  std::vector<int> scol, soff;
+  std::vector<double> sval;
+  if (M->format == PS_FMT_CSR) {
+    blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock);
+    M->nblk = (int)blk.size() - 1;
+    rp32.resize(n + 1);
+    for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
+  } else {
+    M->nslice = (int)nslice;
+    M->slots = slots;
+    M->nblk = (int)((n + kBlock - 1) / kBlock);
+    scol.assign((size_t)slots, -1);
+    sval.assign((size_t)slots, 0.0);
+    soff.assign((size_t)nslice + 1, 0);
+    for (int64_t sl = 0; sl < nslice; ++sl) {
+      int64_t w = 0;
+      for (int64_t r = sl * kWave; r < std::min<int64_t>(n, (sl + 1) * kWave); ++r)
+        w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
+      soff[sl + 1] = (int)(soff[sl] + w * kWave);
+    }
+    for (int64_t r = 0; r < n; ++r) {
+      const int64_t base = soff[r / kWave] + r % kWave;
+      for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+        scol[base + (k - rowptr[r]) * kWave] = col[k];
+        sval[base + (k - rowptr[r]) * kWave] = val[k];
+      }
+    }
+  }
   M->ld = ((size_t)n + 31) / 32 * 32;
   int max_dot_grid = kMaxDotGrid;
   if (const char *e = std::getenv("PIPESAFE_DOT_GRID")) {  // tuning override
@@ -741,10 +793,16 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   do {                                      \
     if ((call) != hipSuccess) return fail(PS_ENOMEM); \
   } while (0)
-  PS_CREATE_HIP(hipMalloc(&M->rowptr, (n + 1) * sizeof(int)));
-  PS_CREATE_HIP(hipMalloc(&M->col, std::max<int64_t>(nnz, 1) * sizeof(int)));
-  PS_CREATE_HIP(hipMalloc(&M->val, std::max<int64_t>(nnz, 1) * sizeof(double)));
-  PS_CREATE_HIP(hipMalloc(&M->blk, blk.size() * sizeof(int)));
+  if (M->format == PS_FMT_CSR) {
+    PS_CREATE_HIP(hipMalloc(&M->rowptr, (n + 1) * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->col, std::max<int64_t>(nnz, 1) * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->val, std::max<int64_t>(nnz, 1) * sizeof(double)));
+    PS_CREATE_HIP(hipMalloc(&M->blk, blk.size() * sizeof(int)));
+  } else {
+    PS_CREATE_HIP(hipMalloc(&M->scol, std::max<int64_t>(slots, 1) * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->sval, std::max<int64_t>(slots, 1) * sizeof(double)));
+    PS_CREATE_HIP(hipMalloc(&M->soff, soff.size() * sizeof(int)));
+  }
   PS_CREATE_HIP(hipMalloc(&M->vec, (size_t)kNumSlots * M->ld * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->sc, SC_COUNT * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->ctl, C_COUNT * sizeof(int)));
@@ -756,10 +814,14 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   PS_CREATE_HIP(hipHostMalloc(&M->pinned, 2 * C_COUNT * sizeof(int), hipHostMallocDefault));
 #undef PS_CREATE_HIP
   auto chk = [&](hipError_t e) { return e == hipSuccess; };
-  if (!chk(hipMemcpy(M->rowptr, rp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice)) ||
-      (nnz > 0 && !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
-      (nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
-      !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice)) ||
+  const bool csr = M->format == PS_FMT_CSR;
+  if ((csr && !chk(hipMemcpy(M->rowptr, rp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice))) ||
+      (csr && nnz > 0 && !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
+      (csr && nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
+      (csr && !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice))) ||
+      (!csr && slots > 0 && !chk(hipMemcpy(M->scol, scol.data(), slots * sizeof(int), hipMemcpyHostToDevice))) ||
+      (!csr && slots > 0 && !chk(hipMemcpy(M->sval, sval.data(), slots * sizeof(double), hipMemcpyHostToDevice))) ||
+      (!csr && !chk(hipMemcpy(M->soff, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice))) ||
       !chk(hipMemset(M->vec, 0, (size_t)kNumSlots * M->ld * sizeof(double))) ||
       !chk(hipMemset(M->sc, 0, SC_COUNT * sizeof(double))) ||
       !chk(hipMemset(M->ctl, 0, C_COUNT * sizeof(int))) ||
@@ -825,6 +887,20 @@ int ps_set_scalars(ps_matrix *A, const double *host_in) {
   if (!A || !host_in) return PS_EINVAL;
   PS_HIP(hipSetDevice(A->device));
   PS_HIP(hipMemcpy(A->sc, host_in, PS_S_COUNT * sizeof(double), hipMemcpyHostToDevice));
+  return PS_OK;
+}
+
+int ps_matrix_info(ps_matrix *A, ps_info *info) {
+  if (!A || !info) return PS_EINVAL;
+  info->format = A->format;
+  info->spmv_shape = A->format == PS_FMT_CSR ? A->shape : -1;
+  info->n = A->n;
+  info->nnz = A->nnz;
+  info->slots = A->format == PS_FMT_CSR ? A->nnz : A->slots;
+  info->spmv_blocks = A->nblk;
+  info->dot_grid = A->dot_grid;
+  info->matrix_bytes = A->format == PS_FMT_CSR ? 12 * A->nnz + 4 * (A->n + 1)
+                                                : 12 * A->slots + 4 * ((int64_t)A->nslice + 1);
   return PS_OK;
 }
 

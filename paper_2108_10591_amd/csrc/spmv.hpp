@@ -133,6 +133,72 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
   }
 }
 
+// Sliced ELLPACK form of the same matrix, for matrices whose rows have nearly
+// equal lengths (stencils): rows are cut into slices of kWave consecutive rows;
+// slice s holds its rows' nonzeros column by column, width w_s = its longest
+// row, so entry j of the row in lane l sits at off[s] + j * kWave + l.  Each
+// row keeps its CSR order; shorter rows are padded with col = -1, which is
+// skipped.  One lane per row: the column/value loads and the gather of x are
+// contiguous across the lanes of a wave, and no LDS staging is needed.
+struct SellDev {
+  const int *col;     // int32[slots], -1 = padding
+  const double *val;  // double[slots]
+  const int *off;     // int32[nslice+1] first slot of each slice
+  int n;
+  int nblk;           // ceil(n / kBlock) workgroups
+};
+
+// Entries of a row loaded ahead of their gathers per step.
+constexpr int kSellUnroll = 8;
+
+template <class Epi>
+__global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__restrict__ x, Epi epi,
+                                                 const int *__restrict__ stop, int rev) {
+  if (stop != nullptr && *stop) return;
+  constexpr int ND = Epi::kDots;
+  DD dacc[ND > 0 ? ND : 1];
+#pragma unroll
+  for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = DD{0.0, 0.0};
+  const int b = sweep_block(xcd_block(blockIdx.x, S.nblk), S.nblk, rev);
+  const int r = b * kBlock + threadIdx.x;
+  if (r < S.n) {
+    const typename Epi::In in = epi.load(r);
+    const int sl = r / kWave, lane = r % kWave;
+    const int end = S.off[sl + 1];
+    DD acc{0.0, 0.0};
+    for (int k = S.off[sl] + lane; k < end; k += kSellUnroll * kWave) {
+      int c[kSellUnroll];
+      double v[kSellUnroll];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) {
+        const int kk = k + u * kWave;
+        c[u] = -1;
+        v[u] = 0.0;
+        if (kk < end) {
+          c[u] = S.col[kk];
+          v[u] = S.val[kk];
+        }
+      }
+      double pr[kSellUnroll];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) pr[u] = c[u] >= 0 ? v[u] * x[c[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u)
+        if (c[u] >= 0) sum_acc(acc, pr[u]);
+    }
+    if constexpr (ND > 0) epi.store(r, acc.hi + acc.lo, in, dacc);
+    else epi.store(r, acc.hi + acc.lo, in);
+  }
+  if constexpr (ND > 0) {
+    __shared__ double red[kWavesPerBlock * ND * 2];
+    const DD t = block_sum_dd<ND>(dacc, red);
+    if (threadIdx.x < ND) {
+      epi.part[(threadIdx.x * S.nblk + b) * 2] = t.hi;
+      epi.part[(threadIdx.x * S.nblk + b) * 2 + 1] = t.lo;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ epilogues
 // load(r) fetches the row's operands before the products; store(r, ax, in)
 // finishes the row once its sum A x is known.

@@ -38,6 +38,14 @@ class Options(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
+class Info(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_int32), ("spmv_shape", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("slots", ctypes.c_int64), ("spmv_blocks", ctypes.c_int32),
+                ("dot_grid", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64)]
+
+
+FORMATS = {0: "csr", 1: "sell"}
+
 _L = None
 
 
@@ -60,13 +68,14 @@ def _lib():
         L.ps_get_scalars.argtypes = [P, P]
         L.ps_set_scalars.argtypes = [P, P]
         L.ps_kernel_stats.argtypes = [P, i32, Pf64, Pi64]
+        L.ps_matrix_info.argtypes = [P, ctypes.POINTER(Info)]
         L.ps_stream_copy.argtypes = [P, P, i64, P]
         L.ps_destroy.argtypes = [P]
         L.ps_strerror.argtypes = [ctypes.c_int]
         L.ps_strerror.restype = ctypes.c_char_p
         L.ps_version.restype = ctypes.c_char_p
         for name in ("ps_create", "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
-                     "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats",
+                     "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats", "ps_matrix_info",
                      "ps_stream_copy", "ps_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _L = L
@@ -223,6 +232,14 @@ class Matrix:
         for k, v in values.items():
             cur[SCAL.index(k)] = v
         _check(_lib().ps_set_scalars(self._h, _ptr(cur)), "ps_set_scalars")
+
+    def info(self) -> dict:
+        """The device layout ps_create chose (format, slots, product grid, matrix bytes)."""
+        i = Info()
+        _check(_lib().ps_matrix_info(self._h, ctypes.byref(i)), "ps_matrix_info")
+        d = {k: getattr(i, k) for k, _ in Info._fields_}
+        d["format"] = FORMATS.get(d["format"], d["format"])
+        return d
 
     def kernel_stats(self) -> dict:
         """{class: (total_ms, launches)} of the last profiled solve."""

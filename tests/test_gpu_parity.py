@@ -10,7 +10,9 @@ Bars (derivations are in the design notes):
   * full solve: iteration count within max(1, ceil(0.02 * iters_oracle)) of the
     oracle's, same status, solution within 1e-8 relative infinity-norm.
 """
+import contextlib
 import math
+import os
 import sys
 
 import numpy as np
@@ -73,14 +75,30 @@ def _spmv_matrix(case):
     return W.random_csr(n, seed, lengths=lens, **kw)
 
 
+@contextlib.contextmanager
+def device_format(fmt):
+    """Force the device layout ps_create picks (PIPESAFE_FORMAT: 0 CSR, 1 sliced ELLPACK)."""
+    old = os.environ.get("PIPESAFE_FORMAT")
+    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "sell": "1"}[fmt]
+    try:
+        yield
+    finally:
+        if old is None:
+            del os.environ["PIPESAFE_FORMAT"]
+        else:
+            os.environ["PIPESAFE_FORMAT"] = old
+
+
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
 @pytest.mark.parametrize("case", sorted(SPMV_CASES))
-def test_spmv_matches_oracle(case):
+def test_spmv_matches_oracle(case, fmt):
     import torch
-    say(f"spmv case {case}")
+    say(f"spmv case {case} {fmt}")
     A = _spmv_matrix(case)
     x = np.random.default_rng(7).standard_normal(A.n)
     ref = O.spmv(A, x)
-    with pipesafe.Matrix.from_csr(A) as M:
+    with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
+        assert M.info()["format"] == fmt
         y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     # every row, long ones included: both sides round each product, carry the
     # row's sum with two-sum accumulators and round once, so any order of the
@@ -149,6 +167,45 @@ def test_trajectory_bit_identical_to_oracle(variant):
         assert res.status == ref.status and res.iters == ref.iters, (name, res.iters, ref.iters)
         assert np.array_equal(res.hist, ref.hist), name
         assert np.array_equal(res.x, ref.x), name
+
+
+def test_device_layout_choice():
+    """Stencils get the sliced ELLPACK layout (padding <= 10%), uneven rows keep CSR."""
+    for name, A, fmt in [("cd2d_64", W.workload("cd2d_64"), "sell"),
+                         ("cd3d_16", W.cd3d(16, 20.0, seed=1), "sell"),
+                         ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), "csr"),
+                         ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "csr")]:
+        with pipesafe.Matrix.from_csr(A) as M:
+            info = M.info()
+        assert info["format"] == fmt, name
+        assert info["n"] == A.n and info["nnz"] == A.nnz
+        if fmt == "sell":
+            L = np.diff(A.rowptr)
+            ns = (A.n + 63) // 64
+            Lp = np.zeros(ns * 64, dtype=np.int64)
+            Lp[:A.n] = L
+            slots = int(Lp.reshape(ns, 64).max(axis=1).sum()) * 64
+            assert info["slots"] == slots and slots <= 1.1 * A.nnz + 64
+            assert info["matrix_bytes"] == 12 * slots + 4 * (ns + 1)
+        else:
+            assert info["slots"] == A.nnz and info["matrix_bytes"] == 12 * A.nnz + 4 * (A.n + 1)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_both_layouts_reproduce_oracle(variant):
+    """Each matrix in the layout ps_create would not pick for it: the same bits."""
+    for name, A, fmt in [("cd2d_64", W.workload("cd2d_64"), "csr"),
+                         ("cd3d_16", W.cd3d(16, 20.0, seed=1), "csr"),
+                         ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), "sell"),
+                         ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell"),
+                         ("cd2d_5", W.cd2d(5, 10.0), "sell")]:
+        say(f"layout {fmt} {name} {variant}")
+        ref = O.solve(A, tol=1e-10, maxit=3000, variant=variant, rr_m=25)
+        with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
+            assert M.info()["format"] == fmt
+            res = M.solve(A.b, tol=1e-10, maxit=3000, variant=variant, rr_m=25)
+        assert res.status == ref.status and res.iters == ref.iters, (name, res.iters, ref.iters)
+        assert np.array_equal(res.hist, ref.hist) and np.array_equal(res.x, ref.x), name
 
 
 def test_rr_replaces_every_m():
