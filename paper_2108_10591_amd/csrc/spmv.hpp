@@ -82,24 +82,48 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
   if (nz > IPT * kBlock) {
     // one long row: strided pair sums, then a fixed-order block combination
     DD acc[1] = {DD{0.0, 0.0}};
-    for (int k = k0 + threadIdx.x; k < k1; k += kBlock) sum_acc(acc[0], A.val[k] * x[A.col[k]]);
+    constexpr int kU = 4;  // nonzeros per lane in flight
+    for (int k = k0 + threadIdx.x; k < k1; k += kU * kBlock) {
+      int cc[kU];
+      double vv[kU], xx[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        cc[u] = 0;
+        vv[u] = 0.0;
+        if (k + u * kBlock < k1) {
+          cc[u] = A.col[k + u * kBlock];
+          vv[u] = A.val[k + u * kBlock];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) xx[u] = x[cc[u]];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (k + u * kBlock < k1) sum_acc(acc[0], vv[u] * xx[u]);
+    }
     const DD t = block_sum_dd<1>(acc, prod);
     if (threadIdx.x == 0) put(r0, t.hi + t.lo, epi.load(r0));
   } else {
     int c[IPT];
-    double v[IPT];
+    double v[IPT], xv[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const int k = threadIdx.x + i * kBlock;
+      c[i] = 0;
+      v[i] = 0.0;
       if (k < nz) {
         c[i] = A.col[k0 + k];
         v[i] = A.val[k0 + k];
       }
     }
+    // every gather unconditional (unused slots read x[0]), so that all IPT are
+    // in flight together instead of one memory latency each
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) xv[i] = x[c[i]];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const int k = threadIdx.x + i * kBlock;
-      if (k < nz) prod[k] = v[i] * x[c[i]];
+      if (k < nz) prod[k] = v[i] * xv[i];
     }
     __syncthreads();
     if constexpr (LPR == 1) {
@@ -179,12 +203,13 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__rest
           v[u] = S.val[kk];
         }
       }
-      double pr[kSellUnroll];
+      // unconditional gathers (padding reads x[0]): all kSellUnroll in flight at once
+      double xv[kSellUnroll];
 #pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) pr[u] = c[u] >= 0 ? v[u] * x[c[u]] : 0.0;
+      for (int u = 0; u < kSellUnroll; ++u) xv[u] = x[c[u] < 0 ? 0 : c[u]];
 #pragma unroll
       for (int u = 0; u < kSellUnroll; ++u)
-        if (c[u] >= 0) sum_acc(acc, pr[u]);
+        if (c[u] >= 0) sum_acc(acc, v[u] * xv[u]);
     }
     if constexpr (ND > 0) epi.store(r, acc.hi + acc.lo, in, dacc);
     else epi.store(r, acc.hi + acc.lo, in);
