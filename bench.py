@@ -84,13 +84,15 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(cls):
-    """Counter-measured bytes per launch of class `cls`, or None if absent or stale."""
+def load_traffic(cls, workload, schedule):
+    """Counter-measured bytes per launch of class `cls`, or None if absent, taken on
+    another workload or schedule, or stale (kernel sources changed since)."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("source_digest") != source_digest():
+    if t.get("source_digest") != source_digest() or t.get("workload") != workload \
+            or t.get("schedule") != schedule:
         return None
     k = t.get("kernels", {}).get(cls)
     return None if k is None else k.get("bytes_per_launch")
@@ -118,8 +120,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
-    ap.add_argument("--schedule", type=int, default=0,
-                    help="p-BiCGSafe: 0 separate inner-product pass, 1 fused inner products")
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="p-BiCGSafe: 0 separate inner-product pass, 1 fused inner products, "
+                         "-1 the library's automatic choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the library's streaming copy on MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -169,7 +172,10 @@ def main():
     variant = args.variant
 
     # one profiled solve to find the dominant kernel class
-    sched = args.schedule if variant == "pbicgsafe" else 0
+    if variant != "pbicgsafe":
+        sched = 0
+    else:
+        sched = info["auto_schedule"] if args.schedule < 0 else args.schedule
     res = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, overlap=args.overlap,
                       schedule=sched, profile=CLASSES[:4], hist=False)
     stats = M.kernel_stats()
@@ -217,7 +223,7 @@ def main():
     avg_us = 1e3 * kms / max(kcnt, 1)
     bpl = bytes_per_launch(dominant, A.n, A.nnz, sched, info)
     achieved = bpl / (avg_us * 1e-6) / 1e9
-    traffic = load_traffic(dominant) if sched == 0 else None
+    traffic = load_traffic(dominant, args.workload, sched) if variant == "pbicgsafe" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": KERNEL_NAMES[dominant].replace("k_spmv", "k_sell" if info["format"] == "sell"

@@ -79,9 +79,10 @@ typedef struct {
                           no-ops, so the result does not depend on this value.           */
   int32_t overlap;     /* 1: the reduction phase runs on a second stream concurrently
                           with the sparse product it is independent of; 0: everything
-                          on one stream; -1 (default): on for n >= 2^18 (below that the
-                          products are too short to hide the cross-stream waits).
-                          Results are bit-identical in every case.                     */
+                          on one stream; -1 (default): on when one product streams at
+                          least 128 MiB (shorter products cannot hide the cross-stream
+                          waits); ps_info.auto_overlap tells.  Results are
+                          bit-identical in every case.                                 */
   int32_t profile;     /* bit mask of ps_kernel classes to time with HIP events on the
                           stream each kernel runs on; 0 (default) = none.               */
   int32_t resume;      /* 0 (default): initialise from b and x0.  1: skip initialisation
@@ -91,7 +92,10 @@ typedef struct {
   int32_t graph;       /* 1 (default): replay batches of identical iterations as cached
                           HIP graphs; 0: launch every kernel directly.  Results are
                           bit-identical either way.  Ignored while profiling.          */
-  int32_t schedule;    /* p-BiCGSafe only.  0 (default): the reduction phase of Algorithm 4
+  int32_t schedule;    /* p-BiCGSafe only.  -1 (default): automatic, 1 on the sliced
+                          layout from 2^18 rows on, else 0 (ps_info.auto_schedule tells;
+                          other variants ignore -1).
+                          0: the reduction phase of Algorithm 4
                           as its own multi-inner-product pass, concurrent with A s_i.
                           1: fused inner products -- pass A and the epilogue of A w_i of
                           iteration i also form the per-block partial sums of the nine
@@ -100,7 +104,7 @@ typedef struct {
                           (r0*,s) from the epilogue), so that only their final sums and
                           the coefficients remain, concurrent with A s_{i+1}.  Reads
                           32n bytes more and skips the 40n-byte pass.  Results are
-                          bit-identical to schedule 0.  Other variants: must be 0.      */
+                          bit-identical to schedule 0.  Other variants: 1 is PS_EINVAL.  */
   void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
                           caller's current stream).  NULL: ps_solve_dev uses the null
                           stream, ps_solve the library's own stream.                   */
@@ -127,6 +131,8 @@ typedef struct {
   int32_t dot_grid;      /* workgroups of the multi-inner-product kernel                */
   int64_t matrix_bytes;  /* bytes one sparse product must stream from the matrix arrays:
                             CSR 12 nnz + 4 (n+1); SELL 12 slots + 4 (slices+1)          */
+  int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
+  int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe    */
 } ps_info;
 
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */

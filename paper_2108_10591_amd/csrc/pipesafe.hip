@@ -45,7 +45,15 @@ namespace {
 constexpr int kSlotTmp = PS_V_COUNT;  // internal scratch vector
 constexpr int kNumSlots = PS_V_COUNT + 1;
 constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
-constexpr int64_t kOverlapMinRows = 1 << 18;  // automatic second stream from this size on
+// Automatic choices (options overlap = -1, schedule = -1), from measurements on
+// 4k..2M-row stencils and band matrices: a second stream pays once one sparse
+// product streams at least kOverlapMinBytes (below that the cross-stream waits
+// cost more than they hide); the fused-dot schedule pays on the sliced layout
+// from kFusedMinRows rows on, and not on CSR matrices with uneven rows, whose
+// gather-bound product gains little from the skipped pass and pays for the
+// extra reads in its epilogue.
+constexpr int64_t kOverlapMinBytes = 128ll << 20;
+constexpr int64_t kFusedMinRows = 1 << 18;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 
 struct Timer {
@@ -510,6 +518,13 @@ int collect_profile(ps_matrix *M, int stop_iter) {
   return PS_OK;
 }
 
+int64_t matrix_bytes(const ps_matrix *M) {
+  return M->format == PS_FMT_CSR ? 12 * M->nnz + 4 * (M->n + 1)
+                                 : 12 * M->slots + 4 * ((int64_t)M->nslice + 1);
+}
+bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
+bool auto_fused(const ps_matrix *M) { return M->format == PS_FMT_SELL && M->n >= kFusedMinRows; }
+
 int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, double tol,
                int32_t maxit, int32_t variant, const ps_options *opt, double *x, int32_t *iters,
                double *hist, int32_t *status) {
@@ -522,7 +537,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (!o.resume && !b) return PS_EINVAL;
   if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
   if (o.resume && (o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
-  if (o.schedule != 0 && (o.schedule != 1 || variant != PS_PBICGSAFE)) return PS_EINVAL;
+  if (o.schedule < -1 || o.schedule > 1 || (o.schedule == 1 && variant != PS_PBICGSAFE))
+    return PS_EINVAL;
   BusyGuard guard(M->busy);
   if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(M->device));
@@ -549,10 +565,10 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
     P.A = M->own;
   }
   // a second stream pays only when the product it hides behind is long
-  const bool want_overlap = o.overlap > 0 || (o.overlap < 0 && M->n >= kOverlapMinRows);
+  const bool want_overlap = o.overlap > 0 || (o.overlap < 0 && auto_overlap(M));
   P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
-  P.fused = o.schedule == 1;
+  P.fused = variant == PS_PBICGSAFE && (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
   M->prof_mask = o.profile;
   M->cur_iter = -1;
   M->sweep = 0;
@@ -695,7 +711,7 @@ void ps_default_options(ps_options *opt) {
   opt->resume = 0;
   opt->resume_iter = 0;
   opt->graph = 1;
-  opt->schedule = 0;
+  opt->schedule = -1;
   opt->stream = nullptr;
 }
 
@@ -899,8 +915,9 @@ int ps_matrix_info(ps_matrix *A, ps_info *info) {
   info->slots = A->format == PS_FMT_CSR ? A->nnz : A->slots;
   info->spmv_blocks = A->nblk;
   info->dot_grid = A->dot_grid;
-  info->matrix_bytes = A->format == PS_FMT_CSR ? 12 * A->nnz + 4 * (A->n + 1)
-                                                : 12 * A->slots + 4 * ((int64_t)A->nslice + 1);
+  info->matrix_bytes = matrix_bytes(A);
+  info->auto_overlap = auto_overlap(A) ? 1 : 0;
+  info->auto_schedule = auto_fused(A) ? 1 : 0;
   return PS_OK;
 }
 

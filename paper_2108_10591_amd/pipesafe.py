@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("format", ctypes.c_int32), ("spmv_shape", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("nnz", ctypes.c_int64), ("slots", ctypes.c_int64), ("spmv_blocks", ctypes.c_int32),
-                ("dot_grid", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64)]
+                ("dot_grid", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
+                ("auto_overlap", ctypes.c_int32), ("auto_schedule", ctypes.c_int32)]
 
 
 FORMATS = {0: "csr", 1: "sell"}

@@ -69,7 +69,10 @@ def test_full_solve_reproduces_oracle(case, golden, variant):
 def test_spmv_full_size_bit_exact(case):
     import torch
     name, A, M, b = case
-    assert M.info()["format"] == {"cd3d_128": "sell", "rand_band_1m": "csr"}[name]
+    info = M.info()
+    assert info["format"] == {"cd3d_128": "sell", "rand_band_1m": "csr"}[name]
+    assert info["auto_overlap"] == 1
+    assert info["auto_schedule"] == {"cd3d_128": 1, "rand_band_1m": 0}[name]
     x = np.random.default_rng(3).standard_normal(A.n)
     y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.array_equal(y, O.spmv(A, x)), name
