@@ -125,7 +125,7 @@ enum ps_format {
 typedef struct {
   int32_t format;        /* ps_format                                                   */
   int32_t spmv_shape;    /* CSR product shape 0..4 (lanes per row, LDS budget); -1 SELL */
-  int64_t n, nnz;
+  int64_t n, nnz;         /* as given to ps_create / ps_create_batch                     */
   int64_t slots;         /* stored matrix entries including padding (= nnz for CSR)     */
   int32_t spmv_blocks;   /* workgroups of one sparse product                            */
   int32_t dot_grid;      /* workgroups of the multi-inner-product kernel                */
@@ -133,6 +133,10 @@ typedef struct {
                             CSR 12 nnz + 4 (n+1); SELL 12 slots + 4 (slices+1)          */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe    */
+  int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
+  int32_t reserved;
+  int64_t n_padded;      /* rows on the device: n, or for a batch the systems padded to
+                            multiples of 512 rows                                      */
 } ps_info;
 
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */
@@ -212,6 +216,41 @@ int ps_solve(ps_matrix *A, const double *b, const double *x0, double tol, int32_
 int ps_solve_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol, int32_t maxit,
                  int32_t variant, const ps_options *opt, double *x_dev, int32_t *iters,
                  double *hist, int32_t *status);
+
+/*
+ * Batched systems: nsys independent systems A_k x_k = b_k given as one
+ * block-diagonal CSR (HOST pointers as in ps_create, global column indices);
+ * sys_ptr int64[nsys+1]: the rows of system k are sys_ptr[k] .. sys_ptr[k+1]-1
+ * (sys_ptr[0] = 0, strictly increasing, sys_ptr[nsys] = n), and every column of
+ * those rows lies in the same range; otherwise PS_EINVAL.  Each system is
+ * solved exactly as ps_solve would solve it alone (same iterations, residual
+ * history and solution bits), but all systems share every kernel launch: each
+ * is padded on the device to a multiple of 512 rows with empty rows, each has
+ * its own coefficients, stop test and iteration count, and a system that has
+ * stopped makes its share of every later launch a no-op.  ps_solve,
+ * ps_solve_dev, ps_spmv_dev and the state functions return PS_EINVAL on a
+ * batch handle (nsys > 1); nsys = 1 gives an ordinary handle.
+ */
+int ps_create_batch(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n, int64_t nnz,
+                    const int64_t *rowptr, const int32_t *col, const double *val);
+
+/*
+ * Solve every system of a batch handle (or the one system of a handle).
+ * b, x0 (NULL: zero), x: HOST double[n] in the caller's row order; iters,
+ * status: HOST int32[nsys] per system (as in ps_solve); hist: NULL or HOST
+ * double[nsys * (maxit+1)], row k holding system k's history (entries past
+ * iters[k] are undefined).  opt as in ps_solve, except: resume is not
+ * supported (PS_EINVAL), schedule 1 is PS_EINVAL and -1 means 0 for nsys > 1.
+ * The solve runs until every system has stopped.
+ */
+int ps_solve_batch(ps_matrix *A, const double *b, const double *x0, double tol, int32_t maxit,
+                   int32_t variant, const ps_options *opt, double *x, int32_t *iters, double *hist,
+                   int32_t *status);
+/* ps_solve_batch with b, x0, x DEVICE double[n] (iters, status, hist on the host),
+   ordered on opt->stream as ps_solve_dev. */
+int ps_solve_batch_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol,
+                       int32_t maxit, int32_t variant, const ps_options *opt, double *x_dev,
+                       int32_t *iters, double *hist, int32_t *status);
 
 /* y = A x with x, y DEVICE double[n] (x and y must not overlap), ordered on
    `stream` (hipStream_t, NULL = the null stream); returns after completion. */

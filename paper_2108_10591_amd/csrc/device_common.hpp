@@ -32,6 +32,25 @@ enum Sc : int {
 
 __device__ __forceinline__ bool bad_den(double d) { return d == 0.0 || !isfinite(d); }
 
+// Batched solves: independent systems share every launch.  Each system's rows
+// are padded to a multiple of 512, so a workgroup of 256 rows (products) or
+// 512 rows (streaming passes) belongs to one system; chunk_sys[row / 256]
+// names it.  Every system has its own control block (C_COUNT ints) and scalar
+// block (SC_COUNT doubles).  chunk_sys = nullptr: one system.
+__device__ __forceinline__ int system_of(const int *chunk_sys, int64_t row) {
+  return chunk_sys ? chunk_sys[row >> 8] : 0;
+}
+
+// The control word that turns a sparse product into a no-op (see k_spmv).
+struct Stop {
+  const int *ctl;        // control blocks, [systems][C_COUNT]
+  int word;              // C_DONE, C_HALT, or -1 (never stop)
+  const int *chunk_sys;  // system of each 256-row chunk, or nullptr
+  __device__ __forceinline__ bool stopped(int sys) const {
+    return word >= 0 && ctl[(size_t)sys * C_COUNT + word] != 0;
+  }
+};
+
 // Sweep direction.  Consecutive streaming kernels of an iteration walk the
 // rows in alternating directions, so each one starts on the rows the previous
 // one touched last -- the lines most likely still held in the 256 MB

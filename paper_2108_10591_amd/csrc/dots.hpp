@@ -36,6 +36,7 @@ struct DotArgs {
   int maxit;
   double tol;
   int flags;           // finish-specific flags
+  int *running;        // systems still running; a finish that stops its system decrements it
 };
 
 enum DotFlags : int {
@@ -343,6 +344,66 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
 #pragma unroll
     for (int j = 0; j < ND; ++j) d[j] = fin[j];
     Fin::run(A, d);
+    if (A.ctl[C_DONE]) atomicSub(A.running, 1);
+  }
+}
+
+// ------------------------------------------------------- batched solves
+// Every system is padded to a multiple of 512 rows, so workgroup b (rows
+// 512 b .. 512 b + 511, one pair per lane) lies in one system; it writes its
+// partial sums, or nothing once its system has stopped.
+template <class Prod>
+__global__ __launch_bounds__(kBlock) void k_dots_batch(DotArgs A, const int *__restrict__ chunk_sys) {
+  constexpr int ND = Prod::ND;
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  const int sys = chunk_sys[2 * blockIdx.x];
+  if (A.ctl[(size_t)sys * C_COUNT + C_DONE]) return;
+  DD acc[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) acc[j] = DD{0.0, 0.0};
+  double a0[5], a1[5];
+  load_in2<Prod::MASK>(A, 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x), a0, a1);
+  Prod::acc(a0, acc);
+  Prod::acc(a1, acc);
+  const DD s = block_sum_dd<ND>(acc, lds);
+  const int G = gridDim.x;
+  if (threadIdx.x < ND) {
+    A.partials[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
+    A.partials[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
+  }
+}
+
+// One workgroup per system: add the partials of the system's workgroups
+// first_blk[k] .. first_blk[k+1]-1 (G in all) in order, round once, and run
+// the phase's finish on the system's control and scalar blocks and history.
+template <int ND, class Fin>
+__global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const int *__restrict__ first_blk,
+                                                              int G, int64_t hist_stride) {
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double fin[9];
+  const int k = blockIdx.x;
+  DotArgs Ak = A;
+  Ak.ctl += (size_t)k * C_COUNT;
+  Ak.sc += (size_t)k * SC_COUNT;
+  Ak.hist += k * hist_stride;
+  if (Ak.ctl[C_DONE]) return;
+  DD tot[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) tot[j] = DD{0.0, 0.0};
+  for (int b = first_blk[k] + threadIdx.x; b < first_blk[k + 1]; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      dd_add(tot[j], A.partials[(j * G + b) * 2], A.partials[(j * G + b) * 2 + 1]);
+  }
+  const DD s = block_sum_dd<ND>(tot, lds);
+  if (threadIdx.x < ND) fin[threadIdx.x] = s.hi + s.lo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) d[j] = fin[j];
+    Fin::run(Ak, d);
+    if (Ak.ctl[C_DONE]) atomicSub(A.running, 1);
   }
 }
 

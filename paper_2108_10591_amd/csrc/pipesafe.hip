@@ -104,6 +104,17 @@ struct ps_matrix {
   // folded partials [9][gfold], all (hi, lo) pairs, in one allocation
   double *fpart = nullptr;
   int ga = 0, gfold = 0;
+  // batched solves (nsys > 1): the caller's rows map to padded rows (each
+  // system padded to a multiple of 512), one control/scalar block and history
+  // row per system, inner-product partials per 512-row workgroup
+  int nsys = 1;
+  int64_t n_orig = 0;            // rows of the caller's concatenation (= n for one system)
+  int *chunk_sys = nullptr;      // device: system of each 256-row chunk (nullptr: one system)
+  int *first_blk = nullptr;      // device: first 512-row workgroup of each system, [nsys+1]
+  int *row_map = nullptr;        // device: padded row of each caller row
+  double *stage = nullptr;       // device: n_orig doubles for host input/output
+  double *bpart = nullptr;       // device: [9][n/512] partial pairs
+  int64_t hist_stride = 0;       // history entries per system
   double *hist = nullptr;
   int64_t hist_cap = 0;
   int *pinned = nullptr;    // 2 * C_COUNT ints of pinned host memory
@@ -122,6 +133,8 @@ struct ps_matrix {
   int64_t prof_cnt[PS_K_COUNT] = {};
 
   double *slot(int s) const { return vec + (size_t)s * ld; }
+  int *running() const { return ctl + (size_t)nsys * C_COUNT; }
+  int nblk512() const { return (int)(n / 512); }
   CsrDev csr() const { return CsrDev{rowptr, col, val, blk, nblk}; }
   SellDev sell() const { return SellDev{scol, sval, soff, (int)n, nblk}; }
 };
@@ -196,15 +209,18 @@ int next_rev(ps_matrix *M) {
 }
 
 template <int IPT, int LPR, class Epi>
-int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop,
+int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, Stop stop,
                 int rev) {
   const size_t lds = (size_t)IPT * kBlock * sizeof(double);
   return launch(M, s, cls, k_spmv<IPT, LPR, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
 }
 
+// One sparse product with epilogue `epi`; `stop_word` (C_DONE, C_HALT or -1)
+// names the control word that makes it a no-op (per system).
 template <class Epi>
-int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, const int *stop) {
+int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, int stop_word) {
   const int rev = next_rev(M);
+  const Stop stop{M->ctl, stop_word, M->chunk_sys};
   if (M->format == PS_FMT_SELL)
     return launch(M, s, cls, k_sell<Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
   switch (M->shape) {
@@ -230,6 +246,14 @@ int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, 
   A.maxit = maxit;
   A.tol = tol;
   A.flags = flags;
+  A.running = M->running();
+  if (M->nsys > 1) {
+    A.partials = M->bpart;
+    PS_TRY(launch(M, s, PS_K_DOTS, k_dots_batch<Prod>, dim3(M->nblk512()), 0, A,
+                  (const int *)M->chunk_sys));
+    return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish_batch<Prod::ND, Fin>, dim3(M->nsys), 0, A,
+                  (const int *)M->first_blk, M->nblk512(), M->hist_stride);
+  }
   PS_TRY(launch(M, s, PS_K_DOTS, k_dots<Prod>, dim3(M->dot_grid), 0, A));
   return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<Prod::ND, Fin>, dim3(1), 0, A, M->dot_grid);
 }
@@ -269,18 +293,18 @@ int enqueue_setup(ps_matrix *M, const Plan &P) {
     PS_TRY(zero_slots(M, s, {PS_V_Y, PS_V_T, PS_V_P, PS_V_U, PS_V_Z, PS_V_W, PS_V_L, PS_V_G,
                              PS_V_Q, PS_V_O, PS_V_AS, PS_V_V}));
   }
-  PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, nullptr));
+  PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, -1));
   if (P.variant == PS_PBICGSAFE || P.variant == PS_PBICGSAFE_RR) {
     // s_0 = A r_0 (its definition s_i := A r_i; Algorithm 4 uses s_0 without forming it)
-    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, nullptr));
+    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, -1));
   }
   if (P.norm_ref == 1) {
     PS_TRY(dots<ProdNorm, FinNormRef>(M, s, {Bv}, P.maxit, P.tol, 0, M->hist));
   }
   if (P.variant == PS_PBICGSTAB) {
     double *W = M->slot(PS_V_W), *T = M->slot(PS_V_T);
-    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{W}, nullptr));  // w_0 = A r_0
-    PS_TRY(spmv(M, s, PS_K_OTHER, W, EpiStore{T}, nullptr));  // t_0 = A w_0
+    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{W}, -1));  // w_0 = A r_0
+    PS_TRY(spmv(M, s, PS_K_OTHER, W, EpiStore{T}, -1));  // t_0 = A w_0
     PS_TRY(dots<ProdStab3, FinStabSetup>(M, s, {RS, R, W}, P.maxit, P.tol,
                                          P.norm_ref == 0 ? DF_SET_REF : 0, M->hist));
   }
@@ -328,6 +352,7 @@ int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
   D.maxit = P.maxit;
   D.tol = P.tol;
   D.flags = 0;
+  D.running = M->running();
   return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<9, FinSafe>, dim3(1), 0, D, M->gfold);
 }
 
@@ -339,40 +364,43 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
          *O = M->slot(PS_V_O), *As = M->slot(PS_V_AS), *Bv = M->slot(PS_V_B);
   const bool replace = P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && (i % P.rr_m) == 0 && i > 0 &&
                        i < P.rr_M;
-  int *done = M->ctl + C_DONE;
   if (!replace) {
     PS_TRY(fork(M, P));
-    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, M->ctl + C_HALT));  // As_i
+    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT));  // As_i
     if (P.fused && i > P.i0) PS_TRY(fused_finish(M, P, P.B));        // concurrently
     else PS_TRY(iter_safe_dots(M, P, P.B, i));
     PS_TRY(join(M, P));
     if (!P.fused) {
       PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                    nullptr, nullptr};
+      pa.chunk_sys = M->chunk_sys;
       PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false>, pair_grid(M->n), 0, pa));
-      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, done));
+      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, C_DONE));
       return PS_OK;
     }
     double *pa_part = M->fpart, *pb_part = pa_part + 2 * 5 * (size_t)M->ga;
     PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                  M->slot(PS_V_RS), pa_part};
+    pa.chunk_sys = M->chunk_sys;
     PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true>, pair_grid(M->n), 0, pa));
     PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
-                EpiPBiCGSafeBDots{Q, As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part}, done));
+                EpiPBiCGSafeBDots{Q, As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part}, C_DONE));
     return PS_OK;
   }
   // replacement step (Algorithm 5): true values of q, w, r, l, g, s
   PS_TRY(iter_safe_dots(M, P, A, i));
   PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n, next_rev(M)};
+  po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_OTHER, k_pou, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, done));  // q_i = A o_i
-  PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, done));  // w_i = A u_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, C_DONE));  // q_i = A o_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, C_DONE));  // w_i = A u_i
   TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n, next_rev(M)};
+  tz.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_OTHER, k_tzyx, pair_grid(M->n), 0, tz));
-  PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, done));  // r_{i+1} = b - A x_{i+1}
-  PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, done));                  // l_i = A t_i
-  PS_TRY(spmv(M, A, PS_K_OTHER, Y, EpiStore{G}, done));                  // g_{i+1} = A y_{i+1}
-  PS_TRY(spmv(M, A, PS_K_OTHER, R, EpiStore{S}, done));                  // s_{i+1} = A r_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, C_DONE));  // r_{i+1} = b - A x_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, C_DONE));                  // l_i = A t_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, Y, EpiStore{G}, C_DONE));                  // g_{i+1} = A y_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, R, EpiStore{S}, C_DONE));                  // s_{i+1} = A r_{i+1}
   return PS_OK;
 }
 
@@ -380,12 +408,12 @@ int iter_ssbicgsafe2(ps_matrix *M, const Plan &P, int i) {
   hipStream_t A = P.A;
   double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y),
          *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P), *U = M->slot(PS_V_U), *Z = M->slot(PS_V_Z);
-  int *done = M->ctl + C_DONE;
-  PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, done));  // s_i = A r_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, C_DONE));  // s_i = A r_i
   PS_TRY(iter_safe_dots(M, P, A, i));
   PouArgs po{R, S, T, Y, Pp, U, nullptr, M->sc, M->ctl, M->n, next_rev(M)};
+  po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_pu, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, done));
+  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, C_DONE));
   return PS_OK;
 }
 
@@ -395,15 +423,17 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
          *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y), *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P),
          *Z = M->slot(PS_V_Z), *W = M->slot(PS_V_W), *Q = M->slot(PS_V_Q), *V = M->slot(PS_V_V);
   Stab1Args s1{R, W, T, V, Pp, S, Z, Q, Y, M->sc, M->ctl, M->n, next_rev(M)};
+  s1.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1, pair_grid(M->n), 0, s1));
   PS_TRY(fork(M, P));
-  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, M->ctl + C_HALT));  // v_i = A z_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, C_HALT));  // v_i = A z_i
   PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, P.maxit, P.tol, 0, M->hist));
   PS_TRY(join(M, P));
   Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
+  s2.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2, pair_grid(M->n), 0, s2));
   PS_TRY(fork(M, P));
-  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, M->ctl + C_HALT));  // t_{i+1} = A w_{i+1}
+  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, C_HALT));  // t_{i+1} = A w_{i+1}
   PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, P.maxit, P.tol, 0,
                                            M->hist));
   PS_TRY(join(M, P));
@@ -525,6 +555,9 @@ int64_t matrix_bytes(const ps_matrix *M) {
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
 bool auto_fused(const ps_matrix *M) { return M->format == PS_FMT_SELL && M->n >= kFusedMinRows; }
 
+// One solve of every system of the handle.  iters, status: int32[nsys];
+// hist: NULL or double[nsys][maxit+1]; b, x0, x: double[n_orig] (the caller's
+// row order), on the device or the host.
 int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, double tol,
                int32_t maxit, int32_t variant, const ps_options *opt, double *x, int32_t *iters,
                double *hist, int32_t *status) {
@@ -534,10 +567,12 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   ps_options o;
   ps_default_options(&o);
   if (opt) o = *opt;
+  const bool batch = M->nsys > 1;
   if (!o.resume && !b) return PS_EINVAL;
   if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
-  if (o.resume && (o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
-  if (o.schedule < -1 || o.schedule > 1 || (o.schedule == 1 && variant != PS_PBICGSAFE))
+  if (o.resume && (batch || o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
+  if (o.schedule < -1 || o.schedule > 1 ||
+      (o.schedule == 1 && (variant != PS_PBICGSAFE || batch)))
     return PS_EINVAL;
   BusyGuard guard(M->busy);
   if (!guard.ok) return PS_EBUSY;
@@ -568,27 +603,52 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool want_overlap = o.overlap > 0 || (o.overlap < 0 && auto_overlap(M));
   P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
-  P.fused = variant == PS_PBICGSAFE && (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
+  P.fused = variant == PS_PBICGSAFE && !batch &&
+            (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
   M->prof_mask = o.profile;
   M->cur_iter = -1;
   M->sweep = 0;
   M->timers.clear();
   M->ev_used = 0;
-  PS_TRY(ensure_hist(M, (int64_t)maxit + 2));
+  M->hist_stride = (int64_t)maxit + 2;
+  PS_TRY(ensure_hist(M, M->hist_stride * M->nsys));
 
-  const size_t vbytes = (size_t)M->n * sizeof(double);
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  PS_TRY(launch(M, P.A, PS_K_OTHER, k_init_ctl, dim3(1), 0, M->ctl, P.i0));
+  PS_TRY(launch(M, P.A, PS_K_OTHER, k_init_ctl, elem_grid((int64_t)M->nsys * C_COUNT + 1), 0,
+                M->ctl, P.i0, M->nsys));
   if (!P.resume) {
-    PS_HIP(hipMemcpyAsync(M->slot(PS_V_B), b, vbytes, kind, P.A));
-    if (x0) PS_HIP(hipMemcpyAsync(M->slot(PS_V_X), x0, vbytes, kind, P.A));
-    else PS_TRY(zero_slots(M, P.A, {PS_V_X}));
+    if (!batch) {
+      const size_t vbytes = (size_t)M->n * sizeof(double);
+      PS_HIP(hipMemcpyAsync(M->slot(PS_V_B), b, vbytes, kind, P.A));
+      if (x0) PS_HIP(hipMemcpyAsync(M->slot(PS_V_X), x0, vbytes, kind, P.A));
+      else PS_TRY(zero_slots(M, P.A, {PS_V_X}));
+    } else {
+      // padded rows keep b = x = 0 (empty rows: they stay zero in every vector)
+      PS_TRY(zero_slots(M, P.A, {PS_V_B, PS_V_X}));
+      const size_t obytes = (size_t)M->n_orig * sizeof(double);
+      const double *src = b;
+      if (!on_device) {
+        PS_HIP(hipMemcpyAsync(M->stage, b, obytes, hipMemcpyHostToDevice, P.A));
+        src = M->stage;
+      }
+      PS_TRY(launch(M, P.A, PS_K_OTHER, k_scatter, elem_grid(M->n_orig), 0, M->slot(PS_V_B), src,
+                    (const int *)M->row_map, M->n_orig));
+      if (x0) {
+        src = x0;
+        if (!on_device) {
+          PS_HIP(hipMemcpyAsync(M->stage, x0, obytes, hipMemcpyHostToDevice, P.A));
+          src = M->stage;
+        }
+        PS_TRY(launch(M, P.A, PS_K_OTHER, k_scatter, elem_grid(M->n_orig), 0, M->slot(PS_V_X),
+                      src, (const int *)M->row_map, M->n_orig));
+      }
+    }
     PS_TRY(enqueue_setup(M, P));
   }
 
   const int last = last_iteration(P);
   const int K = o.batch_iters > 0 ? o.batch_iters : auto_batch(M);
-  int batch = 0;
+  int nbatch = 0;
   bool stopped = false;
   for (int i = P.i0; i <= last && !stopped;) {
     const int end = std::min(last, i + K - 1);
@@ -613,33 +673,57 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
       }
     }
     PS_HIP(hipGetLastError());
-    const int cur = batch & 1;
-    PS_HIP(hipMemcpyAsync(M->pinned + cur * C_COUNT, M->ctl, C_COUNT * sizeof(int),
+    // the count of systems still running, read one batch behind
+    const int cur = nbatch & 1;
+    PS_HIP(hipMemcpyAsync(M->pinned + cur * C_COUNT, M->running(), sizeof(int),
                           hipMemcpyDeviceToHost, P.A));
     PS_HIP(hipEventRecord(M->ev_batch[cur], P.A));
-    if (batch > 0) {
+    if (nbatch > 0) {
       PS_HIP(hipEventSynchronize(M->ev_batch[cur ^ 1]));
-      if (M->pinned[(cur ^ 1) * C_COUNT + C_DONE]) stopped = true;
+      if (M->pinned[(cur ^ 1) * C_COUNT] == 0) stopped = true;
     }
-    ++batch;
+    ++nbatch;
   }
   PS_HIP(hipStreamSynchronize(P.A));
   if (P.overlap) PS_HIP(hipStreamSynchronize(P.B));
 
-  int c[C_COUNT];
-  PS_HIP(hipMemcpy(c, M->ctl, sizeof(c), hipMemcpyDeviceToHost));
-  int st = c[C_STATUS], it = c[C_ITERS];
-  if (!c[C_DONE]) {  // cannot happen: the finish at the last iteration always stops
-    st = PS_MAXIT;
-    it = maxit;
+  std::vector<int> c((size_t)M->nsys * C_COUNT);
+  PS_HIP(hipMemcpy(c.data(), M->ctl, c.size() * sizeof(int), hipMemcpyDeviceToHost));
+  int it_max = 0;
+  for (int k = 0; k < M->nsys; ++k) {
+    const int *ck = c.data() + (size_t)k * C_COUNT;
+    int st = ck[C_STATUS], it = ck[C_ITERS];
+    if (!ck[C_DONE]) {  // cannot happen: the finish at the last iteration always stops
+      st = PS_MAXIT;
+      it = maxit;
+    }
+    iters[k] = it;
+    status[k] = st;
+    it_max = std::max(it_max, it);
   }
-  *iters = it;
-  *status = st;
-  if (hist) PS_HIP(hipMemcpy(hist, M->hist, (size_t)(it + 1) * sizeof(double),
-                             hipMemcpyDeviceToHost));
-  PS_HIP(hipMemcpy(x, M->slot(PS_V_X), vbytes,
-                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
-  if (M->prof_mask) PS_TRY(collect_profile(M, it));
+  if (hist) {
+    if (!batch) {
+      PS_HIP(hipMemcpy(hist, M->hist, (size_t)(iters[0] + 1) * sizeof(double),
+                       hipMemcpyDeviceToHost));
+    } else {
+      PS_HIP(hipMemcpy2D(hist, (size_t)(maxit + 1) * sizeof(double), M->hist,
+                         (size_t)M->hist_stride * sizeof(double), (size_t)(maxit + 1) * sizeof(double),
+                         (size_t)M->nsys, hipMemcpyDeviceToHost));
+    }
+  }
+  if (!batch) {
+    PS_HIP(hipMemcpy(x, M->slot(PS_V_X), (size_t)M->n * sizeof(double),
+                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  } else {
+    double *dst = on_device ? x : M->stage;
+    hipLaunchKernelGGL(k_gather, elem_grid(M->n_orig), dim3(kBlock), 0, P.A, dst,
+                       (const double *)M->slot(PS_V_X), (const int *)M->row_map, M->n_orig);
+    PS_HIP(hipGetLastError());
+    PS_HIP(hipStreamSynchronize(P.A));
+    if (!on_device)
+      PS_HIP(hipMemcpy(x, M->stage, (size_t)M->n_orig * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (M->prof_mask) PS_TRY(collect_profile(M, it_max));
   return PS_OK;
 }
 
@@ -660,6 +744,11 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->ctl);
   (void)hipFree(M->partials);
   (void)hipFree(M->fpart);
+  (void)hipFree(M->chunk_sys);
+  (void)hipFree(M->first_blk);
+  (void)hipFree(M->row_map);
+  (void)hipFree(M->stage);
+  (void)hipFree(M->bpart);
   (void)hipFree(M->hist);
   if (M->pinned) (void)hipHostFree(M->pinned);
   for (hipEvent_t e : M->ev_pool) (void)hipEventDestroy(e);
@@ -673,15 +762,20 @@ void free_matrix(ps_matrix *M) {
 }
 
 // Cut rows into blocks of <= kBlock rows whose nonzeros fit `budget`; a row
-// longer than the budget forms a block of its own.
-std::vector<int> row_blocks(int64_t n, const int64_t *rowptr, int budget) {
+// longer than the budget forms a block of its own.  No block crosses one of
+// the ascending row indices in `cuts` (the systems of a batch).
+std::vector<int> row_blocks(int64_t n, const int64_t *rowptr, int budget,
+                            const std::vector<int64_t> &cuts) {
   std::vector<int> blk;
   blk.push_back(0);
   int64_t r = 0;
+  size_t c = 0;
   while (r < n) {
     const int64_t start = r;
+    while (c < cuts.size() && cuts[c] <= start) ++c;
+    const int64_t limit = c < cuts.size() ? std::min<int64_t>(n, cuts[c]) : n;
     int64_t nz = 0;
-    while (r < n && r - start < kBlock) {
+    while (r < limit && r - start < kBlock) {
       const int64_t len = rowptr[r + 1] - rowptr[r];
       if (nz + len > budget) break;
       nz += len;
@@ -692,6 +786,33 @@ std::vector<int> row_blocks(int64_t n, const int64_t *rowptr, int budget) {
   }
   return blk;
 }
+
+// Host-side description of a batch: the systems' padded starts and the maps
+// built from them (see ps_create_batch).
+struct BatchLayout {
+  int nsys = 1;
+  int64_t n_orig = 0;
+  std::vector<int64_t> pstart;   // [nsys+1] first padded row of each system
+  std::vector<int> row_map;      // [n_orig] padded row of each caller row
+  std::vector<int> chunk_sys;    // [n_pad/256]
+  std::vector<int> first_blk;    // [nsys+1] first 512-row workgroup of each system
+};
+
+// CSR checks shared by the create entry points
+bool valid_csr(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
+                      const double *val) {
+  if (n < 1 || n >= INT32_MAX - 1 || nnz < 0 || nnz >= INT32_MAX || !rowptr) return false;
+  if (nnz > 0 && (!col || !val)) return false;
+  if (rowptr[0] != 0 || rowptr[n] != nnz) return false;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return false;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (col[k] < 0 || col[k] >= n || !std::isfinite(val[k])) return false;
+  return true;
+}
+
+int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                const int32_t *col, const double *val, const BatchLayout *bl);
 
 }  // namespace
 
@@ -719,14 +840,59 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
               const double *val) {
   if (!out) return PS_EINVAL;
   *out = nullptr;
-  if (n < 1 || n >= INT32_MAX - 1 || nnz < 0 || nnz >= INT32_MAX || !rowptr) return PS_EINVAL;
-  if (nnz > 0 && (!col || !val)) return PS_EINVAL;
-  if (rowptr[0] != 0 || rowptr[n] != nnz) return PS_EINVAL;
-  for (int64_t i = 0; i < n; ++i)
-    if (rowptr[i + 1] < rowptr[i]) return PS_EINVAL;
-  for (int64_t k = 0; k < nnz; ++k)
-    if (col[k] < 0 || col[k] >= n || !std::isfinite(val[k])) return PS_EINVAL;
+  if (!valid_csr(n, nnz, rowptr, col, val)) return PS_EINVAL;
+  return create_impl(out, n, nnz, rowptr, col, val, nullptr);
+}
 
+int ps_create_batch(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n, int64_t nnz,
+                    const int64_t *rowptr, const int32_t *col, const double *val) {
+  if (!out) return PS_EINVAL;
+  *out = nullptr;
+  if (nsys < 1 || !sys_ptr || !valid_csr(n, nnz, rowptr, col, val)) return PS_EINVAL;
+  if (sys_ptr[0] != 0 || sys_ptr[nsys] != n) return PS_EINVAL;
+  for (int32_t k = 0; k < nsys; ++k)
+    if (sys_ptr[k + 1] <= sys_ptr[k]) return PS_EINVAL;
+  // every row of a system references columns of that system only
+  for (int32_t k = 0; k < nsys; ++k)
+    for (int64_t r = sys_ptr[k]; r < sys_ptr[k + 1]; ++r)
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+        if (col[e] < sys_ptr[k] || col[e] >= sys_ptr[k + 1]) return PS_EINVAL;
+  if (nsys == 1) return create_impl(out, n, nnz, rowptr, col, val, nullptr);
+  // pad each system to a multiple of 512 rows with empty rows
+  BatchLayout bl;
+  bl.nsys = nsys;
+  bl.n_orig = n;
+  bl.pstart.resize((size_t)nsys + 1, 0);
+  for (int32_t k = 0; k < nsys; ++k)
+    bl.pstart[k + 1] = bl.pstart[k] + (sys_ptr[k + 1] - sys_ptr[k] + 511) / 512 * 512;
+  const int64_t np = bl.pstart[nsys];
+  if (np >= INT32_MAX - 1) return PS_EINVAL;
+  std::vector<int64_t> prow((size_t)np + 1, 0);
+  std::vector<int32_t> pcol((size_t)std::max<int64_t>(nnz, 1));
+  bl.row_map.resize((size_t)n);
+  bl.chunk_sys.resize((size_t)(np / 256));
+  bl.first_blk.resize((size_t)nsys + 1);
+  for (int32_t k = 0; k < nsys; ++k) {
+    const int64_t shift = bl.pstart[k] - sys_ptr[k];
+    for (int64_t r = sys_ptr[k]; r < sys_ptr[k + 1]; ++r) {
+      bl.row_map[r] = (int)(r + shift);
+      prow[r + shift + 1] = rowptr[r + 1] - rowptr[r];
+      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) pcol[e] = (int32_t)(col[e] + shift);
+    }
+    for (int64_t c = bl.pstart[k] / 256; c < bl.pstart[k + 1] / 256; ++c) bl.chunk_sys[c] = k;
+    bl.first_blk[k] = (int)(bl.pstart[k] / 512);
+  }
+  bl.first_blk[nsys] = (int)(np / 512);
+  for (int64_t r = 0; r < np; ++r) prow[r + 1] += prow[r];
+  return create_impl(out, np, nnz, prow.data(), pcol.data(), val, &bl);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                const int32_t *col, const double *val, const BatchLayout *bl) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PS_ENODEV;
   int dev = 0;
@@ -768,7 +934,9 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   std::vector<int> scol, soff;
   std::vector<double> sval;
   if (M->format == PS_FMT_CSR) {
-    blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock);
+    blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock,
+                     bl ? std::vector<int64_t>(bl->pstart.begin() + 1, bl->pstart.end())
+                        : std::vector<int64_t>());
     M->nblk = (int)blk.size() - 1;
     rp32.resize(n + 1);
     for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
@@ -820,8 +988,18 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
     PS_CREATE_HIP(hipMalloc(&M->soff, soff.size() * sizeof(int)));
   }
   PS_CREATE_HIP(hipMalloc(&M->vec, (size_t)kNumSlots * M->ld * sizeof(double)));
-  PS_CREATE_HIP(hipMalloc(&M->sc, SC_COUNT * sizeof(double)));
-  PS_CREATE_HIP(hipMalloc(&M->ctl, C_COUNT * sizeof(int)));
+  const int nsys = bl ? bl->nsys : 1;
+  M->nsys = nsys;
+  M->n_orig = bl ? bl->n_orig : n;
+  PS_CREATE_HIP(hipMalloc(&M->sc, (size_t)nsys * SC_COUNT * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->ctl, ((size_t)nsys + 1) * C_COUNT * sizeof(int)));
+  if (bl) {
+    PS_CREATE_HIP(hipMalloc(&M->chunk_sys, bl->chunk_sys.size() * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->first_blk, bl->first_blk.size() * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->row_map, bl->row_map.size() * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->stage, (size_t)bl->n_orig * sizeof(double)));
+    PS_CREATE_HIP(hipMalloc(&M->bpart, 2 * 9 * (size_t)(n / 512) * sizeof(double)));
+  }
   PS_CREATE_HIP(hipMalloc(&M->partials, 2 * 9 * (size_t)M->dot_grid * sizeof(double)));
   M->ga = (int)pair_grid(n).x;
   M->gfold = (std::max(M->ga, M->nblk) + kBlock - 1) / kBlock;
@@ -839,8 +1017,14 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
       (!csr && slots > 0 && !chk(hipMemcpy(M->sval, sval.data(), slots * sizeof(double), hipMemcpyHostToDevice))) ||
       (!csr && !chk(hipMemcpy(M->soff, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice))) ||
       !chk(hipMemset(M->vec, 0, (size_t)kNumSlots * M->ld * sizeof(double))) ||
-      !chk(hipMemset(M->sc, 0, SC_COUNT * sizeof(double))) ||
-      !chk(hipMemset(M->ctl, 0, C_COUNT * sizeof(int))) ||
+      !chk(hipMemset(M->sc, 0, (size_t)nsys * SC_COUNT * sizeof(double))) ||
+      !chk(hipMemset(M->ctl, 0, ((size_t)nsys + 1) * C_COUNT * sizeof(int))) ||
+      (bl && !chk(hipMemcpy(M->chunk_sys, bl->chunk_sys.data(), bl->chunk_sys.size() * sizeof(int),
+                            hipMemcpyHostToDevice))) ||
+      (bl && !chk(hipMemcpy(M->first_blk, bl->first_blk.data(), bl->first_blk.size() * sizeof(int),
+                            hipMemcpyHostToDevice))) ||
+      (bl && !chk(hipMemcpy(M->row_map, bl->row_map.data(), bl->row_map.size() * sizeof(int),
+                            hipMemcpyHostToDevice))) ||
       !chk(hipStreamCreateWithFlags(&M->own, hipStreamNonBlocking)) ||
       !chk(hipStreamCreateWithFlags(&M->aux, hipStreamNonBlocking)) ||
       !chk(hipEventCreateWithFlags(&M->ev_fork, hipEventDisableTiming)) ||
@@ -853,54 +1037,72 @@ int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, co
   return PS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int ps_solve(ps_matrix *A, const double *b, const double *x0, double tol, int32_t maxit,
              int32_t variant, const ps_options *opt, double *x, int32_t *iters, double *hist,
              int32_t *status) {
+  if (A && A->nsys > 1) return PS_EINVAL;  // batches return per-system results: ps_solve_batch
   return solve_impl(A, b, x0, false, tol, maxit, variant, opt, x, iters, hist, status);
 }
 
 int ps_solve_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol, int32_t maxit,
                  int32_t variant, const ps_options *opt, double *x_dev, int32_t *iters,
                  double *hist, int32_t *status) {
+  if (A && A->nsys > 1) return PS_EINVAL;
+  return solve_impl(A, b_dev, x0_dev, true, tol, maxit, variant, opt, x_dev, iters, hist, status);
+}
+
+int ps_solve_batch(ps_matrix *A, const double *b, const double *x0, double tol, int32_t maxit,
+                   int32_t variant, const ps_options *opt, double *x, int32_t *iters, double *hist,
+                   int32_t *status) {
+  return solve_impl(A, b, x0, false, tol, maxit, variant, opt, x, iters, hist, status);
+}
+
+int ps_solve_batch_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol,
+                       int32_t maxit, int32_t variant, const ps_options *opt, double *x_dev,
+                       int32_t *iters, double *hist, int32_t *status) {
   return solve_impl(A, b_dev, x0_dev, true, tol, maxit, variant, opt, x_dev, iters, hist, status);
 }
 
 int ps_spmv_dev(ps_matrix *A, const double *x_dev, double *y_dev, void *stream) {
-  if (!A || !x_dev || !y_dev) return PS_EINVAL;
+  if (!A || !x_dev || !y_dev || A->nsys > 1) return PS_EINVAL;
   BusyGuard guard(A->busy);
   if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(A->device));
   hipStream_t s = (hipStream_t)stream;
   A->prof_mask = 0;
-  PS_TRY(spmv(A, s, PS_K_SPMV, x_dev, EpiStore{y_dev}, nullptr));
+  PS_TRY(spmv(A, s, PS_K_SPMV, x_dev, EpiStore{y_dev}, -1));
   PS_HIP(hipGetLastError());
   PS_HIP(hipStreamSynchronize(s));
   return PS_OK;
 }
 
 int ps_get_state(ps_matrix *A, int32_t which, double *host_out) {
-  if (!A || !host_out || which < 0 || which >= PS_V_COUNT) return PS_EINVAL;
+  if (!A || !host_out || which < 0 || which >= PS_V_COUNT || A->nsys > 1) return PS_EINVAL;
   PS_HIP(hipSetDevice(A->device));
   PS_HIP(hipMemcpy(host_out, A->slot(which), A->n * sizeof(double), hipMemcpyDeviceToHost));
   return PS_OK;
 }
 
 int ps_set_state(ps_matrix *A, int32_t which, const double *host_in) {
-  if (!A || !host_in || which < 0 || which >= PS_V_COUNT) return PS_EINVAL;
+  if (!A || !host_in || which < 0 || which >= PS_V_COUNT || A->nsys > 1) return PS_EINVAL;
   PS_HIP(hipSetDevice(A->device));
   PS_HIP(hipMemcpy(A->slot(which), host_in, A->n * sizeof(double), hipMemcpyHostToDevice));
   return PS_OK;
 }
 
 int ps_get_scalars(ps_matrix *A, double *host_out) {
-  if (!A || !host_out) return PS_EINVAL;
+  if (!A || !host_out || A->nsys > 1) return PS_EINVAL;
   PS_HIP(hipSetDevice(A->device));
   PS_HIP(hipMemcpy(host_out, A->sc, PS_S_COUNT * sizeof(double), hipMemcpyDeviceToHost));
   return PS_OK;
 }
 
 int ps_set_scalars(ps_matrix *A, const double *host_in) {
-  if (!A || !host_in) return PS_EINVAL;
+  if (!A || !host_in || A->nsys > 1) return PS_EINVAL;
   PS_HIP(hipSetDevice(A->device));
   PS_HIP(hipMemcpy(A->sc, host_in, PS_S_COUNT * sizeof(double), hipMemcpyHostToDevice));
   return PS_OK;
@@ -910,14 +1112,16 @@ int ps_matrix_info(ps_matrix *A, ps_info *info) {
   if (!A || !info) return PS_EINVAL;
   info->format = A->format;
   info->spmv_shape = A->format == PS_FMT_CSR ? A->shape : -1;
-  info->n = A->n;
+  info->n = A->n_orig;
   info->nnz = A->nnz;
   info->slots = A->format == PS_FMT_CSR ? A->nnz : A->slots;
   info->spmv_blocks = A->nblk;
   info->dot_grid = A->dot_grid;
   info->matrix_bytes = matrix_bytes(A);
   info->auto_overlap = auto_overlap(A) ? 1 : 0;
-  info->auto_schedule = auto_fused(A) ? 1 : 0;
+  info->auto_schedule = auto_fused(A) && A->nsys == 1 ? 1 : 0;
+  info->nsys = A->nsys;
+  info->n_padded = A->n;
   return PS_OK;
 }
 

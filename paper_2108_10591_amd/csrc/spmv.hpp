@@ -46,19 +46,24 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // product and their pairs are combined across the group, which keeps lanes
 // busy on long, uneven rows.
 //
-// `stop` (may be null) points at the control word that turns the launch into a
-// no-op: C_DONE for products that follow a finish in stream order, C_HALT for
-// products that may run concurrently with one.  `rev` = 1 walks the row blocks
-// from the last to the first (see sweep_block).
+// `st` names the control word that turns the launch (for a batch: the row
+// block's system) into a no-op: C_DONE for products that follow a finish in
+// stream order, C_HALT for products that may run concurrently with one.  The
+// epilogue reads the scalars of the row block's system.  `rev` = 1 walks the
+// row blocks from the last to the first (see sweep_block).
 //
 // An epilogue with kDots > 0 also accumulates per-row terms of inner products
 // (compensated pairs, see dots.hpp) and writes the block's partial sums for row
 // block b; all lanes of the block take part in that reduction.
 template <int IPT, int LPR, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restrict__ x, Epi epi,
-                                                 const int *__restrict__ stop, int rev) {
-  if (stop != nullptr && *stop) return;
+__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restrict__ x, Epi epi_all,
+                                                 Stop st, int rev) {
   extern __shared__ double prod[];
+  const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
+  const int r0 = A.blk[b], r1 = A.blk[b + 1];
+  const int sys = system_of(st.chunk_sys, r0);
+  if (st.stopped(sys)) return;
+  const Epi epi = epi_all.at(sys);
   constexpr int ND = Epi::kDots;
   DD dacc[ND > 0 ? ND : 1];
 #pragma unroll
@@ -67,8 +72,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
     if constexpr (ND > 0) epi.store(row, ax, in, dacc);
     else epi.store(row, ax, in);
   };
-  const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
-  const int r0 = A.blk[b], r1 = A.blk[b + 1];
   const int r = r0 + threadIdx.x;
   int ra = 0, re = 0;
   typename Epi::In ein{};
@@ -176,14 +179,16 @@ struct SellDev {
 constexpr int kSellUnroll = 8;
 
 template <class Epi>
-__global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__restrict__ x, Epi epi,
-                                                 const int *__restrict__ stop, int rev) {
-  if (stop != nullptr && *stop) return;
+__global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__restrict__ x, Epi epi_all,
+                                                 Stop st, int rev) {
   constexpr int ND = Epi::kDots;
   DD dacc[ND > 0 ? ND : 1];
 #pragma unroll
   for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = DD{0.0, 0.0};
   const int b = sweep_block(xcd_block(blockIdx.x, S.nblk), S.nblk, rev);
+  const int sys = system_of(st.chunk_sys, (int64_t)b * kBlock);
+  if (st.stopped(sys)) return;
+  const Epi epi = epi_all.at(sys);
   const int r = b * kBlock + threadIdx.x;
   if (r < S.n) {
     const typename Epi::In in = epi.load(r);
@@ -231,6 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__rest
 // y = A x
 struct EpiStore {
   static constexpr int kDots = 0;
+  __device__ __forceinline__ EpiStore at(int) const { return *this; }
   double *y;
   struct In {};
   __device__ __forceinline__ In load(int) const { return In{}; }
@@ -241,6 +247,7 @@ struct EpiStore {
 // algorithm, and the true residual of a replacement step (Algorithm 5)
 struct EpiResidual {
   static constexpr int kDots = 0;
+  __device__ __forceinline__ EpiResidual at(int) const { return *this; }
   const double *b;
   double *r;
   double *rs;  // may be null
@@ -261,6 +268,12 @@ struct EpiResidual {
 // A w_i itself is never stored.
 struct EpiPBiCGSafeB {
   static constexpr int kDots = 0;
+  // the scalars of system `sys`
+  __device__ __forceinline__ EpiPBiCGSafeB at(int sys) const {
+    EpiPBiCGSafeB e = *this;
+    e.sc += (size_t)sys * SC_COUNT;
+    return e;
+  }
   const double *q, *As;
   double *l, *g, *s;
   const double *sc;
@@ -283,6 +296,12 @@ struct EpiPBiCGSafeB {
 // x_{i+1} = x_i + alpha p_i + z_i, r_{i+1} = r_i - alpha o_i - y_{i+1}.
 struct EpiSsBiCGSafe2B {
   static constexpr int kDots = 0;
+  // the scalars of system `sys`
+  __device__ __forceinline__ EpiSsBiCGSafe2B at(int sys) const {
+    EpiSsBiCGSafe2B e = *this;
+    e.sc += (size_t)sys * SC_COUNT;
+    return e;
+  }
   const double *s, *u, *p;
   double *t, *z, *y, *x, *r;
   const double *sc;
@@ -311,6 +330,12 @@ struct EpiSsBiCGSafe2B {
 // part: [4][nblk] (hi, lo) pairs.
 struct EpiPBiCGSafeBDots {
   static constexpr int kDots = 4;
+  // the scalars of system `sys`
+  __device__ __forceinline__ EpiPBiCGSafeBDots at(int sys) const {
+    EpiPBiCGSafeBDots e = *this;
+    e.sc += (size_t)sys * SC_COUNT;
+    return e;
+  }
   const double *q, *As;
   double *l, *g, *s;
   const double *y, *r, *rs;

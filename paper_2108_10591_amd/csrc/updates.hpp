@@ -28,15 +28,30 @@ __device__ __forceinline__ void stv(double *__restrict__ p, int64_t k, const dou
   }
 }
 
-// A kernel that follows a reduction phase: if that phase stopped the solve,
-// note it in C_HALT (read by the sparse products of later iterations, which
-// may run concurrently with a finish and so must not read C_DONE) and return.
+// A kernel that follows a reduction phase: if that phase stopped the solve
+// (of the workgroup's system), note it in C_HALT (read by the sparse products
+// of later iterations, which may run concurrently with a finish and so must
+// not read C_DONE) and return.  Every workgroup that sees the stop writes the
+// same value.
 __device__ __forceinline__ bool halted_after_finish(int *ctl) {
   if (ctl[C_DONE]) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[C_HALT] = 1;
+    if (threadIdx.x == 0) ctl[C_HALT] = 1;
     return true;
   }
   return false;
+}
+
+// The arguments with the scalar and control blocks of the system that the
+// workgroup's 512 rows belong to (batched solves; chunk_sys = nullptr: one
+// system).
+template <class Args>
+__device__ __forceinline__ Args bind_system(Args P) {
+  if (P.chunk_sys) {
+    const int sys = P.chunk_sys[2 * sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev)];
+    P.sc += (size_t)sys * SC_COUNT;
+    P.ctl += (size_t)sys * C_COUNT;
+  }
+  return P;
 }
 
 // Entry index of this thread (two entries per thread), blocks taken in the
@@ -77,6 +92,7 @@ struct PassAArgs {
   // b = (y,y), e = (y,r), f = (r0*,r), h = (r0*,t), rho = (r,r)
   const double *rs;
   double *part;
+  const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
 template <int W, bool DOTS>
@@ -133,7 +149,8 @@ __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, DD (&a
 }
 
 template <bool DOTS>
-__global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P) {
+__global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
+  const PassAArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   DD acc[5];
 #pragma unroll
@@ -163,6 +180,7 @@ struct PouArgs {
   int *ctl;
   int64_t n;
   int rev;  // sweep direction
+  const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
 template <int W, bool STORE_O>
@@ -195,12 +213,14 @@ __device__ __forceinline__ void pou_body_o(const PouArgs &P, int64_t k) {
   pou_body<W, true>(P, k);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pu(PouArgs P) {
+__global__ __launch_bounds__(kBlock) void k_pu(PouArgs P_) {
+  const PouArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   PS_DISPATCH_PAIRS(P.n, pou_body_noo);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pou(PouArgs P) {
+__global__ __launch_bounds__(kBlock) void k_pou(PouArgs P_) {
+  const PouArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   PS_DISPATCH_PAIRS(P.n, pou_body_o);
 }
@@ -215,6 +235,7 @@ struct TzyxArgs {
   int *ctl;
   int64_t n;
   int rev;  // sweep direction
+  const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
 template <int W>
@@ -243,7 +264,8 @@ __device__ __forceinline__ void tzyx_body(const TzyxArgs &P, int64_t k) {
   stv<W>(P.x, k, x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_tzyx(TzyxArgs P) {
+__global__ __launch_bounds__(kBlock) void k_tzyx(TzyxArgs P_) {
+  const TzyxArgs P = bind_system(P_);
   if (P.ctl[C_DONE]) return;
   PS_DISPATCH_PAIRS(P.n, tzyx_body);
 }
@@ -259,6 +281,7 @@ struct Stab1Args {
   int *ctl;
   int64_t n;
   int rev;  // sweep direction
+  const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
 template <int W>
@@ -287,7 +310,8 @@ __device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k) {
   stv<W>(P.y, k, y);
 }
 
-__global__ __launch_bounds__(kBlock) void k_stab_pass1(Stab1Args P) {
+__global__ __launch_bounds__(kBlock) void k_stab_pass1(Stab1Args P_) {
+  const Stab1Args P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   PS_DISPATCH_PAIRS(P.n, stab1_body);
 }
@@ -302,6 +326,7 @@ struct Stab2Args {
   int *ctl;
   int64_t n;
   int rev;  // sweep direction
+  const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
 template <int W>
@@ -325,7 +350,8 @@ __device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k) {
   stv<W>(P.w, k, w);
 }
 
-__global__ __launch_bounds__(kBlock) void k_stab_pass2(Stab2Args P) {
+__global__ __launch_bounds__(kBlock) void k_stab_pass2(Stab2Args P_) {
+  const Stab2Args P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   PS_DISPATCH_PAIRS(P.n, stab2_body);
 }
@@ -354,9 +380,31 @@ __global__ __launch_bounds__(kBlock) void k_stream_copy(double2 *__restrict__ ds
     dst[k] = src[k];
 }
 
-__global__ void k_init_ctl(int *ctl, int first_iter) {
-  const int k = threadIdx.x;
-  if (k < C_COUNT) ctl[k] = (k == C_STATUS) ? -1 : (k == C_ITER ? first_iter : 0);
+// control blocks of `nsys` systems, then the count of systems still running
+__global__ __launch_bounds__(kBlock) void k_init_ctl(int *ctl, int first_iter, int nsys) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t words = (int64_t)nsys * C_COUNT;
+  if (k < words) {
+    const int w = (int)(k % C_COUNT);
+    ctl[k] = (w == C_STATUS) ? -1 : (w == C_ITER ? first_iter : 0);
+  } else if (k == words) {
+    ctl[k] = nsys;
+  }
+}
+
+// batched solves: dst[map[i]] = src[i] (map: row i of the caller's
+// concatenation -> its padded row), and the inverse gather
+__global__ __launch_bounds__(kBlock) void k_scatter(double *__restrict__ dst,
+                                                    const double *__restrict__ src,
+                                                    const int *__restrict__ map, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) dst[map[k]] = src[k];
+}
+__global__ __launch_bounds__(kBlock) void k_gather(double *__restrict__ dst,
+                                                   const double *__restrict__ src,
+                                                   const int *__restrict__ map, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) dst[k] = src[map[k]];
 }
 
 }  // namespace ps

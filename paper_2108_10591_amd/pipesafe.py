@@ -42,7 +42,8 @@ class Info(ctypes.Structure):
     _fields_ = [("format", ctypes.c_int32), ("spmv_shape", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("nnz", ctypes.c_int64), ("slots", ctypes.c_int64), ("spmv_blocks", ctypes.c_int32),
                 ("dot_grid", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
-                ("auto_overlap", ctypes.c_int32), ("auto_schedule", ctypes.c_int32)]
+                ("auto_overlap", ctypes.c_int32), ("auto_schedule", ctypes.c_int32),
+                ("nsys", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_padded", ctypes.c_int64)]
 
 
 FORMATS = {0: "csr", 1: "sell"}
@@ -63,6 +64,9 @@ def _lib():
         L.ps_create.argtypes = [ctypes.POINTER(P), i64, i64, P, P, P]
         L.ps_solve.argtypes = [P, P, P, f64, i32, i32, ctypes.POINTER(Options), P, Pi32, P, Pi32]
         L.ps_solve_dev.argtypes = L.ps_solve.argtypes
+        L.ps_create_batch.argtypes = [ctypes.POINTER(P), i32, P, i64, i64, P, P, P]
+        L.ps_solve_batch.argtypes = [P, P, P, f64, i32, i32, ctypes.POINTER(Options), P, P, P, P]
+        L.ps_solve_batch_dev.argtypes = L.ps_solve_batch.argtypes
         L.ps_spmv_dev.argtypes = [P, P, P, P]
         L.ps_get_state.argtypes = [P, i32, P]
         L.ps_set_state.argtypes = [P, i32, P]
@@ -75,7 +79,8 @@ def _lib():
         L.ps_strerror.argtypes = [ctypes.c_int]
         L.ps_strerror.restype = ctypes.c_char_p
         L.ps_version.restype = ctypes.c_char_p
-        for name in ("ps_create", "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
+        for name in ("ps_create", "ps_create_batch", "ps_solve_batch", "ps_solve_batch_dev",
+                     "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
                      "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats", "ps_matrix_info",
                      "ps_stream_copy", "ps_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -251,6 +256,78 @@ class Matrix:
                    "ps_kernel_stats")
             out[name] = (ms.value, cnt.value)
         return out
+
+
+@dataclass
+class BatchResult:
+    x: object                 # concatenated solutions (numpy or torch, like the inputs)
+    iters: np.ndarray         # int32[nsys]
+    status: np.ndarray        # int32[nsys]
+    hist: np.ndarray | None   # [nsys, maxit+1]; row k valid up to iters[k]
+
+    def system_hist(self, k: int) -> np.ndarray:
+        return self.hist[k, : int(self.iters[k]) + 1]
+
+
+class BatchMatrix(Matrix):
+    """Independent systems solved together (ps_create_batch / ps_solve_batch)."""
+
+    def __init__(self, sys_ptr, n: int, rowptr, col, val):
+        sys_ptr = np.ascontiguousarray(sys_ptr, dtype=np.int64)
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        self.n = int(n)
+        self.nnz = int(rowptr[-1]) if rowptr.size else 0
+        self.nsys = int(sys_ptr.size - 1)
+        self.sys_ptr = sys_ptr
+        h = ctypes.c_void_p()
+        _check(_lib().ps_create_batch(ctypes.byref(h), self.nsys, _ptr(sys_ptr), self.n, self.nnz,
+                                      _ptr(rowptr), _ptr(col), _ptr(val)), "ps_create_batch")
+        self._h = h
+
+    @classmethod
+    def from_batch(cls, B) -> "BatchMatrix":
+        """From a workloads.Batch (its block-diagonal concatenation)."""
+        C = B.concat()
+        return cls(B.sys_ptr(), C.n, C.rowptr, C.col, C.val)
+
+    def solve(self, b, x0=None, tol=1e-8, maxit=10_000, variant="pbicgsafe", hist=True, **opt):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        x = np.empty(self.n)
+        h = np.empty((self.nsys, maxit + 1)) if hist else None
+        iters = np.zeros(self.nsys, dtype=np.int32)
+        status = np.zeros(self.nsys, dtype=np.int32)
+        o = options(**opt)
+        _check(_lib().ps_solve_batch(self._h, _ptr(b), None if x0a is None else _ptr(x0a),
+                                     float(tol), int(maxit), _vid(variant), ctypes.byref(o), _ptr(x),
+                                     _ptr(iters), None if h is None else _ptr(h), _ptr(status)),
+               "ps_solve_batch")
+        return BatchResult(x, iters, status, h)
+
+    def solve_dev(self, b, x0=None, x=None, tol=1e-8, maxit=10_000, variant="pbicgsafe",
+                  hist=True, stream=None, **opt):
+        import torch
+        for t in (b, x0, x):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != self.n):
+                raise ValueError("expected contiguous float64 CUDA tensors of length n")
+        if x is None:
+            x = torch.empty(self.n, dtype=torch.float64, device=b.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(b.device).cuda_stream
+        h = np.empty((self.nsys, maxit + 1)) if hist else None
+        iters = np.zeros(self.nsys, dtype=np.int32)
+        status = np.zeros(self.nsys, dtype=np.int32)
+        o = options(stream=stream, **opt)
+        _check(_lib().ps_solve_batch_dev(self._h, ctypes.c_void_p(b.data_ptr()),
+                                         None if x0 is None else ctypes.c_void_p(x0.data_ptr()),
+                                         float(tol), int(maxit), _vid(variant), ctypes.byref(o),
+                                         ctypes.c_void_p(x.data_ptr()), _ptr(iters),
+                                         None if h is None else _ptr(h), _ptr(status)),
+               "ps_solve_batch_dev")
+        return BatchResult(x, iters, status, h)
 
 
 def stream_copy(dst, src, stream=None):

@@ -272,6 +272,57 @@ def random_csr(n: int, seed: int, lengths=None, unsorted: bool = False, duplicat
 
 
 # ----------------------------------------------------------------------------
+# Batches of independent systems
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Batch:
+    """Independent systems A_k x_k = b_k, solved together."""
+    systems: list
+    name: str = ""
+
+    @property
+    def nsys(self) -> int:
+        return len(self.systems)
+
+    def sys_ptr(self) -> np.ndarray:
+        """int64[nsys+1]: first row of each system in the concatenation."""
+        p = np.zeros(self.nsys + 1, dtype=np.int64)
+        np.cumsum([A.n for A in self.systems], out=p[1:])
+        return p
+
+    def concat(self) -> CSR:
+        """The block-diagonal matrix of all systems (global column indices) and the
+        concatenated right-hand sides."""
+        ptr = self.sys_ptr()
+        rowptr = [np.zeros(1, dtype=np.int64)]
+        off = 0
+        for A in self.systems:
+            rowptr.append(A.rowptr[1:] + off)
+            off += A.nnz
+        col = np.concatenate([A.col.astype(np.int64) + ptr[k] for k, A in enumerate(self.systems)])
+        return CSR(int(ptr[-1]), np.concatenate(rowptr), col.astype(np.int32),
+                   np.concatenate([A.val for A in self.systems]),
+                   np.concatenate([A.b for A in self.systems]), self.name)
+
+
+def cd2d_batch(nsys: int = 512, seed: int = 3, nmin: int = 32, nmax: int = 256,
+               beta_max: float = 50.0, sigma: float = 0.5) -> Batch:
+    """``nsys`` 2D upwind convection-diffusion systems: grid side N uniform in
+    [nmin, nmax], convection (beta, beta) with beta ~ U(0, beta_max), diffusion
+    exp(N(0, sigma^2)) per node; b = A*1 for each."""
+    rng = np.random.default_rng(seed)
+    systems = []
+    for k in range(nsys):
+        N = int(rng.integers(nmin, nmax + 1))
+        beta = float(rng.uniform(0.0, beta_max))
+        kf = np.exp(sigma * rng.standard_normal((N, N)))
+        A = convection_diffusion(N, (beta, beta), kf, name=f"cd2d_{N}_{k}")
+        systems.append(A)
+    return Batch(systems, f"cd2d_batch_{nsys}")
+
+
+# ----------------------------------------------------------------------------
 # Named workloads
 # ----------------------------------------------------------------------------
 
@@ -283,6 +334,18 @@ WORKLOADS = {
     # random power-law rows in [3, 200] (mean 27), band +-5000, n = 1M, seed 10591, tol 1e-10
     "rand_band_1m": dict(tol=1e-10, make=lambda: rand_band(1_000_000, 10591)),
 }
+
+
+BATCHES = {
+    # 512 systems, N ~ U[32, 256], beta ~ U(0, 50), diffusion exp(N(0, 0.5^2)), tol 1e-8
+    "cd2d_batch_512": dict(tol=1e-8, make=lambda: cd2d_batch(512, 3)),
+}
+
+
+@functools.lru_cache(maxsize=2)
+def batch(name: str) -> Batch:
+    """Build (and cache per process) one of the named batches."""
+    return BATCHES[name]["make"]()
 
 
 @functools.lru_cache(maxsize=4)

@@ -29,7 +29,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["ps_create", "ps_solve", "ps_solve_dev", "ps_destroy", "ps_strerror",
-                     "ps_default_options", "ps_spmv_dev"]:
+                     "ps_default_options", "ps_spmv_dev", "ps_create_batch", "ps_solve_batch",
+                     "ps_solve_batch_dev", "ps_matrix_info"]:
         assert required in names
 
 
@@ -49,7 +50,7 @@ def test_options_defaults_and_strerror(lib):
     assert (o.rr_m, o.rr_M, o.norm_ref, o.batch_iters, o.overlap, o.profile, o.resume, o.graph,
             o.schedule) == (100, 0, 0, 0, -1, 0, 0, 1, -1)
     assert ctypes.sizeof(pipesafe.Options) == 48
-    assert ctypes.sizeof(pipesafe.Info) == 56
+    assert ctypes.sizeof(pipesafe.Info) == 72
     pipesafe.library().ps_strerror.restype = ctypes.c_char_p
     for code in (0, 1, 2, 3, -1, -2, -3, -4, -5):
         assert pipesafe.library().ps_strerror(code)
@@ -103,3 +104,31 @@ def test_solve_rejects_null_handle(lib):
                     None, ctypes.byref(st))
     assert rc == -1
     assert L.ps_destroy(None) == 0
+
+
+@pytest.mark.parametrize("case", ["sys_ptr_start", "sys_ptr_end", "empty_system", "cross_system_col",
+                                  "no_systems"])
+def test_create_batch_rejects_invalid_layout_before_touching_the_device(lib, case):
+    from paper_2108_10591_amd import pipesafe
+    L = pipesafe.library()
+    # two 2x2 diagonal systems
+    rowptr = np.array([0, 1, 2, 3, 4], dtype=np.int64)
+    col = np.array([0, 1, 2, 3], dtype=np.int32)
+    val = np.ones(4)
+    sys_ptr = np.array([0, 2, 4], dtype=np.int64)
+    nsys = 2
+    if case == "sys_ptr_start":
+        sys_ptr = np.array([1, 2, 4], dtype=np.int64)
+    elif case == "sys_ptr_end":
+        sys_ptr = np.array([0, 2, 3], dtype=np.int64)
+    elif case == "empty_system":
+        sys_ptr = np.array([0, 2, 2, 4], dtype=np.int64)
+        nsys = 3
+    elif case == "cross_system_col":
+        col = np.array([0, 2, 2, 3], dtype=np.int32)  # row 1 (system 0) references column 2
+    elif case == "no_systems":
+        nsys = 0
+    h = ctypes.c_void_p()
+    rc = L.ps_create_batch(ctypes.byref(h), nsys, sys_ptr.ctypes.data, 4, 4, rowptr.ctypes.data,
+                           col.ctypes.data, val.ctypes.data)
+    assert rc == -1 and not h.value
