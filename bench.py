@@ -54,26 +54,27 @@ def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
     """Algorithmic HBM bytes of one iteration of the implemented schedule (FP64 vectors,
     each vector entry read or written once per kernel that needs it, x-gather once).
 
-    p-BiCGSafe:  A s (M+16n) + 9 dots (40n) + pass A (168n) + A w with l, g, s (M+64n)
+    p-BiCGSafe:  A s (M+16n) + 9 dots (40n) + pass A (160n: 12 reads, 8 writes; q_i stays in
+                 registers) + A w with q, l, g, s (M+64n)
     ssBiCGSafe2: A r (M+16n) + 9 dots (40n) + p, u (64n) + A u with t, z, y, x, r (M+104n)
     p-BiCGStab:  pass 1 (96n) + A z (M+16n) + 2 dots (16n) + pass 2 (72n) + A w (M+16n)
                  + 5 dots (40n)
     (p-BiCGSafe-rr is counted as p-BiCGSafe; its replacement steps add ~1% at m = 100.)
-    p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (176n) + A w with l, g, s
+    p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (168n) + A w with q, l, g, s
                  and y, r, r0* (M+88n)
     """
     M = matrix_bytes(n, nnz, info)
     if variant == "pbicgsafe" and schedule == 1:
-        return 2 * M + 280 * n
-    return {"pbicgsafe": 2 * M + 288 * n, "pbicgsafe_rr": 2 * M + 288 * n,
+        return 2 * M + 272 * n
+    return {"pbicgsafe": 2 * M + 280 * n, "pbicgsafe_rr": 2 * M + 280 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
 
 
 def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
     M = matrix_bytes(n, nnz, info)
     if schedule == 1:
-        return {"spmv": M + 16 * n, "update": 176 * n, "spmv_fused": M + 88 * n}[cls]
-    return {"spmv": M + 16 * n, "dots": 40 * n, "update": 168 * n, "spmv_fused": M + 64 * n}[cls]
+        return {"spmv": M + 16 * n, "update": 168 * n, "spmv_fused": M + 88 * n}[cls]
+    return {"spmv": M + 16 * n, "dots": 40 * n, "update": 160 * n, "spmv_fused": M + 64 * n}[cls]
 
 
 def source_digest():
@@ -109,6 +110,65 @@ def cpu_baseline(A, iters, variant="pbicgsafe", info=None):
                       f"{dt:.2f} s, single-threaded C, FP64; {res.iters / dt:.2f} iterations/s"}
 
 
+def bench_batch(name, reps=3):
+    """The batched-systems workload: solves/s of one batched solve of every system, and
+    of the same systems solved one after another with single-system handles."""
+    import numpy as np
+    import torch
+
+    from paper_2108_10591_amd import pipesafe, workloads
+    B = workloads.batch(name)
+    tol = workloads.BATCHES[name]["tol"]
+    C = B.concat()
+    log(f"batch {name}: {B.nsys} systems, n = {C.n}, nnz = {C.nnz}")
+    b = torch.from_numpy(C.b).cuda()
+    x = torch.empty_like(b)
+    with pipesafe.BatchMatrix.from_batch(B) as M:
+        info = M.info()
+        r = M.solve_dev(b, None, x, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = M.solve_dev(b, None, x, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / reps
+    assert np.all(r.status == pipesafe.CONVERGED), r.status
+    # algorithmic bytes: each system's own iterations at its CSR byte model
+    gb = sum(int(r.iters[k]) * bytes_per_iteration("pbicgsafe", A.n, A.nnz) / 1e9
+             for k, A in enumerate(B.systems))
+    log(f"  batched: {1e3 * t_batch:.1f} ms, {B.nsys / t_batch:.0f} solves/s, "
+        f"iterations {int(r.iters.min())}..{int(r.iters.max())}")
+    # one after another (handles created and warmed up outside the timed region)
+    mats, bs, xs = [], [], []
+    for A in B.systems:
+        mats.append(pipesafe.Matrix.from_csr(A))
+        bs.append(torch.from_numpy(A.b).cuda())
+        xs.append(torch.empty_like(bs[-1]))
+    for M1, b1, x1 in zip(mats, bs, xs):
+        M1.solve_dev(b1, None, x1, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_seq = []
+    for M1, b1, x1 in zip(mats, bs, xs):
+        it_seq.append(M1.solve_dev(b1, None, x1, tol=tol, maxit=10_000, variant="pbicgsafe",
+                                   hist=False).iters)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for M1 in mats:
+        M1.close()
+    assert it_seq == [int(i) for i in r.iters]
+    log(f"  one at a time: {1e3 * t_seq:.1f} ms, {B.nsys / t_seq:.0f} solves/s")
+    return {"workload": name, "systems": B.nsys, "rows": C.n, "nnz": C.nnz, "tol": tol,
+            "variant": "pbicgsafe", "layout": info["format"],
+            "iterations_min_mean_max": [int(r.iters.min()), round(float(r.iters.mean()), 1),
+                                        int(r.iters.max())],
+            "time_ms": round(1e3 * t_batch, 2), "solves_per_s": round(B.nsys / t_batch, 1),
+            "GBps": round(gb / t_batch, 1),
+            "one_at_a_time": {"time_ms": round(1e3 * t_seq, 2),
+                              "solves_per_s": round(B.nsys / t_seq, 1)},
+            "speedup": round(t_seq / t_batch, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +178,7 @@ def main():
     ap.add_argument("--variant", default="pbicgsafe")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
     ap.add_argument("--schedule", type=int, default=-1,
@@ -265,6 +326,9 @@ def main():
                       "us_per_iter": round(1e3 * ms / max(rv.iters, 1), 2), "GBps": round(gbps, 1)}
             log(f"{v}: {var[v]}")
         out["variants"] = var
+
+    if not args.no_batch:
+        out["batched"] = bench_batch("cd2d_batch_512")
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_iters} iterations ...")

@@ -152,7 +152,9 @@ enum ps_kernel {
 
 /* state vectors, for ps_get_state / ps_set_state (names follow Algorithms 3-5;
    for PS_PBICGSTAB: s = A p, z = A s, w = A r, t = A w, v = A z, q = r - alpha s,
-   y = A q).  Each is double[n]. */
+   y = A q).  Each is double[n].  p-BiCGSafe keeps q_i and o_i in registers (q_i
+   is formed in pass A and again in the epilogue of A w_i), so their slots hold
+   values only after a replacement step (A o_i, o_i) or in the other variants. */
 enum ps_vec {
   PS_V_X = 0, PS_V_R, PS_V_RS /* r0* */, PS_V_S, PS_V_Y, PS_V_T, PS_V_P, PS_V_U, PS_V_Z,
   PS_V_W, PS_V_L, PS_V_G, PS_V_Q, PS_V_O, PS_V_AS, PS_V_V, PS_V_B, PS_V_COUNT

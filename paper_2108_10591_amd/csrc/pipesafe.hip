@@ -371,20 +371,20 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
     else PS_TRY(iter_safe_dots(M, P, P.B, i));
     PS_TRY(join(M, P));
     if (!P.fused) {
-      PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
+      PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                    nullptr, nullptr};
       pa.chunk_sys = M->chunk_sys;
       PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false>, pair_grid(M->n), 0, pa));
-      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{Q, As, L, G, S, M->sc}, C_DONE));
+      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{As, L, G, S, M->sc}, C_DONE));
       return PS_OK;
     }
     double *pa_part = M->fpart, *pb_part = pa_part + 2 * 5 * (size_t)M->ga;
-    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, Q, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
+    PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                  M->slot(PS_V_RS), pa_part};
     pa.chunk_sys = M->chunk_sys;
     PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true>, pair_grid(M->n), 0, pa));
     PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
-                EpiPBiCGSafeBDots{Q, As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part}, C_DONE));
+                EpiPBiCGSafeBDots{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part}, C_DONE));
     return PS_OK;
   }
   // replacement step (Algorithm 5): true values of q, w, r, l, g, s

@@ -264,8 +264,9 @@ struct EpiResidual {
 
 // p-BiCGSafe, the product A w_i and the three recurrences that follow it in
 // Algorithm 4: l_i = q_i - A w_i (Eq. (l)), g_{i+1} = zeta A s_i + eta g_i -
-// alpha A w_i (Eq. (g)), s_{i+1} = s_i - alpha q_i - g_{i+1} (Eq. (sip1)).
-// A w_i itself is never stored.
+// alpha A w_i (Eq. (g)), s_{i+1} = s_i - alpha q_i - g_{i+1} (Eq. (sip1)),
+// with q_i = As_i + beta l_{i-1} (Eq. (q)) formed here from the old l, as in
+// pass A, instead of being stored there.  A w_i itself is never stored.
 struct EpiPBiCGSafeB {
   static constexpr int kDots = 0;
   // the scalars of system `sys`
@@ -274,19 +275,20 @@ struct EpiPBiCGSafeB {
     e.sc += (size_t)sys * SC_COUNT;
     return e;
   }
-  const double *q, *As;
+  const double *As;
   double *l, *g, *s;
   const double *sc;
   struct In {
-    double q, As, g, s;
+    double l, As, g, s;
   };
-  __device__ __forceinline__ In load(int r) const { return In{q[r], As[r], g[r], s[r]}; }
+  __device__ __forceinline__ In load(int r) const { return In{l[r], As[r], g[r], s[r]}; }
   __device__ __forceinline__ void store(int r, double aw, const In &in) const {
-    const double al = sc[PS_S_ALPHA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
-    l[r] = in.q - aw;
+    const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
+    const double q = in.As + be * in.l;
+    l[r] = q - aw;
     const double gn = ze * in.As + et * in.g - al * aw;
     g[r] = gn;
-    s[r] = in.s - al * in.q - gn;
+    s[r] = in.s - al * q - gn;
   }
 };
 
@@ -336,23 +338,24 @@ struct EpiPBiCGSafeBDots {
     e.sc += (size_t)sys * SC_COUNT;
     return e;
   }
-  const double *q, *As;
+  const double *As;
   double *l, *g, *s;
   const double *y, *r, *rs;
   const double *sc;
   double *part;
   struct In {
-    double q, As, g, s, y, r, rs;
+    double l, As, g, s, y, r, rs;
   };
   __device__ __forceinline__ In load(int k) const {
-    return In{q[k], As[k], g[k], s[k], y[k], r[k], rs[k]};
+    return In{l[k], As[k], g[k], s[k], y[k], r[k], rs[k]};
   }
   __device__ __forceinline__ void store(int k, double aw, const In &in, DD (&acc)[4]) const {
-    const double al = sc[PS_S_ALPHA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
-    l[k] = in.q - aw;
+    const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
+    const double q = in.As + be * in.l;
+    l[k] = q - aw;
     const double gn = ze * in.As + et * in.g - al * aw;
     g[k] = gn;
-    const double sn = in.s - al * in.q - gn;
+    const double sn = in.s - al * q - gn;
     s[k] = sn;
     dd_fma(acc[0], sn, sn);
     dd_fma(acc[1], sn, in.y);

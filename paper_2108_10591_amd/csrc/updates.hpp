@@ -79,9 +79,10 @@ __device__ __forceinline__ int64_t pair_index(int rev) {
 //   t_i = o_i - w_i                              z_i = zeta r_i + eta z_{i-1} - alpha u_i
 //   y_{i+1} = zeta s_i + eta y_i - alpha w_i     x_{i+1} = x_i + alpha p_i + z_i
 //   r_{i+1} = r_i - alpha o_i - y_{i+1}
-// o_i stays in registers.
+// o_i and q_i stay in registers: the epilogue of A w_i forms q_i again from
+// the same operands (As_i, l_{i-1}), which it reads anyway.
 struct PassAArgs {
-  double *x, *r, *p, *u, *t, *y, *z, *w, *q;
+  double *x, *r, *p, *u, *t, *y, *z, *w;
   const double *s, *As, *l, *g;
   const double *sc;
   int *ctl;
@@ -139,7 +140,6 @@ __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, DD (&a
   }
   stv<W>(P.p, k, p);
   stv<W>(P.u, k, u);
-  stv<W>(P.q, k, q);
   stv<W>(P.w, k, w);
   stv<W>(P.t, k, t);
   stv<W>(P.z, k, z);

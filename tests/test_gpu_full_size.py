@@ -93,7 +93,7 @@ def test_one_iteration_full_size(case, k):
     assert res.status == O.MAXIT and res.iters == k + 1
     B = bounds.Bounds(A, st, st1)
     coef, E = bounds.safe_family(B, variant, k, False)
-    for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q"]:
+    for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g"]:  # q_i is transient
         got, ref = M.get_state(v), st1.vec(v)
         assert np.all(np.abs(got - ref) <= 4.0 * E[v]), (name, k, v)
         assert np.array_equal(got, ref), (name, k, v)  # compensated inner products: exact
