@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpipesafe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["pipesafe.hip"]
+SOURCES = ["pipesafe.hip", "wsnet.hip"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
