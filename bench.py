@@ -169,6 +169,22 @@ def bench_batch(name, reps=3):
             "speedup": round(t_seq / t_batch, 2)}
 
 
+def bench_warmstart(count, epochs):
+    """The learned initial guess on 128 x 128 variable-coefficient problems: training data
+    solved on the GPU, the network trained on the GPU, then 64 held-out problems solved to
+    1e-10 ||b|| by p-BiCGSafe-rr from x0 = 0 and from the prediction."""
+    from paper_2108_10591_amd import warmstart
+    log(f"warm start: {count} training problems, {epochs} epochs ...")
+    m = warmstart.train(N=128, count=count, epochs=epochs, lr=1e-3, seed=1, verbose=log)
+    r = warmstart.evaluate(m, N=128, count=64, seed=2)
+    log(f"  {r}")
+    r.update({"train_problems": count, "train_samples_kept": m.samples, "epochs": epochs,
+              "params": m.net.num_params, "train_s": round(m.train_seconds, 2),
+              "data": m.data, "loss_first_last": [float(m.loss_hist[0]), float(m.loss_hist[-1])]})
+    m.net.close()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +195,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
+    ap.add_argument("--no-warmstart", action="store_true", help="skip the learned-initial-guess leg")
+    ap.add_argument("--warmstart-count", type=int, default=4096,
+                    help="training problems of the learned-initial-guess leg (20000 for the full run)")
+    ap.add_argument("--warmstart-epochs", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
     ap.add_argument("--schedule", type=int, default=-1,
@@ -329,6 +349,9 @@ def main():
 
     if not args.no_batch:
         out["batched"] = bench_batch("cd2d_batch_512")
+
+    if not args.no_warmstart:
+        out["warm_start"] = bench_warmstart(args.warmstart_count, args.warmstart_epochs)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_iters} iterations ...")

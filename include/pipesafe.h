@@ -105,6 +105,10 @@ typedef struct {
                           the coefficients remain, concurrent with A s_{i+1}.  Reads
                           32n bytes more and skips the 40n-byte pass.  Results are
                           bit-identical to schedule 0.  Other variants: 1 is PS_EINVAL.  */
+  int32_t x0_fallback; /* 1: if x0 is given and ||b - A x0|| > ||b|| (or is not finite),
+                          start from x0 = 0 instead (per system for a batch); a guess
+                          that is worse than zero costs nothing then.  0 (default): use
+                          x0 as given.                                                 */
   void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
                           caller's current stream).  NULL: ps_solve_dev uses the null
                           stream, ps_solve the library's own stream.                   */

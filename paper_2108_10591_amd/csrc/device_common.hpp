@@ -26,7 +26,8 @@ enum Ctl : int {
 
 // double scalar block on the device: the public ps_scalar slots, then private ones
 enum Sc : int {
-  SC_DOTS = 16,   // raw inner products of the last reduction phase (up to 9)
+  SC_DOTS = 16,      // raw inner products of the last reduction phase (up to 9)
+  SC_FALLBACK = 30,  // 1: the initial guess was worse than zero and has been replaced
   SC_COUNT = 32
 };
 

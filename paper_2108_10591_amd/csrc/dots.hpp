@@ -105,6 +105,16 @@ struct ProdStab3 {
   }
 };
 
+// (r0, r0) and (b, b) of an initial guess x0 (inputs v = {r0, b})
+struct ProdFallback {
+  static constexpr unsigned MASK = 0b11u;
+  static constexpr int ND = 2;
+  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
+    dd_fma(a[0], in[0], in[0]);
+    dd_fma(a[1], in[1], in[1]);
+  }
+};
+
 // (v, v): the squared norm of b for the ||b|| stop-test scale
 struct ProdNorm {
   static constexpr unsigned MASK = 0b1u;
@@ -282,6 +292,14 @@ struct FinStabSetup {
     }
     if (stop_test(rho, sc, A.ctl, A.hist, 0, A.maxit, A.tol)) return;
     if (pend) set_stop(A.ctl, PS_BREAKDOWN, 0);
+  }
+};
+
+// Keep an initial guess only if ||b - A x0|| <= ||b|| (a non-finite residual
+// does not qualify); otherwise the set-up continues from x0 = 0.
+struct FinFallback {
+  __device__ static void run(const DotArgs &A, const double (&d)[2]) {
+    A.sc[SC_FALLBACK] = (d[0] <= d[1]) ? 0.0 : 1.0;
   }
 };
 

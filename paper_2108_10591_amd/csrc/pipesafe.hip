@@ -277,7 +277,8 @@ struct Plan {
   int i0;
   hipStream_t A, B;
   bool overlap;
-  bool fused;  // fused-dot schedule (p-BiCGSafe)
+  bool fused;     // fused-dot schedule (p-BiCGSafe)
+  bool fallback;  // replace an initial guess that is worse than zero
 };
 
 // r_0 = b - A x_0, r0* = r_0 and the zero vectors of each algorithm (x_0 and b
@@ -294,6 +295,11 @@ int enqueue_setup(ps_matrix *M, const Plan &P) {
                              PS_V_Q, PS_V_O, PS_V_AS, PS_V_V}));
   }
   PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, -1));
+  if (P.fallback) {
+    PS_TRY(dots<ProdFallback, FinFallback>(M, s, {R, Bv}, P.maxit, P.tol, 0, M->hist));
+    PS_TRY(launch(M, s, PS_K_OTHER, k_fallback, elem_grid(M->n), 0, X, R, RS, (const double *)Bv,
+                  (const double *)M->sc, (const int *)M->chunk_sys, M->n));
+  }
   if (P.variant == PS_PBICGSAFE || P.variant == PS_PBICGSAFE_RR) {
     // s_0 = A r_0 (its definition s_i := A r_i; Algorithm 4 uses s_0 without forming it)
     PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, -1));
@@ -603,6 +609,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool want_overlap = o.overlap > 0 || (o.overlap < 0 && auto_overlap(M));
   P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
+  P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
   P.fused = variant == PS_PBICGSAFE && !batch &&
             (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
   M->prof_mask = o.profile;
@@ -833,6 +840,7 @@ void ps_default_options(ps_options *opt) {
   opt->resume_iter = 0;
   opt->graph = 1;
   opt->schedule = -1;
+  opt->x0_fallback = 0;
   opt->stream = nullptr;
 }
 

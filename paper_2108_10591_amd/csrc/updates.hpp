@@ -380,6 +380,21 @@ __global__ __launch_bounds__(kBlock) void k_stream_copy(double2 *__restrict__ ds
     dst[k] = src[k];
 }
 
+// x0 fallback: where the system's guess was rejected, x = 0 and r = r0* = b
+__global__ __launch_bounds__(kBlock) void k_fallback(double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ rs, const double *__restrict__ b,
+                                                     const double *__restrict__ sc,
+                                                     const int *__restrict__ chunk_sys, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int sys = system_of(chunk_sys, k);
+  if (sc[(size_t)sys * SC_COUNT + SC_FALLBACK] != 0.0) {
+    x[k] = 0.0;
+    r[k] = b[k];
+    rs[k] = b[k];
+  }
+}
+
 // control blocks of `nsys` systems, then the count of systems still running
 __global__ __launch_bounds__(kBlock) void k_init_ctl(int *ctl, int first_iter, int nsys) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;

@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
                 ("batch_iters", ctypes.c_int32), ("overlap", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("resume", ctypes.c_int32),
                 ("resume_iter", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("schedule", ctypes.c_int32), ("x0_fallback", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):

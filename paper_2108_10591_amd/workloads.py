@@ -322,6 +322,52 @@ def cd2d_batch(nsys: int = 512, seed: int = 3, nmin: int = 32, nmax: int = 256,
     return Batch(systems, f"cd2d_batch_{nsys}")
 
 
+def grf(count: int, N: int, corr_len: float, rng) -> np.ndarray:
+    """``count`` Gaussian random fields on the N x N interior nodes of the unit
+    square (spacing 1/(N+1)): zero mean, unit variance, covariance
+    exp(-d^2 / (2 corr_len^2)).  White noise filtered with the square root of
+    that covariance's spectral density, exp(-2 pi^2 corr_len^2 |f|^2), on a
+    periodic grid twice as large, of which one quarter is kept (so that the
+    wrap-around does not couple opposite edges)."""
+    M = 2 * N
+    f = np.fft.fftfreq(M, d=1.0 / (N + 1))
+    FX, FY = np.meshgrid(f, f, indexing="ij")
+    dens = np.exp(-2.0 * np.pi ** 2 * corr_len ** 2 * (FX ** 2 + FY ** 2))
+    amp = np.sqrt(dens)
+    out = np.empty((count, N, N))
+    for c0 in range(0, count, 128):
+        m = min(128, count - c0)
+        z = rng.standard_normal((m, M, M))
+        out[c0:c0 + m] = np.fft.ifft2(np.fft.fft2(z) * amp).real[:, :N, :N]
+    return out / np.sqrt(dens.sum() / M ** 2)
+
+
+def varcoef_problems(count: int, N: int = 128, seed: int = 0, corr_len: float = 0.1,
+                     vmax: float = 30.0):
+    """Variable-coefficient 2D convection-diffusion problems for the learned
+    initial guess: diffusion exp(g) with g a unit-variance Gaussian random field
+    of correlation length ``corr_len``, convection v = U(0, vmax) (cos t, sin t)
+    with t ~ U(0, 2 pi), unit source (b = h^2 per row, the rows being scaled by
+    h^2).  Returns the Batch and the network input per problem,
+    float32[count, N, N, 3] = (g, v_x / vmax, v_y / vmax) at every node."""
+    rng = np.random.default_rng(seed)
+    g = grf(count, N, corr_len, rng)
+    speed = rng.uniform(0.0, vmax, count)
+    theta = rng.uniform(0.0, 2.0 * np.pi, count)
+    vx, vy = speed * np.cos(theta), speed * np.sin(theta)
+    h2 = 1.0 / (N + 1) ** 2
+    systems = []
+    for k in range(count):
+        A = convection_diffusion(N, (vx[k], vy[k]), np.exp(g[k]), name=f"varcoef_{N}_{k}")
+        A.b = np.full(A.n, h2)
+        systems.append(A)
+    feats = np.empty((count, N, N, 3), dtype=np.float32)
+    feats[..., 0] = g
+    feats[..., 1] = (vx / vmax)[:, None, None]
+    feats[..., 2] = (vy / vmax)[:, None, None]
+    return Batch(systems, f"varcoef_{N}_{count}_{seed}"), feats
+
+
 # ----------------------------------------------------------------------------
 # Named workloads
 # ----------------------------------------------------------------------------

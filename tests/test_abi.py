@@ -48,8 +48,8 @@ def test_options_defaults_and_strerror(lib):
     from paper_2108_10591_amd import pipesafe
     o = pipesafe.options()
     assert (o.rr_m, o.rr_M, o.norm_ref, o.batch_iters, o.overlap, o.profile, o.resume, o.graph,
-            o.schedule) == (100, 0, 0, 0, -1, 0, 0, 1, -1)
-    assert ctypes.sizeof(pipesafe.Options) == 48
+            o.schedule, o.x0_fallback) == (100, 0, 0, 0, -1, 0, 0, 1, -1, 0)
+    assert ctypes.sizeof(pipesafe.Options) == 56
     assert ctypes.sizeof(pipesafe.Info) == 72
     pipesafe.library().ps_strerror.restype = ctypes.c_char_p
     for code in (0, 1, 2, 3, -1, -2, -3, -4, -5):
