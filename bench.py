@@ -32,9 +32,19 @@ sys.path.insert(0, ROOT)
 METRIC = "HBM GB/s per pipelined iteration; time-to-1e-8 residual vs plain FP64"
 PEAK_GBPS = 8000.0
 CLASSES = ["spmv", "dots", "update", "spmv_fused", "other"]
-KERNEL_NAMES = {"spmv": "k_spmv<EpiStore> (A s_i)", "dots": "k_dots<ProdSafe9, FinSafe>",
-                "update": "k_passA_pbicgsafe", "spmv_fused": "k_spmv<EpiPBiCGSafeB> (A w_i + l, g, s)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cd3d_128.json")
+
+
+def kernel_name(cls, layout, schedule):
+    """The kernel a class means for this layout and schedule (as rocprofv3 names it, shortened)."""
+    k = "k_sell" if layout == "sell" else "k_spmv"
+    if schedule == 1:
+        return {"spmv": f"{k}<EpiStore> (A s_i)",
+                "update": "k_passA_pbicgsafe<true> (pass A + 5 partial inner products)",
+                "spmv_fused": f"{k}<EpiPBiCGSafeBDots> (A w_i + q, l, g, s + 4 partial inner products)"}[cls]
+    return {"spmv": f"{k}<EpiStore> (A s_i)", "dots": "k_dots<ProdSafe9<false>> (9 inner products)",
+            "update": "k_passA_pbicgsafe<false> (pass A)",
+            "spmv_fused": f"{k}<EpiPBiCGSafeB> (A w_i + q, l, g, s)"}[cls]
 
 
 def log(*a):
@@ -77,10 +87,15 @@ def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 160 * n, "spmv_fused": M + 64 * n}[cls]
 
 
+SOLVER_SOURCES = ["device_common.hpp", "dots.hpp", "pipesafe.hip", "spmv.hpp", "updates.hpp"]
+
+
 def source_digest():
+    """SHA-256 prefix of the solver's sources (kernels and launch code); recorded traffic is
+    used only while it matches."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2108_10591_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in SOLVER_SOURCES:
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -307,8 +322,7 @@ def main():
     traffic = load_traffic(dominant, args.workload, sched) if variant == "pbicgsafe" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": KERNEL_NAMES[dominant].replace("k_spmv", "k_sell" if info["format"] == "sell"
-                                                         else "k_spmv"), "bytes_per_launch": bpl,
+                "kernel": kernel_name(dominant, info["format"], sched), "bytes_per_launch": bpl,
                 "avg_launch_us": round(avg_us, 3), "launches": kcnt,
                 "measured_over": f"{args.steps} profiled solves ({ms_profiled:.1f} ms each)"}
 

@@ -22,6 +22,7 @@
 //     A t, A y, A r (A s_i, unused there, is skipped).
 //   p-BiCGStab: pass 1; [A z_i || (q,y),(y,y) + omega]; pass 2;
 //     [A w_{i+1} || 5 inner products + stop test + beta, alpha].
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -172,22 +173,22 @@ int next_event(ps_matrix *M, hipEvent_t *ev) {
   return PS_OK;
 }
 
-// Launch `kernel` on `s`, bracketed by timing events when class `cls` is profiled.
+// Launch `kernel` on `s`; when class `cls` is profiled, the runtime records a
+// pair of events at the start and the end of the kernel's execution itself
+// (hipExtLaunchKernelGGL), so the timing excludes the dispatch around it.
 template <typename Kernel, typename... Args>
 int launch(ps_matrix *M, hipStream_t s, int cls, Kernel kernel, dim3 grid, size_t shmem,
            Args... args) {
   if (grid.x == 0) return PS_OK;
   const bool prof = (M->prof_mask >> cls) & 1;
+  if (!prof) {
+    hipLaunchKernelGGL(kernel, grid, dim3(kBlock), shmem, s, args...);
+    return PS_OK;
+  }
   hipEvent_t a = nullptr, b = nullptr;
-  if (prof) {
-    if (next_event(M, &a) || next_event(M, &b)) return PS_EHIP;
-    PS_HIP(hipEventRecord(a, s));
-  }
-  hipLaunchKernelGGL(kernel, grid, dim3(kBlock), shmem, s, args...);
-  if (prof) {
-    PS_HIP(hipEventRecord(b, s));
-    M->timers.push_back(Timer{a, b, cls, M->cur_iter});
-  }
+  if (next_event(M, &a) || next_event(M, &b)) return PS_EHIP;
+  hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), (uint32_t)shmem, s, a, b, 0u, args...);
+  M->timers.push_back(Timer{a, b, cls, M->cur_iter});
   return PS_OK;
 }
 
