@@ -193,9 +193,11 @@ void ps_default_options(ps_options *opt);
  * not be sorted; duplicate (row, col) entries are summed; empty rows are
  * allowed (they make A singular).  The device layout (ps_format) and the
  * product's launch shape are chosen here from the row lengths; the
- * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SPMV_SHAPE
- * (0..4) and PIPESAFE_DOT_GRID (1..8192 workgroups) override the choices, for
- * tuning and tests.  Every choice gives the same results.
+ * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SELL_RPL
+ * (rows per lane of the sliced layout: 1, the default, or 2 with 128-row
+ * slices), PIPESAFE_SPMV_SHAPE (0..4) and PIPESAFE_DOT_GRID (1..8192
+ * workgroups) override the choices, for tuning and tests.  Every choice gives
+ * the same results.
  */
 int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
               const double *val);

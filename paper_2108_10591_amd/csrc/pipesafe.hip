@@ -56,6 +56,7 @@ constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 constexpr int64_t kOverlapMinBytes = 128ll << 20;
 constexpr int64_t kFusedMinRows = 1 << 18;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
+constexpr int kSellRowsPerLane = 1;       // 64-row slices
 
 struct Timer {
   hipEvent_t a, b;
@@ -95,6 +96,7 @@ struct ps_matrix {
   double *sval = nullptr;
   int64_t slots = 0;
   int nslice = 0;
+  int sell_rpl = 1;                      // rows per lane of the sliced layout (1 or 2)
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -222,8 +224,11 @@ template <class Epi>
 int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, int stop_word) {
   const int rev = next_rev(M);
   const Stop stop{M->ctl, stop_word, M->chunk_sys};
-  if (M->format == PS_FMT_SELL)
-    return launch(M, s, cls, k_sell<Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
+  if (M->format == PS_FMT_SELL) {
+    if (M->sell_rpl == 2)
+      return launch(M, s, cls, k_sell<2, Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
+    return launch(M, s, cls, k_sell<1, Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
+  }
   switch (M->shape) {
     case 0: return spmv_launch<4, 1>(M, s, cls, x, epi, stop, rev);
     case 1: return spmv_launch<8, 1>(M, s, cls, x, epi, stop, rev);
@@ -513,12 +518,15 @@ int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **
 // Iterations past this index are never needed: the finish at the last one stops.
 int last_iteration(const Plan &P) { return P.variant == PS_PBICGSTAB ? P.maxit - 1 : P.maxit; }
 
+// Iterations per host check (and per cached graph).  Measured: longer batches
+// spread the graph launch and the check over more iterations, but the check
+// runs one batch behind, so up to two batches of no-op iterations follow the
+// stop; 16 was best for the 2M-row systems (~165 us per iteration), 8 for
+// small ones (~25 us per iteration).
 int auto_batch(const ps_matrix *M) {
-  // keep a batch around 1.5 ms of device time
   const double bytes = 24.0 * (double)M->nnz + 300.0 * (double)M->n;
-  const double us = bytes / 4.0e6 + 30.0;
-  int k = (int)(1500.0 / us);
-  return std::max(2, std::min(64, k));
+  const double us = bytes / 5.0e6 + 20.0;  // rough time of one iteration
+  return us >= 100.0 ? 16 : 8;
 }
 
 int ensure_hist(ps_matrix *M, int64_t need) {
@@ -925,15 +933,21 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   }
   static const int kIpt[] = {4, 8, 16, 16, 16};
   // sliced ELLPACK when padding every slice to its longest row costs little
-  const int64_t nslice = (n + kWave - 1) / kWave;
+  M->sell_rpl = kSellRowsPerLane;
+  if (const char *e = std::getenv("PIPESAFE_SELL_RPL")) {  // tuning override
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2) M->sell_rpl = v;
+  }
+  const int64_t SH = (int64_t)kWave * M->sell_rpl;  // rows per slice
+  const int64_t nslice = (n + SH - 1) / SH;
   int64_t slots = 0;
   for (int64_t sl = 0; sl < nslice; ++sl) {
     int64_t w = 0;
-    for (int64_t r = sl * kWave; r < std::min<int64_t>(n, (sl + 1) * kWave); ++r)
+    for (int64_t r = sl * SH; r < std::min<int64_t>(n, (sl + 1) * SH); ++r)
       w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
-    slots += w * kWave;
+    slots += w * SH;
   }
-  M->format = (double)slots <= kSellMaxPadding * (double)nnz + kWave ? PS_FMT_SELL : PS_FMT_CSR;
+  M->format = (double)slots <= kSellMaxPadding * (double)nnz + SH ? PS_FMT_SELL : PS_FMT_CSR;
   if (const char *e = std::getenv("PIPESAFE_FORMAT")) {  // tuning override
     const int v = std::atoi(e);
     if (v == PS_FMT_CSR || v == PS_FMT_SELL) M->format = v;
@@ -952,21 +966,21 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   } else {
     M->nslice = (int)nslice;
     M->slots = slots;
-    M->nblk = (int)((n + kBlock - 1) / kBlock);
+    M->nblk = (int)((n + kBlock * M->sell_rpl - 1) / (kBlock * M->sell_rpl));
     scol.assign((size_t)slots, -1);
     sval.assign((size_t)slots, 0.0);
     soff.assign((size_t)nslice + 1, 0);
     for (int64_t sl = 0; sl < nslice; ++sl) {
       int64_t w = 0;
-      for (int64_t r = sl * kWave; r < std::min<int64_t>(n, (sl + 1) * kWave); ++r)
+      for (int64_t r = sl * SH; r < std::min<int64_t>(n, (sl + 1) * SH); ++r)
         w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
-      soff[sl + 1] = (int)(soff[sl] + w * kWave);
+      soff[sl + 1] = (int)(soff[sl] + w * SH);
     }
     for (int64_t r = 0; r < n; ++r) {
-      const int64_t base = soff[r / kWave] + r % kWave;
+      const int64_t base = soff[r / SH] + r % SH;
       for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
-        scol[base + (k - rowptr[r]) * kWave] = col[k];
-        sval[base + (k - rowptr[r]) * kWave] = val[k];
+        scol[base + (k - rowptr[r]) * SH] = col[k];
+        sval[base + (k - rowptr[r]) * SH] = val[k];
       }
     }
   }

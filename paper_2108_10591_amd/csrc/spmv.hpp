@@ -161,63 +161,99 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
 }
 
 // Sliced ELLPACK form of the same matrix, for matrices whose rows have nearly
-// equal lengths (stencils): rows are cut into slices of kWave consecutive rows;
-// slice s holds its rows' nonzeros column by column, width w_s = its longest
-// row, so entry j of the row in lane l sits at off[s] + j * kWave + l.  Each
-// row keeps its CSR order; shorter rows are padded with col = -1, which is
-// skipped.  One lane per row: the column/value loads and the gather of x are
-// contiguous across the lanes of a wave, and no LDS staging is needed.
+// equal lengths (stencils): rows are cut into slices of SH = 64 * RPL
+// consecutive rows (one wavefront, RPL rows per lane); slice s holds its
+// rows' nonzeros column by column, width w_s = its longest row, so entry j of
+// row q of the slice sits at off[s] + j * SH + q.  Each row keeps its CSR
+// order; shorter rows are padded with col = -1, which is skipped.  The
+// column/value loads (RPL consecutive entries per lane: one 8- or 16-byte
+// load) and the gather of x are contiguous across the lanes of a wave, and no
+// LDS staging is needed.
 struct SellDev {
   const int *col;     // int32[slots], -1 = padding
   const double *val;  // double[slots]
   const int *off;     // int32[nslice+1] first slot of each slice
   int n;
-  int nblk;           // ceil(n / kBlock) workgroups
+  int nblk;           // ceil(n / (kBlock * RPL)) workgroups
 };
 
-// Entries of a row loaded ahead of their gathers per step.
+// Slots per row loaded ahead of their gathers per step.
 constexpr int kSellUnroll = 8;
 
-template <class Epi>
+template <int RPL>
+__device__ __forceinline__ void sell_load(const SellDev &S, int kk, int (&c)[RPL], double (&v)[RPL]) {
+  if constexpr (RPL == 2) {
+    const int2 cc = *reinterpret_cast<const int2 *>(S.col + kk);
+    const double2 vv = *reinterpret_cast<const double2 *>(S.val + kk);
+    c[0] = cc.x;
+    c[1] = cc.y;
+    v[0] = vv.x;
+    v[1] = vv.y;
+  } else {
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      c[u] = S.col[kk + u];
+      v[u] = S.val[kk + u];
+    }
+  }
+}
+
+template <int RPL, class Epi>
 __global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__restrict__ x, Epi epi_all,
                                                  Stop st, int rev) {
   constexpr int ND = Epi::kDots;
+  constexpr int SH = kWave * RPL;
   DD dacc[ND > 0 ? ND : 1];
 #pragma unroll
   for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = DD{0.0, 0.0};
   const int b = sweep_block(xcd_block(blockIdx.x, S.nblk), S.nblk, rev);
-  const int sys = system_of(st.chunk_sys, (int64_t)b * kBlock);
+  const int sys = system_of(st.chunk_sys, (int64_t)b * kBlock * RPL);
   if (st.stopped(sys)) return;
   const Epi epi = epi_all.at(sys);
-  const int r = b * kBlock + threadIdx.x;
-  if (r < S.n) {
-    const typename Epi::In in = epi.load(r);
-    const int sl = r / kWave, lane = r % kWave;
+  const int lane = threadIdx.x % kWave;
+  const int sl = b * kWavesPerBlock + threadIdx.x / kWave;
+  const int r0 = sl * SH + lane * RPL;  // the lane's first row
+  if (r0 < S.n) {
+    typename Epi::In in[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+      if (r0 + u < S.n) in[u] = epi.load(r0 + u);
     const int end = S.off[sl + 1];
-    DD acc{0.0, 0.0};
-    for (int k = S.off[sl] + lane; k < end; k += kSellUnroll * kWave) {
-      int c[kSellUnroll];
-      double v[kSellUnroll];
+    DD acc[RPL];
 #pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) {
-        const int kk = k + u * kWave;
-        c[u] = -1;
-        v[u] = 0.0;
-        if (kk < end) {
-          c[u] = S.col[kk];
-          v[u] = S.val[kk];
+    for (int u = 0; u < RPL; ++u) acc[u] = DD{0.0, 0.0};
+    for (int k = S.off[sl] + lane * RPL; k < end; k += kSellUnroll * SH) {
+      int c[kSellUnroll][RPL];
+      double v[kSellUnroll][RPL];
+#pragma unroll
+      for (int t = 0; t < kSellUnroll; ++t) {
+        const int kk = k + t * SH;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          c[t][u] = -1;
+          v[t][u] = 0.0;
         }
+        if (kk < end) sell_load<RPL>(S, kk, c[t], v[t]);
       }
-      // unconditional gathers (padding reads x[0]): all kSellUnroll in flight at once
-      double xv[kSellUnroll];
+      // unconditional gathers (padding reads x[0]): all of them in flight at once
+      double xv[kSellUnroll][RPL];
 #pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) xv[u] = x[c[u] < 0 ? 0 : c[u]];
+      for (int t = 0; t < kSellUnroll; ++t)
 #pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u)
-        if (c[u] >= 0) sum_acc(acc, v[u] * xv[u]);
+        for (int u = 0; u < RPL; ++u) xv[t][u] = x[c[t][u] < 0 ? 0 : c[t][u]];
+#pragma unroll
+      for (int t = 0; t < kSellUnroll; ++t)
+#pragma unroll
+        for (int u = 0; u < RPL; ++u)
+          if (c[t][u] >= 0) sum_acc(acc[u], v[t][u] * xv[t][u]);
     }
-    if constexpr (ND > 0) epi.store(r, acc.hi + acc.lo, in, dacc);
-    else epi.store(r, acc.hi + acc.lo, in);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      if (r0 + u < S.n) {
+        if constexpr (ND > 0) epi.store(r0 + u, acc[u].hi + acc[u].lo, in[u], dacc);
+        else epi.store(r0 + u, acc[u].hi + acc[u].lo, in[u]);
+      }
+    }
   }
   if constexpr (ND > 0) {
     __shared__ double red[kWavesPerBlock * ND * 2];

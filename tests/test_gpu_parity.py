@@ -77,19 +77,23 @@ def _spmv_matrix(case):
 
 @contextlib.contextmanager
 def device_format(fmt):
-    """Force the device layout ps_create picks (PIPESAFE_FORMAT: 0 CSR, 1 sliced ELLPACK)."""
-    old = os.environ.get("PIPESAFE_FORMAT")
-    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "sell": "1"}[fmt]
+    """Force the device layout ps_create picks (PIPESAFE_FORMAT: 0 CSR, 1 sliced ELLPACK;
+    "sell2": sliced with two rows per lane, PIPESAFE_SELL_RPL=2)."""
+    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SELL_RPL")
+    old = {k: os.environ.get(k) for k in keys}
+    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "sell": "1", "sell2": "1"}[fmt]
+    os.environ["PIPESAFE_SELL_RPL"] = "2" if fmt == "sell2" else "1"
     try:
         yield
     finally:
-        if old is None:
-            del os.environ["PIPESAFE_FORMAT"]
-        else:
-            os.environ["PIPESAFE_FORMAT"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("fmt", ["csr", "sell", "sell2"])
 @pytest.mark.parametrize("case", sorted(SPMV_CASES))
 def test_spmv_matches_oracle(case, fmt):
     import torch
@@ -98,7 +102,7 @@ def test_spmv_matches_oracle(case, fmt):
     x = np.random.default_rng(7).standard_normal(A.n)
     ref = O.spmv(A, x)
     with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
-        assert M.info()["format"] == fmt
+        assert M.info()["format"] == fmt.rstrip("2")
         y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     # every row, long ones included: both sides round each product, carry the
     # row's sum with two-sum accumulators and round once, so any order of the
@@ -197,13 +201,15 @@ def test_both_layouts_reproduce_oracle(variant):
     """Each matrix in the layout ps_create would not pick for it: the same bits."""
     for name, A, fmt in [("cd2d_64", W.workload("cd2d_64"), "csr"),
                          ("cd3d_16", W.cd3d(16, 20.0, seed=1), "csr"),
+                         ("cd3d_16", W.cd3d(16, 20.0, seed=1), "sell2"),
                          ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), "sell"),
                          ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell"),
+                         ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell2"),
                          ("cd2d_5", W.cd2d(5, 10.0), "sell")]:
         say(f"layout {fmt} {name} {variant}")
         ref = O.solve(A, tol=1e-10, maxit=3000, variant=variant, rr_m=25)
         with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
-            assert M.info()["format"] == fmt
+            assert M.info()["format"] == fmt.rstrip("2")
             res = M.solve(A.b, tol=1e-10, maxit=3000, variant=variant, rr_m=25)
         assert res.status == ref.status and res.iters == ref.iters, (name, res.iters, ref.iters)
         assert np.array_equal(res.hist, ref.hist) and np.array_equal(res.x, ref.x), name
