@@ -35,16 +35,18 @@ CLASSES = ["spmv", "dots", "update", "spmv_fused", "other"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cd3d_128.json")
 
 
-def kernel_name(cls, layout, schedule):
-    """The kernel a class means for this layout and schedule (as rocprofv3 names it, shortened)."""
+def kernel_name(cls, layout, schedule, streaming=0):
+    """The kernel a class means for this layout, schedule and streaming choice (as rocprofv3
+    names it, shortened)."""
     k = "k_sell" if layout == "sell" else "k_spmv"
+    nt = "true" if streaming else "false"
     if schedule == 1:
         return {"spmv": f"{k}<EpiStore> (A s_i)",
-                "update": "k_passA_pbicgsafe<true> (pass A + 5 partial inner products)",
-                "spmv_fused": f"{k}<EpiPBiCGSafeBDots> (A w_i + q, l, g, s + 4 partial inner products)"}[cls]
+                "update": f"k_passA_pbicgsafe<true, {nt}> (pass A + 5 partial inner products)",
+                "spmv_fused": f"{k}<EpiPBiCGSafeBDots<{nt}>> (A w_i + l, g, s + 4 partial inner products)"}[cls]
     return {"spmv": f"{k}<EpiStore> (A s_i)", "dots": "k_dots<ProdSafe9<false>> (9 inner products)",
-            "update": "k_passA_pbicgsafe<false> (pass A)",
-            "spmv_fused": f"{k}<EpiPBiCGSafeB> (A w_i + q, l, g, s)"}[cls]
+            "update": f"k_passA_pbicgsafe<false, {nt}> (pass A)",
+            "spmv_fused": f"{k}<EpiPBiCGSafeB> (A w_i + l, g, s)"}[cls]
 
 
 def log(*a):
@@ -322,7 +324,8 @@ def main():
     traffic = load_traffic(dominant, args.workload, sched) if variant == "pbicgsafe" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": kernel_name(dominant, info["format"], sched), "bytes_per_launch": bpl,
+                "kernel": kernel_name(dominant, info["format"], sched,
+                                      info["streaming"] if variant == "pbicgsafe" else 0), "bytes_per_launch": bpl,
                 "avg_launch_us": round(avg_us, 3), "launches": kcnt,
                 "measured_over": f"{args.steps} profiled solves ({ms_profiled:.1f} ms each)"}
 

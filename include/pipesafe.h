@@ -138,7 +138,11 @@ typedef struct {
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe    */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
-  int32_t reserved;
+  int32_t streaming;     /* 1: p-BiCGSafe's update passes load and store the vectors that
+                            no kernel reads before the next iteration with streaming
+                            (nontemporal) hints -- when an iteration moves at least
+                            512 MiB (two products plus 272 bytes per row), or as
+                            PIPESAFE_STREAM=0|1 sets; the results are the same       */
   int64_t n_padded;      /* rows on the device: n, or for a batch the systems padded to
                             multiples of 512 rows                                      */
 } ps_info;
@@ -195,8 +199,9 @@ void ps_default_options(ps_options *opt);
  * product's launch shape are chosen here from the row lengths; the
  * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SELL_RPL
  * (rows per lane of the sliced layout: 1, the default, or 2 with 128-row
- * slices), PIPESAFE_SPMV_SHAPE (0..4) and PIPESAFE_DOT_GRID (1..8192
- * workgroups) override the choices, for tuning and tests.  Every choice gives
+ * slices), PIPESAFE_SPMV_SHAPE (0..4), PIPESAFE_DOT_GRID (1..8192
+ * workgroups) and PIPESAFE_STREAM (0 or 1, ps_info.streaming) override the
+ * choices, for tuning and tests.  Every choice gives
  * the same results.
  */
 int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,

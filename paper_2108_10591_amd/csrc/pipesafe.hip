@@ -55,6 +55,11 @@ constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 // extra reads in its epilogue.
 constexpr int64_t kOverlapMinBytes = 128ll << 20;
 constexpr int64_t kFusedMinRows = 1 << 18;
+// p-BiCGSafe's update passes stream the vectors they do not hand to the next
+// kernel past the cache once an iteration moves at least kStreamMinBytes (well
+// above the 256 MiB last-level cache; below it the cache still holds part of
+// the previous iteration's vectors and the hint costs a little).
+constexpr int64_t kStreamMinBytes = 512ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 constexpr int kSellRowsPerLane = 1;       // 64-row slices
 
@@ -97,6 +102,7 @@ struct ps_matrix {
   int64_t slots = 0;
   int nslice = 0;
   int sell_rpl = 1;                      // rows per lane of the sliced layout (1 or 2)
+  int stream_override = -1;              // streaming update passes: -1 automatic, 0, 1
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -285,6 +291,7 @@ struct Plan {
   bool overlap;
   bool fused;     // fused-dot schedule (p-BiCGSafe)
   bool fallback;  // replace an initial guess that is worse than zero
+  bool stream_nt; // streaming (nontemporal) loads and stores in the update passes
 };
 
 // r_0 = b - A x_0, r0* = r_0 and the zero vectors of each algorithm (x_0 and b
@@ -386,7 +393,10 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
       PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                    nullptr, nullptr};
       pa.chunk_sys = M->chunk_sys;
-      PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false>, pair_grid(M->n), 0, pa));
+      PS_TRY(P.stream_nt
+                 ? launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, true>, pair_grid(M->n), 0, pa)
+                 : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, false>, pair_grid(M->n), 0,
+                          pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{As, L, G, S, M->sc}, C_DONE));
       return PS_OK;
     }
@@ -394,9 +404,17 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
     PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                  M->slot(PS_V_RS), pa_part};
     pa.chunk_sys = M->chunk_sys;
-    PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true>, pair_grid(M->n), 0, pa));
-    PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
-                EpiPBiCGSafeBDots{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part}, C_DONE));
+    if (P.stream_nt) {
+      PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, true>, pair_grid(M->n), 0, pa));
+      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                  EpiPBiCGSafeBDots<true>{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part},
+                  C_DONE));
+    } else {
+      PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, false>, pair_grid(M->n), 0, pa));
+      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                  EpiPBiCGSafeBDots<false>{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part},
+                  C_DONE));
+    }
     return PS_OK;
   }
   // replacement step (Algorithm 5): true values of q, w, r, l, g, s
@@ -480,7 +498,8 @@ void clear_graphs(ps_matrix *M) {
 // current sweep phase, captured from the launch sequence on first use.
 int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **out) {
   const GraphKey key{P.variant, P.maxit,   P.rr_m,           P.rr_M, P.overlap ? 1 : 0,
-                     count,     M->sweep,  P.fused ? 1 : 0, P.tol,  P.A};
+                     count,     M->sweep,  (P.fused ? 1 : 0) | (P.stream_nt ? 2 : 0),
+                     P.tol,     P.A};
   for (GraphEntry &g : M->graphs)
     if (g.key == key) {
       *out = &g;
@@ -569,6 +588,11 @@ int64_t matrix_bytes(const ps_matrix *M) {
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
 bool auto_fused(const ps_matrix *M) { return M->format == PS_FMT_SELL && M->n >= kFusedMinRows; }
+// two sparse products and the update passes' 34 vector reads and writes
+bool streaming(const ps_matrix *M) {
+  if (M->stream_override >= 0) return M->stream_override != 0;
+  return 2 * matrix_bytes(M) + 272 * M->n >= kStreamMinBytes;
+}
 
 // One solve of every system of the handle.  iters, status: int32[nsys];
 // hist: NULL or double[nsys][maxit+1]; b, x0, x: double[n_orig] (the caller's
@@ -621,6 +645,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
   P.fused = variant == PS_PBICGSAFE && !batch &&
             (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
+  P.stream_nt = variant == PS_PBICGSAFE && streaming(M);
   M->prof_mask = o.profile;
   M->cur_iter = -1;
   M->sweep = 0;
@@ -991,6 +1016,9 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     if (v >= 1 && v <= 8192) max_dot_grid = v;
   }
   M->dot_grid = (int)std::max<int64_t>(1, std::min<int64_t>(max_dot_grid, (n / 2 + kBlock - 1) / kBlock));
+  if (const char *e = std::getenv("PIPESAFE_STREAM")) {  // tuning override: 0 or 1
+    if (e[0] == '0' || e[0] == '1') M->stream_override = e[0] - '0';
+  }
 
   auto fail = [&](int code) {
     free_matrix(M);
@@ -1144,6 +1172,7 @@ int ps_matrix_info(ps_matrix *A, ps_info *info) {
   info->auto_overlap = auto_overlap(A) ? 1 : 0;
   info->auto_schedule = auto_fused(A) && A->nsys == 1 ? 1 : 0;
   info->nsys = A->nsys;
+  info->streaming = streaming(A) ? 1 : 0;
   info->n_padded = A->n;
   return PS_OK;
 }

@@ -365,7 +365,9 @@ struct EpiSsBiCGSafe2B {
 // EpiPBiCGSafeB, plus the partial sums of the four inner products of the next
 // iteration that involve s_{i+1}: a = (s,s), c = (s,y), d = (s,r), g = (r0*,s),
 // with y_{i+1} and r_{i+1} from the pass A that precedes this product.
-// part: [4][nblk] (hi, lo) pairs.
+// part: [4][nblk] (hi, lo) pairs.  NT: l and g (next read by the next pass A)
+// and As (dead after this product) stream past the cache.
+template <bool NT>
 struct EpiPBiCGSafeBDots {
   static constexpr int kDots = 4;
   // the scalars of system `sys`
@@ -383,14 +385,24 @@ struct EpiPBiCGSafeBDots {
     double l, As, g, s, y, r, rs;
   };
   __device__ __forceinline__ In load(int k) const {
-    return In{l[k], As[k], g[k], s[k], y[k], r[k], rs[k]};
+    if constexpr (NT)
+      return In{__builtin_nontemporal_load(l + k), __builtin_nontemporal_load(As + k),
+                __builtin_nontemporal_load(g + k), s[k], y[k], r[k], rs[k]};
+    else
+      return In{l[k], As[k], g[k], s[k], y[k], r[k], rs[k]};
   }
   __device__ __forceinline__ void store(int k, double aw, const In &in, DD (&acc)[4]) const {
     const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
     const double q = in.As + be * in.l;
-    l[k] = q - aw;
+    const double ln = q - aw;
     const double gn = ze * in.As + et * in.g - al * aw;
-    g[k] = gn;
+    if constexpr (NT) {
+      __builtin_nontemporal_store(ln, l + k);
+      __builtin_nontemporal_store(gn, g + k);
+    } else {
+      l[k] = ln;
+      g[k] = gn;
+    }
     const double sn = in.s - al * q - gn;
     s[k] = sn;
     dd_fma(acc[0], sn, sn);

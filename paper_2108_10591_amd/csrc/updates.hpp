@@ -28,6 +28,37 @@ __device__ __forceinline__ void stv(double *__restrict__ p, int64_t k, const dou
   }
 }
 
+// Streaming (nontemporal) forms, for vectors that no kernel reads again before
+// the next iteration's pass: on systems whose iteration traffic is well above
+// the last-level cache, keeping their lines only evicts the ones that are
+// read again soon (the matrix, the SpMV inputs, the epilogue's operands).
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <int W, bool NT>
+__device__ __forceinline__ void ldv_s(const double *__restrict__ p, int64_t k, double (&o)[W]) {
+  if constexpr (!NT) {
+    ldv<W>(p, k, o);
+  } else if constexpr (W == 2) {
+    const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p + k));
+    o[0] = v.x;
+    o[1] = v.y;
+  } else {
+    o[0] = __builtin_nontemporal_load(p + k);
+  }
+}
+
+template <int W, bool NT>
+__device__ __forceinline__ void stv_s(double *__restrict__ p, int64_t k, const double (&o)[W]) {
+  if constexpr (!NT) {
+    stv<W>(p, k, o);
+  } else if constexpr (W == 2) {
+    const d2v v = {o[0], o[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<d2v *>(p + k));
+  } else {
+    __builtin_nontemporal_store(o[0], p + k);
+  }
+}
+
 // A kernel that follows a reduction phase: if that phase stopped the solve
 // (of the workgroup's system), note it in C_HALT (read by the sparse products
 // of later iterations, which may run concurrently with a finish and so must
@@ -88,7 +119,7 @@ struct PassAArgs {
   int *ctl;
   int64_t n;
   int rev;  // sweep direction
-  // fused inner products (k_passA_pbicgsafe<true> only): r0* and the
+  // fused inner products (k_passA_pbicgsafe<true, NT> only): r0* and the
   // [5][gridDim.x] (hi, lo) partial sums of the next iteration's
   // b = (y,y), e = (y,r), f = (r0*,r), h = (r0*,t), rho = (r,r)
   const double *rs;
@@ -96,23 +127,23 @@ struct PassAArgs {
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
-template <int W, bool DOTS>
+template <int W, bool DOTS, bool NT>
 __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, DD (&acc)[5]) {
   const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA],
                et = P.sc[PS_S_ETA];
   double r[W], p[W], u[W], s[W], t[W], y[W], As[W], l[W], g[W], w[W], z[W], x[W], q[W];
   ldv<W>(P.r, k, r);
-  ldv<W>(P.p, k, p);
-  ldv<W>(P.u, k, u);
+  ldv_s<W, NT>(P.p, k, p);
+  ldv_s<W, NT>(P.u, k, u);
   ldv<W>(P.s, k, s);
-  ldv<W>(P.t, k, t);
+  ldv_s<W, NT>(P.t, k, t);
   ldv<W>(P.y, k, y);
   ldv<W>(P.As, k, As);
   ldv<W>(P.l, k, l);
   ldv<W>(P.g, k, g);
   ldv<W>(P.w, k, w);
-  ldv<W>(P.z, k, z);
-  ldv<W>(P.x, k, x);
+  ldv_s<W, NT>(P.z, k, z);
+  ldv_s<W, NT>(P.x, k, x);
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     p[j] = r[j] + be * (p[j] - u[j]);
@@ -138,17 +169,19 @@ __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, DD (&a
       dd_fma(acc[4], r[j], r[j]);
     }
   }
-  stv<W>(P.p, k, p);
-  stv<W>(P.u, k, u);
+  stv_s<W, NT>(P.p, k, p);
+  stv_s<W, NT>(P.u, k, u);
   stv<W>(P.w, k, w);
-  stv<W>(P.t, k, t);
-  stv<W>(P.z, k, z);
+  stv_s<W, NT>(P.t, k, t);
+  stv_s<W, NT>(P.z, k, z);
   stv<W>(P.y, k, y);
-  stv<W>(P.x, k, x);
+  stv_s<W, NT>(P.x, k, x);
   stv<W>(P.r, k, r);
 }
 
-template <bool DOTS>
+// NT: p, u, t, z, x (read and written here, next read by the next pass A)
+// stream past the cache.
+template <bool DOTS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   const PassAArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
@@ -157,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   for (int j = 0; j < 5; ++j) acc[j] = DD{0.0, 0.0};
   const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
-  if (k + 1 < P.n) passA_body<2, DOTS>(P, k, acc);
-  else if (k < P.n) passA_body<1, DOTS>(P, k, acc);
+  if (k + 1 < P.n) passA_body<2, DOTS, NT>(P, k, acc);
+  else if (k < P.n) passA_body<1, DOTS, NT>(P, k, acc);
   if constexpr (DOTS) {
     __shared__ double red[kWavesPerBlock * 5 * 2];
     const DD t = block_sum_dd<5>(acc, red);

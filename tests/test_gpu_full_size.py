@@ -73,6 +73,7 @@ def test_spmv_full_size_bit_exact(case):
     assert info["format"] == {"cd3d_128": "sell", "rand_band_1m": "csr"}[name]
     assert info["auto_overlap"] == 1
     assert info["auto_schedule"] == {"cd3d_128": 1, "rand_band_1m": 0}[name]
+    assert info["streaming"] == 1  # both move ~0.9 GiB per p-BiCGSafe iteration
     x = np.random.default_rng(3).standard_normal(A.n)
     y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.array_equal(y, O.spmv(A, x)), name

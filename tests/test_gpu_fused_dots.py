@@ -6,6 +6,7 @@ iteration, instead of a pass of their own), not what they are: the partial sums
 are compensated pairs rounded once, as in the separate pass.  So every result
 must equal the oracle's p-BiCGSafe bit for bit, like schedule 0.
 """
+import os
 import sys
 
 import numpy as np
@@ -86,6 +87,36 @@ def test_fused_schedule_graphs_and_batches_bit_identical():
         for k, r in enumerate(runs):
             assert r.iters == ref.iters and r.status == ref.status, (name, k)
             assert np.array_equal(r.x, ref.x) and np.array_equal(r.hist, ref.hist), (name, k)
+
+
+@pytest.mark.parametrize("case", ["cd2d_64", "nonsym_ragged_3001", "long_rows_600"])
+def test_streaming_update_passes_bit_identical_to_oracle(case):
+    """PIPESAFE_STREAM=1 forces the streaming (nontemporal) loads and stores of p-BiCGSafe's
+    update passes, which the library picks by itself only for systems far above the
+    last-level cache: a cache hint, so both schedules keep the oracle's bits (odd n: the
+    one-entry tail of each pass)."""
+    A = CASES[case]()
+    ref = O.solve(A, tol=1e-10, maxit=3000, variant="pbicgsafe")
+    old = os.environ.get("PIPESAFE_STREAM")
+    os.environ["PIPESAFE_STREAM"] = "1"
+    try:
+        M = pipesafe.Matrix.from_csr(A)
+    finally:
+        if old is None:
+            del os.environ["PIPESAFE_STREAM"]
+        else:
+            os.environ["PIPESAFE_STREAM"] = old
+    with M:
+        assert M.info()["streaming"] == 1
+        for kw in (dict(schedule=0), dict(schedule=1), dict(schedule=1, graph=1, batch_iters=4),
+                   dict(schedule=0, graph=0, overlap=1)):
+            say(f"streaming {case} {kw}")
+            res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgsafe", **kw)
+            assert res.status == ref.status and res.iters == ref.iters, (case, kw)
+            assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, kw)
+            assert np.array_equal(res.x, ref.x, equal_nan=True), (case, kw)
+    with pipesafe.Matrix.from_csr(A) as M2:
+        assert M2.info()["streaming"] == 0  # small systems: automatic choice is off
 
 
 def test_fused_schedule_resume_from_oracle_state():
