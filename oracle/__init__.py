@@ -93,11 +93,12 @@ class Oracle:
         L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, f64, cint = ctypes.c_int64, ctypes.c_double, ctypes.c_int
-        L.orc_setup.argtypes = [cint, i64, P, P, P, P, P, cint, P, P]
+        L.orc_setup.argtypes = [cint, cint, i64, P, P, P, P, P, cint, P, P]
         L.orc_setup.restype = cint
-        L.orc_run.argtypes = [cint, i64, P, P, P, P, P, P, i64, i64, f64, i64, i64, P, P, P, P]
+        L.orc_run.argtypes = [cint, cint, i64, P, P, P, P, P, P, i64, i64, f64, i64, i64, P, P, P, P]
         L.orc_run.restype = cint
-        L.orc_solve.argtypes = [cint, i64, P, P, P, P, P, f64, i64, i64, i64, cint, P, P, P, P, P, P]
+        L.orc_solve.argtypes = [cint, cint, i64, P, P, P, P, P, f64, i64, i64, i64, cint, P, P, P, P, P,
+                                P]
         L.orc_solve.restype = cint
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
         L.orc_spmv.restype = None
@@ -113,8 +114,12 @@ class Oracle:
         return y
 
     def solve(self, A, b=None, x0=None, tol=1e-8, maxit=10_000, variant="pbicgsafe", rr_m=100,
-              rr_M=None, norm_ref=0):
-        """Full solve: x, iters, status, hist[0..iters], coef[0..iters) and operation counters."""
+              rr_M=None, norm_ref=0, precision=0):
+        """Full solve: x, iters, status, hist[0..iters], coef[0..iters) and operation counters.
+
+        precision: 0 FP64; 1 every product with the matrix values rounded to FP32;
+        2 the residual statements (set-up, replacement steps) with the FP64 values and every
+        other product with the rounded ones (see oracle.c)."""
         rowptr, col, val = _csr(A)
         b = np.ascontiguousarray(A.b if b is None else b, dtype=np.float64)
         x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
@@ -124,7 +129,7 @@ class Oracle:
         hist = np.full(maxit + 1, np.nan)
         coef = np.zeros((maxit + 1, NCOEF))
         counters = np.zeros(3)
-        rc = self.L.orc_solve(_vid(variant), A.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x0a), tol,
+        rc = self.L.orc_solve(_vid(variant), precision, A.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x0a), tol,
                               maxit, rr_m, maxit if rr_M is None else rr_M, norm_ref, _p(x),
                               ctypes.byref(iters), _p(hist), _p(coef), ctypes.byref(status),
                               _p(counters))
@@ -134,17 +139,19 @@ class Oracle:
         return Result(x=x, iters=it, status=status.value, hist=hist[: it + 1], coef=coef[:it],
                       nspmv=int(counters[0]), ndot=int(counters[1]), nphase=int(counters[2]))
 
-    def setup(self, A, b=None, x0=None, variant="pbicgsafe", norm_ref=0) -> State:
+    def setup(self, A, b=None, x0=None, variant="pbicgsafe", norm_ref=0, precision=0) -> State:
         rowptr, col, val = _csr(A)
         b = np.ascontiguousarray(A.b if b is None else b, dtype=np.float64)
         x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
         st = State(A.n)
-        self.L.orc_setup(_vid(variant), A.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x0a), norm_ref,
-                         _p(st.V), _p(st.S))
+        rc = self.L.orc_setup(_vid(variant), precision, A.n, _p(rowptr), _p(col), _p(val), _p(b),
+                              _p(x0a), norm_ref, _p(st.V), _p(st.S))
+        if rc != 0:
+            raise RuntimeError(f"orc_setup failed: {rc}")
         return st
 
     def run(self, A, st: State, i_begin, maxit, b=None, tol=0.0, variant="pbicgsafe", rr_m=100,
-            rr_M=None):
+            rr_M=None, precision=0):
         """Advance ``st`` in place from iteration ``i_begin`` until a stop (at the latest i = maxit)."""
         rowptr, col, val = _csr(A)
         b = np.ascontiguousarray(A.b if b is None else b, dtype=np.float64)
@@ -152,15 +159,20 @@ class Oracle:
         status = ctypes.c_int32()
         hist = np.full(maxit + 1, np.nan)
         coef = np.zeros((maxit + 1, NCOEF))
-        self.L.orc_run(_vid(variant), A.n, _p(rowptr), _p(col), _p(val), _p(b), _p(st.V), _p(st.S),
-                       i_begin, maxit, tol, rr_m, maxit if rr_M is None else rr_M,
-                       ctypes.byref(iters), _p(hist), _p(coef), ctypes.byref(status))
+        rc = self.L.orc_run(_vid(variant), precision, A.n, _p(rowptr), _p(col), _p(val), _p(b),
+                            _p(st.V), _p(st.S), i_begin, maxit, tol, rr_m,
+                            maxit if rr_M is None else rr_M, ctypes.byref(iters), _p(hist),
+                            _p(coef), ctypes.byref(status))
+        if rc != 0:
+            raise RuntimeError(f"orc_run failed: {rc}")
         return Result(iters=iters.value, status=status.value, hist=hist, coef=coef)
 
-    def state_at(self, A, i, variant="pbicgsafe", b=None, x0=None, rr_m=100, rr_M=None):
+    def state_at(self, A, i, variant="pbicgsafe", b=None, x0=None, rr_m=100, rr_M=None,
+                 precision=0):
         """State at the start of iteration ``i`` (the solve stopped there with status MAXIT)."""
-        st = self.setup(A, b=b, x0=x0, variant=variant)
-        res = self.run(A, st, 0, i, b=b, tol=0.0, variant=variant, rr_m=rr_m, rr_M=rr_M)
+        st = self.setup(A, b=b, x0=x0, variant=variant, precision=precision)
+        res = self.run(A, st, 0, i, b=b, tol=0.0, variant=variant, rr_m=rr_m, rr_M=rr_M,
+                       precision=precision)
         return st, res
 
 

@@ -30,6 +30,18 @@
  *   4  BiCGStab               Algorithm 1 (Section 2), with omega written for
  *                             the coefficient the listing calls zeta
  *
+ * Precision (argument `precision` of orc_setup, orc_run and orc_solve): the
+ * mixed-precision forms keep every vector, inner product, coefficient and the
+ * stop test in FP64 and change only the matrix values a product reads:
+ *   0  the given FP64 values everywhere;
+ *   1  every product reads the values rounded to the nearest FP32 number (ties
+ *      to even) and widened back, so the system solved is that rounded matrix;
+ *   2  the residual statements -- r_0 = b - A x_0 at set-up and the true
+ *      residual r_{i+1} = b - A x_{i+1} of a replacement step (Algorithm 5,
+ *      Section 4) -- read the FP64 values, every other product the rounded
+ *      ones, so the replacement steps re-anchor the iteration to the FP64
+ *      system (R23).
+ *
  * Readings of points the paper leaves open (each is used below):
  *   R1  the shadow residual is r0* = r0, fixed for the whole solve.
  *   R2  Algorithms 4/5 use s_0 without computing it; s_0 = A r_0 by its
@@ -46,6 +58,8 @@
  *   R9  the replacement cut-off M defaults to maxit.
  *   R10 a zero or non-finite denominator in alpha, beta, zeta, eta (or
  *       omega's successor) stops the solve with status BREAKDOWN and x_i.
+ *   R23 mixed precision (precision 1, 2) rounds only the matrix values; the
+ *       paper's experiments are FP64 throughout (Section 5).
  *
  * Status codes: 0 converged, 1 maxit, 2 breakdown, 3 non-finite inner product.
  */
@@ -134,15 +148,39 @@ static int bad(double d) { return d == 0.0 || !isfinite(d); }
 
 /* ----------------------------------------------------------- entry points */
 
+/* The matrices of a solve at `precision` (see the header): Ak for the Krylov
+   products, Ar for the residual statements.  *rounded receives the rounded
+   copy of the values (to be freed), or NULL. */
+static int precision_pair(int precision, const csr_t *A, csr_t *Ak, csr_t *Ar, double **rounded) {
+  *rounded = NULL;
+  *Ak = *A;
+  *Ar = *A;
+  if (precision == 0) return 0;
+  if (precision != 1 && precision != 2) return -1;
+  const int64_t nnz = A->rowptr[A->n];
+  double *v = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  if (!v) return -2;
+  for (int64_t k = 0; k < nnz; ++k) v[k] = (double)(float)A->val[k];
+  Ak->val = v;
+  if (precision == 1) Ar->val = v;
+  *rounded = v;
+  return 0;
+}
+
 /*
  * Initialise the state for `variant` (the steps before each listing's loop).
  * V holds NV vectors of length n (zeroed here); S holds NS scalars.
  * x0 may be NULL (zero initial guess).  norm_ref selects the stop-test scale:
  * 0 = ||r_0|| (the paper's criterion, Section 5), 1 = ||b||.
  */
-int orc_setup(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-              const double *b, const double *x0, int norm_ref, double *V, double *S) {
-  csr_t A = {n, rowptr, col, val};
+int orc_setup(int variant, int precision, int64_t n, const int64_t *rowptr, const int32_t *col,
+              const double *val, const double *b, const double *x0, int norm_ref, double *V,
+              double *S) {
+  const csr_t A64 = {n, rowptr, col, val};
+  csr_t A, Ares;
+  double *rounded;
+  const int rc = precision_pair(precision, &A64, &A, &Ares, &rounded);
+  if (rc) return rc;
   double *v[NV];
   for (int k = 0; k < NV; ++k) v[k] = V + (size_t)k * (size_t)n;
   memset(V, 0, sizeof(double) * (size_t)NV * (size_t)n);   /* R3: everything starts at zero */
@@ -151,7 +189,7 @@ int orc_setup(int variant, int64_t n, const int64_t *rowptr, const int32_t *col,
 
   /* x_0 and r_0 = b - A x_0 */
   for (int64_t k = 0; k < n; ++k) x[k] = x0 ? x0[k] : 0.0;
-  spmv(&A, x, tmp, S);
+  spmv(&Ares, x, tmp, S);
   for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];
   /* R1: r0* = r0 */
   for (int64_t k = 0; k < n; ++k) rs[k] = r[k];
@@ -181,6 +219,7 @@ int orc_setup(int variant, int64_t n, const int64_t *rowptr, const int32_t *col,
   /* reference norm for the stop test */
   if (norm_ref == 1) S[S_RHOREF] = dot(n, b, b, S), S[S_NDOT] -= 1.0;
   else S[S_RHOREF] = dot(n, r, r, S), S[S_NDOT] -= 1.0;
+  free(rounded);
   return 0;
 }
 
@@ -294,9 +333,9 @@ static int iter_ssbicgsafe2(const csr_t *A, double **v, double *S, int64_t i, in
 }
 
 /* p-BiCGSafe, Algorithm 4, and p-BiCGSafe-rr, Algorithm 5: one iteration i */
-static int iter_pbicgsafe(const csr_t *A, const double *b, double **v, double *S, int64_t i,
-                          int64_t maxit, double tol, int rr, int64_t m, int64_t M, double *hist,
-                          double *coef) {
+static int iter_pbicgsafe(const csr_t *A, const csr_t *Ares, const double *b, double **v,
+                          double *S, int64_t i, int64_t maxit, double tol, int rr, int64_t m,
+                          int64_t M, double *hist, double *coef) {
   int64_t n = A->n;
   double *x = v[VX], *r = v[VR], *s = v[VS], *y = v[VY], *t = v[VT], *p = v[VP], *u = v[VU];
   double *z = v[VZ], *w = v[VW], *l = v[VL], *g = v[VG], *q = v[VQ], *o = v[VO];
@@ -322,7 +361,7 @@ static int iter_pbicgsafe(const csr_t *A, const double *b, double **v, double *S
   for (int64_t k = 0; k < n; ++k) y[k] = ze * s[k] + et * y[k] - al * w[k];  /* y_{i+1} */
   for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + z[k];            /* x_{i+1} */
   if (replace) {
-    spmv(A, x, tmp, S);                                    /* A x_{i+1} */
+    spmv(Ares, x, tmp, S);                                 /* A x_{i+1} (precision 2: FP64) */
     for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];                    /* r_{i+1} = b - A x_{i+1} */
     spmv(A, t, l, S);                                      /* R7: l_i = A t_i */
     spmv(A, y, g, S);                                      /* g_{i+1} = A y_{i+1} */
@@ -476,10 +515,15 @@ static int iter_bicgstab(const csr_t *A, double **v, double *S, int64_t i, int64
  * index i at which the solve stopped (= the number of x updates from 0) and
  * V holds the state at the start of that iteration.
  */
-int orc_run(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-            const double *b, double *V, double *S, int64_t i_begin, int64_t maxit, double tol,
-            int64_t rr_m, int64_t rr_M, int64_t *iters, double *hist, double *coef, int32_t *status) {
-  csr_t A = {n, rowptr, col, val};
+int orc_run(int variant, int precision, int64_t n, const int64_t *rowptr, const int32_t *col,
+            const double *val, const double *b, double *V, double *S, int64_t i_begin,
+            int64_t maxit, double tol, int64_t rr_m, int64_t rr_M, int64_t *iters, double *hist,
+            double *coef, int32_t *status) {
+  const csr_t A64 = {n, rowptr, col, val};
+  csr_t A, Ares;
+  double *rounded;
+  const int rc = precision_pair(precision, &A64, &A, &Ares, &rounded);
+  if (rc) return rc;
   double *v[NV];
   for (int k = 0; k < NV; ++k) v[k] = V + (size_t)k * (size_t)n;
   int st = ST_RUNNING;
@@ -495,32 +539,41 @@ int orc_run(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, c
     }
     switch (variant) {
       case V_SSBICGSAFE2: st = iter_ssbicgsafe2(&A, v, S, i, maxit, tol, hist, coef); break;
-      case V_PBICGSAFE: st = iter_pbicgsafe(&A, b, v, S, i, maxit, tol, 0, 0, 0, hist, coef); break;
+      case V_PBICGSAFE:
+        st = iter_pbicgsafe(&A, &Ares, b, v, S, i, maxit, tol, 0, 0, 0, hist, coef);
+        break;
       case V_PBICGSAFE_RR:
-        st = iter_pbicgsafe(&A, b, v, S, i, maxit, tol, 1, rr_m, rr_M, hist, coef);
+        st = iter_pbicgsafe(&A, &Ares, b, v, S, i, maxit, tol, 1, rr_m, rr_M, hist, coef);
         break;
       case V_PBICGSTAB: st = iter_pbicgstab(&A, v, S, i, maxit, tol, hist, coef); break;
       case V_BICGSTAB: st = iter_bicgstab(&A, v, S, i, maxit, tol, hist, coef); break;
-      default: return -1;
+      default: free(rounded); return -1;
     }
     if (st != ST_RUNNING) break;
   }
   *iters = i;
   *status = st;
+  free(rounded);
   return 0;
 }
 
 /* setup + run from i = 0; x (length n) receives the final iterate. */
-int orc_solve(int variant, int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
-              const double *b, const double *x0, double tol, int64_t maxit, int64_t rr_m,
-              int64_t rr_M, int norm_ref, double *x, int64_t *iters, double *hist, double *coef,
-              int32_t *status, double *counters) {
-  if (n < 1 || variant < 0 || variant > 4) return -1;
+int orc_solve(int variant, int precision, int64_t n, const int64_t *rowptr, const int32_t *col,
+              const double *val, const double *b, const double *x0, double tol, int64_t maxit,
+              int64_t rr_m, int64_t rr_M, int norm_ref, double *x, int64_t *iters, double *hist,
+              double *coef, int32_t *status, double *counters) {
+  if (n < 1 || variant < 0 || variant > 4 || precision < 0 || precision > 2) return -1;
   double *V = (double *)malloc(sizeof(double) * (size_t)NV * (size_t)n);
   double S[NS];
   if (!V) return -2;
-  orc_setup(variant, n, rowptr, col, val, b, x0, norm_ref, V, S);
-  orc_run(variant, n, rowptr, col, val, b, V, S, 0, maxit, tol, rr_m, rr_M, iters, hist, coef, status);
+  int rc = orc_setup(variant, precision, n, rowptr, col, val, b, x0, norm_ref, V, S);
+  if (!rc)
+    rc = orc_run(variant, precision, n, rowptr, col, val, b, V, S, 0, maxit, tol, rr_m, rr_M,
+                 iters, hist, coef, status);
+  if (rc) {
+    free(V);
+    return rc;
+  }
   memcpy(x, V + (size_t)VX * (size_t)n, sizeof(double) * (size_t)n);
   if (counters) { counters[0] = S[S_NSPMV]; counters[1] = S[S_NDOT]; counters[2] = S[S_NPHASE]; }
   free(V);

@@ -53,6 +53,12 @@ MUTANTS = {
     "pbicgstab_alpha_drops_gz": ("den_alpha = gw + beta * gs - beta * om * gz", "den_alpha = gw + beta * gs"),
     "pbicgstab_y_uses_s": ("y[k] = w[k] - al * z[k]", "y[k] = w[k] - al * s[k]"),
     "pbicgstab_omega_inverted": ("qy / yy", "yy / qy"),
+    "prec_no_rounding": ("v[k] = (double)(float)A->val[k];", "v[k] = A->val[k];"),
+    "prec_residual_rounded": ("  if (precision == 1) Ar->val = v;", "  Ar->val = v;"),
+    "prec_krylov_fp64": ("  Ak->val = v;\n", "\n"),
+    "prec_setup_residual_rounded": ("spmv(&Ares, x, tmp, S);", "spmv(&A, x, tmp, S);"),
+    "prec_rr_residual_rounded": ("spmv(Ares, x, tmp, S);", "spmv(A, x, tmp, S);"),
+    "prec_setup_s_fp64": ("spmv(&A, r, v[VS], S);", "spmv(&Ares, r, v[VS], S);"),
 }
 
 

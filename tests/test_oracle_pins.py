@@ -21,6 +21,16 @@ mathematics, not against the oracle itself.
   P13 inner products and sparse-product rows are the correctly rounded sums on
       inputs with massive cancellation (closed form: e.g. 1e16 + 1 - 1e16 = 1),
       which plain recursive summation gets wrong.
+  P14 mixed precision: precision 1 is the FP64 method on the matrix that numpy
+      rounds to float32 (an independent rounding); precision 2 equals FP64 when
+      every value is a float32 number; under precision 2 the set-up residual and
+      the replacement step's residual are b - A x with the FP64 matrix (scipy),
+      the Krylov products (s_0, and l, g, s after a replacement) use the rounded
+      one, and under precision 1 the replacement residual uses the rounded one.
+  P15 what the precision modes are for: with replacement steps (Algorithm 5,
+      m = 10) precision 2 reaches the FP64 system's residual ||b - A x|| <=
+      tol ||b||, while precision 1 reaches it only for the rounded matrix and
+      stays at the rounding level (~1e-8..1e-6) on the FP64 one.
 """
 import json
 import os
@@ -297,8 +307,72 @@ def check_p13(orc):
     return None
 
 
+def rounded32(A):
+    """A with its values rounded to float32 by numpy (round to nearest even) and widened."""
+    return W.CSR(A.n, A.rowptr, A.col, A.val.astype(np.float32).astype(np.float64), A.b,
+                 name=A.name + "_f32")
+
+
+def check_p14(orc):
+    A = W.cd2d(32, 10.0)
+    A32 = rounded32(A)
+    if np.array_equal(A.val, A32.val):
+        return "P14 test matrix is already float32"
+    # precision 1 = FP64 on the numpy-rounded matrix; precision 2 = FP64 when nothing rounds
+    for v in SAFE:
+        ref = orc.solve(A32, tol=1e-10, maxit=60, variant=v, rr_m=7)
+        for prec, M in ((1, A), (2, A32)):
+            R = orc.solve(M, tol=1e-10, maxit=60, variant=v, rr_m=7, precision=prec)
+            if not (R.iters == ref.iters and np.array_equal(R.x, ref.x)
+                    and np.array_equal(R.hist, ref.hist)):
+                return f"P14 {v} precision {prec}: not the FP64 method on the rounded matrix"
+    S64, S32 = A.to_scipy(), A32.to_scipy()
+    nb = np.linalg.norm(A.b)
+    x0 = np.random.default_rng(4).standard_normal(A.n)
+    # set-up under precision 2: r_0 = b - A x_0 with FP64 values, s_0 = A r_0 with rounded ones
+    st = orc.setup(A, x0=x0, variant="pbicgsafe", precision=2)
+    r0 = st.vec("r")
+    if np.linalg.norm(r0 - (A.b - S64 @ x0)) > 1e-14 * np.linalg.norm(r0):
+        return "P14 precision 2: r_0 is not b - A x_0 with the FP64 matrix"
+    if _nrm_rel(st.vec("s"), S32 @ r0) > 1e-13:
+        return "P14 precision 2: s_0 is not the rounded matrix times r_0"
+    # the replacement step (i = 4, m = 4): true residual with FP64 (precision 2) or rounded
+    # (precision 1) values; l, g, s recomputed with the rounded matrix
+    for prec, Sr in ((2, S64), (1, S32)):
+        st, res = orc.state_at(A, 5, variant="pbicgsafe_rr", rr_m=4, precision=prec)
+        x, r = st.vec("x"), st.vec("r")
+        if np.linalg.norm(r - (A.b - Sr @ x)) > 1e-14 * nb:
+            return f"P14 precision {prec}: replacement residual is not b - A x with its matrix"
+        other = S32 if Sr is S64 else S64
+        if np.linalg.norm(r - (A.b - other @ x)) < 1e-12 * nb:
+            return f"P14 precision {prec}: replacement residual does not tell the matrices apart"
+    st, _ = orc.state_at(A, 5, variant="pbicgsafe_rr", rr_m=4, precision=2)
+    for out, inp in (("s", "r"), ("g", "y"), ("l", "t")):
+        if _nrm_rel(st.vec(out), S32 @ st.vec(inp)) > 1e-12:
+            return f"P14 precision 2: {out} is not the rounded matrix times {inp} after a replacement"
+    return None
+
+
+def check_p15(orc):
+    tol = 1e-12
+    for A in (W.cd2d(64, 10.0), W.small_nonsym(3001, 11, density=0.003)):
+        S64, S32 = A.to_scipy(), rounded32(A).to_scipy()
+        nb = np.linalg.norm(A.b)
+        R2 = orc.solve(A, tol=tol, maxit=2000, variant="pbicgsafe_rr", rr_m=10, norm_ref=1,
+                       precision=2)
+        e64 = np.linalg.norm(A.b - S64 @ R2.x) / nb
+        if R2.status != O.CONVERGED or e64 > 3 * tol:
+            return f"P15 {A.name} precision 2: status {R2.status}, FP64 residual {e64:.2e}"
+        R1 = orc.solve(A, tol=tol, maxit=2000, variant="pbicgsafe", norm_ref=1, precision=1)
+        e32 = np.linalg.norm(A.b - S32 @ R1.x) / nb
+        e64 = np.linalg.norm(A.b - S64 @ R1.x) / nb
+        if R1.status != O.CONVERGED or e32 > 10 * tol or e64 < 1e-9:
+            return f"P15 {A.name} precision 1: residuals {e32:.2e} (rounded), {e64:.2e} (FP64)"
+    return None
+
+
 CHECKS = [check_p1, check_p2, check_p3, check_p4, check_p5, check_p6, check_p7, check_p8, check_p11,
-          check_p12, check_p13]
+          check_p12, check_p13, check_p14, check_p15]
 
 
 # --------------------------------------------------------------------------- tests
