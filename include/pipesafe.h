@@ -109,10 +109,32 @@ typedef struct {
                           start from x0 = 0 instead (per system for a batch); a guess
                           that is worse than zero costs nothing then.  0 (default): use
                           x0 as given.                                                 */
+  int32_t precision;   /* ps_precision: the matrix values the products read.
+                          PS_PREC_FP64 (default): the FP64 values.  PS_PREC_FP32_MATRIX:
+                          every product reads the values rounded to the nearest FP32
+                          number (ties to even), so the system solved is that rounded
+                          matrix.  PS_PREC_FP32_KRYLOV: the residual statements
+                          (r_0 = b - A x_0, the x0_fallback test and the true residual of
+                          p-BiCGSafe-rr's replacement steps, Algorithm 5) read the FP64
+                          values, every other product the rounded ones; with
+                          PS_PBICGSAFE_RR the replacement steps re-anchor the iteration
+                          to the FP64 system (a solve that stops before its first
+                          replacement is only as accurate as the rounded matrix).
+                          Vectors, inner products, coefficients and x are FP64 in every
+                          mode.  The FP32 copy is made on the device at the first such
+                          solve (4 bytes per stored value) and kept; a value beyond the
+                          FP32 range makes these modes PS_EINVAL.                      */
   void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
                           caller's current stream).  NULL: ps_solve_dev uses the null
                           stream, ps_solve the library's own stream.                   */
 } ps_options;
+
+/* ps_options.precision */
+enum ps_precision {
+  PS_PREC_FP64 = 0,
+  PS_PREC_FP32_MATRIX = 1,
+  PS_PREC_FP32_KRYLOV = 2
+};
 
 /* device layout of the matrix, chosen by ps_create (ps_info.format) */
 enum ps_format {

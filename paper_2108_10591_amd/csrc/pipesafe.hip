@@ -71,13 +71,14 @@ struct Timer {
 
 // Everything a captured batch of iterations depends on.
 struct GraphKey {
-  int variant, maxit, rr_m, rr_M, overlap, count, phase, schedule;
+  int variant, maxit, rr_m, rr_M, overlap, count, phase, schedule, precision;
   double tol;
   hipStream_t stream;
   bool operator==(const GraphKey &o) const {
     return variant == o.variant && maxit == o.maxit && rr_m == o.rr_m && rr_M == o.rr_M &&
            overlap == o.overlap && count == o.count && phase == o.phase &&
-           schedule == o.schedule && tol == o.tol && stream == o.stream;
+           schedule == o.schedule && precision == o.precision && tol == o.tol &&
+           stream == o.stream;
   }
 };
 
@@ -103,6 +104,9 @@ struct ps_matrix {
   int nslice = 0;
   int sell_rpl = 1;                      // rows per lane of the sliced layout (1 or 2)
   int stream_override = -1;              // streaming update passes: -1 automatic, 0, 1
+  // the values rounded to FP32 (mixed-precision solves), made on first use
+  float *val32 = nullptr, *sval32 = nullptr;
+  bool f32_ok = true;                    // every value rounds to a finite FP32 number
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -144,8 +148,10 @@ struct ps_matrix {
   double *slot(int s) const { return vec + (size_t)s * ld; }
   int *running() const { return ctl + (size_t)nsys * C_COUNT; }
   int nblk512() const { return (int)(n / 512); }
-  CsrDev csr() const { return CsrDev{rowptr, col, val, blk, nblk}; }
-  SellDev sell() const { return SellDev{scol, sval, soff, (int)n, nblk}; }
+  CsrDev<double> csr() const { return {rowptr, col, val, blk, nblk}; }
+  CsrDev<float> csr32() const { return {rowptr, col, val32, blk, nblk}; }
+  SellDev<double> sell() const { return {scol, sval, soff, (int)n, nblk}; }
+  SellDev<float> sell32() const { return {scol, sval32, soff, (int)n, nblk}; }
 };
 
 namespace {
@@ -219,28 +225,39 @@ int next_rev(ps_matrix *M) {
 
 template <int IPT, int LPR, class Epi>
 int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, Stop stop,
-                int rev) {
+                int rev, bool f32) {
   const size_t lds = (size_t)IPT * kBlock * sizeof(double);
-  return launch(M, s, cls, k_spmv<IPT, LPR, Epi>, dim3(M->nblk), lds, M->csr(), x, epi, stop, rev);
+  if (f32)
+    return launch(M, s, cls, k_spmv<IPT, LPR, float, Epi>, dim3(M->nblk), lds, M->csr32(), x, epi,
+                  stop, rev);
+  return launch(M, s, cls, k_spmv<IPT, LPR, double, Epi>, dim3(M->nblk), lds, M->csr(), x, epi,
+                stop, rev);
 }
 
 // One sparse product with epilogue `epi`; `stop_word` (C_DONE, C_HALT or -1)
-// names the control word that makes it a no-op (per system).
+// names the control word that makes it a no-op (per system).  f32: read the
+// values rounded to FP32 (mixed-precision solves) instead of the FP64 ones.
 template <class Epi>
-int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, int stop_word) {
+int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, int stop_word,
+         bool f32 = false) {
   const int rev = next_rev(M);
   const Stop stop{M->ctl, stop_word, M->chunk_sys};
   if (M->format == PS_FMT_SELL) {
-    if (M->sell_rpl == 2)
-      return launch(M, s, cls, k_sell<2, Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
-    return launch(M, s, cls, k_sell<1, Epi>, dim3(M->nblk), 0, M->sell(), x, epi, stop, rev);
+    const dim3 g(M->nblk);
+    if (f32)
+      return M->sell_rpl == 2
+                 ? launch(M, s, cls, k_sell<2, float, Epi>, g, 0, M->sell32(), x, epi, stop, rev)
+                 : launch(M, s, cls, k_sell<1, float, Epi>, g, 0, M->sell32(), x, epi, stop, rev);
+    return M->sell_rpl == 2
+               ? launch(M, s, cls, k_sell<2, double, Epi>, g, 0, M->sell(), x, epi, stop, rev)
+               : launch(M, s, cls, k_sell<1, double, Epi>, g, 0, M->sell(), x, epi, stop, rev);
   }
   switch (M->shape) {
-    case 0: return spmv_launch<4, 1>(M, s, cls, x, epi, stop, rev);
-    case 1: return spmv_launch<8, 1>(M, s, cls, x, epi, stop, rev);
-    case 2: return spmv_launch<16, 4>(M, s, cls, x, epi, stop, rev);
-    case 3: return spmv_launch<16, 8>(M, s, cls, x, epi, stop, rev);
-    default: return spmv_launch<16, 16>(M, s, cls, x, epi, stop, rev);
+    case 0: return spmv_launch<4, 1>(M, s, cls, x, epi, stop, rev, f32);
+    case 1: return spmv_launch<8, 1>(M, s, cls, x, epi, stop, rev, f32);
+    case 2: return spmv_launch<16, 4>(M, s, cls, x, epi, stop, rev, f32);
+    case 3: return spmv_launch<16, 8>(M, s, cls, x, epi, stop, rev, f32);
+    default: return spmv_launch<16, 16>(M, s, cls, x, epi, stop, rev, f32);
   }
 }
 
@@ -292,6 +309,9 @@ struct Plan {
   bool fused;     // fused-dot schedule (p-BiCGSafe)
   bool fallback;  // replace an initial guess that is worse than zero
   bool stream_nt; // streaming (nontemporal) loads and stores in the update passes
+  int precision;  // 0 FP64; 1 FP32 values in every product; 2 FP32 in the Krylov products
+  bool kry32;     // the Krylov products read the FP32 values
+  bool res32;     // the residual statements (r = b - A x) read the FP32 values
 };
 
 // r_0 = b - A x_0, r0* = r_0 and the zero vectors of each algorithm (x_0 and b
@@ -307,7 +327,7 @@ int enqueue_setup(ps_matrix *M, const Plan &P) {
     PS_TRY(zero_slots(M, s, {PS_V_Y, PS_V_T, PS_V_P, PS_V_U, PS_V_Z, PS_V_W, PS_V_L, PS_V_G,
                              PS_V_Q, PS_V_O, PS_V_AS, PS_V_V}));
   }
-  PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, -1));
+  PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, -1, P.res32));
   if (P.fallback) {
     PS_TRY(dots<ProdFallback, FinFallback>(M, s, {R, Bv}, P.maxit, P.tol, 0, M->hist));
     PS_TRY(launch(M, s, PS_K_OTHER, k_fallback, elem_grid(M->n), 0, X, R, RS, (const double *)Bv,
@@ -315,15 +335,15 @@ int enqueue_setup(ps_matrix *M, const Plan &P) {
   }
   if (P.variant == PS_PBICGSAFE || P.variant == PS_PBICGSAFE_RR) {
     // s_0 = A r_0 (its definition s_i := A r_i; Algorithm 4 uses s_0 without forming it)
-    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, -1));
+    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{M->slot(PS_V_S)}, -1, P.kry32));
   }
   if (P.norm_ref == 1) {
     PS_TRY(dots<ProdNorm, FinNormRef>(M, s, {Bv}, P.maxit, P.tol, 0, M->hist));
   }
   if (P.variant == PS_PBICGSTAB) {
     double *W = M->slot(PS_V_W), *T = M->slot(PS_V_T);
-    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{W}, -1));  // w_0 = A r_0
-    PS_TRY(spmv(M, s, PS_K_OTHER, W, EpiStore{T}, -1));  // t_0 = A w_0
+    PS_TRY(spmv(M, s, PS_K_OTHER, R, EpiStore{W}, -1, P.kry32));  // w_0 = A r_0
+    PS_TRY(spmv(M, s, PS_K_OTHER, W, EpiStore{T}, -1, P.kry32));  // t_0 = A w_0
     PS_TRY(dots<ProdStab3, FinStabSetup>(M, s, {RS, R, W}, P.maxit, P.tol,
                                          P.norm_ref == 0 ? DF_SET_REF : 0, M->hist));
   }
@@ -385,7 +405,7 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
                        i < P.rr_M;
   if (!replace) {
     PS_TRY(fork(M, P));
-    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT));  // As_i
+    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT, P.kry32));  // As_i
     if (P.fused && i > P.i0) PS_TRY(fused_finish(M, P, P.B));        // concurrently
     else PS_TRY(iter_safe_dots(M, P, P.B, i));
     PS_TRY(join(M, P));
@@ -397,7 +417,7 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
                  ? launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, true>, pair_grid(M->n), 0, pa)
                  : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, false>, pair_grid(M->n), 0,
                           pa));
-      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{As, L, G, S, M->sc}, C_DONE));
+      PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{As, L, G, S, M->sc}, C_DONE, P.kry32));
       return PS_OK;
     }
     double *pa_part = M->fpart, *pb_part = pa_part + 2 * 5 * (size_t)M->ga;
@@ -408,12 +428,12 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
       PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, true>, pair_grid(M->n), 0, pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
                   EpiPBiCGSafeBDots<true>{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part},
-                  C_DONE));
+                  C_DONE, P.kry32));
     } else {
       PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, false>, pair_grid(M->n), 0, pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
                   EpiPBiCGSafeBDots<false>{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part},
-                  C_DONE));
+                  C_DONE, P.kry32));
     }
     return PS_OK;
   }
@@ -422,15 +442,15 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n, next_rev(M)};
   po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_OTHER, k_pou, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, C_DONE));  // q_i = A o_i
-  PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, C_DONE));  // w_i = A u_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, C_DONE, P.kry32));  // q_i = A o_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, C_DONE, P.kry32));  // w_i = A u_i
   TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n, next_rev(M)};
   tz.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_OTHER, k_tzyx, pair_grid(M->n), 0, tz));
-  PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, C_DONE));  // r_{i+1} = b - A x_{i+1}
-  PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, C_DONE));                  // l_i = A t_i
-  PS_TRY(spmv(M, A, PS_K_OTHER, Y, EpiStore{G}, C_DONE));                  // g_{i+1} = A y_{i+1}
-  PS_TRY(spmv(M, A, PS_K_OTHER, R, EpiStore{S}, C_DONE));                  // s_{i+1} = A r_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, C_DONE, P.res32));  // b - A x_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, C_DONE, P.kry32));  // l_i = A t_i
+  PS_TRY(spmv(M, A, PS_K_OTHER, Y, EpiStore{G}, C_DONE, P.kry32));  // g_{i+1} = A y_{i+1}
+  PS_TRY(spmv(M, A, PS_K_OTHER, R, EpiStore{S}, C_DONE, P.kry32));  // s_{i+1} = A r_{i+1}
   return PS_OK;
 }
 
@@ -438,12 +458,13 @@ int iter_ssbicgsafe2(ps_matrix *M, const Plan &P, int i) {
   hipStream_t A = P.A;
   double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y),
          *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P), *U = M->slot(PS_V_U), *Z = M->slot(PS_V_Z);
-  PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, C_DONE));  // s_i = A r_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, C_DONE, P.kry32));  // s_i = A r_i
   PS_TRY(iter_safe_dots(M, P, A, i));
   PouArgs po{R, S, T, Y, Pp, U, nullptr, M->sc, M->ctl, M->n, next_rev(M)};
   po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_pu, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, C_DONE));
+  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, C_DONE,
+              P.kry32));
   return PS_OK;
 }
 
@@ -456,14 +477,14 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
   s1.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1, pair_grid(M->n), 0, s1));
   PS_TRY(fork(M, P));
-  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, C_HALT));  // v_i = A z_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, C_HALT, P.kry32));  // v_i = A z_i
   PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, P.maxit, P.tol, 0, M->hist));
   PS_TRY(join(M, P));
   Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
   s2.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2, pair_grid(M->n), 0, s2));
   PS_TRY(fork(M, P));
-  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, C_HALT));  // t_{i+1} = A w_{i+1}
+  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, C_HALT, P.kry32));  // t_{i+1} = A w_{i+1}
   PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, P.maxit, P.tol, 0,
                                            M->hist));
   PS_TRY(join(M, P));
@@ -499,7 +520,7 @@ void clear_graphs(ps_matrix *M) {
 int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **out) {
   const GraphKey key{P.variant, P.maxit,   P.rr_m,           P.rr_M, P.overlap ? 1 : 0,
                      count,     M->sweep,  (P.fused ? 1 : 0) | (P.stream_nt ? 2 : 0),
-                     P.tol,     P.A};
+                     P.precision, P.tol,   P.A};
   for (GraphEntry &g : M->graphs)
     if (g.key == key) {
       *out = &g;
@@ -562,6 +583,20 @@ int ensure_hist(ps_matrix *M, int64_t need) {
   return PS_OK;
 }
 
+// The matrix values rounded to FP32 (nearest, ties to even), made on the
+// device from the FP64 values at the first mixed-precision solve and kept.
+int ensure_f32(ps_matrix *M, hipStream_t s) {
+  const bool csr = M->format == PS_FMT_CSR;
+  float *&dst = csr ? M->val32 : M->sval32;
+  if (dst) return PS_OK;
+  const int64_t cnt = csr ? M->nnz : M->slots;
+  PS_HIP(hipMalloc(&dst, std::max<int64_t>(cnt, 1) * sizeof(float)));
+  if (cnt > 0)
+    PS_TRY(launch(M, s, PS_K_OTHER, k_round_f32, elem_grid(cnt), 0,
+                  (const double *)(csr ? M->val : M->sval), dst, cnt));
+  return PS_OK;
+}
+
 // Sum the timed launches of iterations before the stop; launches of the
 // stopping iteration and of iterations enqueued after it may be no-ops and are
 // left out.
@@ -613,6 +648,9 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (o.schedule < -1 || o.schedule > 1 ||
       (o.schedule == 1 && (variant != PS_PBICGSAFE || batch)))
     return PS_EINVAL;
+  if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_KRYLOV ||
+      (o.precision != PS_PREC_FP64 && !M->f32_ok))
+    return PS_EINVAL;
   BusyGuard guard(M->busy);
   if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(M->device));
@@ -646,6 +684,10 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.fused = variant == PS_PBICGSAFE && !batch &&
             (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
   P.stream_nt = variant == PS_PBICGSAFE && streaming(M);
+  P.precision = o.precision;
+  P.kry32 = o.precision != PS_PREC_FP64;
+  P.res32 = o.precision == PS_PREC_FP32_MATRIX;
+  if (P.kry32) PS_TRY(ensure_f32(M, P.A));
   M->prof_mask = o.profile;
   M->cur_iter = -1;
   M->sweep = 0;
@@ -779,6 +821,8 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->blk);
   (void)hipFree(M->scol);
   (void)hipFree(M->sval);
+  (void)hipFree(M->val32);
+  (void)hipFree(M->sval32);
   (void)hipFree(M->soff);
   (void)hipFree(M->vec);
   (void)hipFree(M->sc);
@@ -875,6 +919,7 @@ void ps_default_options(ps_options *opt) {
   opt->graph = 1;
   opt->schedule = -1;
   opt->x0_fallback = 0;
+  opt->precision = PS_PREC_FP64;
   opt->stream = nullptr;
 }
 
@@ -947,6 +992,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   M->device = dev;
   M->n = n;
   M->nnz = nnz;
+  for (int64_t k = 0; k < nnz && M->f32_ok; ++k) M->f32_ok = std::isfinite((float)val[k]);
   // SpMV shape from the mean row length: short rows one lane each with the
   // smallest per-thread budget that holds kBlock average rows; longer rows get
   // 4, 8 or 16 lanes each

@@ -13,10 +13,14 @@
 
 namespace ps {
 
+// VT: the stored type of the values, double or float (the matrix rounded to
+// FP32 for the mixed-precision solves); a float value is widened exactly, so
+// every product and sum below is the same FP64 arithmetic either way.
+template <class VT>
 struct CsrDev {
   const int *rowptr;   // int32[n+1]
   const int *col;      // int32[nnz]
-  const double *val;   // double[nnz]
+  const VT *val;       // VT[nnz]
   const int *blk;      // int32[nblk+1] first row of each row block
   int nblk;
 };
@@ -55,9 +59,9 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // An epilogue with kDots > 0 also accumulates per-row terms of inner products
 // (compensated pairs, see dots.hpp) and writes the block's partial sums for row
 // block b; all lanes of the block take part in that reduction.
-template <int IPT, int LPR, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restrict__ x, Epi epi_all,
-                                                 Stop st, int rev) {
+template <int IPT, int LPR, class VT, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__restrict__ x,
+                                                 Epi epi_all, Stop st, int rev) {
   extern __shared__ double prod[];
   const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
   const int r0 = A.blk[b], r1 = A.blk[b + 1];
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
         vv[u] = 0.0;
         if (k + u * kBlock < k1) {
           cc[u] = A.col[k + u * kBlock];
-          vv[u] = A.val[k + u * kBlock];
+          vv[u] = (double)A.val[k + u * kBlock];
         }
       }
 #pragma unroll
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
       v[i] = 0.0;
       if (k < nz) {
         c[i] = A.col[k0 + k];
-        v[i] = A.val[k0 + k];
+        v[i] = (double)A.val[k0 + k];
       }
     }
     // every gather unconditional (unused slots read x[0]), so that all IPT are
@@ -169,9 +173,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, const double *__restr
 // column/value loads (RPL consecutive entries per lane: one 8- or 16-byte
 // load) and the gather of x are contiguous across the lanes of a wave, and no
 // LDS staging is needed.
+template <class VT>
 struct SellDev {
   const int *col;     // int32[slots], -1 = padding
-  const double *val;  // double[slots]
+  const VT *val;      // VT[slots] (double, or float: see CsrDev)
   const int *off;     // int32[nslice+1] first slot of each slice
   int n;
   int nblk;           // ceil(n / (kBlock * RPL)) workgroups
@@ -180,27 +185,34 @@ struct SellDev {
 // Slots per row loaded ahead of their gathers per step.
 constexpr int kSellUnroll = 8;
 
-template <int RPL>
-__device__ __forceinline__ void sell_load(const SellDev &S, int kk, int (&c)[RPL], double (&v)[RPL]) {
+template <int RPL, class VT>
+__device__ __forceinline__ void sell_load(const SellDev<VT> &S, int kk, int (&c)[RPL],
+                                          double (&v)[RPL]) {
   if constexpr (RPL == 2) {
     const int2 cc = *reinterpret_cast<const int2 *>(S.col + kk);
-    const double2 vv = *reinterpret_cast<const double2 *>(S.val + kk);
     c[0] = cc.x;
     c[1] = cc.y;
-    v[0] = vv.x;
-    v[1] = vv.y;
+    if constexpr (sizeof(VT) == 8) {
+      const double2 vv = *reinterpret_cast<const double2 *>(S.val + kk);
+      v[0] = vv.x;
+      v[1] = vv.y;
+    } else {
+      const float2 vv = *reinterpret_cast<const float2 *>(S.val + kk);
+      v[0] = (double)vv.x;
+      v[1] = (double)vv.y;
+    }
   } else {
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
       c[u] = S.col[kk + u];
-      v[u] = S.val[kk + u];
+      v[u] = (double)S.val[kk + u];
     }
   }
 }
 
-template <int RPL, class Epi>
-__global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__restrict__ x, Epi epi_all,
-                                                 Stop st, int rev) {
+template <int RPL, class VT, class Epi>
+__global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT> S, const double *__restrict__ x,
+                                                 Epi epi_all, Stop st, int rev) {
   constexpr int ND = Epi::kDots;
   constexpr int SH = kWave * RPL;
   DD dacc[ND > 0 ? ND : 1];
@@ -233,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev S, const double *__rest
           c[t][u] = -1;
           v[t][u] = 0.0;
         }
-        if (kk < end) sell_load<RPL>(S, kk, c[t], v[t]);
+        if (kk < end) sell_load<RPL, VT>(S, kk, c[t], v[t]);
       }
       // unconditional gathers (padding reads x[0]): all of them in flight at once
       double xv[kSellUnroll][RPL];

@@ -398,6 +398,14 @@ __global__ __launch_bounds__(kBlock) void k_zero(double *base, int64_t ld, int c
   for (int c = 0; c < count; ++c) base[c * ld + k] = 0.0;
 }
 
+// dst = src rounded to the nearest FP32 number (ties to even: the default
+// rounding mode of the conversion)
+__global__ __launch_bounds__(kBlock) void k_round_f32(const double *__restrict__ src,
+                                                      float *__restrict__ dst, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) dst[k] = (float)src[k];
+}
+
 __global__ __launch_bounds__(kBlock) void k_copy(double *__restrict__ dst,
                                                  const double *__restrict__ src, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;

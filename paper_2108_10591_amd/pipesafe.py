@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpipesafe
 VARIANTS = {"ssbicgsafe2": 0, "pbicgsafe": 1, "pbicgsafe_rr": 2, "pbicgstab": 3}
 CONVERGED, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 STATUS_NAMES = {0: "converged", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
+# ps_options.precision: the matrix values the products read (include/pipesafe.h)
+PRECISIONS = {"fp64": 0, "fp32_matrix": 1, "fp32_krylov": 2}
 VEC = ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o", "As", "v", "b"]
 SCAL = ["alpha", "beta", "zeta", "eta", "omega", "f", "rhoref", "rho", "pending", "gs", "gw", "gz"]
 KERNEL_CLASSES = {"spmv": 0, "dots": 1, "update": 2, "spmv_fused": 3, "other": 4, "dots_finish": 5}
@@ -36,7 +38,7 @@ class Options(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("resume", ctypes.c_int32),
                 ("resume_iter", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("x0_fallback", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -113,6 +115,8 @@ def options(**kw) -> Options:
     for k, v in kw.items():
         if k == "profile" and isinstance(v, (list, tuple, set)):
             v = sum(1 << KERNEL_CLASSES[c] for c in v)
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
         setattr(o, k, v)
     return o
 

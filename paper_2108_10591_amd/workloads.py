@@ -141,7 +141,8 @@ def rand_band(n: int = 1_000_000, seed: int = 10591, gamma: float = 1.37629, lmi
     """Random nonsymmetric CSR with uneven rows.
 
     Row lengths (diagonal included) follow p(L) ~ L^-gamma on [lmin, lmax]
-    (gamma = 1.37629 gives mean 27 on [3, 200]); off-diagonal columns are drawn
+    (gamma = 1.37629 gives mean 27 on [3, 200]), capped by the columns the band
+    holds; off-diagonal columns are drawn
     uniformly without replacement within +-band of the diagonal; off-diagonal
     values are U(-1, 1) and the diagonal is diag_factor times the row's
     absolute off-diagonal sum.
@@ -151,8 +152,11 @@ def rand_band(n: int = 1_000_000, seed: int = 10591, gamma: float = 1.37629, lmi
     p = lengths.astype(np.float64) ** -gamma
     p /= p.sum()
     L = rng.choice(lengths, size=n, p=p)
-    m = (L - 1).astype(np.int64)
-    rows = np.repeat(np.arange(n, dtype=np.int64), m)
+    # a row cannot hold more off-diagonal entries than its band has columns
+    r = np.arange(n, dtype=np.int64)
+    cand = np.minimum(n - 1, r + band) - np.maximum(0, r - band)
+    m = np.minimum(L - 1, cand).astype(np.int64)
+    rows = np.repeat(r, m)
     lo = np.maximum(0, rows - band)
     hi = np.minimum(n - 1, rows + band)
     width = hi - lo  # candidates excluding the diagonal
@@ -183,7 +187,7 @@ def rand_band(n: int = 1_000_000, seed: int = 10591, gamma: float = 1.37629, lmi
     col = allcols[order].astype(np.int32)
     val = allvals[order]
     rowptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(L, out=rowptr[1:])
+    np.cumsum(m + 1, out=rowptr[1:])
     return CSR(n, rowptr, col, val, rhs_ones(rowptr, val), f"rand_band_{n}")
 
 
