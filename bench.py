@@ -186,6 +186,57 @@ def bench_batch(name, reps=3):
             "speedup": round(t_seq / t_batch, 2)}
 
 
+def bench_mixed(name, rr_ms, reps=3):
+    """Mixed precision on one system: time to the workload's tolerance from x0 = 0 in FP64
+    (p-BiCGSafe, and p-BiCGSafe-rr at each replacement period m), with the matrix values
+    rounded to FP32 in every product (p-BiCGSafe), and with them rounded in the Krylov
+    products only (p-BiCGSafe-rr, FP64 replacement residual).  Each result states its true
+    FP64 residual ||b - A x|| / ||b|| (FP64 product on the GPU) and its distance from the
+    FP64 p-BiCGSafe solution."""
+    import torch
+
+    from paper_2108_10591_amd import pipesafe, workloads
+    A = workloads.workload(name)
+    tol = workloads.WORKLOADS[name]["tol"]
+    log(f"mixed precision {name}: n = {A.n}, nnz = {A.nnz}, tol {tol}")
+    b = torch.from_numpy(A.b).cuda()
+    x = torch.empty_like(b)
+    runs = [("fp64", "pbicgsafe", 0, 100), ("fp32_matrix", "pbicgsafe", 1, 100)]
+    for m in rr_ms:
+        runs += [(f"fp64_rr_m{m}", "pbicgsafe_rr", 0, m), (f"fp32_krylov_rr_m{m}", "pbicgsafe_rr", 2, m)]
+    out = {"workload": name, "n": A.n, "nnz": A.nnz, "tol": tol, "x0": "zero",
+           "stop": "||r_i|| <= tol ||r_0|| (recursive residual)"}
+    with pipesafe.Matrix.from_csr(A) as M:
+        out["layout"] = M.info()["format"]
+        nb = float(torch.linalg.vector_norm(b))
+        x64 = None
+        for label, variant, prec, m in runs:
+            kw = dict(tol=tol, maxit=10_000, variant=variant, rr_m=m, precision=prec, hist=False)
+            r = M.solve_dev(b, None, x, **kw)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                r = M.solve_dev(b, None, x, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = sorted(ts)[len(ts) // 2]
+            res = float(torch.linalg.vector_norm(b - M.spmv_dev(x))) / nb
+            if x64 is None:
+                x64 = x.clone()
+            err = float((x - x64).abs().max() / x64.abs().max())
+            out[label] = {"variant": variant, "rr_m": m if variant == "pbicgsafe_rr" else None,
+                          "iterations": r.iters, "status": r.status_name,
+                          "time_to_tol_ms": round(1e3 * t, 3),
+                          "us_per_iter": round(1e6 * t / max(r.iters, 1), 2),
+                          "true_residual_fp64": res, "err_vs_fp64_solution": err}
+            log(f"  {label}: {out[label]}")
+    t64 = out["fp64"]["time_to_tol_ms"]
+    for label, *_ in runs[1:]:
+        out[label]["speedup_vs_fp64"] = round(t64 / out[label]["time_to_tol_ms"], 3)
+    return out
+
+
 def bench_warmstart(count, epochs):
     """The learned initial guess on 128 x 128 variable-coefficient problems: training data
     solved on the GPU, the network trained on the GPU, then 64 held-out problems solved to
@@ -216,6 +267,9 @@ def main():
     ap.add_argument("--warmstart-count", type=int, default=4096,
                     help="training problems of the learned-initial-guess leg (20000 for the full run)")
     ap.add_argument("--warmstart-epochs", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--mixed-rr-m", default="100",
+                    help="replacement periods of the mixed-precision leg (comma-separated)")
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
     ap.add_argument("--schedule", type=int, default=-1,
@@ -369,6 +423,9 @@ def main():
 
     if not args.no_warmstart:
         out["warm_start"] = bench_warmstart(args.warmstart_count, args.warmstart_epochs)
+    if not args.no_mixed:
+        out["mixed_precision"] = bench_mixed("rand_band_1m",
+                                             [int(m) for m in args.mixed_rr_m.split(",")])
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_iters} iterations ...")

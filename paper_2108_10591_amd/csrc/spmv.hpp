@@ -91,36 +91,58 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
     DD acc[1] = {DD{0.0, 0.0}};
     constexpr int kU = 4;  // nonzeros per lane in flight
     for (int k = k0 + threadIdx.x; k < k1; k += kU * kBlock) {
+      // loads from a clamped slot (this row's first) instead of a guarded branch, and
+      // values widened only at the product: with FP32 values a branch around each
+      // load would hold its conversion and make every load wait for itself
       int cc[kU];
-      double vv[kU], xx[kU];
+      VT vv[kU];
+      double xx[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        cc[u] = 0;
-        vv[u] = 0.0;
-        if (k + u * kBlock < k1) {
-          cc[u] = A.col[k + u * kBlock];
-          vv[u] = (double)A.val[k + u * kBlock];
-        }
+        const int kk = k + u * kBlock < k1 ? k + u * kBlock : k0;
+        cc[u] = A.col[kk];
+        vv[u] = A.val[kk];
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) xx[u] = x[cc[u]];
 #pragma unroll
       for (int u = 0; u < kU; ++u)
-        if (k + u * kBlock < k1) sum_acc(acc[0], vv[u] * xx[u]);
+        if (k + u * kBlock < k1) sum_acc(acc[0], (double)vv[u] * xx[u]);
     }
     const DD t = block_sum_dd<1>(acc, prod);
     if (threadIdx.x == 0) put(r0, t.hi + t.lo, epi.load(r0));
   } else {
     int c[IPT];
-    double v[IPT], xv[IPT];
+    VT v[IPT];  // widened at the product
+    double xv[IPT];
+    if constexpr (sizeof(VT) == 8) {
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const int k = threadIdx.x + i * kBlock;
-      c[i] = 0;
-      v[i] = 0.0;
-      if (k < nz) {
-        c[i] = A.col[k0 + k];
-        v[i] = (double)A.val[k0 + k];
+      for (int i = 0; i < IPT; ++i) {
+        const int k = threadIdx.x + i * kBlock;
+        c[i] = 0;
+        v[i] = 0.0;
+        if (k < nz) {
+          c[i] = A.col[k0 + k];
+          v[i] = A.val[k0 + k];
+        }
+      }
+    } else {
+      // FP32 values: a guarded load would be widened inside its branch and wait
+      // for itself there, so unused slots load the block's first slot instead
+      // (a line lane 0 loads anyway); their products are never stored
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        c[i] = 0;
+        v[i] = VT(0);
+      }
+      if (nz > 0) {
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+          const int k = threadIdx.x + i * kBlock;
+          const int kk = k0 + (k < nz ? k : 0);
+          c[i] = A.col[kk];
+          v[i] = A.val[kk];
+        }
       }
     }
     // every gather unconditional (unused slots read x[0]), so that all IPT are
@@ -130,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const int k = threadIdx.x + i * kBlock;
-      if (k < nz) prod[k] = v[i] * xv[i];
+      if (k < nz) prod[k] = (double)v[i] * xv[i];
     }
     __syncthreads();
     if constexpr (LPR == 1) {
@@ -187,7 +209,7 @@ constexpr int kSellUnroll = 8;
 
 template <int RPL, class VT>
 __device__ __forceinline__ void sell_load(const SellDev<VT> &S, int kk, int (&c)[RPL],
-                                          double (&v)[RPL]) {
+                                          VT (&v)[RPL]) {
   if constexpr (RPL == 2) {
     const int2 cc = *reinterpret_cast<const int2 *>(S.col + kk);
     c[0] = cc.x;
@@ -198,14 +220,14 @@ __device__ __forceinline__ void sell_load(const SellDev<VT> &S, int kk, int (&c)
       v[1] = vv.y;
     } else {
       const float2 vv = *reinterpret_cast<const float2 *>(S.val + kk);
-      v[0] = (double)vv.x;
-      v[1] = (double)vv.y;
+      v[0] = vv.x;
+      v[1] = vv.y;
     }
   } else {
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
       c[u] = S.col[kk + u];
-      v[u] = (double)S.val[kk + u];
+      v[u] = S.val[kk + u];
     }
   }
 }
@@ -236,14 +258,15 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT> S, const double *__
     for (int u = 0; u < RPL; ++u) acc[u] = DD{0.0, 0.0};
     for (int k = S.off[sl] + lane * RPL; k < end; k += kSellUnroll * SH) {
       int c[kSellUnroll][RPL];
-      double v[kSellUnroll][RPL];
+      VT v[kSellUnroll][RPL];  // widened at the product: a conversion next to its load
+                               // would make each load wait for itself
 #pragma unroll
       for (int t = 0; t < kSellUnroll; ++t) {
         const int kk = k + t * SH;
 #pragma unroll
         for (int u = 0; u < RPL; ++u) {
           c[t][u] = -1;
-          v[t][u] = 0.0;
+          v[t][u] = VT(0);
         }
         if (kk < end) sell_load<RPL, VT>(S, kk, c[t], v[t]);
       }
@@ -257,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT> S, const double *__
       for (int t = 0; t < kSellUnroll; ++t)
 #pragma unroll
         for (int u = 0; u < RPL; ++u)
-          if (c[t][u] >= 0) sum_acc(acc[u], v[t][u] * xv[t][u]);
+          if (c[t][u] >= 0) sum_acc(acc[u], (double)v[t][u] * xv[t][u]);
     }
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
