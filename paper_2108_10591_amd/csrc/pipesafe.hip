@@ -995,9 +995,10 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   for (int64_t k = 0; k < nnz && M->f32_ok; ++k) M->f32_ok = std::isfinite((float)val[k]);
   // SpMV shape from the mean row length: short rows one lane each with the
   // smallest per-thread budget that holds kBlock average rows; longer rows get
-  // 4, 8 or 16 lanes each
+  // 4, 8 or 16 lanes each (4 up to a mean of 40: measured best on power-law
+  // band matrices with means 18-31, equal to 8 lanes at 40)
   const double mean = (double)nnz / (double)n;
-  M->shape = mean * 1.1 <= 4.0 ? 0 : (mean * 1.1 <= 8.0 ? 1 : (mean <= 16.0 ? 2 : (mean <= 64.0 ? 3 : 4)));
+  M->shape = mean * 1.1 <= 4.0 ? 0 : (mean * 1.1 <= 8.0 ? 1 : (mean <= 40.0 ? 2 : (mean <= 64.0 ? 3 : 4)));
   if (const char *e = std::getenv("PIPESAFE_SPMV_SHAPE")) {  // tuning override
     const int v = std::atoi(e);
     if (v >= 0 && v <= 4) M->shape = v;

@@ -84,6 +84,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
     re = A.rowptr[r + 1];
     ein = epi.load(r);
   }
+  // LPR > 1: lane j of each group finishes the group's row of round j (the group
+  // sum leaves the row's value in every lane), so it loads that row's epilogue
+  // operands here, before the products, instead of after the sum
+  if constexpr (LPR > 1) {
+    const int rr = r0 + (threadIdx.x % LPR) * (kBlock / LPR) + threadIdx.x / LPR;
+    if (rr < r1) ein = epi.load(rr);
+  }
   const int k0 = A.rowptr[r0], k1 = A.rowptr[r1];
   const int nz = k1 - k0;
   if (nz > IPT * kBlock) {
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
     } else {
       constexpr int kGroups = kBlock / LPR;
       const int g = threadIdx.x / LPR, j = threadIdx.x % LPR;
-      for (int base = 0; base < r1 - r0; base += kGroups) {  // same trip count in every lane
+      for (int t = 0, base = 0; base < r1 - r0; ++t, base += kGroups) {  // same trip count
         const int rr = r0 + base + g;
         DD acc{0.0, 0.0};
         if (rr < r1) {
@@ -172,7 +179,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
           for (int k = a + j; k < e; k += LPR) sum_acc(acc, prod[k]);
         }
         group_sum_dd<LPR>(acc);
-        if (j == 0 && rr < r1) put(rr, acc.hi + acc.lo, epi.load(rr));
+        if (rr < r1) {
+          if (t < LPR) {
+            if (j == t) put(rr, acc.hi + acc.lo, ein);
+          } else if (j == 0) {
+            put(rr, acc.hi + acc.lo, epi.load(rr));
+          }
+        }
       }
     }
   }

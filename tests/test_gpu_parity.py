@@ -126,6 +126,57 @@ def _solve_both(A, variant, tol, maxit=5000, **opt):
     return ref, res
 
 
+@contextlib.contextmanager
+def csr_shape(shape):
+    """Force the CSR layout and the product's launch shape (PIPESAFE_SPMV_SHAPE 0..4:
+    (nonzeros per thread, lanes per row) = (4,1) (8,1) (16,4) (16,8) (16,16))."""
+    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SPMV_SHAPE")
+    old = {k: os.environ.get(k) for k in keys}
+    os.environ["PIPESAFE_FORMAT"] = "0"
+    os.environ["PIPESAFE_SPMV_SHAPE"] = str(shape)
+    try:
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def _uneven_rows():
+    """Short and long rows mixed, one row past a block's LDS budget, diagonally dominant."""
+    rng = np.random.default_rng(17)
+    lens = rng.integers(1, 40, 2500)
+    lens[[3, 700, 701, 2499]] = [150, 900, 5000, 300]
+    S = W.random_csr(2500, 5, lengths=lens).to_scipy().tolil()
+    S.setdiag(1.5 * np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)
+    S = S.tocsr()
+    S.sort_indices()
+    rowptr = S.indptr.astype(np.int64)
+    val = S.data.astype(np.float64)
+    return W.CSR(n=2500, rowptr=rowptr, col=S.indices.astype(np.int32), val=val,
+                 b=W.rhs_ones(rowptr, val), name="uneven_rows_2500")
+
+
+@pytest.mark.parametrize("shape", range(5))
+def test_every_csr_shape_reproduces_oracle(shape):
+    """Each launch shape of the CSR product with every epilogue that finishes a row (the
+    multi-lane shapes load a row's epilogue operands before its sum, in the lane that
+    stores it): p-BiCGSafe in both schedules, ssBiCGSafe2, p-BiCGSafe-rr."""
+    for A in (_uneven_rows(), W.small_nonsym(3001, 11, density=0.003)):
+        with csr_shape(shape), pipesafe.Matrix.from_csr(A) as M:
+            assert M.info()["format"] == "csr" and M.info()["spmv_shape"] == shape
+            for variant, kw in (("pbicgsafe", dict(schedule=0)), ("pbicgsafe", dict(schedule=1)),
+                                ("ssbicgsafe2", {}), ("pbicgsafe_rr", dict(rr_m=7))):
+                say(f"csr shape {shape} {A.name} {variant} {kw}")
+                ref = O.solve(A, tol=1e-10, maxit=800, variant=variant, rr_m=kw.get("rr_m", 100))
+                res = M.solve(A.b, tol=1e-10, maxit=800, variant=variant, **kw)
+                assert res.status == ref.status and res.iters == ref.iters, (shape, variant)
+                assert np.array_equal(res.hist, ref.hist), (shape, variant)
+                assert np.array_equal(res.x, ref.x), (shape, variant)
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_full_solve_cd2d_64(variant):
     say(f"full solve cd2d_64 {variant}")
