@@ -56,7 +56,8 @@ def log(*a):
 def matrix_bytes(n, nnz, info=None):
     """Bytes one sparse product streams from the matrix: CSR int32 column index + FP64
     value per nonzero and an int32 row pointer, or (when the library chose the sliced
-    ELLPACK layout) 12 bytes per stored slot and an int32 offset per 64-row slice."""
+    ELLPACK layout) an FP64 value and a 32- or 16-bit column index per stored slot and an
+    int32 offset per 64-row slice (ps_info.matrix_bytes)."""
     if info is not None:
         return info["matrix_bytes"]
     return 12 * nnz + 4 * (n + 1)

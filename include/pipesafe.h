@@ -156,7 +156,8 @@ typedef struct {
   int32_t spmv_blocks;   /* workgroups of one sparse product                            */
   int32_t dot_grid;      /* workgroups of the multi-inner-product kernel                */
   int64_t matrix_bytes;  /* bytes one sparse product must stream from the matrix arrays:
-                            CSR 12 nnz + 4 (n+1); SELL 12 slots + 4 (slices+1)          */
+                            CSR 12 nnz + 4 (n+1); SELL (8 + index_bits/8) slots +
+                            4 (slices+1)                                                */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe    */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
@@ -167,6 +168,11 @@ typedef struct {
                             PIPESAFE_STREAM=0|1 sets; the results are the same       */
   int64_t n_padded;      /* rows on the device: n, or for a batch the systems padded to
                             multiples of 512 rows                                      */
+  int32_t index_bits;    /* stored column index: 32, or 16 for the sliced layout when
+                            every entry lies within 32767 of its row's diagonal (then
+                            column - row is stored: 10 instead of 12 bytes per slot;
+                            PIPESAFE_SELL_INDEX=32 keeps 32)                           */
+  int32_t reserved;
 } ps_info;
 
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */
@@ -221,9 +227,10 @@ void ps_default_options(ps_options *opt);
  * product's launch shape are chosen here from the row lengths; the
  * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SELL_RPL
  * (rows per lane of the sliced layout: 1, the default, or 2 with 128-row
- * slices), PIPESAFE_SPMV_SHAPE (0..4), PIPESAFE_DOT_GRID (1..8192
- * workgroups) and PIPESAFE_STREAM (0 or 1, ps_info.streaming) override the
- * choices, for tuning and tests.  Every choice gives
+ * slices), PIPESAFE_SELL_INDEX (32: no 16-bit column offsets),
+ * PIPESAFE_SPMV_SHAPE (0..4), PIPESAFE_DOT_GRID (1..8192 workgroups) and
+ * PIPESAFE_STREAM (0 or 1, ps_info.streaming) override the choices, for
+ * tuning and tests.  Every choice gives
  * the same results.
  */
 int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,

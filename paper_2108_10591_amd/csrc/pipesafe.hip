@@ -99,6 +99,8 @@ struct ps_matrix {
   int shape = 1;            // SpMV shape: 0..4 = (IPT, LPR) (4,1) (8,1) (16,4) (16,8) (16,16)
   int format = PS_FMT_CSR;  // device layout of the matrix
   int *scol = nullptr, *soff = nullptr;  // sliced ELLPACK arrays (format PS_FMT_SELL)
+  short *scol16 = nullptr;               // sliced ELLPACK column - row (index_bits 16)
+  int index_bits = 32;                   // stored column index of the sliced layout
   double *sval = nullptr;
   int64_t slots = 0;
   int nslice = 0;
@@ -150,8 +152,18 @@ struct ps_matrix {
   int nblk512() const { return (int)(n / 512); }
   CsrDev<double> csr() const { return {rowptr, col, val, blk, nblk}; }
   CsrDev<float> csr32() const { return {rowptr, col, val32, blk, nblk}; }
-  SellDev<double> sell() const { return {scol, sval, soff, (int)n, nblk}; }
-  SellDev<float> sell32() const { return {scol, sval32, soff, (int)n, nblk}; }
+  template <class VT, class IT>
+  SellDev<VT, IT> sell() const {
+    SellDev<VT, IT> S{};
+    if constexpr (sizeof(IT) == 4) S.col = scol;
+    else S.col = scol16;
+    if constexpr (sizeof(VT) == 8) S.val = sval;
+    else S.val = sval32;
+    S.off = soff;
+    S.n = (int)n;
+    S.nblk = nblk;
+    return S;
+  }
 };
 
 namespace {
@@ -234,6 +246,15 @@ int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, 
                 stop, rev);
 }
 
+template <class VT, class IT, class Epi>
+int sell_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, Stop stop,
+                int rev) {
+  const SellDev<VT, IT> S = M->template sell<VT, IT>();
+  const dim3 g(M->nblk);
+  return M->sell_rpl == 2 ? launch(M, s, cls, k_sell<2, VT, IT, Epi>, g, 0, S, x, epi, stop, rev)
+                          : launch(M, s, cls, k_sell<1, VT, IT, Epi>, g, 0, S, x, epi, stop, rev);
+}
+
 // One sparse product with epilogue `epi`; `stop_word` (C_DONE, C_HALT or -1)
 // names the control word that makes it a no-op (per system).  f32: read the
 // values rounded to FP32 (mixed-precision solves) instead of the FP64 ones.
@@ -243,14 +264,11 @@ int spmv(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, int sto
   const int rev = next_rev(M);
   const Stop stop{M->ctl, stop_word, M->chunk_sys};
   if (M->format == PS_FMT_SELL) {
-    const dim3 g(M->nblk);
-    if (f32)
-      return M->sell_rpl == 2
-                 ? launch(M, s, cls, k_sell<2, float, Epi>, g, 0, M->sell32(), x, epi, stop, rev)
-                 : launch(M, s, cls, k_sell<1, float, Epi>, g, 0, M->sell32(), x, epi, stop, rev);
-    return M->sell_rpl == 2
-               ? launch(M, s, cls, k_sell<2, double, Epi>, g, 0, M->sell(), x, epi, stop, rev)
-               : launch(M, s, cls, k_sell<1, double, Epi>, g, 0, M->sell(), x, epi, stop, rev);
+    if (M->index_bits == 16)
+      return f32 ? sell_launch<float, short>(M, s, cls, x, epi, stop, rev)
+                 : sell_launch<double, short>(M, s, cls, x, epi, stop, rev);
+    return f32 ? sell_launch<float, int>(M, s, cls, x, epi, stop, rev)
+               : sell_launch<double, int>(M, s, cls, x, epi, stop, rev);
   }
   switch (M->shape) {
     case 0: return spmv_launch<4, 1>(M, s, cls, x, epi, stop, rev, f32);
@@ -618,8 +636,9 @@ int collect_profile(ps_matrix *M, int stop_iter) {
 }
 
 int64_t matrix_bytes(const ps_matrix *M) {
-  return M->format == PS_FMT_CSR ? 12 * M->nnz + 4 * (M->n + 1)
-                                 : 12 * M->slots + 4 * ((int64_t)M->nslice + 1);
+  return M->format == PS_FMT_CSR
+             ? 12 * M->nnz + 4 * (M->n + 1)
+             : (8 + M->index_bits / 8) * M->slots + 4 * ((int64_t)M->nslice + 1);
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
 bool auto_fused(const ps_matrix *M) { return M->format == PS_FMT_SELL && M->n >= kFusedMinRows; }
@@ -820,6 +839,7 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->val);
   (void)hipFree(M->blk);
   (void)hipFree(M->scol);
+  (void)hipFree(M->scol16);
   (void)hipFree(M->sval);
   (void)hipFree(M->val32);
   (void)hipFree(M->sval32);
@@ -1027,6 +1047,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   if (slots >= INT32_MAX) M->format = PS_FMT_CSR;
   std::vector<int> blk, rp32;
   std::vector<int> scol, soff;
+  std::vector<short> scol16;
   std::vector<double> sval;
   if (M->format == PS_FMT_CSR) {
     blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock,
@@ -1039,7 +1060,20 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     M->nslice = (int)nslice;
     M->slots = slots;
     M->nblk = (int)((n + kBlock * M->sell_rpl - 1) / (kBlock * M->sell_rpl));
-    scol.assign((size_t)slots, -1);
+    // 16-bit column offsets when every entry lies within 32767 of its diagonal
+    bool fits16 = true;
+    for (int64_t r = 0; r < n && fits16; ++r)
+      for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+        if (col[k] - r > 32767 || r - col[k] > 32767) {
+          fits16 = false;
+          break;
+        }
+    M->index_bits = fits16 ? 16 : 32;
+    if (const char *e = std::getenv("PIPESAFE_SELL_INDEX")) {  // tuning override: 16 or 32
+      if (std::atoi(e) == 32) M->index_bits = 32;
+    }
+    if (M->index_bits == 16) scol16.assign((size_t)slots, kSellPad16);
+    else scol.assign((size_t)slots, -1);
     sval.assign((size_t)slots, 0.0);
     soff.assign((size_t)nslice + 1, 0);
     for (int64_t sl = 0; sl < nslice; ++sl) {
@@ -1051,7 +1085,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     for (int64_t r = 0; r < n; ++r) {
       const int64_t base = soff[r / SH] + r % SH;
       for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
-        scol[base + (k - rowptr[r]) * SH] = col[k];
+        if (M->index_bits == 16) scol16[base + (k - rowptr[r]) * SH] = (short)(col[k] - r);
+        else scol[base + (k - rowptr[r]) * SH] = col[k];
         sval[base + (k - rowptr[r]) * SH] = val[k];
       }
     }
@@ -1081,7 +1116,10 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     PS_CREATE_HIP(hipMalloc(&M->val, std::max<int64_t>(nnz, 1) * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->blk, blk.size() * sizeof(int)));
   } else {
-    PS_CREATE_HIP(hipMalloc(&M->scol, std::max<int64_t>(slots, 1) * sizeof(int)));
+    if (M->index_bits == 16)
+      PS_CREATE_HIP(hipMalloc(&M->scol16, std::max<int64_t>(slots, 1) * sizeof(short)));
+    else
+      PS_CREATE_HIP(hipMalloc(&M->scol, std::max<int64_t>(slots, 1) * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->sval, std::max<int64_t>(slots, 1) * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->soff, soff.size() * sizeof(int)));
   }
@@ -1111,7 +1149,10 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
       (csr && nnz > 0 && !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
       (csr && nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
       (csr && !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice))) ||
-      (!csr && slots > 0 && !chk(hipMemcpy(M->scol, scol.data(), slots * sizeof(int), hipMemcpyHostToDevice))) ||
+      (!csr && slots > 0 && M->index_bits == 32 &&
+       !chk(hipMemcpy(M->scol, scol.data(), slots * sizeof(int), hipMemcpyHostToDevice))) ||
+      (!csr && slots > 0 && M->index_bits == 16 &&
+       !chk(hipMemcpy(M->scol16, scol16.data(), slots * sizeof(short), hipMemcpyHostToDevice))) ||
       (!csr && slots > 0 && !chk(hipMemcpy(M->sval, sval.data(), slots * sizeof(double), hipMemcpyHostToDevice))) ||
       (!csr && !chk(hipMemcpy(M->soff, soff.data(), soff.size() * sizeof(int), hipMemcpyHostToDevice))) ||
       !chk(hipMemset(M->vec, 0, (size_t)kNumSlots * M->ld * sizeof(double))) ||
@@ -1220,6 +1261,7 @@ int ps_matrix_info(ps_matrix *A, ps_info *info) {
   info->auto_schedule = auto_fused(A) && A->nsys == 1 ? 1 : 0;
   info->nsys = A->nsys;
   info->streaming = streaming(A) ? 1 : 0;
+  info->index_bits = A->format == PS_FMT_SELL ? A->index_bits : 32;
   info->n_padded = A->n;
   return PS_OK;
 }

@@ -204,13 +204,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
 // consecutive rows (one wavefront, RPL rows per lane); slice s holds its
 // rows' nonzeros column by column, width w_s = its longest row, so entry j of
 // row q of the slice sits at off[s] + j * SH + q.  Each row keeps its CSR
-// order; shorter rows are padded with col = -1, which is skipped.  The
-// column/value loads (RPL consecutive entries per lane: one 8- or 16-byte
-// load) and the gather of x are contiguous across the lanes of a wave, and no
-// LDS staging is needed.
-template <class VT>
+// order; shorter rows are padded, and padding is skipped.  The column/value
+// loads (RPL consecutive entries per lane) and the gather of x are contiguous
+// across the lanes of a wave, and no LDS staging is needed.
+//
+// IT: the stored column index.  int: the column itself, -1 = padding.  short:
+// the column minus the row (when every entry lies within 32767 of its row's
+// diagonal, as in stencils), kSellPad16 = padding -- 10 instead of 12 bytes
+// per FP64 slot.
+constexpr short kSellPad16 = -32768;
+
+template <class VT, class IT>
 struct SellDev {
-  const int *col;     // int32[slots], -1 = padding
+  const IT *col;      // IT[slots] (see above)
   const VT *val;      // VT[slots] (double, or float: see CsrDev)
   const int *off;     // int32[nslice+1] first slot of each slice
   int n;
@@ -220,13 +226,19 @@ struct SellDev {
 // Slots per row loaded ahead of their gathers per step.
 constexpr int kSellUnroll = 8;
 
-template <int RPL, class VT>
-__device__ __forceinline__ void sell_load(const SellDev<VT> &S, int kk, int (&c)[RPL],
+template <int RPL, class VT, class IT>
+__device__ __forceinline__ void sell_load(const SellDev<VT, IT> &S, int kk, IT (&c)[RPL],
                                           VT (&v)[RPL]) {
   if constexpr (RPL == 2) {
-    const int2 cc = *reinterpret_cast<const int2 *>(S.col + kk);
-    c[0] = cc.x;
-    c[1] = cc.y;
+    if constexpr (sizeof(IT) == 4) {
+      const int2 cc = *reinterpret_cast<const int2 *>(S.col + kk);
+      c[0] = cc.x;
+      c[1] = cc.y;
+    } else {
+      const short2 cc = *reinterpret_cast<const short2 *>(S.col + kk);
+      c[0] = cc.x;
+      c[1] = cc.y;
+    }
     if constexpr (sizeof(VT) == 8) {
       const double2 vv = *reinterpret_cast<const double2 *>(S.val + kk);
       v[0] = vv.x;
@@ -245,8 +257,8 @@ __device__ __forceinline__ void sell_load(const SellDev<VT> &S, int kk, int (&c)
   }
 }
 
-template <int RPL, class VT, class Epi>
-__global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT> S, const double *__restrict__ x,
+template <int RPL, class VT, class IT, class Epi>
+__global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double *__restrict__ x,
                                                  Epi epi_all, Stop st, int rev) {
   constexpr int ND = Epi::kDots;
   constexpr int SH = kWave * RPL;
@@ -273,15 +285,35 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT> S, const double *__
       int c[kSellUnroll][RPL];
       VT v[kSellUnroll][RPL];  // widened at the product: a conversion next to its load
                                // would make each load wait for itself
+      if constexpr (sizeof(IT) == 4) {
 #pragma unroll
-      for (int t = 0; t < kSellUnroll; ++t) {
-        const int kk = k + t * SH;
+        for (int t = 0; t < kSellUnroll; ++t) {
+          const int kk = k + t * SH;
 #pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-          c[t][u] = -1;
-          v[t][u] = VT(0);
+          for (int u = 0; u < RPL; ++u) {
+            c[t][u] = -1;
+            v[t][u] = VT(0);
+          }
+          if (kk < end) sell_load<RPL, VT, IT>(S, kk, c[t], v[t]);
         }
-        if (kk < end) sell_load<RPL, VT>(S, kk, c[t], v[t]);
+      } else {
+        // 16-bit offsets: loads from a clamped slot (this step's first, which is in
+        // range) instead of a guarded branch, columns formed after all loads are
+        // issued, so that no load waits for itself
+        IT d[kSellUnroll][RPL];
+#pragma unroll
+        for (int t = 0; t < kSellUnroll; ++t) {
+          const int kk = k + t * SH < end ? k + t * SH : k;
+          sell_load<RPL, VT, IT>(S, kk, d[t], v[t]);
+        }
+        // keep the scheduler from moving the column arithmetic (and so a wait)
+        // between the loads
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < kSellUnroll; ++t)
+#pragma unroll
+          for (int u = 0; u < RPL; ++u)
+            c[t][u] = (k + t * SH < end && d[t][u] != kSellPad16) ? r0 + u + (int)d[t][u] : -1;
       }
       // unconditional gathers (padding reads x[0]): all of them in flight at once
       double xv[kSellUnroll][RPL];

@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
                 ("nnz", ctypes.c_int64), ("slots", ctypes.c_int64), ("spmv_blocks", ctypes.c_int32),
                 ("dot_grid", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
                 ("auto_overlap", ctypes.c_int32), ("auto_schedule", ctypes.c_int32),
-                ("nsys", ctypes.c_int32), ("streaming", ctypes.c_int32), ("n_padded", ctypes.c_int64)]
+                ("nsys", ctypes.c_int32), ("streaming", ctypes.c_int32), ("n_padded", ctypes.c_int64),
+                ("index_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 FORMATS = {0: "csr", 1: "sell"}

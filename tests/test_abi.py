@@ -50,7 +50,7 @@ def test_options_defaults_and_strerror(lib):
     assert (o.rr_m, o.rr_M, o.norm_ref, o.batch_iters, o.overlap, o.profile, o.resume, o.graph,
             o.schedule, o.x0_fallback) == (100, 0, 0, 0, -1, 0, 0, 1, -1, 0)
     assert ctypes.sizeof(pipesafe.Options) == 56
-    assert ctypes.sizeof(pipesafe.Info) == 72
+    assert ctypes.sizeof(pipesafe.Info) == 80
     pipesafe.library().ps_strerror.restype = ctypes.c_char_p
     for code in (0, 1, 2, 3, -1, -2, -3, -4, -5):
         assert pipesafe.library().ps_strerror(code)

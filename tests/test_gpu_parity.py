@@ -79,10 +79,13 @@ def _spmv_matrix(case):
 def device_format(fmt):
     """Force the device layout ps_create picks (PIPESAFE_FORMAT: 0 CSR, 1 sliced ELLPACK;
     "sell2": sliced with two rows per lane, PIPESAFE_SELL_RPL=2)."""
-    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SELL_RPL")
+    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SELL_RPL", "PIPESAFE_SELL_INDEX")
     old = {k: os.environ.get(k) for k in keys}
-    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "sell": "1", "sell2": "1"}[fmt]
-    os.environ["PIPESAFE_SELL_RPL"] = "2" if fmt == "sell2" else "1"
+    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "sell": "1", "sell2": "1", "sell32": "1",
+                                     "sell2_32": "1"}[fmt]
+    os.environ["PIPESAFE_SELL_RPL"] = "2" if fmt.startswith("sell2") else "1"
+    # the sliced layout stores 16-bit column offsets when they fit; "..32" keeps columns
+    os.environ["PIPESAFE_SELL_INDEX"] = "32" if fmt.endswith("32") else "16"
     try:
         yield
     finally:
@@ -93,7 +96,7 @@ def device_format(fmt):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell", "sell2"])
+@pytest.mark.parametrize("fmt", ["csr", "sell", "sell2", "sell32", "sell2_32"])
 @pytest.mark.parametrize("case", sorted(SPMV_CASES))
 def test_spmv_matches_oracle(case, fmt):
     import torch
@@ -102,7 +105,11 @@ def test_spmv_matches_oracle(case, fmt):
     x = np.random.default_rng(7).standard_normal(A.n)
     ref = O.spmv(A, x)
     with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
-        assert M.info()["format"] == fmt.rstrip("2")
+        info = M.info()
+        assert info["format"] == fmt[:4].rstrip("2")
+        if info["format"] == "sell":
+            span = int(np.abs(A.col - np.repeat(np.arange(A.n), np.diff(A.rowptr))).max(initial=0))
+            assert info["index_bits"] == (32 if fmt.endswith("32") or span > 32767 else 16)
         y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     # every row, long ones included: both sides round each product, carry the
     # row's sum with two-sum accumulators and round once, so any order of the
@@ -242,7 +249,9 @@ def test_device_layout_choice():
             Lp[:A.n] = L
             slots = int(Lp.reshape(ns, 64).max(axis=1).sum()) * 64
             assert info["slots"] == slots and slots <= 1.1 * A.nnz + 64
-            assert info["matrix_bytes"] == 12 * slots + 4 * (ns + 1)
+            # stencil offsets fit 16 bits: column - row is stored, 10 bytes per slot
+            assert info["index_bits"] == 16
+            assert info["matrix_bytes"] == 10 * slots + 4 * (ns + 1)
         else:
             assert info["slots"] == A.nnz and info["matrix_bytes"] == 12 * A.nnz + 4 * (A.n + 1)
 
@@ -256,11 +265,13 @@ def test_both_layouts_reproduce_oracle(variant):
                          ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), "sell"),
                          ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell"),
                          ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell2"),
+                         ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell2_32"),
+                         ("cd3d_16", W.cd3d(16, 20.0, seed=1), "sell32"),
                          ("cd2d_5", W.cd2d(5, 10.0), "sell")]:
         say(f"layout {fmt} {name} {variant}")
         ref = O.solve(A, tol=1e-10, maxit=3000, variant=variant, rr_m=25)
         with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
-            assert M.info()["format"] == fmt.rstrip("2")
+            assert M.info()["format"] == fmt[:4].rstrip("2")
             res = M.solve(A.b, tol=1e-10, maxit=3000, variant=variant, rr_m=25)
         assert res.status == ref.status and res.iters == ref.iters, (name, res.iters, ref.iters)
         assert np.array_equal(res.hist, ref.hist) and np.array_equal(res.x, ref.x), name
