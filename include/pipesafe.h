@@ -236,6 +236,70 @@ void ps_default_options(ps_options *opt);
 int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
               const double *val);
 
+/* An explicit device layout (ps_create_ex, ps_create_batch_ex); -1 in a field
+   keeps the automatic choice for it. */
+typedef struct ps_layout {
+  int32_t format;             /* PS_FMT_CSR or PS_FMT_SELL (any padding)            */
+  int32_t sell_rows_per_lane; /* sliced layout: 1 (64-row slices) or 2 (128-row)    */
+  int32_t spmv_shape;         /* CSR launch shape 0..4: (nonzeros per thread, lanes
+                                 per row) = (4,1) (8,1) (16,4) (16,8) (16,16)        */
+  int32_t index_bits;         /* sliced layout: 32 keeps 32-bit columns; 16 (or -1)
+                                 stores 16-bit offsets where every entry fits        */
+} ps_layout;
+
+/* ps_create / ps_create_batch with an explicit layout (NULL: automatic, as
+   they are); the layout overrides the environment variables above.  Results
+   do not depend on the layout.  PS_EINVAL also for a field out of range. */
+int ps_create_ex(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                 const int32_t *col, const double *val, const ps_layout *layout);
+int ps_create_batch_ex(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
+                       int64_t nnz, const int64_t *rowptr, const int32_t *col, const double *val,
+                       const ps_layout *layout);
+
+/*
+ * Autotuner.  Every layout, launch shape and schedule computes the same
+ * iterates (compensated sums rounded once), so the tuner picks by measured
+ * time only.
+ */
+#define PS_TUNE_MAX 48
+typedef struct ps_tune_entry {
+  ps_layout layout;     /* the layout timed (ps_autotune_layout), else all -1            */
+  int32_t schedule;     /* the options timed (ps_tune_options), else -1                  */
+  int32_t overlap;
+  int32_t streaming;
+  int32_t batch_iters;
+  double us;            /* microseconds per product (layout) or per iteration (options) */
+} ps_tune_entry;
+typedef struct ps_tune_report {
+  int32_t count;        /* entries filled                                               */
+  int32_t best;         /* index of the chosen entry                                    */
+  ps_tune_entry entry[PS_TUNE_MAX];
+} ps_tune_report;
+
+/* Create the matrix in every candidate layout -- the sliced layout with 1 and 2
+   rows per lane and 16- and 32-bit columns (where its padding stays within
+   1.5x the nonzeros), CSR with each of the 5 launch shapes -- time `reps`
+   sparse products of each on the library's stream (after 2 untimed ones),
+   and keep the fastest: *out receives that handle, the others are destroyed.
+   nsys = 1 (sys_ptr ignored) for one system, else the batch arguments of
+   ps_create_batch.  report: NULL or HOST, filled with every timed layout.
+   Costs one creation per candidate (host layout build and upload). */
+int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
+                       int64_t nnz, const int64_t *rowptr, const int32_t *col, const double *val,
+                       int32_t reps, ps_tune_report *report);
+
+/* Time `iters` iterations of `variant` from b_dev (DEVICE, the caller's row
+   order, as ps_solve_batch_dev; x0 = 0, tol = 0) for every combination of
+   schedule (p-BiCGSafe, one system: 0, 1), overlap (0, 1; ssBiCGSafe2: 0),
+   streaming update passes (p-BiCGSafe: off, on) and graph batch (8, 16, 32
+   iterations), each run once to capture its graphs and once timed (host
+   clock around the call), and write the fastest into opt->schedule,
+   opt->overlap and opt->batch_iters (the other fields of *opt are the base
+   of every run and stay as given).  The streaming choice is stored in the
+   handle and applies to its later solves.  report: NULL or HOST. */
+int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t iters,
+                    ps_options *opt, ps_tune_report *report);
+
 /*
  * Solve A x = b from HOST buffers.  b: double[n]; x0: double[n] or NULL (zero,
  * the paper's x_0); x: double[n] output, x_{iters}.  tol: the run stops when

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -62,6 +63,7 @@ constexpr int64_t kFusedMinRows = 1 << 18;
 constexpr int64_t kStreamMinBytes = 512ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 constexpr int kSellRowsPerLane = 1;       // 64-row slices
+constexpr double kTuneMaxPadding = 1.5;   // the autotuner tries the sliced layout up to this
 
 struct Timer {
   hipEvent_t a, b;
@@ -917,7 +919,22 @@ bool valid_csr(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col
 }
 
 int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
-                const int32_t *col, const double *val, const BatchLayout *bl);
+                const int32_t *col, const double *val, const BatchLayout *bl,
+                const ps_layout *lay);
+
+// every field -1 (automatic) or a value the field allows
+bool valid_layout(const ps_layout *l) {
+  if (!l) return true;
+  return (l->format == -1 || l->format == PS_FMT_CSR || l->format == PS_FMT_SELL) &&
+         (l->sell_rows_per_lane == -1 || l->sell_rows_per_lane == 1 ||
+          l->sell_rows_per_lane == 2) &&
+         (l->spmv_shape >= -1 && l->spmv_shape <= 4) &&
+         (l->index_bits == -1 || l->index_bits == 16 || l->index_bits == 32);
+}
+
+int create_batch_impl(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
+                      int64_t nnz, const int64_t *rowptr, const int32_t *col, const double *val,
+                      const ps_layout *lay);
 
 }  // namespace
 
@@ -945,17 +962,39 @@ void ps_default_options(ps_options *opt) {
 
 int ps_create(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
               const double *val) {
+  return ps_create_ex(out, n, nnz, rowptr, col, val, nullptr);
+}
+
+int ps_create_ex(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
+                 const int32_t *col, const double *val, const ps_layout *layout) {
   if (!out) return PS_EINVAL;
   *out = nullptr;
-  if (!valid_csr(n, nnz, rowptr, col, val)) return PS_EINVAL;
-  return create_impl(out, n, nnz, rowptr, col, val, nullptr);
+  if (!valid_csr(n, nnz, rowptr, col, val) || !valid_layout(layout)) return PS_EINVAL;
+  return create_impl(out, n, nnz, rowptr, col, val, nullptr, layout);
 }
 
 int ps_create_batch(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n, int64_t nnz,
                     const int64_t *rowptr, const int32_t *col, const double *val) {
+  return create_batch_impl(out, nsys, sys_ptr, n, nnz, rowptr, col, val, nullptr);
+}
+
+int ps_create_batch_ex(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
+                       int64_t nnz, const int64_t *rowptr, const int32_t *col, const double *val,
+                       const ps_layout *layout) {
+  return create_batch_impl(out, nsys, sys_ptr, n, nnz, rowptr, col, val, layout);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_batch_impl(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
+                      int64_t nnz, const int64_t *rowptr, const int32_t *col, const double *val,
+                      const ps_layout *lay) {
   if (!out) return PS_EINVAL;
   *out = nullptr;
-  if (nsys < 1 || !sys_ptr || !valid_csr(n, nnz, rowptr, col, val)) return PS_EINVAL;
+  if (nsys < 1 || !sys_ptr || !valid_csr(n, nnz, rowptr, col, val) || !valid_layout(lay))
+    return PS_EINVAL;
   if (sys_ptr[0] != 0 || sys_ptr[nsys] != n) return PS_EINVAL;
   for (int32_t k = 0; k < nsys; ++k)
     if (sys_ptr[k + 1] <= sys_ptr[k]) return PS_EINVAL;
@@ -964,7 +1003,7 @@ int ps_create_batch(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64
     for (int64_t r = sys_ptr[k]; r < sys_ptr[k + 1]; ++r)
       for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
         if (col[e] < sys_ptr[k] || col[e] >= sys_ptr[k + 1]) return PS_EINVAL;
-  if (nsys == 1) return create_impl(out, n, nnz, rowptr, col, val, nullptr);
+  if (nsys == 1) return create_impl(out, n, nnz, rowptr, col, val, nullptr, lay);
   // pad each system to a multiple of 512 rows with empty rows
   BatchLayout bl;
   bl.nsys = nsys;
@@ -991,15 +1030,12 @@ int ps_create_batch(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64
   }
   bl.first_blk[nsys] = (int)(np / 512);
   for (int64_t r = 0; r < np; ++r) prow[r + 1] += prow[r];
-  return create_impl(out, np, nnz, prow.data(), pcol.data(), val, &bl);
+  return create_impl(out, np, nnz, prow.data(), pcol.data(), val, &bl, lay);
 }
 
-}  // extern "C"
-
-namespace {
-
 int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
-                const int32_t *col, const double *val, const BatchLayout *bl) {
+                const int32_t *col, const double *val, const BatchLayout *bl,
+                const ps_layout *lay) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PS_ENODEV;
   int dev = 0;
@@ -1023,6 +1059,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     const int v = std::atoi(e);
     if (v >= 0 && v <= 4) M->shape = v;
   }
+  if (lay && lay->spmv_shape >= 0) M->shape = lay->spmv_shape;
   static const int kIpt[] = {4, 8, 16, 16, 16};
   // sliced ELLPACK when padding every slice to its longest row costs little
   M->sell_rpl = kSellRowsPerLane;
@@ -1030,6 +1067,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     const int v = std::atoi(e);
     if (v == 1 || v == 2) M->sell_rpl = v;
   }
+  if (lay && lay->sell_rows_per_lane > 0) M->sell_rpl = lay->sell_rows_per_lane;
   const int64_t SH = (int64_t)kWave * M->sell_rpl;  // rows per slice
   const int64_t nslice = (n + SH - 1) / SH;
   int64_t slots = 0;
@@ -1044,6 +1082,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     const int v = std::atoi(e);
     if (v == PS_FMT_CSR || v == PS_FMT_SELL) M->format = v;
   }
+  if (lay && lay->format >= 0) M->format = lay->format;
   if (slots >= INT32_MAX) M->format = PS_FMT_CSR;
   std::vector<int> blk, rp32;
   std::vector<int> scol, soff;
@@ -1072,6 +1111,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     if (const char *e = std::getenv("PIPESAFE_SELL_INDEX")) {  // tuning override: 16 or 32
       if (std::atoi(e) == 32) M->index_bits = 32;
     }
+    if (lay && lay->index_bits == 32) M->index_bits = 32;
     if (M->index_bits == 16) scol16.assign((size_t)slots, kSellPad16);
     else scol.assign((size_t)slots, -1);
     sval.assign((size_t)slots, 0.0);
@@ -1308,5 +1348,181 @@ const char *ps_strerror(int code) {
 }
 
 const char *ps_version(void) { return "pipesafe 0.1 (gfx950)"; }
+
+
+// ------------------------------------------------------------------ autotuner
+// Every layout, launch shape and schedule gives the same results, so the
+// tuner chooses by measured time alone.
+
+int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
+                       int64_t nnz, const int64_t *rowptr, const int32_t *col, const double *val,
+                       int32_t reps, ps_tune_report *report) {
+  if (!out) return PS_EINVAL;
+  *out = nullptr;
+  if (reps < 1 || reps > 100000 || nsys < 1 || (nsys > 1 && !sys_ptr)) return PS_EINVAL;
+  if (!valid_csr(n, nnz, rowptr, col, val)) return PS_EINVAL;
+  // the sliced forms only where padding every slice to its longest row keeps the
+  // stored slots within kTuneMaxPadding of the nonzeros
+  auto sell_ok = [&](int rpl) {
+    const int64_t SH = (int64_t)kWave * rpl;
+    int64_t slots = 0;
+    for (int64_t r0 = 0; r0 < n; r0 += SH) {
+      int64_t w = 0;
+      for (int64_t r = r0; r < std::min<int64_t>(n, r0 + SH); ++r)
+        w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
+      slots += w * SH;
+    }
+    return (double)slots <= kTuneMaxPadding * (double)nnz + (double)SH;
+  };
+  std::vector<ps_layout> cand;
+  for (int rpl = 1; rpl <= 2; ++rpl)
+    if (sell_ok(rpl)) {
+      cand.push_back(ps_layout{PS_FMT_SELL, rpl, -1, -1});
+      cand.push_back(ps_layout{PS_FMT_SELL, rpl, -1, 32});
+    }
+  for (int sh = 0; sh <= 4; ++sh) cand.push_back(ps_layout{PS_FMT_CSR, -1, sh, -1});
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->best = -1;
+  }
+  ps_matrix *best = nullptr;
+  double best_us = 0.0;
+  for (const ps_layout &l : cand) {
+    ps_matrix *M = nullptr;
+    const int rc = nsys > 1 ? ps_create_batch_ex(&M, nsys, sys_ptr, n, nnz, rowptr, col, val, &l)
+                            : ps_create_ex(&M, n, nnz, rowptr, col, val, &l);
+    if (rc != PS_OK) {
+      if (best) free_matrix(best);
+      return rc;
+    }
+    // a 16-bit request that does not fit gives the 32-bit layout: measured already
+    if (l.format == PS_FMT_SELL && l.index_bits == -1 && M->index_bits == 32) {
+      free_matrix(M);
+      continue;
+    }
+    // time the plain product on the library's stream
+    double ms = 0.0;
+    {
+      double *x = M->slot(PS_V_X), *y = M->slot(kSlotTmp);
+      hipStream_t st = M->own;
+      hipEvent_t e0 = nullptr, e1 = nullptr;  // timing events (the handle's have no timing)
+      int err = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess
+                    ? PS_OK
+                    : PS_EHIP;
+      if (err == PS_OK) err = zero_slots(M, st, {PS_V_X});
+      for (int k = 0; k < 2 && err == PS_OK; ++k)
+        err = spmv(M, st, PS_K_OTHER, x, EpiStore{y}, -1);
+      if (err == PS_OK) err = hipEventRecord(e0, st) == hipSuccess ? PS_OK : PS_EHIP;
+      for (int k = 0; k < reps && err == PS_OK; ++k)
+        err = spmv(M, st, PS_K_OTHER, x, EpiStore{y}, -1);
+      if (err == PS_OK) err = hipEventRecord(e1, st) == hipSuccess ? PS_OK : PS_EHIP;
+      float t = 0.0f;
+      if (err == PS_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        err = PS_EHIP;
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (err != PS_OK) {
+        free_matrix(M);
+        if (best) free_matrix(best);
+        return err;
+      }
+      ms = (double)t;
+    }
+    const double us = 1e3 * ms / reps;
+    if (report && report->count < PS_TUNE_MAX) {
+      ps_tune_entry &e = report->entry[report->count];
+      e.layout = ps_layout{M->format, M->format == PS_FMT_SELL ? M->sell_rpl : -1,
+                           M->format == PS_FMT_CSR ? M->shape : -1,
+                           M->format == PS_FMT_SELL ? M->index_bits : 32};
+      e.schedule = e.overlap = e.streaming = e.batch_iters = -1;
+      e.us = us;
+      if (!best || us < best_us) report->best = report->count;
+      report->count++;
+    }
+    if (!best || us < best_us) {
+      if (best) free_matrix(best);
+      best = M;
+      best_us = us;
+    } else {
+      free_matrix(M);
+    }
+  }
+  *out = best;
+  return PS_OK;
+}
+
+int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t iters,
+                    ps_options *opt, ps_tune_report *report) {
+  if (!A || !b_dev || !opt || iters < 1 || iters > 100000) return PS_EINVAL;
+  if (variant < PS_SSBICGSAFE2 || variant > PS_PBICGSTAB) return PS_EINVAL;
+  const ps_options base = *opt;
+  const bool batch = A->nsys > 1;
+  std::vector<int> scheds = {0}, overlaps = {0, 1}, streams = {-1}, batches = {8, 16, 32};
+  if (variant == PS_PBICGSAFE && !batch) scheds = {0, 1};
+  if (variant == PS_SSBICGSAFE2) overlaps = {0};  // a single stream either way
+  if (variant == PS_PBICGSAFE) streams = {0, 1};
+  double *x = nullptr;
+  PS_HIP(hipSetDevice(A->device));
+  PS_HIP(hipMalloc(&x, std::max<int64_t>(A->n_orig, 1) * sizeof(double)));
+  std::vector<int32_t> it((size_t)A->nsys), st((size_t)A->nsys);
+  const int saved_stream = A->stream_override;
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->best = -1;
+  }
+  int rc = PS_OK;
+  double best_us = -1.0;
+  ps_options best = base;
+  int best_stream = saved_stream;
+  for (int sc : scheds)
+    for (int ov : overlaps)
+      for (int sm : streams)
+        for (int bi : batches) {
+          ps_options o = base;
+          o.schedule = sc;
+          o.overlap = ov;
+          o.batch_iters = bi;
+          o.graph = 1;
+          o.profile = 0;
+          o.resume = 0;
+          A->stream_override = sm;
+          double us = 0.0;
+          for (int rep = 0; rep < 2 && rc == PS_OK; ++rep) {  // the first captures the graphs
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = ps_solve_batch_dev(A, b_dev, nullptr, 0.0, iters, variant, &o, x, it.data(),
+                                    nullptr, st.data());
+            const auto t1 = std::chrono::steady_clock::now();
+            us = std::chrono::duration<double, std::micro>(t1 - t0).count() / iters;
+          }
+          if (rc != PS_OK) break;
+          if (report && report->count < PS_TUNE_MAX) {
+            ps_tune_entry &e = report->entry[report->count];
+            e.layout = ps_layout{-1, -1, -1, -1};
+            e.schedule = sc;
+            e.overlap = ov;
+            e.streaming = sm < 0 ? (streaming(A) ? 1 : 0) : sm;
+            e.batch_iters = bi;
+            e.us = us;
+            if (best_us < 0.0 || us < best_us) report->best = report->count;
+            report->count++;
+          }
+          if (best_us < 0.0 || us < best_us) {
+            best_us = us;
+            best = o;
+            best_stream = sm;
+          }
+        }
+  (void)hipFree(x);
+  if (rc != PS_OK) {
+    A->stream_override = saved_stream;
+    return rc;
+  }
+  opt->schedule = variant == PS_PBICGSAFE && !batch ? best.schedule : base.schedule;
+  opt->overlap = best.overlap;
+  opt->batch_iters = best.batch_iters;
+  A->stream_override = best_stream;
+  return PS_OK;
+}
 
 }  // extern "C"

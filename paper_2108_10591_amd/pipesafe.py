@@ -51,6 +51,41 @@ class Info(ctypes.Structure):
 
 
 FORMATS = {0: "csr", 1: "sell"}
+FORMAT_IDS = {"csr": 0, "sell": 1}
+
+
+class Layout(ctypes.Structure):
+    """ps_layout: an explicit device layout; -1 = automatic."""
+    _fields_ = [("format", ctypes.c_int32), ("sell_rows_per_lane", ctypes.c_int32),
+                ("spmv_shape", ctypes.c_int32), ("index_bits", ctypes.c_int32)]
+
+
+def layout(format=-1, sell_rows_per_lane=-1, spmv_shape=-1, index_bits=-1) -> Layout:
+    return Layout(FORMAT_IDS.get(format, format), sell_rows_per_lane, spmv_shape, index_bits)
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("layout", Layout), ("schedule", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("streaming", ctypes.c_int32), ("batch_iters", ctypes.c_int32),
+                ("us", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("best", ctypes.c_int32), ("entry", TuneEntry * 48)]
+
+    def rows(self) -> list:
+        out = []
+        for k in range(self.count):
+            e = self.entry[k]
+            r = {"us": e.us, "best": k == self.best}
+            if e.layout.format >= 0:
+                r.update(format=FORMATS[e.layout.format], sell_rows_per_lane=e.layout.sell_rows_per_lane,
+                         spmv_shape=e.layout.spmv_shape, index_bits=e.layout.index_bits)
+            else:
+                r.update(schedule=e.schedule, overlap=e.overlap, streaming=e.streaming,
+                         batch_iters=e.batch_iters)
+            out.append(r)
+        return out
 
 _L = None
 
@@ -80,13 +115,21 @@ def _lib():
         L.ps_matrix_info.argtypes = [P, ctypes.POINTER(Info)]
         L.ps_stream_copy.argtypes = [P, P, i64, P]
         L.ps_destroy.argtypes = [P]
+        L.ps_create_ex.argtypes = [ctypes.POINTER(P), i64, i64, P, P, P, ctypes.POINTER(Layout)]
+        L.ps_create_batch_ex.argtypes = [ctypes.POINTER(P), i32, P, i64, i64, P, P, P,
+                                         ctypes.POINTER(Layout)]
+        L.ps_autotune_layout.argtypes = [ctypes.POINTER(P), i32, P, i64, i64, P, P, P, i32,
+                                         ctypes.POINTER(TuneReport)]
+        L.ps_tune_options.argtypes = [P, P, i32, i32, ctypes.POINTER(Options),
+                                      ctypes.POINTER(TuneReport)]
         L.ps_strerror.argtypes = [ctypes.c_int]
         L.ps_strerror.restype = ctypes.c_char_p
         L.ps_version.restype = ctypes.c_char_p
         for name in ("ps_create", "ps_create_batch", "ps_solve_batch", "ps_solve_batch_dev",
                      "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
                      "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats", "ps_matrix_info",
-                     "ps_stream_copy", "ps_destroy"):
+                     "ps_stream_copy", "ps_destroy", "ps_create_ex", "ps_create_batch_ex",
+                     "ps_autotune_layout", "ps_tune_options"):
             getattr(L, name).restype = ctypes.c_int
         _L = L
     return _L
@@ -137,20 +180,49 @@ class SolveResult:
 class Matrix:
     """A CSR matrix resident on the current HIP device, with its solver workspace."""
 
-    def __init__(self, n: int, rowptr, col, val):
+    def __init__(self, n: int, rowptr, col, val, layout: Layout | None = None, _handle=None):
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        val = np.ascontiguousarray(val, dtype=np.float64)
         self.n = int(n)
         self.nnz = int(rowptr[-1]) if rowptr.size else 0
+        if _handle is not None:
+            self._h = _handle
+            return
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
         h = ctypes.c_void_p()
-        _check(_lib().ps_create(ctypes.byref(h), self.n, self.nnz, _ptr(rowptr), _ptr(col), _ptr(val)),
-               "ps_create")
+        _check(_lib().ps_create_ex(ctypes.byref(h), self.n, self.nnz, _ptr(rowptr), _ptr(col),
+                                   _ptr(val), None if layout is None else ctypes.byref(layout)),
+               "ps_create_ex")
         self._h = h
 
     @classmethod
-    def from_csr(cls, A) -> "Matrix":
-        return cls(A.n, A.rowptr, A.col, A.val)
+    def from_csr(cls, A, layout: Layout | None = None) -> "Matrix":
+        return cls(A.n, A.rowptr, A.col, A.val, layout)
+
+    @classmethod
+    def autotuned(cls, A, reps: int = 20):
+        """ps_autotune_layout: the fastest layout for A's sparse product.
+        Returns (Matrix, rows of the tuning report)."""
+        rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(A.col, dtype=np.int32)
+        val = np.ascontiguousarray(A.val, dtype=np.float64)
+        h, rep = ctypes.c_void_p(), TuneReport()
+        _check(_lib().ps_autotune_layout(ctypes.byref(h), 1, None, A.n, int(rowptr[-1]),
+                                         _ptr(rowptr), _ptr(col), _ptr(val), int(reps),
+                                         ctypes.byref(rep)), "ps_autotune_layout")
+        return cls(A.n, rowptr, None, None, _handle=h), rep.rows()
+
+    def tune_options(self, b, variant="pbicgsafe", iters=50, **base):
+        """ps_tune_options from device b (torch CUDA float64, length n): returns (dict of the
+        chosen schedule / overlap / batch_iters, rows of the tuning report)."""
+        import torch
+        if b.dtype != torch.float64 or not b.is_cuda or not b.is_contiguous():
+            raise ValueError("expected a contiguous float64 CUDA tensor")
+        o, rep = options(**base), TuneReport()
+        _check(_lib().ps_tune_options(self._h, ctypes.c_void_p(b.data_ptr()), _vid(variant),
+                                      int(iters), ctypes.byref(o), ctypes.byref(rep)),
+               "ps_tune_options")
+        return {"schedule": o.schedule, "overlap": o.overlap, "batch_iters": o.batch_iters}, rep.rows()
 
     def close(self):
         if getattr(self, "_h", None):
@@ -278,25 +350,45 @@ class BatchResult:
 class BatchMatrix(Matrix):
     """Independent systems solved together (ps_create_batch / ps_solve_batch)."""
 
-    def __init__(self, sys_ptr, n: int, rowptr, col, val):
+    def __init__(self, sys_ptr, n: int, rowptr, col, val, layout: Layout | None = None,
+                 _handle=None):
         sys_ptr = np.ascontiguousarray(sys_ptr, dtype=np.int64)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        val = np.ascontiguousarray(val, dtype=np.float64)
         self.n = int(n)
         self.nnz = int(rowptr[-1]) if rowptr.size else 0
         self.nsys = int(sys_ptr.size - 1)
         self.sys_ptr = sys_ptr
+        if _handle is not None:
+            self._h = _handle
+            return
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
         h = ctypes.c_void_p()
-        _check(_lib().ps_create_batch(ctypes.byref(h), self.nsys, _ptr(sys_ptr), self.n, self.nnz,
-                                      _ptr(rowptr), _ptr(col), _ptr(val)), "ps_create_batch")
+        _check(_lib().ps_create_batch_ex(ctypes.byref(h), self.nsys, _ptr(sys_ptr), self.n,
+                                         self.nnz, _ptr(rowptr), _ptr(col), _ptr(val),
+                                         None if layout is None else ctypes.byref(layout)),
+               "ps_create_batch_ex")
         self._h = h
 
     @classmethod
-    def from_batch(cls, B) -> "BatchMatrix":
+    def from_batch(cls, B, layout: Layout | None = None) -> "BatchMatrix":
         """From a workloads.Batch (its block-diagonal concatenation)."""
         C = B.concat()
-        return cls(B.sys_ptr(), C.n, C.rowptr, C.col, C.val)
+        return cls(B.sys_ptr(), C.n, C.rowptr, C.col, C.val, layout)
+
+    @classmethod
+    def autotuned(cls, B, reps: int = 20):
+        """ps_autotune_layout for a workloads.Batch: returns (BatchMatrix, report rows)."""
+        C = B.concat()
+        sys_ptr = np.ascontiguousarray(B.sys_ptr(), dtype=np.int64)
+        rowptr = np.ascontiguousarray(C.rowptr, dtype=np.int64)
+        col = np.ascontiguousarray(C.col, dtype=np.int32)
+        val = np.ascontiguousarray(C.val, dtype=np.float64)
+        h, rep = ctypes.c_void_p(), TuneReport()
+        _check(_lib().ps_autotune_layout(ctypes.byref(h), int(sys_ptr.size - 1), _ptr(sys_ptr),
+                                         C.n, int(rowptr[-1]), _ptr(rowptr), _ptr(col), _ptr(val),
+                                         int(reps), ctypes.byref(rep)), "ps_autotune_layout")
+        return cls(sys_ptr, C.n, rowptr, None, None, _handle=h), rep.rows()
 
     def solve(self, b, x0=None, tol=1e-8, maxit=10_000, variant="pbicgsafe", hist=True, **opt):
         b = np.ascontiguousarray(b, dtype=np.float64)

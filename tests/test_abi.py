@@ -132,3 +132,42 @@ def test_create_batch_rejects_invalid_layout_before_touching_the_device(lib, cas
     rc = L.ps_create_batch(ctypes.byref(h), nsys, sys_ptr.ctypes.data, 4, 4, rowptr.ctypes.data,
                            col.ctypes.data, val.ctypes.data)
     assert rc == -1 and not h.value
+
+
+@pytest.mark.parametrize("field,value", [("format", 2), ("format", -2), ("sell_rows_per_lane", 3),
+                                         ("sell_rows_per_lane", 0), ("spmv_shape", 5),
+                                         ("index_bits", 8), ("index_bits", 64)])
+def test_create_ex_rejects_invalid_layout_before_touching_the_device(lib, field, value):
+    from paper_2108_10591_amd import pipesafe
+    L = pipesafe.library()
+    lay = pipesafe.layout()
+    setattr(lay, field, value)
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    c = np.array([0, 1], dtype=np.int32)
+    v = np.array([1.0, 2.0])
+    h = ctypes.c_void_p()
+    assert L.ps_create_ex(ctypes.byref(h), 2, 2, rp.ctypes.data, c.ctypes.data, v.ctypes.data,
+                          ctypes.byref(lay)) == -1 and not h.value
+    sp = np.array([0, 2], dtype=np.int64)
+    assert L.ps_create_batch_ex(ctypes.byref(h), 1, sp.ctypes.data, 2, 2, rp.ctypes.data,
+                                c.ctypes.data, v.ctypes.data, ctypes.byref(lay)) == -1
+
+
+def test_tuner_structs_and_argument_checks(lib):
+    from paper_2108_10591_amd import pipesafe
+    L = pipesafe.library()
+    assert ctypes.sizeof(pipesafe.Layout) == 16
+    assert ctypes.sizeof(pipesafe.TuneEntry) == 40
+    assert ctypes.sizeof(pipesafe.TuneReport) == 8 + 48 * 40
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    c = np.array([0, 1], dtype=np.int32)
+    v = np.array([1.0, 2.0])
+    h = ctypes.c_void_p()
+    rep = pipesafe.TuneReport()
+    # reps out of range, or a batch without row ranges: rejected before any device work
+    assert L.ps_autotune_layout(ctypes.byref(h), 1, None, 2, 2, rp.ctypes.data, c.ctypes.data,
+                                v.ctypes.data, 0, ctypes.byref(rep)) == -1
+    assert L.ps_autotune_layout(ctypes.byref(h), 2, None, 2, 2, rp.ctypes.data, c.ctypes.data,
+                                v.ctypes.data, 5, ctypes.byref(rep)) == -1
+    o = pipesafe.options()
+    assert L.ps_tune_options(None, None, 1, 10, ctypes.byref(o), None) == -1
