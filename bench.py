@@ -176,6 +176,25 @@ def bench_batch(name, reps=3):
         M1.close()
     assert it_seq == [int(i) for i in r.iters]
     log(f"  one at a time: {1e3 * t_seq:.1f} ms, {B.nsys / t_seq:.0f} solves/s")
+    # the autotuner: layout by timed products, then options by timed iterations
+    t0 = time.perf_counter()
+    Mt, lrows = pipesafe.BatchMatrix.autotuned(B, reps=10)
+    with Mt:
+        topts, orows = Mt.tune_options(b, variant="pbicgsafe", iters=30)
+        t_tune = time.perf_counter() - t0
+        rt = Mt.solve_dev(b, None, x, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False, **topts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rt = Mt.solve_dev(b, None, x, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False,
+                              **topts)
+        torch.cuda.synchronize()
+        t_tuned = (time.perf_counter() - t0) / reps
+        tinfo = Mt.info()
+    assert np.array_equal(rt.iters, r.iters)
+    best = next(row for row in lrows if row["best"])
+    log(f"  autotuned ({t_tune:.1f} s of tuning): layout {best}, options {topts}: "
+        f"{1e3 * t_tuned:.1f} ms, {B.nsys / t_tuned:.0f} solves/s")
     return {"workload": name, "systems": B.nsys, "rows": C.n, "nnz": C.nnz, "tol": tol,
             "variant": "pbicgsafe", "layout": info["format"],
             "iterations_min_mean_max": [int(r.iters.min()), round(float(r.iters.mean()), 1),
@@ -184,7 +203,14 @@ def bench_batch(name, reps=3):
             "GBps": round(gb / t_batch, 1),
             "one_at_a_time": {"time_ms": round(1e3 * t_seq, 2),
                               "solves_per_s": round(B.nsys / t_seq, 1)},
-            "speedup": round(t_seq / t_batch, 2)}
+            "speedup": round(t_seq / t_batch, 2),
+            "autotuned": {"layout": {k: best[k] for k in ("format", "sell_rows_per_lane",
+                                                            "spmv_shape", "index_bits")},
+                          "options": topts, "tuning_s": round(t_tune, 2),
+                          "layouts_timed_us": [round(row["us"], 2) for row in lrows],
+                          "time_ms": round(1e3 * t_tuned, 2),
+                          "solves_per_s": round(B.nsys / t_tuned, 1),
+                          "same_format_as_automatic": tinfo["format"] == info["format"]}}
 
 
 def bench_mixed(name, rr_ms, reps=3):
