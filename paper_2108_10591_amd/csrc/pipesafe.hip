@@ -96,6 +96,7 @@ struct ps_matrix {
   int device = -1;
   int64_t n = 0, nnz = 0;
   int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
+  unsigned char *rord = nullptr;  // CSR, multi-lane shapes: rows of each block longest first
   double *val = nullptr;
   int nblk = 0;             // workgroups of one sparse product
   int shape = 1;            // SpMV shape: 0..4 = (IPT, LPR) (4,1) (8,1) (16,4) (16,8) (16,16)
@@ -152,8 +153,8 @@ struct ps_matrix {
   double *slot(int s) const { return vec + (size_t)s * ld; }
   int *running() const { return ctl + (size_t)nsys * C_COUNT; }
   int nblk512() const { return (int)(n / 512); }
-  CsrDev<double> csr() const { return {rowptr, col, val, blk, nblk}; }
-  CsrDev<float> csr32() const { return {rowptr, col, val32, blk, nblk}; }
+  CsrDev<double> csr() const { return {rowptr, col, val, blk, rord, nblk}; }
+  CsrDev<float> csr32() const { return {rowptr, col, val32, blk, rord, nblk}; }
   template <class VT, class IT>
   SellDev<VT, IT> sell() const {
     SellDev<VT, IT> S{};
@@ -840,6 +841,7 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->col);
   (void)hipFree(M->val);
   (void)hipFree(M->blk);
+  (void)hipFree(M->rord);
   (void)hipFree(M->scol);
   (void)hipFree(M->scol16);
   (void)hipFree(M->sval);
@@ -1085,6 +1087,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   if (lay && lay->format >= 0) M->format = lay->format;
   if (slots >= INT32_MAX) M->format = PS_FMT_CSR;
   std::vector<int> blk, rp32;
+  std::vector<unsigned char> rord;
   std::vector<int> scol, soff;
   std::vector<short> scol16;
   std::vector<double> sval;
@@ -1095,6 +1098,26 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     M->nblk = (int)blk.size() - 1;
     rp32.resize(n + 1);
     for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
+    // multi-lane shapes sum each block's rows longest first (stable) when the
+    // rows are uneven (longest above twice the mean): power-law band rows
+    // 7-13% faster per product, uniform rows 3% slower (the extra index load)
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < n; ++i) maxlen = std::max<int64_t>(maxlen, rowptr[i + 1] - rowptr[i]);
+    bool order = M->shape >= 2 && (double)maxlen > 2.0 * mean;
+    if (const char *e = std::getenv("PIPESAFE_CSR_ORDER")) order = order && std::atoi(e) != 0;
+    if (order) {
+      rord.resize((size_t)n);
+      std::vector<int> loc;
+      for (int b = 0; b < M->nblk; ++b) {
+        loc.resize((size_t)(blk[b + 1] - blk[b]));
+        for (size_t i = 0; i < loc.size(); ++i) loc[i] = (int)i;
+        const int64_t r0 = blk[b];
+        std::stable_sort(loc.begin(), loc.end(), [&](int a, int c) {
+          return rowptr[r0 + a + 1] - rowptr[r0 + a] > rowptr[r0 + c + 1] - rowptr[r0 + c];
+        });
+        for (size_t i = 0; i < loc.size(); ++i) rord[(size_t)r0 + i] = (unsigned char)loc[i];
+      }
+    }
   } else {
     M->nslice = (int)nslice;
     M->slots = slots;
@@ -1155,6 +1178,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     PS_CREATE_HIP(hipMalloc(&M->col, std::max<int64_t>(nnz, 1) * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->val, std::max<int64_t>(nnz, 1) * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->blk, blk.size() * sizeof(int)));
+    if (!rord.empty()) PS_CREATE_HIP(hipMalloc(&M->rord, rord.size()));
   } else {
     if (M->index_bits == 16)
       PS_CREATE_HIP(hipMalloc(&M->scol16, std::max<int64_t>(slots, 1) * sizeof(short)));
@@ -1189,6 +1213,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
       (csr && nnz > 0 && !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
       (csr && nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
       (csr && !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice))) ||
+      (csr && !rord.empty() &&
+       !chk(hipMemcpy(M->rord, rord.data(), rord.size(), hipMemcpyHostToDevice))) ||
       (!csr && slots > 0 && M->index_bits == 32 &&
        !chk(hipMemcpy(M->scol, scol.data(), slots * sizeof(int), hipMemcpyHostToDevice))) ||
       (!csr && slots > 0 && M->index_bits == 16 &&

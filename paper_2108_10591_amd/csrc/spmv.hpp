@@ -22,6 +22,10 @@ struct CsrDev {
   const int *col;      // int32[nnz]
   const VT *val;       // VT[nnz]
   const int *blk;      // int32[nblk+1] first row of each row block
+  // multi-lane shapes: the order in which a block's rows are summed, longest
+  // first (uint8[n], block-local indices), so that the rows a wave sums in one
+  // round have similar lengths; nullptr = storage order
+  const unsigned char *rord;
   int nblk;
 };
 
@@ -88,8 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
   // sum leaves the row's value in every lane), so it loads that row's epilogue
   // operands here, before the products, instead of after the sum
   if constexpr (LPR > 1) {
-    const int rr = r0 + (threadIdx.x % LPR) * (kBlock / LPR) + threadIdx.x / LPR;
-    if (rr < r1) ein = epi.load(rr);
+    const int li = (threadIdx.x % LPR) * (kBlock / LPR) + threadIdx.x / LPR;
+    if (r0 + li < r1) ein = epi.load(r0 + (A.rord ? (int)A.rord[r0 + li] : li));
   }
   const int k0 = A.rowptr[r0], k1 = A.rowptr[r1];
   const int nz = k1 - k0;
@@ -172,7 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
       constexpr int kGroups = kBlock / LPR;
       const int g = threadIdx.x / LPR, j = threadIdx.x % LPR;
       for (int t = 0, base = 0; base < r1 - r0; ++t, base += kGroups) {  // same trip count
-        const int rr = r0 + base + g;
+        const int li = base + g;
+        const int rr = li < r1 - r0 ? r0 + (A.rord ? (int)A.rord[r0 + li] : li) : r1;
         DD acc{0.0, 0.0};
         if (rr < r1) {
           const int a = A.rowptr[rr] - k0, e = A.rowptr[rr + 1] - k0;
