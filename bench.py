@@ -44,6 +44,9 @@ def kernel_name(cls, layout, schedule, streaming=0):
         return {"spmv": f"{k}<EpiStore> (A s_i)",
                 "update": f"k_passA_pbicgsafe<true, {nt}> (pass A + 5 partial inner products)",
                 "spmv_fused": f"{k}<EpiPBiCGSafeBDots<{nt}>> (A w_i + l, g, s + 4 partial inner products)"}[cls]
+    if schedule == 2:
+        return {"spmv": f"{k}<EpiStore> (A s_i)", "update": "k_pass_w (w_i)",
+                "spmv_fused": f"{k}<EpiPBiCGSafeAll<{nt}>> (A w_i + every other update + 9 partial inner products)"}[cls]
     return {"spmv": f"{k}<EpiStore> (A s_i)", "dots": "k_dots<ProdSafe9<false>> (9 inner products)",
             "update": f"k_passA_pbicgsafe<false, {nt}> (pass A)",
             "spmv_fused": f"{k}<EpiPBiCGSafeB> (A w_i + l, g, s)"}[cls]
@@ -75,10 +78,14 @@ def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
     (p-BiCGSafe-rr is counted as p-BiCGSafe; its replacement steps add ~1% at m = 100.)
     p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (168n) + A w with q, l, g, s
                  and y, r, r0* (M+88n)
+    p-BiCGSafe, fused-epilogue schedule: A s (M+16n) + w pass (40n: As, l, g, w read, w
+                 written) + A w with every other update (M+192n: 13 reads, 10 writes, w gather)
     """
     M = matrix_bytes(n, nnz, info)
     if variant == "pbicgsafe" and schedule == 1:
         return 2 * M + 272 * n
+    if variant == "pbicgsafe" and schedule == 2:
+        return 2 * M + 248 * n
     return {"pbicgsafe": 2 * M + 280 * n, "pbicgsafe_rr": 2 * M + 280 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
 
@@ -87,6 +94,8 @@ def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
     M = matrix_bytes(n, nnz, info)
     if schedule == 1:
         return {"spmv": M + 16 * n, "update": 168 * n, "spmv_fused": M + 88 * n}[cls]
+    if schedule == 2:
+        return {"spmv": M + 16 * n, "update": 40 * n, "spmv_fused": M + 192 * n}[cls]
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 160 * n, "spmv_fused": M + 64 * n}[cls]
 
 
@@ -300,8 +309,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
     ap.add_argument("--schedule", type=int, default=-1,
-                    help="p-BiCGSafe: 0 separate inner-product pass, 1 fused inner products, "
-                         "-1 the library's automatic choice")
+                    help="p-BiCGSafe: 0 separate inner-product pass, 1 fused partial sums, "
+                         "2 fused epilogue, -1 the library's automatic choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run the library's streaming copy on MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -426,10 +435,11 @@ def main():
 
     if not args.no_variants:
         var = {}
-        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", 0), ("pbicgstab", 0),
-                  ("pbicgsafe", 1 - sched)]
+        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", 0), ("pbicgstab", 0)]
+        others += [("pbicgsafe", sc) for sc in (0, 1, 2) if sc != sched]
         for v, sc in others:
-            key = v if v != "pbicgsafe" else ("pbicgsafe_fused_dots" if sc else "pbicgsafe_dot_pass")
+            key = v if v != "pbicgsafe" else {0: "pbicgsafe_dot_pass", 1: "pbicgsafe_fused_dots",
+                                              2: "pbicgsafe_fused_epilogue"}[sc]
             M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc)
             torch.cuda.synchronize()
             t1 = time.perf_counter()

@@ -103,8 +103,14 @@ typedef struct {
                           (r0*,r), (r0*,t), (r,r) from pass A; (s,s), (s,y), (s,r),
                           (r0*,s) from the epilogue), so that only their final sums and
                           the coefficients remain, concurrent with A s_{i+1}.  Reads
-                          32n bytes more and skips the 40n-byte pass.  Results are
-                          bit-identical to schedule 0.  Other variants: 1 is PS_EINVAL.  */
+                          32n bytes more and skips the 40n-byte pass.
+                          2: fused epilogue -- as 1, but a pass forms only w_i (Eqs.
+                          (q), (w)) and the epilogue of A w_i makes every other update
+                          of the iteration and all nine partial sums: 24n bytes fewer
+                          than 1, faster on the largest systems only (the epilogue is
+                          then bound by its many writes).
+                          Results are bit-identical to schedule 0.  Other variants and
+                          batches: 1 and 2 are PS_EINVAL.                               */
   int32_t x0_fallback; /* 1: if x0 is given and ||b - A x0|| > ||b|| (or is not finite),
                           start from x0 = 0 instead (per system for a batch); a guess
                           that is worse than zero costs nothing then.  0 (default): use
@@ -290,7 +296,7 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
 
 /* Time `iters` iterations of `variant` from b_dev (DEVICE, the caller's row
    order, as ps_solve_batch_dev; x0 = 0, tol = 0) for every combination of
-   schedule (p-BiCGSafe, one system: 0, 1), overlap (0, 1; ssBiCGSafe2: 0),
+   schedule (p-BiCGSafe, one system: 0, 1, 2), overlap (0, 1; ssBiCGSafe2: 0),
    streaming update passes (p-BiCGSafe: off, on) and graph batch (8, 16, 32
    iterations), each run once to capture its graphs and once timed (host
    clock around the call), and write the fastest into opt->schedule,

@@ -327,7 +327,8 @@ struct Plan {
   int i0;
   hipStream_t A, B;
   bool overlap;
-  bool fused;     // fused-dot schedule (p-BiCGSafe)
+  bool fused;     // fused-dot schedule (p-BiCGSafe): schedule 1 or 2
+  bool fused2;    // schedule 2: every update but w_i in the epilogue of A w_i
   bool fallback;  // replace an initial guess that is worse than zero
   bool stream_nt; // streaming (nontemporal) loads and stores in the update passes
   int precision;  // 0 FP64; 1 FP32 values in every product; 2 FP32 in the Krylov products
@@ -400,8 +401,12 @@ int iter_safe_dots(ps_matrix *M, const Plan &P, hipStream_t s, int i) {
 // Fused-dot schedule: the reduction phase of iteration i from the partial sums
 // that pass A and the epilogue of A w_{i-1} wrote.
 int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
-  double *pa = M->fpart, *pb = pa + 2 * 5 * (size_t)M->ga, *pf = pb + 2 * 4 * (size_t)M->nblk;
-  PS_TRY(launch(M, s, PS_K_DOTS, k_fold_partials, dim3(M->gfold), 0, (const double *)pa, M->ga,
+  // schedule 1: pass A's [5][ga] then the epilogue's [4][nblk]; schedule 2: the
+  // epilogue's [5][nblk] then [4][nblk]; the folded [9][gfold] after the largest
+  const int ga = P.fused2 ? M->nblk : M->ga;
+  double *pa = M->fpart, *pb = pa + 2 * 5 * (size_t)ga;
+  double *pf = M->fpart + 2 * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk);
+  PS_TRY(launch(M, s, PS_K_DOTS, k_fold_partials, dim3(M->gfold), 0, (const double *)pa, ga,
                 (const double *)pb, M->nblk, pf, (const int *)M->ctl));
   DotArgs D{};
   D.n = M->n;
@@ -439,6 +444,22 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
                  : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, false>, pair_grid(M->n), 0,
                           pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{As, L, G, S, M->sc}, C_DONE, P.kry32));
+      return PS_OK;
+    }
+    if (P.fused2) {
+      // only w_i before the product; everything else in its epilogue, which also
+      // forms the nine partial sums of iteration i+1
+      PassWArgs pw{As, L, G, W, M->sc, M->ctl, M->n, next_rev(M), nullptr};
+      PS_TRY(launch(M, A, PS_K_UPDATE, k_pass_w, pair_grid(M->n), 0, pw));
+      double *part = M->fpart, *RS = M->slot(PS_V_RS);
+      if (P.stream_nt)
+        PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                    EpiPBiCGSafeAll<true>{R, Pp, U, S, T, Y, Z, X, L, G, As, W, RS, M->sc, part},
+                    C_DONE, P.kry32));
+      else
+        PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                    EpiPBiCGSafeAll<false>{R, Pp, U, S, T, Y, Z, X, L, G, As, W, RS, M->sc, part},
+                    C_DONE, P.kry32));
       return PS_OK;
     }
     double *pa_part = M->fpart, *pb_part = pa_part + 2 * 5 * (size_t)M->ga;
@@ -540,7 +561,8 @@ void clear_graphs(ps_matrix *M) {
 // current sweep phase, captured from the launch sequence on first use.
 int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **out) {
   const GraphKey key{P.variant, P.maxit,   P.rr_m,           P.rr_M, P.overlap ? 1 : 0,
-                     count,     M->sweep,  (P.fused ? 1 : 0) | (P.stream_nt ? 2 : 0),
+                     count,     M->sweep,
+                     (P.fused ? 1 : 0) | (P.stream_nt ? 2 : 0) | (P.fused2 ? 4 : 0),
                      P.precision, P.tol,   P.A};
   for (GraphEntry &g : M->graphs)
     if (g.key == key) {
@@ -667,8 +689,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (!o.resume && !b) return PS_EINVAL;
   if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
   if (o.resume && (batch || o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
-  if (o.schedule < -1 || o.schedule > 1 ||
-      (o.schedule == 1 && (variant != PS_PBICGSAFE || batch)))
+  if (o.schedule < -1 || o.schedule > 2 ||
+      (o.schedule >= 1 && (variant != PS_PBICGSAFE || batch)))
     return PS_EINVAL;
   if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_KRYLOV ||
       (o.precision != PS_PREC_FP64 && !M->f32_ok))
@@ -704,7 +726,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.B = P.overlap ? M->aux : P.A;
   P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
   P.fused = variant == PS_PBICGSAFE && !batch &&
-            (o.schedule == 1 || (o.schedule < 0 && auto_fused(M)));
+            (o.schedule >= 1 || (o.schedule < 0 && auto_fused(M)));
+  P.fused2 = P.fused && o.schedule == 2;
   P.stream_nt = variant == PS_PBICGSAFE && streaming(M);
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;
@@ -1203,8 +1226,9 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   PS_CREATE_HIP(hipMalloc(&M->partials, 2 * 9 * (size_t)M->dot_grid * sizeof(double)));
   M->ga = (int)pair_grid(n).x;
   M->gfold = (std::max(M->ga, M->nblk) + kBlock - 1) / kBlock;
-  PS_CREATE_HIP(hipMalloc(&M->fpart, 2 * (5 * (size_t)M->ga + 4 * (size_t)M->nblk +
-                                          9 * (size_t)M->gfold) * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->fpart, 2 * (5 * (size_t)std::max(M->ga, M->nblk) +
+                                          4 * (size_t)M->nblk + 9 * (size_t)M->gfold) *
+                                         sizeof(double)));
   PS_CREATE_HIP(hipHostMalloc(&M->pinned, 2 * C_COUNT * sizeof(int), hipHostMallocDefault));
 #undef PS_CREATE_HIP
   auto chk = [&](hipError_t e) { return e == hipSuccess; };
@@ -1485,7 +1509,7 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
   const ps_options base = *opt;
   const bool batch = A->nsys > 1;
   std::vector<int> scheds = {0}, overlaps = {0, 1}, streams = {-1}, batches = {8, 16, 32};
-  if (variant == PS_PBICGSAFE && !batch) scheds = {0, 1};
+  if (variant == PS_PBICGSAFE && !batch) scheds = {0, 1, 2};
   if (variant == PS_SSBICGSAFE2) overlaps = {0};  // a single stream either way
   if (variant == PS_PBICGSAFE) streams = {0, 1};
   double *x = nullptr;

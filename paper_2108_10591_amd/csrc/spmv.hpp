@@ -497,4 +497,76 @@ struct EpiPBiCGSafeBDots {
   }
 };
 
+// p-BiCGSafe, fused-epilogue schedule: with w_i already formed for every row
+// (k_pass_w), the epilogue of A w_i makes all the other updates of iteration i
+// in the algorithm's order -- p_i, o_i, u_i, q_i, t_i, z_i, y_{i+1}, x_{i+1},
+// r_{i+1} (Algorithm 4; Eqs. (q), (w)), then l_i, g_{i+1}, s_{i+1} (Eqs. (l),
+// (g), (sip1)) -- and the partial sums of all nine inner products of iteration
+// i+1, written as [5][nblk] pairs of (b, e, f, h, rho) followed by [4][nblk]
+// pairs of (a, c, d, g): the layout k_fold_partials takes.  NT: p, u, t, z, x,
+// y, r (next read by the next such epilogue) and As (dead here) stream past the
+// cache; l, g, w and s, read by the next w pass and product, do not.
+template <bool NT>
+struct EpiPBiCGSafeAll {
+  static constexpr int kDots = 9;
+  __device__ __forceinline__ EpiPBiCGSafeAll at(int sys) const {
+    EpiPBiCGSafeAll e = *this;
+    e.sc += (size_t)sys * SC_COUNT;
+    return e;
+  }
+  double *r, *p, *u, *s, *t, *y, *z, *x, *l, *g;
+  const double *As, *w, *rs;
+  const double *sc;
+  double *part;
+  struct In {
+    double r, p, u, s, t, y, As, l, g, z, x, rs, w;
+  };
+  __device__ __forceinline__ static double ld(const double *a, int k) {
+    if constexpr (NT) return __builtin_nontemporal_load(a + k);
+    else return a[k];
+  }
+  __device__ __forceinline__ static void st(double *a, int k, double v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, a + k);
+    else a[k] = v;
+  }
+  __device__ __forceinline__ In load(int k) const {
+    return In{ld(r, k), ld(p, k), ld(u, k), s[k], ld(t, k), ld(y, k), ld(As, k),
+              l[k],     g[k],     ld(z, k), ld(x, k), rs[k], w[k]};
+  }
+  __device__ __forceinline__ void store(int k, double aw, const In &in, DD (&acc)[9]) const {
+    const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
+    const double pn = in.r + be * (in.p - in.u);
+    const double o = in.s + be * in.t;
+    const double un = ze * o + et * (in.y + be * in.u);
+    const double q = in.As + be * in.l;
+    const double tn = o - in.w;
+    const double zn = ze * in.r + et * in.z - al * un;
+    const double yn = ze * in.s + et * in.y - al * in.w;
+    const double xn = in.x + al * pn + zn;
+    const double rn = in.r - al * o - yn;
+    const double ln = q - aw;
+    const double gn = ze * in.As + et * in.g - al * aw;
+    const double sn = in.s - al * q - gn;
+    st(p, k, pn);
+    st(u, k, un);
+    st(t, k, tn);
+    st(z, k, zn);
+    st(y, k, yn);
+    st(x, k, xn);
+    st(r, k, rn);
+    l[k] = ln;
+    g[k] = gn;
+    s[k] = sn;
+    dd_fma(acc[0], yn, yn);
+    dd_fma(acc[1], yn, rn);
+    dd_fma(acc[2], in.rs, rn);
+    dd_fma(acc[3], in.rs, tn);
+    dd_fma(acc[4], rn, rn);
+    dd_fma(acc[5], sn, sn);
+    dd_fma(acc[6], sn, yn);
+    dd_fma(acc[7], sn, rn);
+    dd_fma(acc[8], in.rs, sn);
+  }
+};
+
 }  // namespace ps

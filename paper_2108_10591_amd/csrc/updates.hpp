@@ -203,6 +203,46 @@ __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   }
 }
 
+// ---------------------------------- p-BiCGSafe, fused-epilogue schedule: only
+// w_i = zeta q_i + eta (g_i + beta w_{i-1}), q_i = As_i + beta l_{i-1} (Eqs. (q),
+// (w)) has to exist for every row before the product A w_i; this pass forms it
+// alone, and the product's epilogue (EpiPBiCGSafeAll) makes every other update
+// of the iteration.
+struct PassWArgs {
+  const double *As, *l, *g;
+  double *w;
+  const double *sc;
+  int *ctl;
+  int64_t n;
+  int rev;               // sweep direction
+  const int *chunk_sys;  // always nullptr (one system)
+};
+
+template <int W>
+__device__ __forceinline__ void passW_body(const PassWArgs &P, int64_t k) {
+  const double be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA], et = P.sc[PS_S_ETA];
+  double As[W], l[W], g[W], w[W];
+  ldv<W>(P.As, k, As);
+  ldv<W>(P.l, k, l);
+  ldv<W>(P.g, k, g);
+  ldv<W>(P.w, k, w);
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const double q = As[j] + be * l[j];
+    w[j] = ze * q + et * (g[j] + be * w[j]);
+  }
+  stv<W>(P.w, k, w);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pass_w(PassWArgs P_) {
+  const PassWArgs P = bind_system(P_);
+  if (halted_after_finish(P.ctl)) return;
+  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
+  if (k + 1 < P.n) passW_body<2>(P, k);
+  else if (k < P.n) passW_body<1>(P, k);
+}
+
 // ---------------------------------- ssBiCGSafe2 (Algorithm 3) and the
 // replacement step of Algorithm 5: p_i, o_i, u_i before the product A u_i.
 struct PouArgs {

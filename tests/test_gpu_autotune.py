@@ -74,7 +74,7 @@ def test_tuned_options_reproduce_oracle():
     A = W.rand_band(20_000, seed=3, band=500)
     b = torch.from_numpy(A.b).cuda()
     with pipesafe.Matrix.from_csr(A) as M:
-        for variant, ncand in (("pbicgsafe", 2 * 2 * 2 * 3), ("ssbicgsafe2", 3),
+        for variant, ncand in (("pbicgsafe", 3 * 2 * 2 * 3), ("ssbicgsafe2", 3),
                                ("pbicgstab", 2 * 3)):
             opts, rows = M.tune_options(b, variant=variant, iters=20)
             say(f"tune_options {variant}: {opts}")

@@ -45,15 +45,15 @@ def case(request):
     M.close()
 
 
-@pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots"])
+@pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue"])
 def test_full_solve_reproduces_oracle(case, golden, variant):
     name, A, M, b = case
-    # the fused-dot schedule of p-BiCGSafe computes the same iteration
+    # the fused schedules of p-BiCGSafe compute the same iteration
     variant, _, sched = variant.partition("+")
     g = golden[f"{name}/{variant}"]
     print(f"full size {name} {variant} {sched}", flush=True)
     res = M.solve_dev(b, tol=g["tol"], maxit=10_000, variant=variant, rr_m=100,
-                      schedule=1 if sched == "fused_dots" else 0)
+                      schedule={"fused_dots": 1, "fused_epilogue": 2}.get(sched, 0))
     x = res.x.cpu().numpy()
     # the spec bar ...
     assert res.status == g["status"]

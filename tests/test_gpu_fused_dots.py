@@ -55,15 +55,18 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("schedule", [1, 2])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_fused_schedule_trajectory_bit_identical_to_oracle(case):
+def test_fused_schedule_trajectory_bit_identical_to_oracle(case, schedule):
+    """Schedule 1: partial sums in pass A and the A w epilogue; schedule 2: only w_i in a
+    pass of its own, every other update and all nine partial sums in the A w epilogue."""
     A = CASES[case]()
     for tol, maxit in ((1e-10, 3000), (0.0, 9)):
-        say(f"fused dots {case} tol={tol} maxit={maxit}")
+        say(f"fused schedule {schedule} {case} tol={tol} maxit={maxit}")
         ref = O.solve(A, tol=tol, maxit=maxit, variant="pbicgsafe")
         with pipesafe.Matrix.from_csr(A) as M:
             for overlap in (0, 1):
-                res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=1,
+                res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=schedule,
                               overlap=overlap)
                 assert res.status == ref.status and res.iters == ref.iters, \
                     (case, overlap, res.status, ref.status, res.iters, ref.iters)
@@ -79,7 +82,8 @@ def test_fused_schedule_graphs_and_batches_bit_identical():
         say(f"fused dots determinism {name}")
         with pipesafe.Matrix.from_csr(A) as M:
             ref = M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", graph=0, overlap=0)
-            runs = [M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", schedule=1, **kw)
+            runs = [M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", schedule=sc, **kw)
+                    for sc in (1, 2)
                     for kw in (dict(graph=0, overlap=0), dict(graph=1, batch_iters=4),
                                dict(graph=0, batch_iters=1, overlap=1),
                                dict(graph=1, batch_iters=4), dict(graph=1, batch_iters=7, overlap=0),
@@ -109,7 +113,8 @@ def test_streaming_update_passes_bit_identical_to_oracle(case):
     with M:
         assert M.info()["streaming"] == 1
         for kw in (dict(schedule=0), dict(schedule=1), dict(schedule=1, graph=1, batch_iters=4),
-                   dict(schedule=0, graph=0, overlap=1)):
+                   dict(schedule=0, graph=0, overlap=1), dict(schedule=2),
+                   dict(schedule=2, graph=1, batch_iters=3)):
             say(f"streaming {case} {kw}")
             res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgsafe", **kw)
             assert res.status == ref.status and res.iters == ref.iters, (case, kw)
@@ -131,38 +136,44 @@ def test_fused_schedule_resume_from_oracle_state():
             M.set_state(v, st.vec(v))
         M.set_state("b", A.b)
         M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "f", "rhoref"]})
-        res = M.solve(A.b, tol=0.0, maxit=k + extra, variant="pbicgsafe", resume=1, resume_iter=k,
-                      schedule=1, graph=1, batch_iters=2)
-        assert res.status == O.MAXIT and res.iters == k + extra
-        for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g"]:  # q_i is transient
-            assert np.array_equal(M.get_state(v), st2.vec(v)), v
+        for sched in (1, 2):
+            for v in ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o"]:
+                M.set_state(v, st.vec(v))
+            M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "f",
+                                                        "rhoref"]})
+            res = M.solve(A.b, tol=0.0, maxit=k + extra, variant="pbicgsafe", resume=1,
+                          resume_iter=k, schedule=sched, graph=1, batch_iters=2)
+            assert res.status == O.MAXIT and res.iters == k + extra
+            for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g"]:  # q_i is transient
+                assert np.array_equal(M.get_state(v), st2.vec(v)), (sched, v)
 
 
-def test_fused_schedule_statuses():
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_fused_schedule_statuses(schedule):
     # A = I converges at i = 1, the first stop test that reads fused partial sums
     for n in (1, 2, 63, 1000):
         E = W.identity(n, seed=n)
         with pipesafe.Matrix.from_csr(E) as M:
-            res = M.solve(E.b, tol=1e-12, maxit=50, variant="pbicgsafe", schedule=1)
+            res = M.solve(E.b, tol=1e-12, maxit=50, variant="pbicgsafe", schedule=schedule)
         assert res.status == O.CONVERGED and res.iters == 1 and np.array_equal(res.x, E.b)
     S = W.skew_blocks(64, seed=1)
     with pipesafe.Matrix.from_csr(S) as M:
-        res = M.solve(S.b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=1)
+        res = M.solve(S.b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=schedule)
     assert res.status == O.BREAKDOWN and res.iters == 0
     B = W.small_nonsym(40, 0)
     b = B.b.copy()
     b[7] = np.nan
     with pipesafe.Matrix.from_csr(B) as M:
-        assert M.solve(b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=1).status == \
+        assert M.solve(b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=schedule).status == \
             O.NONFINITE
-        r0 = M.solve(B.b, tol=1e-10, maxit=0, variant="pbicgsafe", schedule=1)
+        r0 = M.solve(B.b, tol=1e-10, maxit=0, variant="pbicgsafe", schedule=schedule)
         assert r0.status == O.MAXIT and r0.iters == 0
-        r3 = M.solve(B.b, tol=1e-30, maxit=3, variant="pbicgsafe", schedule=1)
+        r3 = M.solve(B.b, tol=1e-30, maxit=3, variant="pbicgsafe", schedule=schedule)
         o3 = O.solve(B, tol=1e-30, maxit=3, variant="pbicgsafe")
         assert r3.iters == 3 and np.array_equal(r3.x, o3.x)
         # the schedule exists for p-BiCGSafe only
         for v in ("ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"):
             with pytest.raises(pipesafe.PipesafeError):
-                M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=1)
+                M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=schedule)
         with pytest.raises(pipesafe.PipesafeError):
-            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=2)
+            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=3)

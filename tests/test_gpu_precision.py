@@ -100,7 +100,7 @@ def test_fused_schedule_graphs_and_streaming_in_mixed_precision():
         for prec in (1, 0, 2, 1):
             ref = O.solve(A, tol=1e-10, maxit=1500, variant="pbicgsafe", precision=prec)
             for kw in (dict(schedule=1), dict(schedule=1, graph=1, batch_iters=3),
-                       dict(schedule=0, overlap=1)):
+                       dict(schedule=0, overlap=1), dict(schedule=2)):
                 say(f"precision {prec} fused/graphs {kw}")
                 res = M.solve(A.b, tol=1e-10, maxit=1500, variant="pbicgsafe", precision=prec,
                               **kw)
