@@ -92,9 +92,11 @@ typedef struct {
   int32_t graph;       /* 1 (default): replay batches of identical iterations as cached
                           HIP graphs; 0: launch every kernel directly.  Results are
                           bit-identical either way.  Ignored while profiling.          */
-  int32_t schedule;    /* p-BiCGSafe only.  -1 (default): automatic, 1 on the sliced
-                          layout from 2^18 rows on, else 0 (ps_info.auto_schedule tells;
-                          other variants ignore -1).
+  int32_t schedule;    /* p-BiCGSafe and p-BiCGSafe-rr.  -1 (default): automatic, 1 on
+                          the sliced layout from 2^18 rows on, else 0
+                          (ps_info.auto_schedule tells; other variants ignore -1).
+                          With -rr, a replacement step and the iteration after it form
+                          their inner products in their own pass.
                           0: the reduction phase of Algorithm 4
                           as its own multi-inner-product pass, concurrent with A s_i.
                           1: fused inner products -- pass A and the epilogue of A w_i of
@@ -167,7 +169,7 @@ typedef struct {
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe    */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
-  int32_t streaming;     /* 1: p-BiCGSafe's update passes load and store the vectors that
+  int32_t streaming;     /* 1: p-BiCGSafe(-rr)'s update passes load and store the vectors that
                             no kernel reads before the next iteration with streaming
                             (nontemporal) hints -- when an iteration moves at least
                             512 MiB (two products plus 272 bytes per row), or as
@@ -296,8 +298,8 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
 
 /* Time `iters` iterations of `variant` from b_dev (DEVICE, the caller's row
    order, as ps_solve_batch_dev; x0 = 0, tol = 0) for every combination of
-   schedule (p-BiCGSafe, one system: 0, 1, 2), overlap (0, 1; ssBiCGSafe2: 0),
-   streaming update passes (p-BiCGSafe: off, on) and graph batch (8, 16, 32
+   schedule (p-BiCGSafe(-rr), one system: 0, 1, 2), overlap (0, 1; ssBiCGSafe2: 0),
+   streaming update passes (p-BiCGSafe(-rr): off, on) and graph batch (8, 16, 32
    iterations), each run once to capture its graphs and once timed (host
    clock around the call), and write the fastest into opt->schedule,
    opt->overlap and opt->batch_iters (the other fields of *opt are the base

@@ -421,18 +421,26 @@ int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
   return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<9, FinSafe>, dim3(1), 0, D, M->gfold);
 }
 
+// p-BiCGSafe-rr: iteration i is a replacement step (Algorithm 5)
+bool replacement(const Plan &P, int i) {
+  return P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && (i % P.rr_m) == 0 && i > 0 && i < P.rr_M;
+}
+bool after_replacement(const Plan &P, int i) { return i > 0 && replacement(P, i - 1); }
+
 int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   hipStream_t A = P.A;
   double *X = M->slot(PS_V_X), *R = M->slot(PS_V_R), *S = M->slot(PS_V_S), *Y = M->slot(PS_V_Y),
          *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P), *U = M->slot(PS_V_U), *Z = M->slot(PS_V_Z),
          *W = M->slot(PS_V_W), *L = M->slot(PS_V_L), *G = M->slot(PS_V_G), *Q = M->slot(PS_V_Q),
          *O = M->slot(PS_V_O), *As = M->slot(PS_V_AS), *Bv = M->slot(PS_V_B);
-  const bool replace = P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && (i % P.rr_m) == 0 && i > 0 &&
-                       i < P.rr_M;
+  const bool replace = replacement(P, i);
   if (!replace) {
     PS_TRY(fork(M, P));
     PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT, P.kry32));  // As_i
-    if (P.fused && i > P.i0) PS_TRY(fused_finish(M, P, P.B));        // concurrently
+    // the partial sums come from the previous iteration's passes, which the
+    // first iteration and the one after a replacement step do not have
+    if (P.fused && i > P.i0 && !after_replacement(P, i))
+      PS_TRY(fused_finish(M, P, P.B));  // concurrently
     else PS_TRY(iter_safe_dots(M, P, P.B, i));
     PS_TRY(join(M, P));
     if (!P.fused) {
@@ -543,12 +551,14 @@ int enqueue_iteration(ps_matrix *M, const Plan &P, int i) {
 
 // An iteration whose launches are the same as every other such iteration's
 // (all arguments fixed; the iteration index lives on the device): not the
-// first iteration of the BiCGSafe forms and not a replacement step.
+// first iteration of the BiCGSafe forms, not a replacement step, and with a
+// fused schedule not the iteration after one.
 bool is_standard(const Plan &P, int i) {
   if (P.variant == PS_PBICGSTAB) return true;
   if (i == 0) return false;
   if (P.fused && i == P.i0) return false;  // its inner products come from their own pass
-  if (P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && i % P.rr_m == 0 && i < P.rr_M) return false;
+  if (replacement(P, i)) return false;
+  if (P.fused && after_replacement(P, i)) return false;  // so do this one's
   return true;
 }
 
@@ -689,8 +699,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (!o.resume && !b) return PS_EINVAL;
   if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
   if (o.resume && (batch || o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
-  if (o.schedule < -1 || o.schedule > 2 ||
-      (o.schedule >= 1 && (variant != PS_PBICGSAFE || batch)))
+  const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
+  if (o.schedule < -1 || o.schedule > 2 || (o.schedule >= 1 && (!safe_pipelined || batch)))
     return PS_EINVAL;
   if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_KRYLOV ||
       (o.precision != PS_PREC_FP64 && !M->f32_ok))
@@ -725,10 +735,9 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
   P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
-  P.fused = variant == PS_PBICGSAFE && !batch &&
-            (o.schedule >= 1 || (o.schedule < 0 && auto_fused(M)));
+  P.fused = safe_pipelined && !batch && (o.schedule >= 1 || (o.schedule < 0 && auto_fused(M)));
   P.fused2 = P.fused && o.schedule == 2;
-  P.stream_nt = variant == PS_PBICGSAFE && streaming(M);
+  P.stream_nt = safe_pipelined && streaming(M);
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;
   P.res32 = o.precision == PS_PREC_FP32_MATRIX;
@@ -1509,9 +1518,10 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
   const ps_options base = *opt;
   const bool batch = A->nsys > 1;
   std::vector<int> scheds = {0}, overlaps = {0, 1}, streams = {-1}, batches = {8, 16, 32};
-  if (variant == PS_PBICGSAFE && !batch) scheds = {0, 1, 2};
+  const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
+  if (safe_pipelined && !batch) scheds = {0, 1, 2};
   if (variant == PS_SSBICGSAFE2) overlaps = {0};  // a single stream either way
-  if (variant == PS_PBICGSAFE) streams = {0, 1};
+  if (safe_pipelined) streams = {0, 1};
   double *x = nullptr;
   PS_HIP(hipSetDevice(A->device));
   PS_HIP(hipMalloc(&x, std::max<int64_t>(A->n_orig, 1) * sizeof(double)));
@@ -1568,7 +1578,7 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
     A->stream_override = saved_stream;
     return rc;
   }
-  opt->schedule = variant == PS_PBICGSAFE && !batch ? best.schedule : base.schedule;
+  opt->schedule = safe_pipelined && !batch ? best.schedule : base.schedule;
   opt->overlap = best.overlap;
   opt->batch_iters = best.batch_iters;
   A->stream_override = best_stream;

@@ -124,6 +124,26 @@ def test_streaming_update_passes_bit_identical_to_oracle(case):
         assert M2.info()["streaming"] == 0  # small systems: automatic choice is off
 
 
+@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("case", ["cd2d_64", "rand_band_20k", "nonsym_ragged_3001"])
+def test_fused_schedules_with_residual_replacement(case, schedule):
+    """p-BiCGSafe-rr with a fused schedule: a replacement step and the iteration after it
+    form their inner products in their own pass, every other iteration from the partial
+    sums; every replacement period, graph batch and stream choice gives the oracle's bits."""
+    A = CASES[case]()
+    with pipesafe.Matrix.from_csr(A) as M:
+        for m in (3, 7, 25):
+            ref = O.solve(A, tol=1e-10, maxit=3000, variant="pbicgsafe_rr", rr_m=m)
+            for kw in (dict(), dict(graph=1, batch_iters=4), dict(graph=0, overlap=1),
+                       dict(graph=1, batch_iters=2, overlap=0)):
+                say(f"rr fused {case} schedule={schedule} m={m} {kw}")
+                res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgsafe_rr", rr_m=m,
+                              schedule=schedule, **kw)
+                assert res.status == ref.status and res.iters == ref.iters, (m, kw)
+                assert np.array_equal(res.hist, ref.hist), (m, kw)
+                assert np.array_equal(res.x, ref.x), (m, kw)
+
+
 def test_fused_schedule_resume_from_oracle_state():
     """The first iteration after a resume forms its inner products in their own pass;
     the following ones take them from the fused partial sums."""
@@ -171,8 +191,8 @@ def test_fused_schedule_statuses(schedule):
         r3 = M.solve(B.b, tol=1e-30, maxit=3, variant="pbicgsafe", schedule=schedule)
         o3 = O.solve(B, tol=1e-30, maxit=3, variant="pbicgsafe")
         assert r3.iters == 3 and np.array_equal(r3.x, o3.x)
-        # the schedule exists for p-BiCGSafe only
-        for v in ("ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"):
+        # the schedules exist for p-BiCGSafe and p-BiCGSafe-rr only
+        for v in ("ssbicgsafe2", "pbicgstab"):
             with pytest.raises(pipesafe.PipesafeError):
                 M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=schedule)
         with pytest.raises(pipesafe.PipesafeError):
