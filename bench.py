@@ -82,9 +82,9 @@ def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
                  written) + A w with every other update (M+192n: 13 reads, 10 writes, w gather)
     """
     M = matrix_bytes(n, nnz, info)
-    if variant == "pbicgsafe" and schedule == 1:
+    if variant in ("pbicgsafe", "pbicgsafe_rr") and schedule == 1:
         return 2 * M + 272 * n
-    if variant == "pbicgsafe" and schedule == 2:
+    if variant in ("pbicgsafe", "pbicgsafe_rr") and schedule == 2:
         return 2 * M + 248 * n
     return {"pbicgsafe": 2 * M + 280 * n, "pbicgsafe_rr": 2 * M + 280 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
@@ -435,7 +435,7 @@ def main():
 
     if not args.no_variants:
         var = {}
-        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", 0), ("pbicgstab", 0)]
+        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", -1), ("pbicgstab", 0)]
         others += [("pbicgsafe", sc) for sc in (0, 1, 2) if sc != sched]
         for v, sc in others:
             key = v if v != "pbicgsafe" else {0: "pbicgsafe_dot_pass", 1: "pbicgsafe_fused_dots",
@@ -448,7 +448,8 @@ def main():
                 rv = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc, hist=False)
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t1) / reps
-            gbps = bytes_per_iteration(v, A.n, A.nnz, sc, info) * rv.iters / (ms * 1e-3) / 1e9
+            sc_run = info["auto_schedule"] if sc < 0 else sc  # what the library chose
+            gbps = bytes_per_iteration(v, A.n, A.nnz, sc_run, info) * rv.iters / (ms * 1e-3) / 1e9
             v = key
             var[v] = {"iterations": rv.iters, "status": rv.status_name, "time_to_tol_ms": round(ms, 3),
                       "us_per_iter": round(1e3 * ms / max(rv.iters, 1), 2), "GBps": round(gbps, 1)}
