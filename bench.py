@@ -462,8 +462,9 @@ def main():
     if not args.no_warmstart:
         out["warm_start"] = bench_warmstart(args.warmstart_count, args.warmstart_epochs)
     if not args.no_mixed:
-        out["mixed_precision"] = bench_mixed("rand_band_1m",
-                                             [int(m) for m in args.mixed_rr_m.split(",")])
+        ms = [int(m) for m in args.mixed_rr_m.split(",")]
+        out["mixed_precision"] = bench_mixed("rand_band_1m", ms)
+        out["mixed_precision_stencil"] = bench_mixed(args.workload, ms)
 
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_iters} iterations ...")
