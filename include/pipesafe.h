@@ -167,7 +167,7 @@ typedef struct {
                             CSR 12 nnz + 4 (n+1); SELL (8 + index_bits/8) slots +
                             4 (slices+1)                                                */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
-  int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe    */
+  int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe(-rr) */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
   int32_t streaming;     /* 1: p-BiCGSafe(-rr)'s update passes load and store the vectors that
                             no kernel reads before the next iteration with streaming
