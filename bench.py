@@ -273,6 +273,34 @@ def bench_mixed(name, rr_ms, reps=3):
     return out
 
 
+def bench_small(name, reps=5):
+    """A small system (latency-bound): time to the workload's tolerance and microseconds
+    per iteration of every method, with the library's automatic choices."""
+    import torch
+
+    from paper_2108_10591_amd import pipesafe, workloads
+    A = workloads.workload(name)
+    tol = workloads.WORKLOADS[name]["tol"]
+    b = torch.from_numpy(A.b).cuda()
+    x = torch.empty_like(b)
+    out = {"workload": name, "n": A.n, "nnz": A.nnz, "tol": tol, "x0": "zero"}
+    with pipesafe.Matrix.from_csr(A) as M:
+        out["layout"] = M.info()["format"]
+        for v in ("pbicgsafe", "ssbicgsafe2", "pbicgsafe_rr", "pbicgstab"):
+            r = M.solve_dev(b, None, x, tol=tol, maxit=10_000, variant=v, hist=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = M.solve_dev(b, None, x, tol=tol, maxit=10_000, variant=v, hist=False)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            out[v] = {"iterations": r.iters, "status": r.status_name,
+                      "time_to_tol_ms": round(1e3 * t, 3),
+                      "us_per_iter": round(1e6 * t / max(r.iters, 1), 2)}
+    log(f"small system {name}: {out}")
+    return out
+
+
 def bench_warmstart(count, epochs):
     """The learned initial guess on 128 x 128 variable-coefficient problems: training data
     solved on the GPU, the network trained on the GPU, then 64 held-out problems solved to
@@ -455,6 +483,9 @@ def main():
                       "us_per_iter": round(1e3 * ms / max(rv.iters, 1), 2), "GBps": round(gbps, 1)}
             log(f"{v}: {var[v]}")
         out["variants"] = var
+
+    if not args.no_variants:
+        out["small_system"] = bench_small("cd2d_64")
 
     if not args.no_batch:
         out["batched"] = bench_batch("cd2d_batch_512")
