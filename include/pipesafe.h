@@ -164,8 +164,8 @@ typedef struct {
   int32_t spmv_blocks;   /* workgroups of one sparse product                            */
   int32_t dot_grid;      /* workgroups of the multi-inner-product kernel                */
   int64_t matrix_bytes;  /* bytes one sparse product must stream from the matrix arrays:
-                            CSR 12 nnz + 4 (n+1); SELL (8 + index_bits/8) slots +
-                            4 (slices+1)                                                */
+                            CSR (8 + index_bits/8) nnz + 4 (n+1); SELL (8 +
+                            index_bits/8) slots + 4 (slices+1)                          */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe(-rr) */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
@@ -176,10 +176,10 @@ typedef struct {
                             PIPESAFE_STREAM=0|1 sets; the results are the same       */
   int64_t n_padded;      /* rows on the device: n, or for a batch the systems padded to
                             multiples of 512 rows                                      */
-  int32_t index_bits;    /* stored column index: 32, or 16 for the sliced layout when
-                            every entry lies within 32767 of its row's diagonal (then
-                            column - row is stored: 10 instead of 12 bytes per slot;
-                            PIPESAFE_SELL_INDEX=32 keeps 32)                           */
+  int32_t index_bits;    /* stored column index: 32, or 16 when every entry fits --
+                            sliced layout: column - row within 32767; CSR: column -
+                            the first row of its row block within 32767 -- 10 instead
+                            of 12 bytes per FP64 entry (PIPESAFE_INDEX=32 keeps 32)    */
   int32_t reserved;
 } ps_info;
 
@@ -235,7 +235,7 @@ void ps_default_options(ps_options *opt);
  * product's launch shape are chosen here from the row lengths; the
  * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SELL_RPL
  * (rows per lane of the sliced layout: 1, the default, or 2 with 128-row
- * slices), PIPESAFE_SELL_INDEX (32: no 16-bit column offsets),
+ * slices), PIPESAFE_INDEX (32: no 16-bit column offsets),
  * PIPESAFE_SPMV_SHAPE (0..4), PIPESAFE_DOT_GRID (1..8192 workgroups) and
  * PIPESAFE_STREAM (0 or 1, ps_info.streaming) override the choices, for
  * tuning and tests.  Every choice gives
@@ -251,8 +251,9 @@ typedef struct ps_layout {
   int32_t sell_rows_per_lane; /* sliced layout: 1 (64-row slices) or 2 (128-row)    */
   int32_t spmv_shape;         /* CSR launch shape 0..4: (nonzeros per thread, lanes
                                  per row) = (4,1) (8,1) (16,4) (16,8) (16,16)        */
-  int32_t index_bits;         /* sliced layout: 32 keeps 32-bit columns; 16 (or -1)
-                                 stores 16-bit offsets where every entry fits        */
+  int32_t index_bits;         /* 32 keeps 32-bit columns; 16 (or -1) stores 16-bit
+                                 offsets where every entry fits (sliced: column -
+                                 row; CSR: column - first row of its row block)      */
 } ps_layout;
 
 /* ps_create / ps_create_batch with an explicit layout (NULL: automatic, as

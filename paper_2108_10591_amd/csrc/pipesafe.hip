@@ -97,13 +97,14 @@ struct ps_matrix {
   int64_t n = 0, nnz = 0;
   int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
   unsigned char *rord = nullptr;  // CSR, multi-lane shapes: rows of each block longest first
+  short *col16 = nullptr;         // CSR column - first row of its row block (index_bits 16)
   double *val = nullptr;
   int nblk = 0;             // workgroups of one sparse product
   int shape = 1;            // SpMV shape: 0..4 = (IPT, LPR) (4,1) (8,1) (16,4) (16,8) (16,16)
   int format = PS_FMT_CSR;  // device layout of the matrix
   int *scol = nullptr, *soff = nullptr;  // sliced ELLPACK arrays (format PS_FMT_SELL)
   short *scol16 = nullptr;               // sliced ELLPACK column - row (index_bits 16)
-  int index_bits = 32;                   // stored column index of the sliced layout
+  int index_bits = 32;                   // stored column index (either layout): 32 or 16
   double *sval = nullptr;
   int64_t slots = 0;
   int nslice = 0;
@@ -153,8 +154,19 @@ struct ps_matrix {
   double *slot(int s) const { return vec + (size_t)s * ld; }
   int *running() const { return ctl + (size_t)nsys * C_COUNT; }
   int nblk512() const { return (int)(n / 512); }
-  CsrDev<double> csr() const { return {rowptr, col, val, blk, rord, nblk}; }
-  CsrDev<float> csr32() const { return {rowptr, col, val32, blk, rord, nblk}; }
+  template <class VT, class IT>
+  CsrDev<VT, IT> csr() const {
+    CsrDev<VT, IT> A{};
+    A.rowptr = rowptr;
+    if constexpr (sizeof(IT) == 4) A.col = col;
+    else A.col = col16;
+    if constexpr (sizeof(VT) == 8) A.val = val;
+    else A.val = val32;
+    A.blk = blk;
+    A.rord = rord;
+    A.nblk = nblk;
+    return A;
+  }
   template <class VT, class IT>
   SellDev<VT, IT> sell() const {
     SellDev<VT, IT> S{};
@@ -242,11 +254,16 @@ template <int IPT, int LPR, class Epi>
 int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, Stop stop,
                 int rev, bool f32) {
   const size_t lds = (size_t)IPT * kBlock * sizeof(double);
-  if (f32)
-    return launch(M, s, cls, k_spmv<IPT, LPR, float, Epi>, dim3(M->nblk), lds, M->csr32(), x, epi,
-                  stop, rev);
-  return launch(M, s, cls, k_spmv<IPT, LPR, double, Epi>, dim3(M->nblk), lds, M->csr(), x, epi,
-                stop, rev);
+  const dim3 g(M->nblk);
+  if (M->index_bits == 16)
+    return f32 ? launch(M, s, cls, k_spmv<IPT, LPR, float, short, Epi>, g, lds,
+                        M->template csr<float, short>(), x, epi, stop, rev)
+               : launch(M, s, cls, k_spmv<IPT, LPR, double, short, Epi>, g, lds,
+                        M->template csr<double, short>(), x, epi, stop, rev);
+  return f32 ? launch(M, s, cls, k_spmv<IPT, LPR, float, int, Epi>, g, lds,
+                      M->template csr<float, int>(), x, epi, stop, rev)
+             : launch(M, s, cls, k_spmv<IPT, LPR, double, int, Epi>, g, lds,
+                      M->template csr<double, int>(), x, epi, stop, rev);
 }
 
 template <class VT, class IT, class Epi>
@@ -672,7 +689,7 @@ int collect_profile(ps_matrix *M, int stop_iter) {
 
 int64_t matrix_bytes(const ps_matrix *M) {
   return M->format == PS_FMT_CSR
-             ? 12 * M->nnz + 4 * (M->n + 1)
+             ? (8 + M->index_bits / 8) * M->nnz + 4 * (M->n + 1)
              : (8 + M->index_bits / 8) * M->slots + 4 * ((int64_t)M->nslice + 1);
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
@@ -871,6 +888,7 @@ void free_matrix(ps_matrix *M) {
   clear_graphs(M);
   (void)hipFree(M->rowptr);
   (void)hipFree(M->col);
+  (void)hipFree(M->col16);
   (void)hipFree(M->val);
   (void)hipFree(M->blk);
   (void)hipFree(M->rord);
@@ -1120,6 +1138,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   if (slots >= INT32_MAX) M->format = PS_FMT_CSR;
   std::vector<int> blk, rp32;
   std::vector<unsigned char> rord;
+  std::vector<short> col16;
   std::vector<int> scol, soff;
   std::vector<short> scol16;
   std::vector<double> sval;
@@ -1150,6 +1169,25 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
         for (size_t i = 0; i < loc.size(); ++i) rord[(size_t)r0 + i] = (unsigned char)loc[i];
       }
     }
+    // 16-bit column offsets from each row block's first row when they all fit
+    bool fits16 = true;
+    for (int b = 0; b < M->nblk && fits16; ++b)
+      for (int64_t k = rowptr[blk[b]]; k < rowptr[blk[b + 1]]; ++k)
+        if (col[k] - blk[b] > 32767 || blk[b] - col[k] > 32767) {
+          fits16 = false;
+          break;
+        }
+    M->index_bits = fits16 ? 16 : 32;
+    if (const char *e = std::getenv("PIPESAFE_INDEX")) {  // tuning override: 32
+      if (std::atoi(e) == 32) M->index_bits = 32;
+    }
+    if (lay && lay->index_bits == 32) M->index_bits = 32;
+    if (M->index_bits == 16) {
+      col16.resize((size_t)nnz);
+      for (int b = 0; b < M->nblk; ++b)
+        for (int64_t k = rowptr[blk[b]]; k < rowptr[blk[b + 1]]; ++k)
+          col16[(size_t)k] = (short)(col[k] - blk[b]);
+    }
   } else {
     M->nslice = (int)nslice;
     M->slots = slots;
@@ -1163,7 +1201,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
           break;
         }
     M->index_bits = fits16 ? 16 : 32;
-    if (const char *e = std::getenv("PIPESAFE_SELL_INDEX")) {  // tuning override: 16 or 32
+    if (const char *e = std::getenv("PIPESAFE_INDEX")) {  // tuning override: 32
       if (std::atoi(e) == 32) M->index_bits = 32;
     }
     if (lay && lay->index_bits == 32) M->index_bits = 32;
@@ -1207,7 +1245,10 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   } while (0)
   if (M->format == PS_FMT_CSR) {
     PS_CREATE_HIP(hipMalloc(&M->rowptr, (n + 1) * sizeof(int)));
-    PS_CREATE_HIP(hipMalloc(&M->col, std::max<int64_t>(nnz, 1) * sizeof(int)));
+    if (M->index_bits == 16)
+      PS_CREATE_HIP(hipMalloc(&M->col16, std::max<int64_t>(nnz, 1) * sizeof(short)));
+    else
+      PS_CREATE_HIP(hipMalloc(&M->col, std::max<int64_t>(nnz, 1) * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->val, std::max<int64_t>(nnz, 1) * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->blk, blk.size() * sizeof(int)));
     if (!rord.empty()) PS_CREATE_HIP(hipMalloc(&M->rord, rord.size()));
@@ -1243,7 +1284,10 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   auto chk = [&](hipError_t e) { return e == hipSuccess; };
   const bool csr = M->format == PS_FMT_CSR;
   if ((csr && !chk(hipMemcpy(M->rowptr, rp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice))) ||
-      (csr && nnz > 0 && !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
+      (csr && nnz > 0 && M->index_bits == 32 &&
+       !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
+      (csr && nnz > 0 && M->index_bits == 16 &&
+       !chk(hipMemcpy(M->col16, col16.data(), nnz * sizeof(short), hipMemcpyHostToDevice))) ||
       (csr && nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
       (csr && !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice))) ||
       (csr && !rord.empty() &&
@@ -1360,7 +1404,7 @@ int ps_matrix_info(ps_matrix *A, ps_info *info) {
   info->auto_schedule = auto_fused(A) && A->nsys == 1 ? 1 : 0;
   info->nsys = A->nsys;
   info->streaming = streaming(A) ? 1 : 0;
-  info->index_bits = A->format == PS_FMT_SELL ? A->index_bits : 32;
+  info->index_bits = A->index_bits;
   info->n_padded = A->n;
   return PS_OK;
 }
@@ -1493,7 +1537,7 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
       ps_tune_entry &e = report->entry[report->count];
       e.layout = ps_layout{M->format, M->format == PS_FMT_SELL ? M->sell_rpl : -1,
                            M->format == PS_FMT_CSR ? M->shape : -1,
-                           M->format == PS_FMT_SELL ? M->index_bits : 32};
+                           M->index_bits};
       e.schedule = e.overlap = e.streaming = e.batch_iters = -1;
       e.us = us;
       if (!best || us < best_us) report->best = report->count;

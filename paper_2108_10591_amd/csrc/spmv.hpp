@@ -16,10 +16,13 @@ namespace ps {
 // VT: the stored type of the values, double or float (the matrix rounded to
 // FP32 for the mixed-precision solves); a float value is widened exactly, so
 // every product and sum below is the same FP64 arithmetic either way.
-template <class VT>
+// IT: the stored column index, int (the column) or short (the column minus
+// the first row of the entry's row block, when every entry fits: 10 instead
+// of 12 bytes per FP64 nonzero).
+template <class VT, class IT = int>
 struct CsrDev {
   const int *rowptr;   // int32[n+1]
-  const int *col;      // int32[nnz]
+  const IT *col;       // IT[nnz]
   const VT *val;       // VT[nnz]
   const int *blk;      // int32[nblk+1] first row of each row block
   // multi-lane shapes: the order in which a block's rows are summed, longest
@@ -63,8 +66,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // An epilogue with kDots > 0 also accumulates per-row terms of inner products
 // (compensated pairs, see dots.hpp) and writes the block's partial sums for row
 // block b; all lanes of the block take part in that reduction.
-template <int IPT, int LPR, class VT, class Epi>
-__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__restrict__ x,
+template <int IPT, int LPR, class VT, class IT, class Epi>
+__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double *__restrict__ x,
                                                  Epi epi_all, Stop st, int rev) {
   extern __shared__ double prod[];
   const int b = sweep_block(xcd_block(blockIdx.x, A.nblk), A.nblk, rev);
@@ -105,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
       // loads from a clamped slot (this row's first) instead of a guarded branch, and
       // values widened only at the product: with FP32 values a branch around each
       // load would hold its conversion and make every load wait for itself
-      int cc[kU];
+      IT cc[kU];
       VT vv[kU];
       double xx[kU];
 #pragma unroll
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
         vv[u] = A.val[kk];
       }
 #pragma unroll
-      for (int u = 0; u < kU; ++u) xx[u] = x[cc[u]];
+      for (int u = 0; u < kU; ++u) xx[u] = x[sizeof(IT) == 4 ? (int)cc[u] : r0 + (int)cc[u]];
 #pragma unroll
       for (int u = 0; u < kU; ++u)
         if (k + u * kBlock < k1) sum_acc(acc[0], (double)vv[u] * xx[u]);
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
     int c[IPT];
     VT v[IPT];  // widened at the product
     double xv[IPT];
-    if constexpr (sizeof(VT) == 8) {
+    if constexpr (sizeof(VT) == 8 && sizeof(IT) == 4) {
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
         const int k = threadIdx.x + i * kBlock;
@@ -138,12 +141,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
         }
       }
     } else {
-      // FP32 values: a guarded load would be widened inside its branch and wait
-      // for itself there, so unused slots load the block's first slot instead
-      // (a line lane 0 loads anyway); their products are never stored
+      // FP32 values or 16-bit columns: a guarded load would be widened or offset
+      // inside its branch and wait for itself there, so unused slots load the
+      // block's first slot instead (a line lane 0 loads anyway; their products
+      // are never stored), and columns are formed after all loads are issued
+      IT cr[IPT];
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
-        c[i] = 0;
+        cr[i] = IT(0);
         v[i] = VT(0);
       }
       if (nz > 0) {
@@ -151,10 +156,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT> A, const double *__r
         for (int i = 0; i < IPT; ++i) {
           const int k = threadIdx.x + i * kBlock;
           const int kk = k0 + (k < nz ? k : 0);
-          c[i] = A.col[kk];
+          cr[i] = A.col[kk];
           v[i] = A.val[kk];
         }
       }
+#pragma unroll
+      for (int i = 0; i < IPT; ++i)
+        c[i] = sizeof(IT) == 4 ? (int)cr[i] : (nz > 0 ? r0 + (int)cr[i] : 0);
     }
     // every gather unconditional (unused slots read x[0]), so that all IPT are
     // in flight together instead of one memory latency each

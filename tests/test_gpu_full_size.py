@@ -74,9 +74,12 @@ def test_spmv_full_size_bit_exact(case):
     assert info["auto_overlap"] == 1
     assert info["auto_schedule"] == {"cd3d_128": 1, "rand_band_1m": 0}[name]
     assert info["streaming"] == 1  # both move ~0.9 GiB per p-BiCGSafe iteration
-    if name == "cd3d_128":  # offsets up to 128^2 fit 16 bits: 10 bytes per slot
-        assert info["index_bits"] == 16
+    # offsets fit 16 bits (up to 128^2; the band's +-5000): 10 bytes per stored entry
+    assert info["index_bits"] == 16
+    if name == "cd3d_128":
         assert info["matrix_bytes"] == 10 * info["slots"] + 4 * (A.n // 64 + 1)
+    else:
+        assert info["matrix_bytes"] == 10 * A.nnz + 4 * (A.n + 1)
     x = np.random.default_rng(3).standard_normal(A.n)
     y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.array_equal(y, O.spmv(A, x)), name
