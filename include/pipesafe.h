@@ -164,8 +164,8 @@ typedef struct {
   int32_t spmv_blocks;   /* workgroups of one sparse product                            */
   int32_t dot_grid;      /* workgroups of the multi-inner-product kernel                */
   int64_t matrix_bytes;  /* bytes one sparse product must stream from the matrix arrays:
-                            CSR (8 + index_bits/8) nnz + 4 (n+1); SELL (8 +
-                            index_bits/8) slots + 4 (slices+1)                          */
+                            CSR (8 + index_bits/8 + 2 gather_sort) nnz + 4 (n+1);
+                            SELL (8 + index_bits/8) slots + 4 (slices+1)               */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe(-rr) */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
@@ -180,7 +180,8 @@ typedef struct {
                             sliced layout: column - row within 32767; CSR: column -
                             the first row of its row block within 32767 -- 10 instead
                             of 12 bytes per FP64 entry (PIPESAFE_INDEX=32 keeps 32)    */
-  int32_t reserved;
+  int32_t gather_sort;    /* CSR: 1 when row blocks are stored in column order
+                            (ps_layout.gather_sort; +2 bytes per entry)              */
 } ps_info;
 
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */
@@ -235,7 +236,8 @@ void ps_default_options(ps_options *opt);
  * product's launch shape are chosen here from the row lengths; the
  * environment variables PIPESAFE_FORMAT (0 CSR, 1 SELL), PIPESAFE_SELL_RPL
  * (rows per lane of the sliced layout: 1, the default, or 2 with 128-row
- * slices), PIPESAFE_INDEX (32: no 16-bit column offsets),
+ * slices), PIPESAFE_INDEX (32: no 16-bit column offsets), PIPESAFE_CSR_SORT
+ * (0 or 1: the CSR gather order),
  * PIPESAFE_SPMV_SHAPE (0..4), PIPESAFE_DOT_GRID (1..8192 workgroups) and
  * PIPESAFE_STREAM (0 or 1, ps_info.streaming) override the choices, for
  * tuning and tests.  Every choice gives
@@ -254,6 +256,11 @@ typedef struct ps_layout {
   int32_t index_bits;         /* 32 keeps 32-bit columns; 16 (or -1) stores 16-bit
                                  offsets where every entry fits (sliced: column -
                                  row; CSR: column - first row of its row block)      */
+  int32_t gather_sort;        /* CSR: 1 stores each row block's entries in column
+                                 order (with each one's place in the block's row
+                                 order, 2 bytes), so that a wave's gathers of x touch
+                                 few cache lines; 0 row order; -1 automatic: 1 when a
+                                 typical block's columns span more than 4096       */
 } ps_layout;
 
 /* ps_create / ps_create_batch with an explicit layout (NULL: automatic, as

@@ -98,6 +98,8 @@ struct ps_matrix {
   int *rowptr = nullptr, *col = nullptr, *blk = nullptr;
   unsigned char *rord = nullptr;  // CSR, multi-lane shapes: rows of each block longest first
   short *col16 = nullptr;         // CSR column - first row of its row block (index_bits 16)
+  unsigned short *pos = nullptr;  // CSR gather order: each entry's place in its block's row order
+  bool gather_sort = false;       // CSR: blocks stored in column order (pos != nullptr)
   double *val = nullptr;
   int nblk = 0;             // workgroups of one sparse product
   int shape = 1;            // SpMV shape: 0..4 = (IPT, LPR) (4,1) (8,1) (16,4) (16,8) (16,16)
@@ -164,6 +166,7 @@ struct ps_matrix {
     else A.val = val32;
     A.blk = blk;
     A.rord = rord;
+    A.pos = pos;
     A.nblk = nblk;
     return A;
   }
@@ -689,7 +692,7 @@ int collect_profile(ps_matrix *M, int stop_iter) {
 
 int64_t matrix_bytes(const ps_matrix *M) {
   return M->format == PS_FMT_CSR
-             ? (8 + M->index_bits / 8) * M->nnz + 4 * (M->n + 1)
+             ? (8 + M->index_bits / 8 + (M->gather_sort ? 2 : 0)) * M->nnz + 4 * (M->n + 1)
              : (8 + M->index_bits / 8) * M->slots + 4 * ((int64_t)M->nslice + 1);
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
@@ -889,6 +892,7 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->rowptr);
   (void)hipFree(M->col);
   (void)hipFree(M->col16);
+  (void)hipFree(M->pos);
   (void)hipFree(M->val);
   (void)hipFree(M->blk);
   (void)hipFree(M->rord);
@@ -981,7 +985,8 @@ bool valid_layout(const ps_layout *l) {
          (l->sell_rows_per_lane == -1 || l->sell_rows_per_lane == 1 ||
           l->sell_rows_per_lane == 2) &&
          (l->spmv_shape >= -1 && l->spmv_shape <= 4) &&
-         (l->index_bits == -1 || l->index_bits == 16 || l->index_bits == 32);
+         (l->index_bits == -1 || l->index_bits == 16 || l->index_bits == 32) &&
+         (l->gather_sort >= -1 && l->gather_sort <= 1);
 }
 
 int create_batch_impl(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64_t n,
@@ -1139,6 +1144,11 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   std::vector<int> blk, rp32;
   std::vector<unsigned char> rord;
   std::vector<short> col16;
+  std::vector<unsigned short> gpos;   // CSR gather order (empty: row order)
+  std::vector<int> gcol;              // the columns and values in that order
+  std::vector<double> gval;
+  const int32_t *ccol = col;          // the CSR arrays as uploaded
+  const double *cval = val;
   std::vector<int> scol, soff;
   std::vector<short> scol16;
   std::vector<double> sval;
@@ -1169,11 +1179,56 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
         for (size_t i = 0; i < loc.size(); ++i) rord[(size_t)r0 + i] = (unsigned char)loc[i];
       }
     }
+    // gather order: each short-row block's entries sorted by column (stable),
+    // when a typical block's columns span more than the L1 holds of x (4096
+    // doubles): a wave's gathers then touch a few cache lines instead of up to 64
+    // (1M-row band, +-5000: product 120 -> 100 us; a +-250 band, whose gathers
+    // already hit L1, 87 -> 97 us, hence the condition)
+    std::vector<int64_t> spans;
+    for (int b = 0; b < M->nblk; ++b) {
+      const int64_t k0 = rowptr[blk[b]], k1 = rowptr[blk[b + 1]];
+      if (k1 <= k0 || k1 - k0 > (int64_t)kIpt[M->shape] * kBlock) continue;
+      int cmin = col[k0], cmax = col[k0];
+      for (int64_t k = k0; k < k1; ++k) {
+        cmin = std::min(cmin, col[k]);
+        cmax = std::max(cmax, col[k]);
+      }
+      spans.push_back((int64_t)cmax - cmin + 1);
+    }
+    bool gsort = false;
+    if (!spans.empty()) {
+      std::nth_element(spans.begin(), spans.begin() + spans.size() / 2, spans.end());
+      gsort = spans[spans.size() / 2] > 4096;
+    }
+    if (const char *e = std::getenv("PIPESAFE_CSR_SORT")) gsort = std::atoi(e) != 0;
+    if (lay && lay->gather_sort >= 0) gsort = lay->gather_sort != 0;
+    M->gather_sort = gsort;
+    if (gsort) {
+      gpos.resize((size_t)std::max<int64_t>(nnz, 1));
+      gcol.assign(col, col + nnz);
+      gval.assign(val, val + nnz);
+      std::vector<int> loc;
+      for (int b = 0; b < M->nblk; ++b) {
+        const int64_t k0 = rowptr[blk[b]], k1 = rowptr[blk[b + 1]];
+        loc.resize((size_t)(k1 - k0));
+        for (size_t i = 0; i < loc.size(); ++i) loc[i] = (int)i;
+        if (k1 - k0 <= (int64_t)kIpt[M->shape] * kBlock)  // long rows keep row order
+          std::stable_sort(loc.begin(), loc.end(),
+                           [&](int a, int c) { return col[k0 + a] < col[k0 + c]; });
+        for (size_t i = 0; i < loc.size(); ++i) {
+          gpos[(size_t)k0 + i] = (unsigned short)loc[i];
+          gcol[(size_t)k0 + i] = col[k0 + loc[i]];
+          gval[(size_t)k0 + i] = val[k0 + loc[i]];
+        }
+      }
+      ccol = gcol.data();
+      cval = gval.data();
+    }
     // 16-bit column offsets from each row block's first row when they all fit
     bool fits16 = true;
     for (int b = 0; b < M->nblk && fits16; ++b)
       for (int64_t k = rowptr[blk[b]]; k < rowptr[blk[b + 1]]; ++k)
-        if (col[k] - blk[b] > 32767 || blk[b] - col[k] > 32767) {
+        if (ccol[k] - blk[b] > 32767 || blk[b] - ccol[k] > 32767) {
           fits16 = false;
           break;
         }
@@ -1186,7 +1241,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
       col16.resize((size_t)nnz);
       for (int b = 0; b < M->nblk; ++b)
         for (int64_t k = rowptr[blk[b]]; k < rowptr[blk[b + 1]]; ++k)
-          col16[(size_t)k] = (short)(col[k] - blk[b]);
+          col16[(size_t)k] = (short)(ccol[k] - blk[b]);
     }
   } else {
     M->nslice = (int)nslice;
@@ -1245,6 +1300,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   } while (0)
   if (M->format == PS_FMT_CSR) {
     PS_CREATE_HIP(hipMalloc(&M->rowptr, (n + 1) * sizeof(int)));
+    if (!gpos.empty())
+      PS_CREATE_HIP(hipMalloc(&M->pos, gpos.size() * sizeof(unsigned short)));
     if (M->index_bits == 16)
       PS_CREATE_HIP(hipMalloc(&M->col16, std::max<int64_t>(nnz, 1) * sizeof(short)));
     else
@@ -1285,10 +1342,13 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   const bool csr = M->format == PS_FMT_CSR;
   if ((csr && !chk(hipMemcpy(M->rowptr, rp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice))) ||
       (csr && nnz > 0 && M->index_bits == 32 &&
-       !chk(hipMemcpy(M->col, col, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
+       !chk(hipMemcpy(M->col, ccol, nnz * sizeof(int), hipMemcpyHostToDevice))) ||
+      (csr && !gpos.empty() &&
+       !chk(hipMemcpy(M->pos, gpos.data(), gpos.size() * sizeof(unsigned short),
+                      hipMemcpyHostToDevice))) ||
       (csr && nnz > 0 && M->index_bits == 16 &&
        !chk(hipMemcpy(M->col16, col16.data(), nnz * sizeof(short), hipMemcpyHostToDevice))) ||
-      (csr && nnz > 0 && !chk(hipMemcpy(M->val, val, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
+      (csr && nnz > 0 && !chk(hipMemcpy(M->val, cval, nnz * sizeof(double), hipMemcpyHostToDevice))) ||
       (csr && !chk(hipMemcpy(M->blk, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice))) ||
       (csr && !rord.empty() &&
        !chk(hipMemcpy(M->rord, rord.data(), rord.size(), hipMemcpyHostToDevice))) ||
@@ -1405,6 +1465,7 @@ int ps_matrix_info(ps_matrix *A, ps_info *info) {
   info->nsys = A->nsys;
   info->streaming = streaming(A) ? 1 : 0;
   info->index_bits = A->index_bits;
+  info->gather_sort = A->format == PS_FMT_CSR && A->gather_sort ? 1 : 0;
   info->n_padded = A->n;
   return PS_OK;
 }
@@ -1480,10 +1541,11 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
   std::vector<ps_layout> cand;
   for (int rpl = 1; rpl <= 2; ++rpl)
     if (sell_ok(rpl)) {
-      cand.push_back(ps_layout{PS_FMT_SELL, rpl, -1, -1});
-      cand.push_back(ps_layout{PS_FMT_SELL, rpl, -1, 32});
+      cand.push_back(ps_layout{PS_FMT_SELL, rpl, -1, -1, -1});
+      cand.push_back(ps_layout{PS_FMT_SELL, rpl, -1, 32, -1});
     }
-  for (int sh = 0; sh <= 4; ++sh) cand.push_back(ps_layout{PS_FMT_CSR, -1, sh, -1});
+  for (int gs = 0; gs <= 1; ++gs)
+    for (int sh = 0; sh <= 4; ++sh) cand.push_back(ps_layout{PS_FMT_CSR, -1, sh, -1, gs});
   if (report) {
     std::memset(report, 0, sizeof(*report));
     report->best = -1;
@@ -1536,8 +1598,8 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
     if (report && report->count < PS_TUNE_MAX) {
       ps_tune_entry &e = report->entry[report->count];
       e.layout = ps_layout{M->format, M->format == PS_FMT_SELL ? M->sell_rpl : -1,
-                           M->format == PS_FMT_CSR ? M->shape : -1,
-                           M->index_bits};
+                           M->format == PS_FMT_CSR ? M->shape : -1, M->index_bits,
+                           M->format == PS_FMT_CSR ? (M->gather_sort ? 1 : 0) : -1};
       e.schedule = e.overlap = e.streaming = e.batch_iters = -1;
       e.us = us;
       if (!best || us < best_us) report->best = report->count;
@@ -1602,7 +1664,7 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
           if (rc != PS_OK) break;
           if (report && report->count < PS_TUNE_MAX) {
             ps_tune_entry &e = report->entry[report->count];
-            e.layout = ps_layout{-1, -1, -1, -1};
+            e.layout = ps_layout{-1, -1, -1, -1, -1};
             e.schedule = sc;
             e.overlap = ov;
             e.streaming = sm < 0 ? (streaming(A) ? 1 : 0) : sm;

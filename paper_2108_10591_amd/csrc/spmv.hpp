@@ -29,6 +29,10 @@ struct CsrDev {
   // first (uint8[n], block-local indices), so that the rows a wave sums in one
   // round have similar lengths; nullptr = storage order
   const unsigned char *rord;
+  // gather order: a block's nonzeros stored sorted by column (so that a wave's
+  // gathers touch few cache lines), with each one's position in the block's
+  // row order (uint16[nnz]) for the product's slot; nullptr = row order
+  const unsigned short *pos;
   int nblk;
 };
 
@@ -126,9 +130,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
     const DD t = block_sum_dd<1>(acc, prod);
     if (threadIdx.x == 0) put(r0, t.hi + t.lo, epi.load(r0));
   } else {
-    int c[IPT];
+    int c[IPT], ps[IPT];
     VT v[IPT];  // widened at the product
     double xv[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) ps[i] = threadIdx.x + i * kBlock;
     if constexpr (sizeof(VT) == 8 && sizeof(IT) == 4) {
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
@@ -138,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
         if (k < nz) {
           c[i] = A.col[k0 + k];
           v[i] = A.val[k0 + k];
+          if (A.pos) ps[i] = A.pos[k0 + k];
         }
       }
     } else {
@@ -158,6 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
           const int kk = k0 + (k < nz ? k : 0);
           cr[i] = A.col[kk];
           v[i] = A.val[kk];
+          if (A.pos) ps[i] = A.pos[kk];
         }
       }
 #pragma unroll
@@ -171,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const int k = threadIdx.x + i * kBlock;
-      if (k < nz) prod[k] = (double)v[i] * xv[i];
+      if (k < nz) prod[ps[i]] = (double)v[i] * xv[i];
     }
     __syncthreads();
     if constexpr (LPR == 1) {

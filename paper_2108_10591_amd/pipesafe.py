@@ -47,7 +47,7 @@ class Info(ctypes.Structure):
                 ("dot_grid", ctypes.c_int32), ("matrix_bytes", ctypes.c_int64),
                 ("auto_overlap", ctypes.c_int32), ("auto_schedule", ctypes.c_int32),
                 ("nsys", ctypes.c_int32), ("streaming", ctypes.c_int32), ("n_padded", ctypes.c_int64),
-                ("index_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("index_bits", ctypes.c_int32), ("gather_sort", ctypes.c_int32)]
 
 
 FORMATS = {0: "csr", 1: "sell"}
@@ -57,11 +57,13 @@ FORMAT_IDS = {"csr": 0, "sell": 1}
 class Layout(ctypes.Structure):
     """ps_layout: an explicit device layout; -1 = automatic."""
     _fields_ = [("format", ctypes.c_int32), ("sell_rows_per_lane", ctypes.c_int32),
-                ("spmv_shape", ctypes.c_int32), ("index_bits", ctypes.c_int32)]
+                ("spmv_shape", ctypes.c_int32), ("index_bits", ctypes.c_int32),
+                ("gather_sort", ctypes.c_int32)]
 
 
-def layout(format=-1, sell_rows_per_lane=-1, spmv_shape=-1, index_bits=-1) -> Layout:
-    return Layout(FORMAT_IDS.get(format, format), sell_rows_per_lane, spmv_shape, index_bits)
+def layout(format=-1, sell_rows_per_lane=-1, spmv_shape=-1, index_bits=-1, gather_sort=-1) -> Layout:
+    return Layout(FORMAT_IDS.get(format, format), sell_rows_per_lane, spmv_shape, index_bits,
+                  gather_sort)
 
 
 class TuneEntry(ctypes.Structure):
@@ -80,7 +82,8 @@ class TuneReport(ctypes.Structure):
             r = {"us": e.us, "best": k == self.best}
             if e.layout.format >= 0:
                 r.update(format=FORMATS[e.layout.format], sell_rows_per_lane=e.layout.sell_rows_per_lane,
-                         spmv_shape=e.layout.spmv_shape, index_bits=e.layout.index_bits)
+                         spmv_shape=e.layout.spmv_shape, index_bits=e.layout.index_bits,
+                         gather_sort=e.layout.gather_sort)
             else:
                 r.update(schedule=e.schedule, overlap=e.overlap, streaming=e.streaming,
                          batch_iters=e.batch_iters)

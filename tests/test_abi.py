@@ -136,7 +136,8 @@ def test_create_batch_rejects_invalid_layout_before_touching_the_device(lib, cas
 
 @pytest.mark.parametrize("field,value", [("format", 2), ("format", -2), ("sell_rows_per_lane", 3),
                                          ("sell_rows_per_lane", 0), ("spmv_shape", 5),
-                                         ("index_bits", 8), ("index_bits", 64)])
+                                         ("index_bits", 8), ("index_bits", 64),
+                                         ("gather_sort", 2), ("gather_sort", -2)])
 def test_create_ex_rejects_invalid_layout_before_touching_the_device(lib, field, value):
     from paper_2108_10591_amd import pipesafe
     L = pipesafe.library()
@@ -156,9 +157,9 @@ def test_create_ex_rejects_invalid_layout_before_touching_the_device(lib, field,
 def test_tuner_structs_and_argument_checks(lib):
     from paper_2108_10591_amd import pipesafe
     L = pipesafe.library()
-    assert ctypes.sizeof(pipesafe.Layout) == 16
-    assert ctypes.sizeof(pipesafe.TuneEntry) == 40
-    assert ctypes.sizeof(pipesafe.TuneReport) == 8 + 48 * 40
+    assert ctypes.sizeof(pipesafe.Layout) == 20
+    assert ctypes.sizeof(pipesafe.TuneEntry) == 48
+    assert ctypes.sizeof(pipesafe.TuneReport) == 8 + 48 * 48
     rp = np.array([0, 1, 2], dtype=np.int64)
     c = np.array([0, 1], dtype=np.int32)
     v = np.array([1.0, 2.0])

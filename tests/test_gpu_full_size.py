@@ -78,8 +78,9 @@ def test_spmv_full_size_bit_exact(case):
     assert info["index_bits"] == 16
     if name == "cd3d_128":
         assert info["matrix_bytes"] == 10 * info["slots"] + 4 * (A.n // 64 + 1)
-    else:
-        assert info["matrix_bytes"] == 10 * A.nnz + 4 * (A.n + 1)
+    else:  # blocks span ~10^4 columns: stored in column order, +2 bytes per entry
+        assert info["gather_sort"] == 1
+        assert info["matrix_bytes"] == 12 * A.nnz + 4 * (A.n + 1)
     x = np.random.default_rng(3).standard_normal(A.n)
     y = M.spmv_dev(torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.array_equal(y, O.spmv(A, x)), name

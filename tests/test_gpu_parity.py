@@ -79,13 +79,16 @@ def _spmv_matrix(case):
 def device_format(fmt):
     """Force the device layout ps_create picks (PIPESAFE_FORMAT: 0 CSR, 1 sliced ELLPACK;
     "sell2": sliced with two rows per lane, PIPESAFE_SELL_RPL=2)."""
-    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SELL_RPL", "PIPESAFE_INDEX")
+    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SELL_RPL", "PIPESAFE_INDEX", "PIPESAFE_CSR_SORT")
     old = {k: os.environ.get(k) for k in keys}
-    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "csr32": "0", "sell": "1", "sell2": "1",
+    os.environ["PIPESAFE_FORMAT"] = {"csr": "0", "csr32": "0", "csr_sorted": "0",
+                                     "csr32_sorted": "0", "sell": "1", "sell2": "1",
                                      "sell32": "1", "sell2_32": "1"}[fmt]
+    # CSR row blocks stored in column order ("_sorted") or in row order
+    os.environ["PIPESAFE_CSR_SORT"] = "1" if fmt.endswith("_sorted") else "0"
     os.environ["PIPESAFE_SELL_RPL"] = "2" if fmt.startswith("sell2") else "1"
     # both layouts store 16-bit column offsets when they fit; "..32" keeps columns
-    os.environ["PIPESAFE_INDEX"] = "32" if fmt.endswith("32") else "16"
+    os.environ["PIPESAFE_INDEX"] = "32" if "32" in fmt else "16"
     try:
         yield
     finally:
@@ -96,7 +99,8 @@ def device_format(fmt):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("fmt", ["csr", "csr32", "sell", "sell2", "sell32", "sell2_32"])
+@pytest.mark.parametrize("fmt", ["csr", "csr32", "csr_sorted", "csr32_sorted", "sell", "sell2",
+                                 "sell32", "sell2_32"])
 @pytest.mark.parametrize("case", sorted(SPMV_CASES))
 def test_spmv_matches_oracle(case, fmt):
     import torch
@@ -108,7 +112,7 @@ def test_spmv_matches_oracle(case, fmt):
         info = M.info()
         assert info["format"] == ("csr" if fmt.startswith("csr") else "sell")
         span = int(np.abs(A.col - np.repeat(np.arange(A.n), np.diff(A.rowptr))).max(initial=0))
-        if fmt.endswith("32"):
+        if "32" in fmt:
             assert info["index_bits"] == 32
         elif span + 256 <= 32767:  # fits both the row and the row block's first row
             assert info["index_bits"] == 16
@@ -136,13 +140,14 @@ def _solve_both(A, variant, tol, maxit=5000, **opt):
 
 
 @contextlib.contextmanager
-def csr_shape(shape, index_bits=16):
+def csr_shape(shape, index_bits=16, gather_sort=0):
     """Force the CSR layout and the product's launch shape (PIPESAFE_SPMV_SHAPE 0..4:
     (nonzeros per thread, lanes per row) = (4,1) (8,1) (16,4) (16,8) (16,16))."""
-    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SPMV_SHAPE", "PIPESAFE_INDEX")
+    keys = ("PIPESAFE_FORMAT", "PIPESAFE_SPMV_SHAPE", "PIPESAFE_INDEX", "PIPESAFE_CSR_SORT")
     old = {k: os.environ.get(k) for k in keys}
     os.environ["PIPESAFE_FORMAT"] = "0"
     os.environ["PIPESAFE_INDEX"] = str(index_bits)
+    os.environ["PIPESAFE_CSR_SORT"] = str(gather_sort)
     os.environ["PIPESAFE_SPMV_SHAPE"] = str(shape)
     try:
         yield
@@ -174,12 +179,13 @@ def test_every_csr_shape_reproduces_oracle(shape):
     """Each launch shape of the CSR product with every epilogue that finishes a row (the
     multi-lane shapes load a row's epilogue operands before its sum, in the lane that
     stores it): p-BiCGSafe in both schedules, ssBiCGSafe2, p-BiCGSafe-rr."""
-    for A, bits in ((_uneven_rows(), 16), (_uneven_rows(), 32),
-                    (W.small_nonsym(3001, 11, density=0.003), 16)):
-        with csr_shape(shape, bits), pipesafe.Matrix.from_csr(A) as M:
+    for A, bits, gs in ((_uneven_rows(), 16, 0), (_uneven_rows(), 32, 1), (_uneven_rows(), 16, 1),
+                        (W.small_nonsym(3001, 11, density=0.003), 16, 0),
+                        (W.small_nonsym(3001, 11, density=0.003), 32, 1)):
+        with csr_shape(shape, bits, gs), pipesafe.Matrix.from_csr(A) as M:
             info = M.info()
             assert info["format"] == "csr" and info["spmv_shape"] == shape
-            assert info["index_bits"] == bits
+            assert info["index_bits"] == bits and info["gather_sort"] == gs
             for variant, kw in (("pbicgsafe", dict(schedule=0)), ("pbicgsafe", dict(schedule=1)),
                                 ("ssbicgsafe2", {}), ("pbicgsafe_rr", dict(rr_m=7))):
                 say(f"csr shape {shape} {A.name} {variant} {kw}")
@@ -260,6 +266,7 @@ def test_device_layout_choice():
             assert info["matrix_bytes"] == 10 * slots + 4 * (ns + 1)
         else:  # 16-bit offsets from each row block's first row: 10 bytes per nonzero
             assert info["index_bits"] == 16
+            assert info["gather_sort"] == 0  # blocks span fewer than 4096 columns
             assert info["slots"] == A.nnz and info["matrix_bytes"] == 10 * A.nnz + 4 * (A.n + 1)
 
 
@@ -275,6 +282,8 @@ def test_both_layouts_reproduce_oracle(variant):
                          ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "sell2_32"),
                          ("cd3d_16", W.cd3d(16, 20.0, seed=1), "sell32"),
                          ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), "csr32"),
+                         ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), "csr_sorted"),
+                         ("cd3d_16", W.cd3d(16, 20.0, seed=1), "csr32_sorted"),
                          ("nonsym_ragged_3001", W.small_nonsym(3001, 11, density=0.003), "csr32"),
                          ("cd2d_5", W.cd2d(5, 10.0), "sell")]:
         say(f"layout {fmt} {name} {variant}")
