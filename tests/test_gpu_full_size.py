@@ -72,7 +72,7 @@ def test_spmv_full_size_bit_exact(case):
     info = M.info()
     assert info["format"] == {"cd3d_128": "sell", "rand_band_1m": "csr"}[name]
     assert info["auto_overlap"] == 1
-    assert info["auto_schedule"] == {"cd3d_128": 1, "rand_band_1m": 0}[name]
+    assert info["auto_schedule"] == {"cd3d_128": 2, "rand_band_1m": 0}[name]
     assert info["streaming"] == 1  # both move ~0.9 GiB per p-BiCGSafe iteration
     # offsets fit 16 bits (up to 128^2; the band's +-5000): 10 bytes per stored entry
     assert info["index_bits"] == 16
