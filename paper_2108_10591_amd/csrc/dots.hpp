@@ -366,6 +366,44 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
   }
 }
 
+// The fused schedules' finish when the partial lists are short: add pass A's
+// (or the fused epilogue's) [5][ga] pairs of (b, e, f, h, rho) and the
+// epilogue's [4][gb] pairs of (a, c, d, g) directly, without k_fold_partials --
+// one launch fewer per iteration on small systems.
+template <class Fin>
+__global__ __launch_bounds__(kBlock) void k_dots_finish_direct(DotArgs A,
+                                                               const double *__restrict__ pa,
+                                                               int ga,
+                                                               const double *__restrict__ pb,
+                                                               int gb) {
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double fin[9];
+  if (A.ctl[C_DONE]) return;
+  constexpr int kA[5] = {1, 4, 5, 7, 8};
+  constexpr int kB[4] = {0, 2, 3, 6};
+  DD tot[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) tot[j] = DD{0.0, 0.0};
+  for (int b = threadIdx.x; b < ga; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) dd_add(tot[kA[j]], pa[(j * ga + b) * 2], pa[(j * ga + b) * 2 + 1]);
+  }
+  for (int b = threadIdx.x; b < gb; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dd_add(tot[kB[j]], pb[(j * gb + b) * 2], pb[(j * gb + b) * 2 + 1]);
+  }
+  const DD s = block_sum_dd<9>(tot, lds);
+  if (threadIdx.x < 9) fin[threadIdx.x] = s.hi + s.lo;  // the one final rounding
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) d[j] = fin[j];
+    Fin::run(A, d);
+    if (A.ctl[C_DONE]) atomicSub(A.running, 1);
+  }
+}
+
 // ------------------------------------------------------- batched solves
 // Every system is padded to a multiple of 512 rows, so workgroup b (rows
 // 512 b .. 512 b + 511, one pair per lane) lies in one system; it writes its

@@ -64,6 +64,9 @@ constexpr int64_t kStreamMinBytes = 512ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 constexpr int kSellRowsPerLane = 1;       // 64-row slices
 constexpr double kTuneMaxPadding = 1.5;   // the autotuner tries the sliced layout up to this
+// fused schedules: the finish adds the partial lists itself (no fold kernel)
+// when they hold at most this many workgroups' pairs
+constexpr int kDirectFinishMax = 4096;
 
 struct Timer {
   hipEvent_t a, b;
@@ -426,11 +429,8 @@ int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
   const int ga = P.fused2 ? M->nblk : M->ga;
   double *pa = M->fpart, *pb = pa + 2 * 5 * (size_t)ga;
   double *pf = M->fpart + 2 * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk);
-  PS_TRY(launch(M, s, PS_K_DOTS, k_fold_partials, dim3(M->gfold), 0, (const double *)pa, ga,
-                (const double *)pb, M->nblk, pf, (const int *)M->ctl));
   DotArgs D{};
   D.n = M->n;
-  D.partials = pf;
   D.ctl = M->ctl;
   D.sc = M->sc;
   D.hist = M->hist;
@@ -438,6 +438,12 @@ int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
   D.tol = P.tol;
   D.flags = 0;
   D.running = M->running();
+  if (ga + M->nblk <= kDirectFinishMax)  // short lists: no fold
+    return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish_direct<FinSafe>, dim3(1), 0, D,
+                  (const double *)pa, ga, (const double *)pb, M->nblk);
+  PS_TRY(launch(M, s, PS_K_DOTS, k_fold_partials, dim3(M->gfold), 0, (const double *)pa, ga,
+                (const double *)pb, M->nblk, pf, (const int *)M->ctl));
+  D.partials = pf;
   return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<9, FinSafe>, dim3(1), 0, D, M->gfold);
 }
 
@@ -696,11 +702,18 @@ int64_t matrix_bytes(const ps_matrix *M) {
              : (8 + M->index_bits / 8) * M->slots + 4 * ((int64_t)M->nslice + 1);
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
-// the automatic p-BiCGSafe(-rr) schedule: the fused epilogue (2) on the sliced
-// layout from kFusedMinRows rows (measured on 64^3..128^3 stencils: within 1%
-// of schedule 1 up to 112^3, 5.5% faster at 128^3), else the separate pass (0)
+// The automatic p-BiCGSafe(-rr) schedule, from measurements:
+//  - sliced layout: the fused epilogue (2) from 2^20 rows (5.5% faster than 1
+//    at 128^3, within 1% of it from 64^3 to 112^3), else the fused partial
+//    sums (1: up to 9% faster than 2 near 10^5 rows, and both 15% faster than
+//    0 on small systems, where the finish adds the partial lists itself and
+//    an iteration is one launch shorter);
+//  - CSR: 1 below kFusedMinRows rows (4-9% faster than 0 on small uneven
+//    matrices), else the separate pass (0: gather-bound products gain nothing
+//    from the skipped pass and pay for the extra epilogue reads).
 int auto_schedule(const ps_matrix *M) {
-  return M->format == PS_FMT_SELL && M->n >= kFusedMinRows ? 2 : 0;
+  if (M->format == PS_FMT_SELL) return M->n >= (1 << 20) ? 2 : 1;
+  return M->n < kFusedMinRows ? 1 : 0;
 }
 // two sparse products and the update passes' 34 vector reads and writes
 bool streaming(const ps_matrix *M) {
