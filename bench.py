@@ -160,8 +160,10 @@ def bench_batch(name, reps=3):
         torch.cuda.synchronize()
         t_batch = (time.perf_counter() - t0) / reps
     assert np.all(r.status == pipesafe.CONVERGED), r.status
-    # algorithmic bytes: each system's own iterations at its CSR byte model
-    gb = sum(int(r.iters[k]) * bytes_per_iteration("pbicgsafe", A.n, A.nnz) / 1e9
+    # algorithmic bytes: each system's own iterations at its CSR byte model, for the
+    # schedule the library chose
+    sched = info["auto_schedule"]
+    gb = sum(int(r.iters[k]) * bytes_per_iteration("pbicgsafe", A.n, A.nnz, sched) / 1e9
              for k, A in enumerate(B.systems))
     log(f"  batched: {1e3 * t_batch:.1f} ms, {B.nsys / t_batch:.0f} solves/s, "
         f"iterations {int(r.iters.min())}..{int(r.iters.max())}")
@@ -205,7 +207,7 @@ def bench_batch(name, reps=3):
     log(f"  autotuned ({t_tune:.1f} s of tuning): layout {best}, options {topts}: "
         f"{1e3 * t_tuned:.1f} ms, {B.nsys / t_tuned:.0f} solves/s")
     return {"workload": name, "systems": B.nsys, "rows": C.n, "nnz": C.nnz, "tol": tol,
-            "variant": "pbicgsafe", "layout": info["format"],
+            "variant": "pbicgsafe", "layout": info["format"], "schedule": sched,
             "iterations_min_mean_max": [int(r.iters.min()), round(float(r.iters.mean()), 1),
                                         int(r.iters.max())],
             "time_ms": round(1e3 * t_batch, 2), "solves_per_s": round(B.nsys / t_batch, 1),

@@ -94,7 +94,7 @@ typedef struct {
                           bit-identical either way.  Ignored while profiling.          */
   int32_t schedule;    /* p-BiCGSafe and p-BiCGSafe-rr.  -1 (default): automatic --
                           sliced layout: 2 from 2^20 rows, else 1; CSR: 1 below 2^18
-                          rows, else 0
+                          rows, else 0; batches: 2
                           (ps_info.auto_schedule tells; other variants ignore -1).
                           With -rr, a replacement step and the iteration after it form
                           their inner products in their own pass.
@@ -112,8 +112,9 @@ typedef struct {
                           of the iteration and all nine partial sums: 24n bytes fewer
                           than 1 (measured: equal to 1 within 1% up to 112^3 stencils,
                           5.5% faster at 128^3; slower than 0 on uneven CSR rows).
-                          Results are bit-identical to schedule 0.  Other variants and
-                          batches: 1 and 2 are PS_EINVAL.                               */
+                          Batches: each system's partial sums are added by a workgroup
+                          of its own.  Results are bit-identical to schedule 0.  Other
+                          variants: 1 and 2 are PS_EINVAL.                              */
   int32_t x0_fallback; /* 1: if x0 is given and ||b - A x0|| > ||b|| (or is not finite),
                           start from x0 = 0 instead (per system for a batch); a guess
                           that is worse than zero costs nothing then.  0 (default): use
@@ -307,7 +308,7 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
 
 /* Time `iters` iterations of `variant` from b_dev (DEVICE, the caller's row
    order, as ps_solve_batch_dev; x0 = 0, tol = 0) for every combination of
-   schedule (p-BiCGSafe(-rr), one system: 0, 1, 2), overlap (0, 1; ssBiCGSafe2: 0),
+   schedule (p-BiCGSafe(-rr): 0, 1, 2), overlap (0, 1; ssBiCGSafe2: 0),
    streaming update passes (p-BiCGSafe(-rr): off, on) and graph batch (8, 16, 32
    iterations), each run once to capture its graphs and once timed (host
    clock around the call), and write the fastest into opt->schedule,
@@ -363,7 +364,7 @@ int ps_create_batch(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int64
  * status: HOST int32[nsys] per system (as in ps_solve); hist: NULL or HOST
  * double[nsys * (maxit+1)], row k holding system k's history (entries past
  * iters[k] are undefined).  opt as in ps_solve, except: resume is not
- * supported (PS_EINVAL), schedule 1 is PS_EINVAL and -1 means 0 for nsys > 1.
+ * supported (PS_EINVAL) and schedule -1 means 2 for nsys > 1.
  * The solve runs until every system has stopped.
  */
 int ps_solve_batch(ps_matrix *A, const double *b, const double *x0, double tol, int32_t maxit,

@@ -463,6 +463,47 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const i
   }
 }
 
+// Batched fused schedules: per system k (one workgroup each), add its range of
+// the [5][ga] pairs of (b, e, f, h, rho) -- workgroups a_first[k] ..
+// a_first[k+1]-1 -- and of the [4][gb] pairs of (a, c, d, g) -- b_first[k] ..
+// b_first[k+1]-1 -- and run the system's finish.
+template <class Fin>
+__global__ __launch_bounds__(kBlock) void k_dots_finish_batch_direct(
+    DotArgs A, const double *__restrict__ pa, int ga, const int *__restrict__ a_first,
+    const double *__restrict__ pb, int gb, const int *__restrict__ b_first, int64_t hist_stride) {
+  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double fin[9];
+  const int k = blockIdx.x;
+  DotArgs Ak = A;
+  Ak.ctl += (size_t)k * C_COUNT;
+  Ak.sc += (size_t)k * SC_COUNT;
+  Ak.hist += k * hist_stride;
+  if (Ak.ctl[C_DONE]) return;
+  constexpr int kA[5] = {1, 4, 5, 7, 8};
+  constexpr int kB[4] = {0, 2, 3, 6};
+  DD tot[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) tot[j] = DD{0.0, 0.0};
+  for (int b = a_first[k] + threadIdx.x; b < a_first[k + 1]; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) dd_add(tot[kA[j]], pa[(j * ga + b) * 2], pa[(j * ga + b) * 2 + 1]);
+  }
+  for (int b = b_first[k] + threadIdx.x; b < b_first[k + 1]; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dd_add(tot[kB[j]], pb[(j * gb + b) * 2], pb[(j * gb + b) * 2 + 1]);
+  }
+  const DD s = block_sum_dd<9>(tot, lds);
+  if (threadIdx.x < 9) fin[threadIdx.x] = s.hi + s.lo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) d[j] = fin[j];
+    Fin::run(Ak, d);
+    if (Ak.ctl[C_DONE]) atomicSub(A.running, 1);
+  }
+}
+
 // Fused-dot schedule: the nine inner products of iteration i arrive as block
 // partial sums from the two passes of iteration i-1 -- pass A: [5][ga] pairs of
 // (b, e, f, h, rho), the epilogue of A w_{i-1}: [4][gb] pairs of (a, c, d, g).

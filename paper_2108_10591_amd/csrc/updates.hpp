@@ -215,7 +215,7 @@ struct PassWArgs {
   int *ctl;
   int64_t n;
   int rev;               // sweep direction
-  const int *chunk_sys;  // always nullptr (one system)
+  const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
 template <int W>

@@ -95,7 +95,7 @@ def test_autotuned_batch_reproduces_oracle():
         b = np.concatenate([S.b for S in systems])
         bd = torch.from_numpy(b).cuda()
         opts, orows = M.tune_options(bd, variant="pbicgsafe", iters=10)
-        assert len(orows) == 2 * 2 * 3  # no fused schedule for batches
+        assert len(orows) == 3 * 2 * 2 * 3  # schedules x overlap x streaming x graph batch
         res = M.solve(b, tol=1e-10, maxit=2000, variant="pbicgsafe", **opts)
     off = 0
     for k, S in enumerate(systems):

@@ -82,8 +82,13 @@ def test_batch_equals_each_system_alone(variant):
         with pipesafe.BatchMatrix.from_batch(B) as M:
             info = M.info()
             assert info["nsys"] == B.nsys and info["n"] == C.n and info["n_padded"] % 512 == 0
-            for kw in (dict(overlap=0, graph=0), dict(overlap=1, graph=1, batch_iters=3),
-                       dict(graph=1, batch_iters=5)):
+            runs = [dict(overlap=0, graph=0), dict(overlap=1, graph=1, batch_iters=3),
+                    dict(graph=1, batch_iters=5)]
+            if variant in ("pbicgsafe", "pbicgsafe_rr"):  # the fused-dot schedules
+                runs += [dict(schedule=1, graph=0), dict(schedule=1, graph=1, batch_iters=4),
+                         dict(schedule=2, overlap=0, graph=0),
+                         dict(schedule=2, graph=1, batch_iters=3)]
+            for kw in runs:
                 say(f"batch {variant} tol={tol} {kw}")
                 res = M.solve(b, tol=tol, maxit=maxit, variant=variant, rr_m=9, **kw)
                 check_same(res, refs, B, (variant, tol, str(kw)))
@@ -114,12 +119,14 @@ def test_batch_both_layouts_and_device_buffers(fmt):
             os.environ["PIPESAFE_FORMAT"] = old
     with M:
         assert M.info()["format"] == fmt
-        say(f"batch layout {fmt}, device buffers, x0, norm_ref = 1")
-        res = M.solve_dev(torch.from_numpy(b).cuda(), x0=torch.from_numpy(x0).cuda(), tol=1e-9,
-                          maxit=2000, variant="pbicgsafe", norm_ref=1)
-        torch.cuda.synchronize()
-        res.x = res.x.cpu().numpy()
-        check_same(res, refs, B, fmt)
+        for sched in (0, 1, 2):
+            say(f"batch layout {fmt}, device buffers, x0, norm_ref = 1, schedule {sched}")
+            res = M.solve_dev(torch.from_numpy(b).cuda(), x0=torch.from_numpy(x0).cuda(),
+                              tol=1e-9, maxit=2000, variant="pbicgsafe", norm_ref=1,
+                              schedule=sched)
+            torch.cuda.synchronize()
+            res.x = res.x.cpu().numpy()
+            check_same(res, refs, B, (fmt, sched))
 
 
 def test_batch_rejects_single_system_calls():
@@ -128,18 +135,21 @@ def test_batch_rejects_single_system_calls():
         L = pipesafe.library()
         assert L.ps_solve(M._h, None, None, 1e-8, 10, 1, None, None, None, None, None) == -1
         with pytest.raises(pipesafe.PipesafeError):
-            M.solve(b, tol=1e-8, maxit=10, variant="pbicgsafe", schedule=1)
+            M.solve(b, tol=1e-8, maxit=10, variant="pbicgstab", schedule=1)
         with pytest.raises(pipesafe.PipesafeError):
             M.solve(b, tol=1e-8, maxit=10, variant="pbicgsafe", resume=1)
-        # schedule -1 (automatic) means the separate inner-product pass for batches
+        # schedule -1 (automatic) means the fused epilogue for batches
+        assert M.info()["auto_schedule"] == 2
         res = M.solve(b, tol=1e-10, maxit=50, variant="pbicgsafe", schedule=-1)
         assert res.iters[2] == 1
 
 
-def test_full_batch_512_reproduces_oracle():
+@pytest.mark.parametrize("schedule", [-1, 1, 2])
+def test_full_batch_512_reproduces_oracle(schedule):
     """The 512-system benchmark batch (N ~ U[32, 256], 12.4M rows): every system's
     iteration count, status, history and solution bits against the oracle's
-    independent solves, written by tests/golden/make_batch.py."""
+    independent solves, written by tests/golden/make_batch.py, under each
+    inner-product schedule."""
     import torch
     g = json.load(open(GOLDEN))
     name = g["workload"]
@@ -147,8 +157,9 @@ def test_full_batch_512_reproduces_oracle():
     tol = W.BATCHES[name]["tol"]
     C = Bt.concat()
     with pipesafe.BatchMatrix.from_batch(Bt) as M:
-        say(f"full batch {name}: {Bt.nsys} systems, n = {C.n}")
-        res = M.solve_dev(torch.from_numpy(C.b).cuda(), tol=tol, maxit=10_000, variant="pbicgsafe")
+        say(f"full batch {name}: {Bt.nsys} systems, n = {C.n}, schedule {schedule}")
+        res = M.solve_dev(torch.from_numpy(C.b).cuda(), tol=tol, maxit=10_000, variant="pbicgsafe",
+                          schedule=schedule)
         x = res.x.cpu().numpy()
     p = Bt.sys_ptr()
     for k in range(Bt.nsys):
