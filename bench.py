@@ -187,7 +187,7 @@ def bench_batch(name, reps=3):
         M1.close()
     assert it_seq == [int(i) for i in r.iters]
     log(f"  one at a time: {1e3 * t_seq:.1f} ms, {B.nsys / t_seq:.0f} solves/s")
-    # the autotuner: layout by timed products, then options by timed iterations
+    # the autotuner: layout, then options, each by timed iterations
     t0 = time.perf_counter()
     Mt, lrows = pipesafe.BatchMatrix.autotuned(B, reps=10)
     with Mt:

@@ -286,7 +286,7 @@ typedef struct ps_tune_entry {
   int32_t overlap;
   int32_t streaming;
   int32_t batch_iters;
-  double us;            /* microseconds per product (layout) or per iteration (options) */
+  double us;            /* microseconds per iteration                                   */
 } ps_tune_entry;
 typedef struct ps_tune_report {
   int32_t count;        /* entries filled                                               */
@@ -296,9 +296,13 @@ typedef struct ps_tune_report {
 
 /* Create the matrix in every candidate layout -- the sliced layout with 1 and 2
    rows per lane and 16- and 32-bit columns (where its padding stays within
-   1.5x the nonzeros), CSR with each of the 5 launch shapes -- time `reps`
-   sparse products of each on the library's stream (after 2 untimed ones),
-   and keep the fastest: *out receives that handle, the others are destroyed.
+   1.5x the nonzeros), CSR with each of the 5 launch shapes in row order and in
+   gather order -- time `reps` iterations of p-BiCGSafe on each (b = 1, x0 = 0,
+   tol = 0, default options, so the automatic schedule of that layout; run
+   once to capture the graphs, then timed with the host clock around the
+   call), and keep the fastest: *out receives that handle, the others are
+   destroyed.  Every layout computes the same iterates, so a system that
+   stops early (a breakdown at b = 1) stops at the same iteration in each.
    nsys = 1 (sys_ptr ignored) for one system, else the batch arguments of
    ps_create_batch.  report: NULL or HOST, filled with every timed layout.
    Costs one creation per candidate (host layout build and upload). */

@@ -1597,6 +1597,25 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
     std::memset(report, 0, sizeof(*report));
     report->best = -1;
   }
+  // b = 1 and x on the device, in the caller's row order
+  double *ones = nullptr, *x = nullptr;
+  auto release = [&]() {
+    (void)hipFree(ones);
+    (void)hipFree(x);
+  };
+  {
+    const std::vector<double> h((size_t)std::max<int64_t>(n, 1), 1.0);
+    if (hipMalloc(&ones, h.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&x, h.size() * sizeof(double)) != hipSuccess ||
+        hipMemcpy(ones, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      release();
+      return PS_EHIP;
+    }
+  }
+  ps_options o;
+  ps_default_options(&o);
+  std::vector<int32_t> it((size_t)nsys), st((size_t)nsys);
   ps_matrix *best = nullptr;
   double best_us = 0.0;
   for (const ps_layout &l : cand) {
@@ -1605,6 +1624,7 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
                             : ps_create_ex(&M, n, nnz, rowptr, col, val, &l);
     if (rc != PS_OK) {
       if (best) free_matrix(best);
+      release();
       return rc;
     }
     // a 16-bit request that does not fit gives the 32-bit layout: measured already
@@ -1612,36 +1632,26 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
       free_matrix(M);
       continue;
     }
-    // time the plain product on the library's stream
-    double ms = 0.0;
+    // time `reps` iterations of p-BiCGSafe with the automatic options (the
+    // schedule, and with it the products' epilogues and the passes, depends on
+    // the layout): once to capture the graphs, once timed
+    double us = 0.0;
     {
-      double *x = M->slot(PS_V_X), *y = M->slot(kSlotTmp);
-      hipStream_t st = M->own;
-      hipEvent_t e0 = nullptr, e1 = nullptr;  // timing events (the handle's have no timing)
-      int err = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess
-                    ? PS_OK
-                    : PS_EHIP;
-      if (err == PS_OK) err = zero_slots(M, st, {PS_V_X});
-      for (int k = 0; k < 2 && err == PS_OK; ++k)
-        err = spmv(M, st, PS_K_OTHER, x, EpiStore{y}, -1);
-      if (err == PS_OK) err = hipEventRecord(e0, st) == hipSuccess ? PS_OK : PS_EHIP;
-      for (int k = 0; k < reps && err == PS_OK; ++k)
-        err = spmv(M, st, PS_K_OTHER, x, EpiStore{y}, -1);
-      if (err == PS_OK) err = hipEventRecord(e1, st) == hipSuccess ? PS_OK : PS_EHIP;
-      float t = 0.0f;
-      if (err == PS_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                           hipEventElapsedTime(&t, e0, e1) != hipSuccess))
-        err = PS_EHIP;
-      if (e0) (void)hipEventDestroy(e0);
-      if (e1) (void)hipEventDestroy(e1);
+      int err = PS_OK;
+      for (int rep = 0; rep < 2 && err == PS_OK; ++rep) {
+        const auto t0 = std::chrono::steady_clock::now();
+        err = ps_solve_batch_dev(M, ones, nullptr, 0.0, reps, PS_PBICGSAFE, &o, x, it.data(),
+                                 nullptr, st.data());
+        const auto t1 = std::chrono::steady_clock::now();
+        us = std::chrono::duration<double, std::micro>(t1 - t0).count() / reps;
+      }
       if (err != PS_OK) {
         free_matrix(M);
         if (best) free_matrix(best);
+        release();
         return err;
       }
-      ms = (double)t;
     }
-    const double us = 1e3 * ms / reps;
     if (report && report->count < PS_TUNE_MAX) {
       ps_tune_entry &e = report->entry[report->count];
       e.layout = ps_layout{M->format, M->format == PS_FMT_SELL ? M->sell_rpl : -1,
@@ -1660,6 +1670,7 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
       free_matrix(M);
     }
   }
+  release();
   *out = best;
   return PS_OK;
 }

@@ -204,7 +204,7 @@ class Matrix:
 
     @classmethod
     def autotuned(cls, A, reps: int = 20):
-        """ps_autotune_layout: the fastest layout for A's sparse product.
+        """ps_autotune_layout: the layout with the fastest p-BiCGSafe iterations on A.
         Returns (Matrix, rows of the tuning report)."""
         rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
         col = np.ascontiguousarray(A.col, dtype=np.int32)
