@@ -102,6 +102,8 @@ class Oracle:
         L.orc_solve.restype = cint
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
         L.orc_spmv.restype = None
+        L.orc_dot.argtypes = [i64, P, P]
+        L.orc_dot.restype = f64
         if L.orc_nv() != len(VEC) or L.orc_ns() != len(SCAL):
             raise RuntimeError("oracle state layout mismatch")
         self.L = L
@@ -112,6 +114,13 @@ class Oracle:
         y = np.empty(A.n)
         self.L.orc_spmv(A.n, _p(rowptr), _p(col), _p(val), _p(x), _p(y))
         return y
+
+    def dot(self, u, v):
+        """The oracle's inner product (u, v): the exact sum of the products rounded once."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert u.shape == v.shape and u.ndim == 1
+        return float(self.L.orc_dot(u.size, _p(u), _p(v)))
 
     def solve(self, A, b=None, x0=None, tol=1e-8, maxit=10_000, variant="pbicgsafe", rr_m=100,
               rr_M=None, norm_ref=0, precision=0):

@@ -11,9 +11,8 @@
  * Conventions (kept deliberately simple so the code can be checked against
  * the paper by eye):
  *   - every vector statement is one plain loop over all n entries;
- *   - an inner product is a sequential sum in index order, carried with
- *     compensated summation (see dot() below) so that its value does not
- *     depend on the summation order;
+ *   - an inner product is the exact sum of the products rounded once (see
+ *     dot() below), so its value does not depend on any summation order;
  *   - a sparse product y = A x is, per row, a sequential sum of the rounded
  *     products over the row's entries in storage order, carried with the
  *     same compensated summation (see spmv() below);
@@ -120,28 +119,116 @@ static void spmv(const csr_t *A, const double *x, double *y, double *S) {
 }
 
 /*
- * (u, v) = sum_k u_k v_k in index order, with compensated summation (the
- * algorithm Dot2 of Ogita, Rump & Oishi, "Accurate sum and dot product",
- * SIAM J. Sci. Comput. 26(6), 2005): every product and every partial sum is
- * split into its rounded value and its exact rounding error, the errors are
- * summed alongside, and the total is rounded once at the end.  The result is
- * as accurate as a sum carried in twice the working precision, so it does not
- * depend on the order of summation (except when the exact value lies within
- * about n^2 u^2 sum|u_k v_k| of a rounding boundary).
+ * Exact summation of doubles in a long fixed-point accumulator, used for the
+ * inner products.  Every finite double is an integer multiple of 2^-1074, so
+ * a sum of doubles is an integer in units of 2^-1074.  The accumulator holds
+ * that integer in base 2^32: digit i carries weight 2^(32 i) units, and each
+ * digit is an int64_t, so a digit can take more than 2^30 additions of
+ * magnitude below 2^32 before carries must be propagated.  Adding is exact
+ * integer arithmetic; the only rounding is the final one, to the nearest
+ * double with ties to even.
+ */
+#define XDIG 72          /* 72 * 32 bits > 2098 bit positions of the doubles + carries */
+#define XNORM (1 << 29)  /* additions between carry propagations */
+typedef struct {
+  int64_t d[XDIG];
+  int64_t adds;
+} xsum_t;
+
+/* carry every digit into the next: digits 0..XDIG-2 end in [0, 2^32) */
+static void xsum_carry(xsum_t *X) {
+  for (int i = 0; i < XDIG - 1; ++i) {
+    const int64_t c = X->d[i] >> 32; /* floor division by 2^32 */
+    X->d[i] -= c * ((int64_t)1 << 32);
+    X->d[i + 1] += c;
+  }
+  X->adds = 0;
+}
+
+static void xsum_add(xsum_t *X, double x) {
+  if (x == 0.0) return;
+  uint64_t bits;
+  memcpy(&bits, &x, sizeof bits);
+  const int bexp = (int)((bits >> 52) & 0x7FF);
+  uint64_t m = bits & (((uint64_t)1 << 52) - 1);
+  int pos; /* x = +-m * 2^(pos - 1074) */
+  if (bexp == 0) {
+    pos = 0; /* subnormal: m * 2^-1074 */
+  } else {
+    m |= (uint64_t)1 << 52;
+    pos = bexp - 1;
+  }
+  const int i = pos / 32, sh = pos % 32;
+  const unsigned __int128 w = (unsigned __int128)m << sh; /* at most 85 bits */
+  const int64_t w0 = (int64_t)(uint64_t)(w & 0xFFFFFFFFu);
+  const int64_t w1 = (int64_t)(uint64_t)((w >> 32) & 0xFFFFFFFFu);
+  const int64_t w2 = (int64_t)(uint64_t)(w >> 64);
+  if (bits >> 63) {
+    X->d[i] -= w0; X->d[i + 1] -= w1; X->d[i + 2] -= w2;
+  } else {
+    X->d[i] += w0; X->d[i + 1] += w1; X->d[i + 2] += w2;
+  }
+  if (++X->adds == XNORM) xsum_carry(X);
+}
+
+/* the double nearest to the accumulated integer (ties to even); +-inf beyond
+   the double range */
+static double xsum_round(xsum_t *X) {
+  xsum_carry(X);
+  int neg = X->d[XDIG - 1] < 0;
+  if (neg) { /* work with the magnitude */
+    for (int i = 0; i < XDIG; ++i) X->d[i] = -X->d[i];
+    xsum_carry(X);
+  }
+  int t = XDIG - 1;
+  while (t >= 0 && X->d[t] == 0) --t;
+  if (t < 0) return 0.0;
+  /* the top three digits as one integer, and whether anything lies below them */
+  unsigned __int128 M = 0;
+  for (int i = t; i >= t - 2; --i) M = (M << 32) | (uint64_t)(i >= 0 ? X->d[i] : 0);
+  int sticky = 0;
+  for (int i = t - 3; i >= 0; --i) sticky |= X->d[i] != 0;
+  int scale = 32 * (t - 2) - 1074; /* the value is (M + below) * 2^scale */
+  int len = 0;
+  for (unsigned __int128 v = M; v != 0; v >>= 1) ++len;
+  if (len > 53) {
+    const int drop = len - 53;
+    const unsigned __int128 rem = M & ((((unsigned __int128)1) << drop) - 1);
+    const unsigned __int128 half = ((unsigned __int128)1) << (drop - 1);
+    M >>= drop;
+    scale += drop;
+    if (rem > half || (rem == half && (sticky || (M & 1)))) {
+      M += 1;
+      if (M >> 53) { M >>= 1; scale += 1; }
+    }
+  } /* else: the integer has at most 53 bits and nothing below them -- exact */
+  const double r = ldexp((double)(uint64_t)M, scale);
+  return neg ? -r : r;
+}
+
+/*
+ * (u, v): the inner product rounded once from its exact value (to nearest,
+ * ties to even).  Each product u_k v_k is exactly p + ep (p rounded, ep its
+ * error from one FMA), and all of these are summed exactly.  The value is
+ * thus the plain definition of the inner product in floating point, and it
+ * does not depend on any order of summation.  A non-finite product (or a sum
+ * beyond the double range) makes the result NaN.
  */
 static double dot(int64_t n, const double *u, const double *v, double *S) {
-  double s = 0.0, c = 0.0;
+  xsum_t X;
+  memset(&X, 0, sizeof X);
+  int finite = 1;
   for (int64_t k = 0; k < n; ++k) {
     const double p = u[k] * v[k];
-    const double ep = fma(u[k], v[k], -p);      /* u_k v_k = p + ep exactly */
-    const double t = s + p;
-    const double z = t - s;
-    const double es = (s - (t - z)) + (p - z);  /* s + p = t + es exactly */
-    s = t;
-    c = c + (ep + es);
+    if (!isfinite(p)) finite = 0;
+    if (!finite) continue;
+    xsum_add(&X, p);
+    xsum_add(&X, fma(u[k], v[k], -p)); /* u_k v_k = p + ep exactly */
   }
   S[S_NDOT] += 1.0;
-  return s + c;
+  if (!finite) return NAN;
+  const double r = xsum_round(&X);
+  return isfinite(r) ? r : NAN;
 }
 
 static int bad(double d) { return d == 0.0 || !isfinite(d); }
@@ -586,6 +673,12 @@ void orc_spmv(int64_t n, const int64_t *rowptr, const int32_t *col, const double
   csr_t A = {n, rowptr, col, val};
   double S[NS];
   spmv(&A, x, y, S);
+}
+
+/* (u, v), exposed for checks of the inner product alone */
+double orc_dot(int64_t n, const double *u, const double *v) {
+  double S[NS];
+  return dot(n, u, v, S);
 }
 
 int orc_nv(void) { return NV; }

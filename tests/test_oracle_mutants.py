@@ -45,7 +45,10 @@ MUTANTS = {
     "no_initial_s": ("spmv(&A, r, v[VS], S);                       /* R2", "(void)0;                       /* R2"),
     "spmv_transposed": (SPMV_BODY, SPMV_TRANSPOSED),
     "spmv_drops_compensation": ("    y[i] = s + c;", "    y[i] = s;"),
-    "dot_drops_compensation": ("    c = c + (ep + es);", "    c = c + 0.0 * (ep + es);"),
+    "dot_drops_product_error": ("    xsum_add(&X, fma(u[k], v[k], -p));", "    (void)0;"),
+    "dot_drops_carries": ("    X->d[i + 1] += c;", "    X->d[i + 1] += 0 * c;"),
+    "dot_ties_away": ("(rem == half && (sticky || (M & 1)))", "(rem == half)"),
+    "dot_ignores_sticky": ("(rem == half && (sticky || (M & 1)))", "(rem == half && (M & 1))"),
     "rr_l_from_y": ("spmv(A, t, l, S);", "spmv(A, y, l, S);"),
     "rr_residual_sign": ("r[k] = b[k] - tmp[k]", "r[k] = b[k] + tmp[k]"),
     "pbicgstab_w_sign": ("om * (t[k] - al * vv[k])", "om * (t[k] + al * vv[k])"),

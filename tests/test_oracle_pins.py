@@ -31,6 +31,11 @@ mathematics, not against the oracle itself.
       m = 10) precision 2 reaches the FP64 system's residual ||b - A x|| <=
       tol ||b||, while precision 1 reaches it only for the rounded matrix and
       stays at the rounding level (~1e-8..1e-6) on the FP64 one.
+  P16 an inner product is the exact sum of its products rounded once to the
+      nearest double (ties to even), against exact rational arithmetic: random
+      vectors over wide exponent ranges, cancellation down to 1e-30 of the
+      terms, exact and near half-way cases, any order of the terms, and NaN for
+      a non-finite product.
 """
 import json
 import os
@@ -371,8 +376,56 @@ def check_p15(orc):
     return None
 
 
+def check_p16(orc):
+    import fractions
+    F = fractions.Fraction
+
+    def exact(u, v):
+        return float(sum(F(a) * F(b) for a, b in zip(u, v)))  # int / int: correctly rounded
+
+    rng = np.random.default_rng(16)
+    cases = []
+    for n in (1, 2, 7, 64, 1000):
+        u = rng.standard_normal(n) * 2.0 ** rng.integers(-60, 60, n)
+        v = rng.standard_normal(n) * 2.0 ** rng.integers(-60, 60, n)
+        cases.append((f"random n={n}", u, v))
+    # products that cancel: pairs (x, -x) of large terms plus small ones, shuffled
+    big = rng.standard_normal(200) * 1e20
+    small = rng.standard_normal(20)
+    u = np.concatenate([big, big, small])
+    v = np.concatenate([np.ones(200), -np.ones(200), rng.standard_normal(20) * 1e-10])
+    p = rng.permutation(u.size)
+    cases.append(("cancellation to 1e-30", u[p], v[p]))
+    # near-orthogonal vectors: w = z - ((z, q)/(q, q)) q leaves (q, w) ~ 1e-16 (q, q)
+    q = rng.standard_normal(5000)
+    z = rng.standard_normal(5000)
+    w = z - (q @ z) / (q @ q) * q
+    cases.append(("near-orthogonal", q, w))
+    # half-way: 1 + 2^-53 is a tie (rounds to even 1); a tiny extra term breaks it upward,
+    # a tiny negative one downward; 1 + 3 * 2^-53 ties to 1 + 2^-51 (even)
+    h = 2.0 ** -53
+    for name, t in (("tie to even", [1.0, h]), ("above the tie", [1.0, h, 2.0 ** -200]),
+                    ("below the tie", [1.0, h, -2.0 ** -200]), ("tie up to even", [1.0, h, 2 * h]),
+                    ("exact zero", [1e300, -1e300, 1.0, -1.0]), ("empty", [])):
+        cases.append((name, np.array(t, dtype=np.float64), np.ones(len(t))))
+    for name, u, v in cases:
+        want = exact(u, v)
+        got = orc.dot(u, v)
+        if got != want:
+            return f"P16 {name}: {got!r} != {want!r}"
+        if u.size > 1:
+            p = rng.permutation(u.size)
+            if orc.dot(u[p], v[p]) != want:
+                return f"P16 {name}: the value depends on the order of the terms"
+    if not np.isnan(orc.dot(np.array([1.0, np.inf]), np.array([1.0, 1.0]))):
+        return "P16 a non-finite product must give NaN"
+    if not np.isnan(orc.dot(np.array([1e200, 1.0]), np.array([1e200, np.nan]))):
+        return "P16 an overflowing product must give NaN"
+    return None
+
+
 CHECKS = [check_p1, check_p2, check_p3, check_p4, check_p5, check_p6, check_p7, check_p8, check_p11,
-          check_p12, check_p13, check_p14, check_p15]
+          check_p12, check_p13, check_p14, check_p15, check_p16]
 
 
 # --------------------------------------------------------------------------- tests
