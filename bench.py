@@ -336,7 +336,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--mixed-rr-m", default="100",
                     help="replacement periods of the mixed-precision leg (comma-separated)")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--overlap", type=int, default=-1, help="1 on, 0 off, -1 automatic")
     ap.add_argument("--schedule", type=int, default=-1,
                     help="p-BiCGSafe: 0 separate inner-product pass, 1 fused partial sums, "

@@ -86,21 +86,11 @@ __device__ __forceinline__ bool stop_test(double rho, const double *sc, int *ctl
 }
 
 // ------------------------------------------------------- compensated sums
-// pair accumulator: hi + lo carries a sum to about twice double precision
+// pair accumulator for the sparse products' row sums: hi + lo carries a sum
+// to about twice double precision
 struct DD {
   double hi, lo;
 };
-
-// (hi, lo) += x*y
-__device__ __forceinline__ void dd_fma(DD &a, double x, double y) {
-  const double p = x * y;
-  const double ep = __builtin_fma(x, y, -p);  // x*y = p + ep exactly
-  const double t = a.hi + p;
-  const double z = t - a.hi;
-  const double es = (a.hi - (t - z)) + (p - z);  // a.hi + p = t + es exactly
-  a.hi = t;
-  a.lo = a.lo + (ep + es);
-}
 
 // a += b for two pairs
 __device__ __forceinline__ void dd_add(DD &a, double bhi, double blo) {
@@ -118,6 +108,76 @@ __device__ __forceinline__ void sum_acc(DD &a, double v) {
   const double e = (a.hi - (t - z)) + (v - z);
   a.hi = t;
   a.lo = a.lo + e;
+}
+
+// ------------------------------------------------- inner-product accumulators
+// Triple accumulator for inner products: a + b + c carries a sum to about
+// three times double precision.  Each product is split exactly into its
+// rounded value and error (one FMA); a collects the rounded sum, b the exact
+// errors of a's additions plus the products' errors (themselves summed with
+// exact error terms), and c the errors of b's additions.  Only c rounds, at
+// about u^3 of the terms' magnitudes, so the final rounding of a + b + c gives
+// the inner product rounded once from its exact value except when that value
+// lies within that distance of a rounding boundary -- whatever the order in
+// which the grid adds the terms.
+struct TD {
+  double a, b, c;
+};
+constexpr int kPart = 3;  // doubles per stored partial sum (a, b, c)
+
+// s + e = x + y exactly (Knuth's two-sum)
+__device__ __forceinline__ void two_sum(double x, double y, double &s, double &e) {
+  s = x + y;
+  const double z = s - x;
+  e = (x - (s - z)) + (y - z);
+}
+
+// T += x*y
+__device__ __forceinline__ void td_fma(TD &T, double x, double y) {
+  const double p = x * y;
+  const double ep = __builtin_fma(x, y, -p);  // x*y = p + ep exactly
+  double e1, e2, e3;
+  two_sum(T.a, p, T.a, e1);
+  two_sum(T.b, e1, T.b, e2);
+  two_sum(T.b, ep, T.b, e3);
+  T.c = T.c + (e2 + e3);
+}
+
+// T += U
+__device__ __forceinline__ void td_add(TD &T, const TD &U) {
+  double e1, e2, e3;
+  two_sum(T.a, U.a, T.a, e1);
+  two_sum(T.b, U.b, T.b, e2);
+  two_sum(T.b, e1, T.b, e3);
+  T.c = T.c + (U.c + (e2 + e3));
+}
+
+// partial sum number k of a list of triples
+__device__ __forceinline__ TD td_load(const double *p, int64_t k) {
+  return TD{p[k * kPart], p[k * kPart + 1], p[k * kPart + 2]};
+}
+__device__ __forceinline__ void td_store(double *p, int64_t k, const TD &T) {
+  p[k * kPart] = T.a;
+  p[k * kPart + 1] = T.b;
+  p[k * kPart + 2] = T.c;
+}
+
+// The one rounding of a + b + c to the nearest double (ties to even): the
+// three are brought to t + w + werr exactly by error-free additions, t + w is
+// rounded, and a remainder of exactly half a unit that werr pushes past the
+// midpoint moves the result one unit away.
+__device__ __forceinline__ double td_round(const TD &T) {
+  double s1, e1, t, e0, w, werr, r, rl;
+  two_sum(T.b, T.c, s1, e1);
+  two_sum(T.a, s1, t, e0);
+  two_sum(e0, e1, w, werr);
+  two_sum(t, w, r, rl);
+  if (rl != 0.0 && werr != 0.0 && ((rl < 0.0) == (werr < 0.0))) {
+    const double y = 2.0 * rl;
+    const double x = r + y;
+    if (x - r == y) r = x;
+  }
+  return r;
 }
 
 // Lane permutations of a double within rows of 16 lanes (DPP), and a lane read.
@@ -191,6 +251,53 @@ __device__ __forceinline__ void group_sum_dd(DD &a) {
   if constexpr (LPR >= 4) dd_step<0x4E>(a);   // quad_perm [2,3,0,1]
   if constexpr (LPR >= 8) dd_step<0x141>(a);  // row_half_mirror
   if constexpr (LPR >= 16) dd_step<0x140>(a); // row_mirror
+}
+
+template <int CTRL>
+__device__ __forceinline__ void td_step(TD &T) {
+  const TD U{dpp_f64<CTRL>(T.a), dpp_f64<CTRL>(T.b), dpp_f64<CTRL>(T.c)};
+  td_add(T, U);
+}
+
+// Block-wide triple sums: on return thread k (< K) holds the block total of
+// a[k].  The lanes of each quad are added first (two DPP steps, every lane
+// taking part); the block's kBlock/4 quad totals of each product then go
+// through LDS, where 4K threads add 16 each in index order and a last quad
+// step adds those four.  A full wavefront butterfly would make every lane
+// run all six steps for every product -- six times the additions the sums
+// need, which for nine products costs more issue time than the kernels'
+// memory traffic.  lds: kTdSlots * K * kPart doubles.
+constexpr int kTdSlots = kBlock / 4;
+template <int K>
+__device__ __forceinline__ TD block_sum_td(TD (&a)[K], double *lds) {
+  static_assert(4 * K <= kWave, "the last quad step runs in the first wavefront");
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    td_step<0xB1>(a[k]);  // quad_perm [1,0,3,2]
+    td_step<0x4E>(a[k]);  // quad_perm [2,3,0,1]: every lane holds its quad's total
+  }
+  if ((threadIdx.x & 3) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) td_store(lds, k * kTdSlots + threadIdx.x / 4, a[k]);
+  }
+  __syncthreads();
+  TD r{0.0, 0.0, 0.0};
+  if (threadIdx.x < 4 * K) {
+    const int base = (threadIdx.x / 4) * kTdSlots + (threadIdx.x & 3) * (kTdSlots / 4);
+    r = td_load(lds, base);
+    for (int j = 1; j < kTdSlots / 4; ++j) td_add(r, td_load(lds, base + j));
+  }
+  if (threadIdx.x < kWave) {  // the first wavefront: quarters 4k .. 4k+3 -> lane 4k
+    td_step<0xB1>(r);
+    td_step<0x4E>(r);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 * K && (threadIdx.x & 3) == 0) td_store(lds, threadIdx.x / 4, r);
+  __syncthreads();
+  TD out{0.0, 0.0, 0.0};
+  if (threadIdx.x < K) out = td_load(lds, threadIdx.x);
+  __syncthreads();
+  return out;
 }
 
 }  // namespace ps

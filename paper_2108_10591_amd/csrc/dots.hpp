@@ -15,11 +15,16 @@
 // small launch on the reduction's own stream, hidden behind the concurrent
 // sparse product.
 //
-// Accumulators are unevaluated pairs (hi, lo): each product is split exactly
-// into its rounded value and rounding error (one FMA), each addition into its
-// rounded sum and exact error (Knuth's two-sum), and the errors are carried in
-// lo (compensated dot product, Ogita-Rump-Oishi).  hi + lo is rounded once at
-// the end, so the value does not depend on how the grid splits the sum.
+// Accumulators are unevaluated triples (a, b, c) (TD in device_common.hpp):
+// each product is split exactly into its rounded value and rounding error (one
+// FMA), each addition into its rounded sum and exact error (Knuth's two-sum),
+// and the errors are carried one level down, twice.  a + b + c is rounded once
+// at the end.  Only the third level rounds, near u^3 of the terms, so the
+// result is the inner product rounded once from its exact value whenever that
+// value is not within that distance of a rounding boundary: it does not depend
+// on how the grid splits the sum, even where the terms cancel to 1e-12 of
+// their magnitude (near-orthogonal r0* and r late in a long solve), where a
+// pair accumulator's u^2 error can already move the rounding.
 #pragma once
 
 #include "device_common.hpp"
@@ -29,7 +34,7 @@ namespace ps {
 struct DotArgs {
   const double *v[5];  // input vectors
   int64_t n;
-  double *partials;    // [ND][gridDim.x] (hi, lo) pairs
+  double *partials;    // [ND][gridDim.x] (a, b, c) triples
   int *ctl;
   double *sc;
   double *hist;
@@ -52,19 +57,19 @@ template <bool FIRST>
 struct ProdSafe9 {
   static constexpr unsigned MASK = FIRST ? 0b01101u : 0b11111u;  // s, (y), r, r0*, (t)
   static constexpr int ND = 9;
-  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
     const double s = in[0], r = in[2], rs = in[3];
-    dd_fma(a[0], s, s);
-    dd_fma(a[3], s, r);
-    dd_fma(a[5], rs, r);
-    dd_fma(a[6], rs, s);
-    dd_fma(a[8], r, r);
+    td_fma(a[0], s, s);
+    td_fma(a[3], s, r);
+    td_fma(a[5], rs, r);
+    td_fma(a[6], rs, s);
+    td_fma(a[8], r, r);
     if (!FIRST) {
       const double y = in[1], t = in[4];
-      dd_fma(a[1], y, y);
-      dd_fma(a[2], s, y);
-      dd_fma(a[4], y, r);
-      dd_fma(a[7], rs, t);
+      td_fma(a[1], y, y);
+      td_fma(a[2], s, y);
+      td_fma(a[4], y, r);
+      td_fma(a[7], rs, t);
     }
   }
 };
@@ -73,9 +78,9 @@ struct ProdSafe9 {
 struct ProdStab2 {
   static constexpr unsigned MASK = 0b11u;  // q, y
   static constexpr int ND = 2;
-  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
-    dd_fma(a[0], in[0], in[1]);
-    dd_fma(a[1], in[1], in[1]);
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
+    td_fma(a[0], in[0], in[1]);
+    td_fma(a[1], in[1], in[1]);
   }
 };
 
@@ -84,13 +89,13 @@ struct ProdStab2 {
 struct ProdStab5 {
   static constexpr unsigned MASK = 0b11111u;
   static constexpr int ND = 5;
-  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
     const double rs = in[0], r = in[1];
-    dd_fma(a[0], rs, r);
-    dd_fma(a[1], rs, in[2]);
-    dd_fma(a[2], rs, in[3]);
-    dd_fma(a[3], rs, in[4]);
-    dd_fma(a[4], r, r);
+    td_fma(a[0], rs, r);
+    td_fma(a[1], rs, in[2]);
+    td_fma(a[2], rs, in[3]);
+    td_fma(a[3], rs, in[4]);
+    td_fma(a[4], r, r);
   }
 };
 
@@ -98,10 +103,10 @@ struct ProdStab5 {
 struct ProdStab3 {
   static constexpr unsigned MASK = 0b111u;
   static constexpr int ND = 3;
-  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
-    dd_fma(a[0], in[0], in[1]);
-    dd_fma(a[1], in[0], in[2]);
-    dd_fma(a[2], in[1], in[1]);
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
+    td_fma(a[0], in[0], in[1]);
+    td_fma(a[1], in[0], in[2]);
+    td_fma(a[2], in[1], in[1]);
   }
 };
 
@@ -109,9 +114,9 @@ struct ProdStab3 {
 struct ProdFallback {
   static constexpr unsigned MASK = 0b11u;
   static constexpr int ND = 2;
-  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
-    dd_fma(a[0], in[0], in[0]);
-    dd_fma(a[1], in[1], in[1]);
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
+    td_fma(a[0], in[0], in[0]);
+    td_fma(a[1], in[1], in[1]);
   }
 };
 
@@ -119,8 +124,8 @@ struct ProdFallback {
 struct ProdNorm {
   static constexpr unsigned MASK = 0b1u;
   static constexpr int ND = 1;
-  __device__ __forceinline__ static void acc(const double (&in)[5], DD (&a)[ND]) {
-    dd_fma(a[0], in[0], in[0]);
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
+    td_fma(a[0], in[0], in[0]);
   }
 };
 
@@ -313,11 +318,11 @@ struct FinNormRef {
 template <class Prod>
 __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
   constexpr int ND = Prod::ND;
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   if (A.ctl[C_DONE]) return;
-  DD acc[ND];
+  TD acc[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) acc[j] = DD{0.0, 0.0};
+  for (int j = 0; j < ND; ++j) acc[j] = TD{0.0, 0.0, 0.0};
   // a pair of entries (16-byte loads) per thread per grid-stride step
   double a0[5], a1[5];
   const int64_t npair = A.n / 2;
@@ -331,31 +336,30 @@ __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
     load_in<Prod::MASK>(A, A.n - 1, a0);
     Prod::acc(a0, acc);
   }
-  const DD s = block_sum_dd<ND>(acc, lds);
+  const TD s = block_sum_td<ND>(acc, lds);
   const int G = gridDim.x;
   if (threadIdx.x < ND) {
-    A.partials[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
-    A.partials[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
+    td_store(A.partials, threadIdx.x * G + blockIdx.x, s);
   }
 }
 
-// One block: add the G partial pairs of each product in block order, round
+// One block: add the G partial triples of each product in block order, round
 // once, and run the phase's finish.
 template <int ND, class Fin>
 __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   __shared__ double fin[9];
   if (A.ctl[C_DONE]) return;
-  DD tot[ND];
+  TD tot[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) tot[j] = DD{0.0, 0.0};
+  for (int j = 0; j < ND; ++j) tot[j] = TD{0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < G; b += kBlock) {
 #pragma unroll
     for (int j = 0; j < ND; ++j)
-      dd_add(tot[j], A.partials[(j * G + b) * 2], A.partials[(j * G + b) * 2 + 1]);
+      td_add(tot[j], td_load(A.partials, j * G + b));
   }
-  const DD s = block_sum_dd<ND>(tot, lds);
-  if (threadIdx.x < ND) fin[threadIdx.x] = s.hi + s.lo;  // the one final rounding
+  const TD s = block_sum_td<ND>(tot, lds);
+  if (threadIdx.x < ND) fin[threadIdx.x] = td_round(s);  // the one final rounding
   __syncthreads();
   if (threadIdx.x == 0) {
     double d[ND];
@@ -367,8 +371,8 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
 }
 
 // The fused schedules' finish when the partial lists are short: add pass A's
-// (or the fused epilogue's) [5][ga] pairs of (b, e, f, h, rho) and the
-// epilogue's [4][gb] pairs of (a, c, d, g) directly, without k_fold_partials --
+// (or the fused epilogue's) [5][ga] triples of (b, e, f, h, rho) and the
+// epilogue's [4][gb] triples of (a, c, d, g) directly, without k_fold_partials --
 // one launch fewer per iteration on small systems.
 template <class Fin>
 __global__ __launch_bounds__(kBlock) void k_dots_finish_direct(DotArgs A,
@@ -376,24 +380,24 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_direct(DotArgs A,
                                                                int ga,
                                                                const double *__restrict__ pb,
                                                                int gb) {
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   __shared__ double fin[9];
   if (A.ctl[C_DONE]) return;
   constexpr int kA[5] = {1, 4, 5, 7, 8};
   constexpr int kB[4] = {0, 2, 3, 6};
-  DD tot[9];
+  TD tot[9];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) tot[j] = DD{0.0, 0.0};
+  for (int j = 0; j < 9; ++j) tot[j] = TD{0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < ga; b += kBlock) {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) dd_add(tot[kA[j]], pa[(j * ga + b) * 2], pa[(j * ga + b) * 2 + 1]);
+    for (int j = 0; j < 5; ++j) td_add(tot[kA[j]], td_load(pa, j * ga + b));
   }
   for (int b = threadIdx.x; b < gb; b += kBlock) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) dd_add(tot[kB[j]], pb[(j * gb + b) * 2], pb[(j * gb + b) * 2 + 1]);
+    for (int j = 0; j < 4; ++j) td_add(tot[kB[j]], td_load(pb, j * gb + b));
   }
-  const DD s = block_sum_dd<9>(tot, lds);
-  if (threadIdx.x < 9) fin[threadIdx.x] = s.hi + s.lo;  // the one final rounding
+  const TD s = block_sum_td<9>(tot, lds);
+  if (threadIdx.x < 9) fin[threadIdx.x] = td_round(s);  // the one final rounding
   __syncthreads();
   if (threadIdx.x == 0) {
     double d[9];
@@ -411,21 +415,20 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_direct(DotArgs A,
 template <class Prod>
 __global__ __launch_bounds__(kBlock) void k_dots_batch(DotArgs A, const int *__restrict__ chunk_sys) {
   constexpr int ND = Prod::ND;
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   const int sys = chunk_sys[2 * blockIdx.x];
   if (A.ctl[(size_t)sys * C_COUNT + C_DONE]) return;
-  DD acc[ND];
+  TD acc[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) acc[j] = DD{0.0, 0.0};
+  for (int j = 0; j < ND; ++j) acc[j] = TD{0.0, 0.0, 0.0};
   double a0[5], a1[5];
   load_in2<Prod::MASK>(A, 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x), a0, a1);
   Prod::acc(a0, acc);
   Prod::acc(a1, acc);
-  const DD s = block_sum_dd<ND>(acc, lds);
+  const TD s = block_sum_td<ND>(acc, lds);
   const int G = gridDim.x;
   if (threadIdx.x < ND) {
-    A.partials[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
-    A.partials[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
+    td_store(A.partials, threadIdx.x * G + blockIdx.x, s);
   }
 }
 
@@ -435,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_batch(DotArgs A, const int *__r
 template <int ND, class Fin>
 __global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const int *__restrict__ first_blk,
                                                               int G, int64_t hist_stride) {
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   __shared__ double fin[9];
   const int k = blockIdx.x;
   DotArgs Ak = A;
@@ -443,16 +446,16 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const i
   Ak.sc += (size_t)k * SC_COUNT;
   Ak.hist += k * hist_stride;
   if (Ak.ctl[C_DONE]) return;
-  DD tot[ND];
+  TD tot[ND];
 #pragma unroll
-  for (int j = 0; j < ND; ++j) tot[j] = DD{0.0, 0.0};
+  for (int j = 0; j < ND; ++j) tot[j] = TD{0.0, 0.0, 0.0};
   for (int b = first_blk[k] + threadIdx.x; b < first_blk[k + 1]; b += kBlock) {
 #pragma unroll
     for (int j = 0; j < ND; ++j)
-      dd_add(tot[j], A.partials[(j * G + b) * 2], A.partials[(j * G + b) * 2 + 1]);
+      td_add(tot[j], td_load(A.partials, j * G + b));
   }
-  const DD s = block_sum_dd<ND>(tot, lds);
-  if (threadIdx.x < ND) fin[threadIdx.x] = s.hi + s.lo;
+  const TD s = block_sum_td<ND>(tot, lds);
+  if (threadIdx.x < ND) fin[threadIdx.x] = td_round(s);
   __syncthreads();
   if (threadIdx.x == 0) {
     double d[ND];
@@ -464,14 +467,14 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const i
 }
 
 // Batched fused schedules: per system k (one workgroup each), add its range of
-// the [5][ga] pairs of (b, e, f, h, rho) -- workgroups a_first[k] ..
-// a_first[k+1]-1 -- and of the [4][gb] pairs of (a, c, d, g) -- b_first[k] ..
+// the [5][ga] triples of (b, e, f, h, rho) -- workgroups a_first[k] ..
+// a_first[k+1]-1 -- and of the [4][gb] triples of (a, c, d, g) -- b_first[k] ..
 // b_first[k+1]-1 -- and run the system's finish.
 template <class Fin>
 __global__ __launch_bounds__(kBlock) void k_dots_finish_batch_direct(
     DotArgs A, const double *__restrict__ pa, int ga, const int *__restrict__ a_first,
     const double *__restrict__ pb, int gb, const int *__restrict__ b_first, int64_t hist_stride) {
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   __shared__ double fin[9];
   const int k = blockIdx.x;
   DotArgs Ak = A;
@@ -481,19 +484,19 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch_direct(
   if (Ak.ctl[C_DONE]) return;
   constexpr int kA[5] = {1, 4, 5, 7, 8};
   constexpr int kB[4] = {0, 2, 3, 6};
-  DD tot[9];
+  TD tot[9];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) tot[j] = DD{0.0, 0.0};
+  for (int j = 0; j < 9; ++j) tot[j] = TD{0.0, 0.0, 0.0};
   for (int b = a_first[k] + threadIdx.x; b < a_first[k + 1]; b += kBlock) {
 #pragma unroll
-    for (int j = 0; j < 5; ++j) dd_add(tot[kA[j]], pa[(j * ga + b) * 2], pa[(j * ga + b) * 2 + 1]);
+    for (int j = 0; j < 5; ++j) td_add(tot[kA[j]], td_load(pa, j * ga + b));
   }
   for (int b = b_first[k] + threadIdx.x; b < b_first[k + 1]; b += kBlock) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) dd_add(tot[kB[j]], pb[(j * gb + b) * 2], pb[(j * gb + b) * 2 + 1]);
+    for (int j = 0; j < 4; ++j) td_add(tot[kB[j]], td_load(pb, j * gb + b));
   }
-  const DD s = block_sum_dd<9>(tot, lds);
-  if (threadIdx.x < 9) fin[threadIdx.x] = s.hi + s.lo;
+  const TD s = block_sum_td<9>(tot, lds);
+  if (threadIdx.x < 9) fin[threadIdx.x] = td_round(s);
   __syncthreads();
   if (threadIdx.x == 0) {
     double d[9];
@@ -504,38 +507,41 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch_direct(
   }
 }
 
+constexpr int kFoldPerThread = 1;
+
 // Fused-dot schedule: the nine inner products of iteration i arrive as block
-// partial sums from the two passes of iteration i-1 -- pass A: [5][ga] pairs of
-// (b, e, f, h, rho), the epilogue of A w_{i-1}: [4][gb] pairs of (a, c, d, g).
-// This kernel folds them into [9][gridDim.x] pairs in the layout k_dots
-// writes (thread t of block k takes entry k*kBlock + t of every list), so the
-// same one-block finish follows.
+// partial sums from the two passes of iteration i-1 -- pass A: [5][ga] triples of
+// (b, e, f, h, rho), the epilogue of A w_{i-1}: [4][gb] triples of (a, c, d, g).
+// This kernel folds them into [9][gridDim.x] triples in the layout k_dots
+// writes (block k takes entries k*kFoldPerThread*kBlock .. of every list,
+// kFoldPerThread per thread), so the same one-block finish follows.
 __global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restrict__ pa, int ga,
                                                           const double *__restrict__ pb, int gb,
                                                           double *__restrict__ out,
                                                           const int *__restrict__ ctl) {
-  __shared__ double lds[kWavesPerBlock * 9 * 2];
+  __shared__ double lds[kTdSlots * 9 * kPart];
   if (ctl[C_DONE]) return;
   constexpr int kA[5] = {1, 4, 5, 7, 8};
   constexpr int kB[4] = {0, 2, 3, 6};
-  DD t[9];
+  TD t[9];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) t[j] = DD{0.0, 0.0};
-  const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx < ga) {
+  for (int j = 0; j < 9; ++j) t[j] = TD{0.0, 0.0, 0.0};
+  // kFoldPerThread entries of every list per thread, kBlock apart
 #pragma unroll
-    for (int j = 0; j < 5; ++j) t[kA[j]] = DD{pa[(j * ga + idx) * 2], pa[(j * ga + idx) * 2 + 1]};
+  for (int q = 0; q < kFoldPerThread; ++q) {
+    const int idx = (blockIdx.x * kFoldPerThread + q) * kBlock + threadIdx.x;
+    if (idx < ga) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) td_add(t[kA[j]], td_load(pa, j * ga + idx));
+    }
+    if (idx < gb) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) td_add(t[kB[j]], td_load(pb, j * gb + idx));
+    }
   }
-  if (idx < gb) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) t[kB[j]] = DD{pb[(j * gb + idx) * 2], pb[(j * gb + idx) * 2 + 1]};
-  }
-  const DD s = block_sum_dd<9>(t, lds);
+  const TD s = block_sum_td<9>(t, lds);
   const int G = gridDim.x;
-  if (threadIdx.x < 9) {
-    out[(threadIdx.x * G + blockIdx.x) * 2] = s.hi;
-    out[(threadIdx.x * G + blockIdx.x) * 2 + 1] = s.lo;
-  }
+  if (threadIdx.x < 9) td_store(out, threadIdx.x * G + blockIdx.x, s);
 }
 
 }  // namespace ps

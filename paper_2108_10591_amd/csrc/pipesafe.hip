@@ -125,7 +125,7 @@ struct ps_matrix {
   double *partials = nullptr;
   int dot_grid = 0;
   // fused-dot schedule: pass A partials [5][ga], epilogue partials [4][nblk],
-  // folded partials [9][gfold], all (hi, lo) pairs, in one allocation
+  // folded partials [9][gfold], all (a, b, c) triples, in one allocation
   double *fpart = nullptr;
   int ga = 0, gfold = 0;
   // batched solves (nsys > 1): the caller's rows map to padded rows (each
@@ -138,7 +138,7 @@ struct ps_matrix {
   int *first_pblk = nullptr;     // device: first sparse-product workgroup of each system
   int *row_map = nullptr;        // device: padded row of each caller row
   double *stage = nullptr;       // device: n_orig doubles for host input/output
-  double *bpart = nullptr;       // device: [9][n/512] partial pairs
+  double *bpart = nullptr;       // device: [9][n/512] partial triples
   int64_t hist_stride = 0;       // history entries per system
   double *hist = nullptr;
   int64_t hist_cap = 0;
@@ -428,8 +428,8 @@ int fused_finish(ps_matrix *M, const Plan &P, hipStream_t s) {
   // schedule 1: pass A's [5][ga] then the epilogue's [4][nblk]; schedule 2: the
   // epilogue's [5][nblk] then [4][nblk]; the folded [9][gfold] after the largest
   const int ga = P.fused2 ? M->nblk : M->ga;
-  double *pa = M->fpart, *pb = pa + 2 * 5 * (size_t)ga;
-  double *pf = M->fpart + 2 * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk);
+  double *pa = M->fpart, *pb = pa + kPart * 5 * (size_t)ga;
+  double *pf = M->fpart + kPart * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk);
   DotArgs D{};
   D.n = M->n;
   D.ctl = M->ctl;
@@ -502,7 +502,7 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
                     C_DONE, P.kry32));
       return PS_OK;
     }
-    double *pa_part = M->fpart, *pb_part = pa_part + 2 * 5 * (size_t)M->ga;
+    double *pa_part = M->fpart, *pb_part = pa_part + kPart * 5 * (size_t)M->ga;
     PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                  M->slot(PS_V_RS), pa_part};
     pa.chunk_sys = M->chunk_sys;
@@ -1373,12 +1373,12 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     PS_CREATE_HIP(hipMalloc(&M->first_pblk, pfirst.size() * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->row_map, bl->row_map.size() * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->stage, (size_t)bl->n_orig * sizeof(double)));
-    PS_CREATE_HIP(hipMalloc(&M->bpart, 2 * 9 * (size_t)(n / 512) * sizeof(double)));
+    PS_CREATE_HIP(hipMalloc(&M->bpart, kPart * 9 * (size_t)(n / 512) * sizeof(double)));
   }
-  PS_CREATE_HIP(hipMalloc(&M->partials, 2 * 9 * (size_t)M->dot_grid * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->partials, kPart * 9 * (size_t)M->dot_grid * sizeof(double)));
   M->ga = (int)pair_grid(n).x;
-  M->gfold = (std::max(M->ga, M->nblk) + kBlock - 1) / kBlock;
-  PS_CREATE_HIP(hipMalloc(&M->fpart, 2 * (5 * (size_t)std::max(M->ga, M->nblk) +
+  M->gfold = (std::max(M->ga, M->nblk) + kFoldPerThread * kBlock - 1) / (kFoldPerThread * kBlock);
+  PS_CREATE_HIP(hipMalloc(&M->fpart, kPart * (5 * (size_t)std::max(M->ga, M->nblk) +
                                           4 * (size_t)M->nblk + 9 * (size_t)M->gfold) *
                                          sizeof(double)));
   PS_CREATE_HIP(hipHostMalloc(&M->pinned, 2 * C_COUNT * sizeof(int), hipHostMallocDefault));

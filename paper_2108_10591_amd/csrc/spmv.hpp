@@ -68,7 +68,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // row blocks from the last to the first (see sweep_block).
 //
 // An epilogue with kDots > 0 also accumulates per-row terms of inner products
-// (compensated pairs, see dots.hpp) and writes the block's partial sums for row
+// (compensated triples, see dots.hpp) and writes the block's partial sums for row
 // block b; all lanes of the block take part in that reduction.
 template <int IPT, int LPR, class VT, class IT, class Epi>
 __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double *__restrict__ x,
@@ -80,9 +80,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
   if (st.stopped(sys)) return;
   const Epi epi = epi_all.at(sys);
   constexpr int ND = Epi::kDots;
-  DD dacc[ND > 0 ? ND : 1];
+  TD dacc[ND > 0 ? ND : 1];
 #pragma unroll
-  for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = DD{0.0, 0.0};
+  for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = TD{0.0, 0.0, 0.0};
   auto put = [&](int row, double ax, const typename Epi::In &in) {
     if constexpr (ND > 0) epi.store(row, ax, in, dacc);
     else epi.store(row, ax, in);
@@ -211,11 +211,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
     }
   }
   if constexpr (ND > 0) {
-    __shared__ double red[kWavesPerBlock * ND * 2];
-    const DD t = block_sum_dd<ND>(dacc, red);
+    __shared__ double red[kTdSlots * ND * kPart];
+    const TD t = block_sum_td<ND>(dacc, red);
     if (threadIdx.x < ND) {
-      epi.part[(threadIdx.x * A.nblk + b) * 2] = t.hi;
-      epi.part[(threadIdx.x * A.nblk + b) * 2 + 1] = t.lo;
+      td_store(epi.part, threadIdx.x * A.nblk + b, t);
     }
   }
 }
@@ -283,9 +282,9 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double
                                                  Epi epi_all, Stop st, int rev) {
   constexpr int ND = Epi::kDots;
   constexpr int SH = kWave * RPL;
-  DD dacc[ND > 0 ? ND : 1];
+  TD dacc[ND > 0 ? ND : 1];
 #pragma unroll
-  for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = DD{0.0, 0.0};
+  for (int j = 0; j < (ND > 0 ? ND : 1); ++j) dacc[j] = TD{0.0, 0.0, 0.0};
   const int b = sweep_block(xcd_block(blockIdx.x, S.nblk), S.nblk, rev);
   const int sys = system_of(st.chunk_sys, (int64_t)b * kBlock * RPL);
   if (st.stopped(sys)) return;
@@ -360,11 +359,10 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double
     }
   }
   if constexpr (ND > 0) {
-    __shared__ double red[kWavesPerBlock * ND * 2];
-    const DD t = block_sum_dd<ND>(dacc, red);
+    __shared__ double red[kTdSlots * ND * kPart];
+    const TD t = block_sum_td<ND>(dacc, red);
     if (threadIdx.x < ND) {
-      epi.part[(threadIdx.x * S.nblk + b) * 2] = t.hi;
-      epi.part[(threadIdx.x * S.nblk + b) * 2 + 1] = t.lo;
+      td_store(epi.part, threadIdx.x * S.nblk + b, t);
     }
   }
 }
@@ -469,7 +467,7 @@ struct EpiSsBiCGSafe2B {
 // EpiPBiCGSafeB, plus the partial sums of the four inner products of the next
 // iteration that involve s_{i+1}: a = (s,s), c = (s,y), d = (s,r), g = (r0*,s),
 // with y_{i+1} and r_{i+1} from the pass A that precedes this product.
-// part: [4][nblk] (hi, lo) pairs.  NT: l and g (next read by the next pass A)
+// part: [4][nblk] (a, b, c) triples.  NT: l and g (next read by the next pass A)
 // and As (dead after this product) stream past the cache.
 template <bool NT>
 struct EpiPBiCGSafeBDots {
@@ -495,7 +493,7 @@ struct EpiPBiCGSafeBDots {
     else
       return In{l[k], As[k], g[k], s[k], y[k], r[k], rs[k]};
   }
-  __device__ __forceinline__ void store(int k, double aw, const In &in, DD (&acc)[4]) const {
+  __device__ __forceinline__ void store(int k, double aw, const In &in, TD (&acc)[4]) const {
     const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
     const double q = in.As + be * in.l;
     const double ln = q - aw;
@@ -509,10 +507,10 @@ struct EpiPBiCGSafeBDots {
     }
     const double sn = in.s - al * q - gn;
     s[k] = sn;
-    dd_fma(acc[0], sn, sn);
-    dd_fma(acc[1], sn, in.y);
-    dd_fma(acc[2], sn, in.r);
-    dd_fma(acc[3], in.rs, sn);
+    td_fma(acc[0], sn, sn);
+    td_fma(acc[1], sn, in.y);
+    td_fma(acc[2], sn, in.r);
+    td_fma(acc[3], in.rs, sn);
   }
 };
 
@@ -521,8 +519,8 @@ struct EpiPBiCGSafeBDots {
 // in the algorithm's order -- p_i, o_i, u_i, q_i, t_i, z_i, y_{i+1}, x_{i+1},
 // r_{i+1} (Algorithm 4; Eqs. (q), (w)), then l_i, g_{i+1}, s_{i+1} (Eqs. (l),
 // (g), (sip1)) -- and the partial sums of all nine inner products of iteration
-// i+1, written as [5][nblk] pairs of (b, e, f, h, rho) followed by [4][nblk]
-// pairs of (a, c, d, g): the layout k_fold_partials takes.  NT: p, u, t, z, x,
+// i+1, written as [5][nblk] triples of (b, e, f, h, rho) followed by [4][nblk]
+// triples of (a, c, d, g): the layout k_fold_partials takes.  NT: p, u, t, z, x,
 // y, r (next read by the next such epilogue) and As (dead here) stream past the
 // cache; l, g, w and s, read by the next w pass and product, do not.
 template <bool NT>
@@ -552,7 +550,7 @@ struct EpiPBiCGSafeAll {
     return In{ld(r, k), ld(p, k), ld(u, k), s[k], ld(t, k), ld(y, k), ld(As, k),
               l[k],     g[k],     ld(z, k), ld(x, k), rs[k], w[k]};
   }
-  __device__ __forceinline__ void store(int k, double aw, const In &in, DD (&acc)[9]) const {
+  __device__ __forceinline__ void store(int k, double aw, const In &in, TD (&acc)[9]) const {
     const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
     const double pn = in.r + be * (in.p - in.u);
     const double o = in.s + be * in.t;
@@ -576,15 +574,15 @@ struct EpiPBiCGSafeAll {
     l[k] = ln;
     g[k] = gn;
     s[k] = sn;
-    dd_fma(acc[0], yn, yn);
-    dd_fma(acc[1], yn, rn);
-    dd_fma(acc[2], in.rs, rn);
-    dd_fma(acc[3], in.rs, tn);
-    dd_fma(acc[4], rn, rn);
-    dd_fma(acc[5], sn, sn);
-    dd_fma(acc[6], sn, yn);
-    dd_fma(acc[7], sn, rn);
-    dd_fma(acc[8], in.rs, sn);
+    td_fma(acc[0], yn, yn);
+    td_fma(acc[1], yn, rn);
+    td_fma(acc[2], in.rs, rn);
+    td_fma(acc[3], in.rs, tn);
+    td_fma(acc[4], rn, rn);
+    td_fma(acc[5], sn, sn);
+    td_fma(acc[6], sn, yn);
+    td_fma(acc[7], sn, rn);
+    td_fma(acc[8], in.rs, sn);
   }
 };
 

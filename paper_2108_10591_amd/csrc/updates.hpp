@@ -120,7 +120,7 @@ struct PassAArgs {
   int64_t n;
   int rev;  // sweep direction
   // fused inner products (k_passA_pbicgsafe<true, NT> only): r0* and the
-  // [5][gridDim.x] (hi, lo) partial sums of the next iteration's
+  // [5][gridDim.x] (a, b, c) partial sums of the next iteration's
   // b = (y,y), e = (y,r), f = (r0*,r), h = (r0*,t), rho = (r,r)
   const double *rs;
   double *part;
@@ -128,7 +128,7 @@ struct PassAArgs {
 };
 
 template <int W, bool DOTS, bool NT>
-__device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, DD (&acc)[5]) {
+__device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, TD (&acc)[5]) {
   const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA],
                et = P.sc[PS_S_ETA];
   double r[W], p[W], u[W], s[W], t[W], y[W], As[W], l[W], g[W], w[W], z[W], x[W], q[W];
@@ -162,11 +162,11 @@ __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, DD (&a
     ldv<W>(P.rs, k, rs);
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-      dd_fma(acc[0], y[j], y[j]);
-      dd_fma(acc[1], y[j], r[j]);
-      dd_fma(acc[2], rs[j], r[j]);
-      dd_fma(acc[3], rs[j], t[j]);
-      dd_fma(acc[4], r[j], r[j]);
+      td_fma(acc[0], y[j], y[j]);
+      td_fma(acc[1], y[j], r[j]);
+      td_fma(acc[2], rs[j], r[j]);
+      td_fma(acc[3], rs[j], t[j]);
+      td_fma(acc[4], r[j], r[j]);
     }
   }
   stv_s<W, NT>(P.p, k, p);
@@ -185,20 +185,19 @@ template <bool DOTS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   const PassAArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
-  DD acc[5];
+  TD acc[5];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) acc[j] = DD{0.0, 0.0};
+  for (int j = 0; j < 5; ++j) acc[j] = TD{0.0, 0.0, 0.0};
   const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
   if (k + 1 < P.n) passA_body<2, DOTS, NT>(P, k, acc);
   else if (k < P.n) passA_body<1, DOTS, NT>(P, k, acc);
   if constexpr (DOTS) {
-    __shared__ double red[kWavesPerBlock * 5 * 2];
-    const DD t = block_sum_dd<5>(acc, red);
+    __shared__ double red[kTdSlots * 5 * kPart];
+    const TD t = block_sum_td<5>(acc, red);
     const int G = gridDim.x;
     if (threadIdx.x < 5) {
-      P.part[(threadIdx.x * G + b) * 2] = t.hi;
-      P.part[(threadIdx.x * G + b) * 2 + 1] = t.lo;
+      td_store(P.part, threadIdx.x * G + b, t);
     }
   }
 }
