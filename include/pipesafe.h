@@ -276,8 +276,8 @@ int ps_create_batch_ex(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
 
 /*
  * Autotuner.  Every layout, launch shape and schedule computes the same
- * iterates (compensated sums rounded once), so the tuner picks by measured
- * time only.
+ * iterates (inner products rounded once from their exact value), so the
+ * tuner picks by measured time only.
  */
 #define PS_TUNE_MAX 48
 typedef struct ps_tune_entry {

@@ -99,10 +99,10 @@ def test_batch_both_layouts_and_device_buffers(fmt):
     import torch
     B, C, b = mixed_batch()
     x0 = np.linspace(0.0, 1.0, C.n)
-    # the skew-symmetric system keeps x0 = 0: its (r0*, A r0) is then exactly 0.  With a
-    # non-integer x0 that inner product is pure cancellation (condition ~1e17), beyond what
-    # a compensated sum rounds the same way in every order, and alpha = f / g amplifies
-    # the last bit to 1e19.
+    # the skew-symmetric system keeps x0 = 0: its (r0*, A r0) is then exactly 0 and the
+    # solve stops with a breakdown at i = 0, as in the other batch tests.  With a
+    # non-integer x0 that inner product is pure cancellation (condition ~1e17) and
+    # alpha = f / g would be ~1e19: a test of overflow, not of the method.
     p = B.sys_ptr()
     x0[p[4]:p[5]] = 0.0
     refs = [O.solve(A, b=b[p0:p1], x0=x0[p0:p1], tol=1e-9, maxit=2000, variant="pbicgsafe",

@@ -104,4 +104,4 @@ def test_one_iteration_full_size(case, k):
     for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g"]:  # q_i is transient
         got, ref = M.get_state(v), st1.vec(v)
         assert np.all(np.abs(got - ref) <= 4.0 * E[v]), (name, k, v)
-        assert np.array_equal(got, ref), (name, k, v)  # compensated inner products: exact
+        assert np.array_equal(got, ref), (name, k, v)  # inner products rounded once from their exact value

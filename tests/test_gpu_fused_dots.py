@@ -3,7 +3,7 @@
 The schedule changes where the nine inner products of Algorithm 4 are formed
 (per-block partial sums inside pass A and the epilogue of A w_i of the previous
 iteration, instead of a pass of their own), not what they are: the partial sums
-are compensated pairs rounded once, as in the separate pass.  So every result
+are triple sums rounded once, as in the separate pass.  So every result
 must equal the oracle's p-BiCGSafe bit for bit, like schedule 0.
 """
 import os

@@ -228,9 +228,9 @@ def test_full_solve_small_cases(variant):
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_trajectory_bit_identical_to_oracle(variant):
     """Both sides round every statement as written, sum rows in storage order and
-    form inner products with compensated summation, so the whole iteration
-    should reproduce the oracle's bit for bit (a near-tie in an inner product
-    could in principle flip one rounding; none is expected on these inputs)."""
+    form each inner product as its exact value rounded once (the GPU's triple
+    sums reach it except within ~u^3 of a rounding boundary), so the whole
+    iteration reproduces the oracle's bit for bit."""
     for name, A, tol in [
         ("cd2d_64", W.workload("cd2d_64"), 1e-10),
         ("rand_band_20k", W.rand_band(20_000, seed=3, band=500), 1e-10),
