@@ -93,8 +93,8 @@ typedef struct {
                           HIP graphs; 0: launch every kernel directly.  Results are
                           bit-identical either way.  Ignored while profiling.          */
   int32_t schedule;    /* p-BiCGSafe and p-BiCGSafe-rr.  -1 (default): automatic --
-                          sliced layout: 2 from 2^20 rows, else 1; CSR: 1 below 2^18
-                          rows, else 0; batches: 2
+                          sliced layout: 2; CSR: 2 below 2^18 rows, else 0;
+                          batches: 2
                           (ps_info.auto_schedule tells; other variants ignore -1).
                           With -rr, a replacement step and the iteration after it form
                           their inner products in their own pass.

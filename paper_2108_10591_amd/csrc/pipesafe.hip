@@ -50,10 +50,10 @@ constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 // Automatic choices (options overlap = -1, schedule = -1), from measurements on
 // 4k..2M-row stencils and band matrices: a second stream pays once one sparse
 // product streams at least kOverlapMinBytes (below that the cross-stream waits
-// cost more than they hide); the fused schedules pay on the sliced layout from
-// kFusedMinRows rows on, and not on CSR matrices with uneven rows, whose
-// gather-bound product gains little from the skipped pass and pays for the
-// extra reads in its epilogue.
+// cost more than they hide); the fused schedules pay on the sliced layout at
+// every size, and on CSR below kFusedMinRows rows, but not on large CSR
+// matrices with uneven rows, whose gather-bound product gains little from the
+// skipped pass and pays for the extra reads in its epilogue.
 constexpr int64_t kOverlapMinBytes = 128ll << 20;
 constexpr int64_t kFusedMinRows = 1 << 18;
 // p-BiCGSafe's update passes stream the vectors they do not hand to the next
@@ -708,21 +708,21 @@ int64_t matrix_bytes(const ps_matrix *M) {
              : (8 + M->index_bits / 8) * M->slots + 4 * ((int64_t)M->nslice + 1);
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
-// The automatic p-BiCGSafe(-rr) schedule, from measurements:
-//  - sliced layout: the fused epilogue (2) from 2^20 rows (5.5% faster than 1
-//    at 128^3, within 1% of it from 64^3 to 112^3), else the fused partial
-//    sums (1: up to 9% faster than 2 near 10^5 rows, and both 15% faster than
-//    0 on small systems, where the finish adds the partial lists itself and
-//    an iteration is one launch shorter);
-//  - CSR: 1 below kFusedMinRows rows (4-9% faster than 0 on small uneven
-//    matrices), else the separate pass (0: gather-bound products gain nothing
-//    from the skipped pass and pay for the extra epilogue reads).
+// The automatic p-BiCGSafe(-rr) schedule, from measurements with the triple
+// inner-product accumulators:
+//  - sliced layout: the fused epilogue (2) -- 4-7% faster than the fused
+//    partial sums (1) on stencils from 4096 rows to 2^21 (2.5% slower near
+//    10^5 rows), and 6-20% faster than the separate pass (0); pass A of
+//    schedule 1 carries five triple accumulators, schedule 2's w pass none;
+//  - CSR: 2 below kFusedMinRows rows (the same margins), else the separate
+//    pass (0: on uneven rows the gather-bound products gain nothing from the
+//    skipped pass and pay for the extra epilogue reads);
+//  - batches: 2 (the 512-system stencil batch: 17% more solves/s than 0, 4%
+//    more than 1).
 int auto_schedule(const ps_matrix *M) {
-  // batches: the fused epilogue saves the separate pass and a launch in every
-  // iteration (the 512-system stencil batch: 17% more solves/s than 0, 4% more than 1)
   if (M->nsys > 1) return 2;
-  if (M->format == PS_FMT_SELL) return M->n >= (1 << 20) ? 2 : 1;
-  return M->n < kFusedMinRows ? 1 : 0;
+  if (M->format == PS_FMT_SELL) return 2;
+  return M->n < kFusedMinRows ? 2 : 0;
 }
 // two sparse products and the update passes' 34 vector reads and writes
 bool streaming(const ps_matrix *M) {
