@@ -124,16 +124,18 @@ struct TD {
   double a, b, c;
 };
 constexpr int kPart = 3;  // doubles per stored partial sum (a, b, c)
+// (two_sum, td_fma, td_add and td_round also compile for the host, where the
+// tests check them against exact rational arithmetic)
 
 // s + e = x + y exactly (Knuth's two-sum)
-__device__ __forceinline__ void two_sum(double x, double y, double &s, double &e) {
+__host__ __device__ __forceinline__ void two_sum(double x, double y, double &s, double &e) {
   s = x + y;
   const double z = s - x;
   e = (x - (s - z)) + (y - z);
 }
 
 // T += x*y
-__device__ __forceinline__ void td_fma(TD &T, double x, double y) {
+__host__ __device__ __forceinline__ void td_fma(TD &T, double x, double y) {
   const double p = x * y;
   const double ep = __builtin_fma(x, y, -p);  // x*y = p + ep exactly
   double e1, e2, e3;
@@ -144,7 +146,7 @@ __device__ __forceinline__ void td_fma(TD &T, double x, double y) {
 }
 
 // T += U
-__device__ __forceinline__ void td_add(TD &T, const TD &U) {
+__host__ __device__ __forceinline__ void td_add(TD &T, const TD &U) {
   double e1, e2, e3;
   two_sum(T.a, U.a, T.a, e1);
   two_sum(T.b, U.b, T.b, e2);
@@ -166,7 +168,7 @@ __device__ __forceinline__ void td_store(double *p, int64_t k, const TD &T) {
 // three are brought to t + w + werr exactly by error-free additions, t + w is
 // rounded, and a remainder of exactly half a unit that werr pushes past the
 // midpoint moves the result one unit away.
-__device__ __forceinline__ double td_round(const TD &T) {
+__host__ __device__ __forceinline__ double td_round(const TD &T) {
   double s1, e1, t, e0, w, werr, r, rl;
   two_sum(T.b, T.c, s1, e1);
   two_sum(T.a, s1, t, e0);
