@@ -468,12 +468,14 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   const bool replace = replacement(P, i);
   if (!replace) {
     PS_TRY(fork(M, P));
-    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT, P.kry32));  // As_i
-    // the partial sums come from the previous iteration's passes, which the
-    // first iteration and the one after a replacement step do not have
+    // the reduction phase on the second stream, enqueued first so that its few
+    // workgroups are dispatched ahead of the product's thousands; the partial
+    // sums come from the previous iteration's passes, which the first
+    // iteration and the one after a replacement step do not have
     if (P.fused && i > P.i0 && !after_replacement(P, i))
-      PS_TRY(fused_finish(M, P, P.B));  // concurrently
+      PS_TRY(fused_finish(M, P, P.B));
     else PS_TRY(iter_safe_dots(M, P, P.B, i));
+    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT, P.kry32));  // As_i, concurrently
     PS_TRY(join(M, P));
     if (!P.fused) {
       PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
@@ -559,16 +561,17 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
   s1.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1, pair_grid(M->n), 0, s1));
   PS_TRY(fork(M, P));
-  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, C_HALT, P.kry32));  // v_i = A z_i
+  // each reduction phase enqueued ahead of the product it overlaps
   PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, P.maxit, P.tol, 0, M->hist));
+  PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStore{V}, C_HALT, P.kry32));  // v_i = A z_i
   PS_TRY(join(M, P));
   Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
   s2.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2, pair_grid(M->n), 0, s2));
   PS_TRY(fork(M, P));
-  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, C_HALT, P.kry32));  // t_{i+1} = A w_{i+1}
   PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, P.maxit, P.tol, 0,
                                            M->hist));
+  PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStore{T}, C_HALT, P.kry32));  // t_{i+1} = A w_{i+1}
   PS_TRY(join(M, P));
   return PS_OK;
 }
