@@ -212,7 +212,10 @@ static double xsum_round(xsum_t *X) {
  * error from one FMA), and all of these are summed exactly.  The value is
  * thus the plain definition of the inner product in floating point, and it
  * does not depend on any order of summation.  A non-finite product (or a sum
- * beyond the double range) makes the result NaN.
+ * beyond the double range) makes the result NaN.  The split is exact while
+ * the product's error is representable, i.e. for products above about
+ * 2^-969; below that, far from any value a solve produces, ep is the error
+ * rounded to the subnormal grid.
  */
 static double dot(int64_t n, const double *u, const double *v, double *S) {
   xsum_t X;
