@@ -34,8 +34,8 @@ mathematics, not against the oracle itself.
   P16 an inner product is the exact sum of its products rounded once to the
       nearest double (ties to even), against exact rational arithmetic: random
       vectors over wide exponent ranges, cancellation down to 1e-30 of the
-      terms, exact and near half-way cases, any order of the terms, and NaN for
-      a non-finite product.
+      terms, exact and near half-way cases, a subnormal result, any order of
+      the terms, and NaN for a non-finite product or a sum beyond the range.
 """
 import json
 import os
@@ -406,7 +406,8 @@ def check_p16(orc):
     h = 2.0 ** -53
     for name, t in (("tie to even", [1.0, h]), ("above the tie", [1.0, h, 2.0 ** -200]),
                     ("below the tie", [1.0, h, -2.0 ** -200]), ("tie up to even", [1.0, h, 2 * h]),
-                    ("exact zero", [1e300, -1e300, 1.0, -1.0]), ("empty", [])):
+                    ("exact zero", [1e300, -1e300, 1.0, -1.0]), ("empty", []),
+                    ("subnormal result", [2.0 ** -1020, -2.0 ** -1020, 2.0 ** -1070])):
         cases.append((name, np.array(t, dtype=np.float64), np.ones(len(t))))
     for name, u, v in cases:
         want = exact(u, v)
@@ -421,6 +422,8 @@ def check_p16(orc):
         return "P16 a non-finite product must give NaN"
     if not np.isnan(orc.dot(np.array([1e200, 1.0]), np.array([1e200, np.nan]))):
         return "P16 an overflowing product must give NaN"
+    if not np.isnan(orc.dot(np.array([1e308, 1e308]), np.array([1.0, 1.0]))):
+        return "P16 a sum beyond the double range must give NaN"
     return None
 
 
