@@ -26,11 +26,11 @@ SCAL = ["alpha", "beta", "zeta", "eta", "omega", "f", "rhoref", "rho", "nspmv", 
         "pending_breakdown", "gs", "gw", "gz"]
 NCOEF = 8
 COEF = ["alpha", "beta", "zeta", "eta", "omega", "rho", "f", "spare"]
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(src: str = SRC, out: str = LIB) -> str:
-    """Compile the oracle with gcc (plain -O2, no FMA contraction)."""
+    """Compile the oracle with gcc (plain -O2, no FMA contraction, OpenMP)."""
     tmp = out + ".tmp"
     subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
@@ -93,17 +93,21 @@ class Oracle:
         L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, f64, cint = ctypes.c_int64, ctypes.c_double, ctypes.c_int
-        L.orc_setup.argtypes = [cint, cint, i64, P, P, P, P, P, cint, P, P]
+        L.orc_setup.argtypes = [cint, cint, i64, P, P, P, P, P, cint, cint, P, P]
         L.orc_setup.restype = cint
         L.orc_run.argtypes = [cint, cint, i64, P, P, P, P, P, P, i64, i64, f64, i64, i64, P, P, P, P]
         L.orc_run.restype = cint
-        L.orc_solve.argtypes = [cint, cint, i64, P, P, P, P, P, f64, i64, i64, i64, cint, P, P, P, P, P,
-                                P]
+        L.orc_solve.argtypes = [cint, cint, i64, P, P, P, P, P, cint, f64, i64, i64, i64, cint, P, P, P,
+                                P, P, P]
         L.orc_solve.restype = cint
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
         L.orc_spmv.restype = None
         L.orc_dot.argtypes = [i64, P, P]
         L.orc_dot.restype = f64
+        L.orc_set_threads.argtypes = [cint]
+        L.orc_set_threads.restype = None
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = cint
         if L.orc_nv() != len(VEC) or L.orc_ns() != len(SCAL):
             raise RuntimeError("oracle state layout mismatch")
         self.L = L
@@ -122,13 +126,22 @@ class Oracle:
         assert u.shape == v.shape and u.ndim == 1
         return float(self.L.orc_dot(u.size, _p(u), _p(v)))
 
+    def set_threads(self, n):
+        """OpenMP threads of later calls (results do not depend on it)."""
+        self.L.orc_set_threads(int(n))
+
+    def threads(self):
+        return int(self.L.orc_threads())
+
     def solve(self, A, b=None, x0=None, tol=1e-8, maxit=10_000, variant="pbicgsafe", rr_m=100,
-              rr_M=None, norm_ref=0, precision=0):
+              rr_M=None, norm_ref=0, precision=0, x0_mode=0):
         """Full solve: x, iters, status, hist[0..iters], coef[0..iters) and operation counters.
 
         precision: 0 FP64; 1 every product with the matrix values rounded to FP32;
         2 the residual statements (set-up, replacement steps) with the FP64 values and every
-        other product with the rounded ones (see oracle.c)."""
+        other product with the rounded ones; 3 as 2 with p, u, z held in FP32 (p-BiCGSafe(-rr)).
+        x0_mode (with x0): 0 as given; 1 replaced by 0 if ||b - A x0|| > ||b||; 2 first
+        scaled by (A x0, b)/(A x0, A x0), then the rule of 1 (see oracle.c)."""
         rowptr, col, val = _csr(A)
         b = np.ascontiguousarray(A.b if b is None else b, dtype=np.float64)
         x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
@@ -138,8 +151,9 @@ class Oracle:
         hist = np.full(maxit + 1, np.nan)
         coef = np.zeros((maxit + 1, NCOEF))
         counters = np.zeros(3)
-        rc = self.L.orc_solve(_vid(variant), precision, A.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x0a), tol,
-                              maxit, rr_m, maxit if rr_M is None else rr_M, norm_ref, _p(x),
+        rc = self.L.orc_solve(_vid(variant), precision, A.n, _p(rowptr), _p(col), _p(val), _p(b),
+                              _p(x0a), x0_mode, tol, maxit, rr_m, maxit if rr_M is None else rr_M,
+                              norm_ref, _p(x),
                               ctypes.byref(iters), _p(hist), _p(coef), ctypes.byref(status),
                               _p(counters))
         if rc != 0:
@@ -148,13 +162,14 @@ class Oracle:
         return Result(x=x, iters=it, status=status.value, hist=hist[: it + 1], coef=coef[:it],
                       nspmv=int(counters[0]), ndot=int(counters[1]), nphase=int(counters[2]))
 
-    def setup(self, A, b=None, x0=None, variant="pbicgsafe", norm_ref=0, precision=0) -> State:
+    def setup(self, A, b=None, x0=None, variant="pbicgsafe", norm_ref=0, precision=0,
+              x0_mode=0) -> State:
         rowptr, col, val = _csr(A)
         b = np.ascontiguousarray(A.b if b is None else b, dtype=np.float64)
         x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
         st = State(A.n)
         rc = self.L.orc_setup(_vid(variant), precision, A.n, _p(rowptr), _p(col), _p(val), _p(b),
-                              _p(x0a), norm_ref, _p(st.V), _p(st.S))
+                              _p(x0a), x0_mode, norm_ref, _p(st.V), _p(st.S))
         if rc != 0:
             raise RuntimeError(f"orc_setup failed: {rc}")
         return st

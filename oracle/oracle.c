@@ -39,7 +39,25 @@
  *      residual r_{i+1} = b - A x_{i+1} of a replacement step (Algorithm 5,
  *      Section 4) -- read the FP64 values, every other product the rounded
  *      ones, so the replacement steps re-anchor the iteration to the FP64
- *      system (R23).
+ *      system (R23);
+ *   3  as 2, and the search directions p_i, u_i and the auxiliary vector z_i
+ *      of p-BiCGSafe(-rr) are held as FP32 numbers: each is rounded to the
+ *      nearest FP32 number (ties to even) when it is formed and widened
+ *      exactly when it is read, so all arithmetic stays FP64 (R24).
+ *
+ * Initial guess (argument `x0_mode` of orc_setup and orc_solve; with x0 given):
+ *   0  x_0 as given;
+ *   1  kept only if ||b - A x_0|| <= ||b||, else x_0 = 0 (a guess worse than
+ *      zero costs nothing);
+ *   2  first scaled by the factor c = (A x_0, b) / (A x_0, A x_0) that
+ *      minimises ||b - c A x_0|| (x_0 = 0 when c cannot be formed), then the
+ *      rule of 1.
+ *   The products of these tests are residual statements (FP64 values under
+ *   precision 2 and 3).
+ *
+ * Threads: every vector statement and every row of a sparse product is
+ * computed independently of the others, and an inner product is an exact
+ * integer sum, so the results do not depend on the number of OpenMP threads.
  *
  * Readings of points the paper leaves open (each is used below):
  *   R1  the shadow residual is r0* = r0, fixed for the whole solve.
@@ -59,14 +77,21 @@
  *       omega's successor) stops the solve with status BREAKDOWN and x_i.
  *   R23 mixed precision (precision 1, 2) rounds only the matrix values; the
  *       paper's experiments are FP64 throughout (Section 5).
+ *   R24 precision 3 also stores p, u and z in FP32 (the vectors whose
+ *       rounding leaves the recurrences of Section 3 consistent with A).
  *
  * Status codes: 0 converged, 1 maxit, 2 breakdown, 3 non-finite inner product.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* vectors shorter than this are processed by one thread (thread start-up
+   would cost more than the work) */
+#define ORC_PAR_MIN 32768
 
 /* vector slots in the caller-provided state array V[NV][n] */
 enum {
@@ -110,6 +135,7 @@ static void two_sum_acc(double *s, double *c, double v) {
    rounded once, so that the row's value does not depend on the order in which
    its products are added */
 static void spmv(const csr_t *A, const double *x, double *y, double *S) {
+#pragma omp parallel for schedule(static) if (A->n >= ORC_PAR_MIN)
   for (int64_t i = 0; i < A->n; ++i) {
     double s = 0.0, c = 0.0;
     for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) two_sum_acc(&s, &c, A->val[k] * x[A->col[k]]);
@@ -221,12 +247,27 @@ static double dot(int64_t n, const double *u, const double *v, double *S) {
   xsum_t X;
   memset(&X, 0, sizeof X);
   int finite = 1;
-  for (int64_t k = 0; k < n; ++k) {
-    const double p = u[k] * v[k];
-    if (!isfinite(p)) finite = 0;
-    if (!finite) continue;
-    xsum_add(&X, p);
-    xsum_add(&X, fma(u[k], v[k], -p)); /* u_k v_k = p + ep exactly */
+#pragma omp parallel if (n >= ORC_PAR_MIN)
+  {
+    /* each thread sums its share exactly; the shares are added digit by digit,
+       which is exact integer addition, so the thread count changes nothing */
+    xsum_t T;
+    memset(&T, 0, sizeof T);
+    int fin = 1;
+#pragma omp for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+      const double p = u[k] * v[k];
+      if (!isfinite(p)) fin = 0;
+      if (!fin) continue;
+      xsum_add(&T, p);
+      xsum_add(&T, fma(u[k], v[k], -p)); /* u_k v_k = p + ep exactly */
+    }
+    xsum_carry(&T);
+#pragma omp critical(orc_dot_merge)
+    {
+      for (int i = 0; i < XDIG; ++i) X.d[i] += T.d[i];
+      finite = finite && fin;
+    }
   }
   S[S_NDOT] += 1.0;
   if (!finite) return NAN;
@@ -246,7 +287,7 @@ static int precision_pair(int precision, const csr_t *A, csr_t *Ak, csr_t *Ar, d
   *Ak = *A;
   *Ar = *A;
   if (precision == 0) return 0;
-  if (precision != 1 && precision != 2) return -1;
+  if (precision < 1 || precision > 3) return -1;
   const int64_t nnz = A->rowptr[A->n];
   double *v = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
   if (!v) return -2;
@@ -257,15 +298,22 @@ static int precision_pair(int precision, const csr_t *A, csr_t *Ak, csr_t *Ar, d
   return 0;
 }
 
+/* A vector entry as stored: FP64, or (f32 != 0: precision 3's p, u, z) the
+   nearest FP32 number, widened exactly */
+static double held(int f32, double v) { return f32 ? (double)(float)v : v; }
+
 /*
  * Initialise the state for `variant` (the steps before each listing's loop).
  * V holds NV vectors of length n (zeroed here); S holds NS scalars.
- * x0 may be NULL (zero initial guess).  norm_ref selects the stop-test scale:
- * 0 = ||r_0|| (the paper's criterion, Section 5), 1 = ||b||.
+ * x0 may be NULL (zero initial guess); x0_mode as in the header.  norm_ref
+ * selects the stop-test scale: 0 = ||r_0|| (the paper's criterion, Section 5),
+ * 1 = ||b||.
  */
 int orc_setup(int variant, int precision, int64_t n, const int64_t *rowptr, const int32_t *col,
-              const double *val, const double *b, const double *x0, int norm_ref, double *V,
-              double *S) {
+              const double *val, const double *b, const double *x0, int x0_mode, int norm_ref,
+              double *V, double *S) {
+  if (x0_mode < 0 || x0_mode > 2) return -1;
+  if (precision == 3 && variant != V_PBICGSAFE && variant != V_PBICGSAFE_RR) return -1;
   const csr_t A64 = {n, rowptr, col, val};
   csr_t A, Ares;
   double *rounded;
@@ -277,10 +325,29 @@ int orc_setup(int variant, int precision, int64_t n, const int64_t *rowptr, cons
   memset(S, 0, sizeof(double) * NS);
   double *x = v[VX], *r = v[VR], *rs = v[VRS], *tmp = v[VTMP];
 
-  /* x_0 and r_0 = b - A x_0 */
+  /* x_0 */
   for (int64_t k = 0; k < n; ++k) x[k] = x0 ? x0[k] : 0.0;
+  if (x0 && x0_mode == 2) {
+    /* the multiple c x_0 with the least residual: c = (A x_0, b) / (A x_0, A x_0) */
+    spmv(&Ares, x, tmp, S);
+    const double num = dot(n, tmp, b, S), den = dot(n, tmp, tmp, S);
+    S[S_NDOT] -= 2.0; /* not inner products of the method */
+    const double c = num / den;
+    const int ok = den != 0.0 && isfinite(c);
+    for (int64_t k = 0; k < n; ++k) x[k] = ok ? c * x[k] : 0.0;
+  }
+  /* r_0 = b - A x_0 */
   spmv(&Ares, x, tmp, S);
   for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];
+  if (x0 && x0_mode >= 1) {
+    /* a guess whose residual exceeds ||b|| (or is not finite) is replaced by 0 */
+    const double rr = dot(n, r, r, S), bb = dot(n, b, b, S);
+    S[S_NDOT] -= 2.0;
+    if (!(rr <= bb)) {
+      for (int64_t k = 0; k < n; ++k) x[k] = 0.0;
+      for (int64_t k = 0; k < n; ++k) r[k] = b[k]; /* b - A 0 */
+    }
+  }
   /* R1: r0* = r0 */
   for (int64_t k = 0; k < n; ++k) rs[k] = r[k];
 
@@ -400,7 +467,15 @@ static int safe_phase(int64_t n, double **v, double *S, int64_t i, int64_t maxit
   return ST_RUNNING;
 }
 
-/* ssBiCGSafe2, Algorithm 3: one iteration i */
+/*
+ * ssBiCGSafe2, Algorithm 3: one iteration i.  After the reduction phase the
+ * updates fall into two row-local groups around the product A u_i:
+ *   directions   p_i = r_i + beta (p_{i-1} - u_{i-1}),  u_i = zeta o_i + eta (y_i + beta u_{i-1}),
+ *                with o_i = s_i + beta t_{i-1} (kept for t_i and r_{i+1});
+ *   residuals    t_i = o_i - w_i,  z_i = zeta r_i + eta z_{i-1} - alpha u_i,
+ *                y_{i+1} = zeta s_i + eta y_i - alpha w_i,  x_{i+1} = x_i + alpha p_i + z_i,
+ *                r_{i+1} = r_i - alpha o_i - y_{i+1}   (w_i = A u_i).
+ */
 static int iter_ssbicgsafe2(const csr_t *A, double **v, double *S, int64_t i, int64_t maxit,
                             double tol, double *hist, double *coef) {
   int64_t n = A->n;
@@ -410,22 +485,39 @@ static int iter_ssbicgsafe2(const csr_t *A, double **v, double *S, int64_t i, in
   int st = safe_phase(n, v, S, i, maxit, tol, hist, coef);
   if (st != ST_RUNNING) return st;
   const double al = S[S_ALPHA], be = S[S_BETA], ze = S[S_ZETA], et = S[S_ETA];
-  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - u[k]);          /* p_i */
-  for (int64_t k = 0; k < n; ++k) o[k] = s[k] + be * t[k];                   /* o_i */
-  for (int64_t k = 0; k < n; ++k) u[k] = ze * o[k] + et * (y[k] + be * u[k]); /* u_i */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    o[k] = s[k] + be * t[k];
+    p[k] = r[k] + be * (p[k] - u[k]);
+    u[k] = ze * o[k] + et * (y[k] + be * u[k]);
+  }
   spmv(A, u, w, S);                                        /* w_i = A u_i */
-  for (int64_t k = 0; k < n; ++k) t[k] = o[k] - w[k];                        /* t_i */
-  for (int64_t k = 0; k < n; ++k) z[k] = ze * r[k] + et * z[k] - al * u[k];  /* z_i */
-  for (int64_t k = 0; k < n; ++k) y[k] = ze * s[k] + et * y[k] - al * w[k];  /* y_{i+1} */
-  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + z[k];            /* x_{i+1} */
-  for (int64_t k = 0; k < n; ++k) r[k] = r[k] - al * o[k] - y[k];            /* r_{i+1} */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    t[k] = o[k] - w[k];
+    z[k] = ze * r[k] + et * z[k] - al * u[k];
+    y[k] = ze * s[k] + et * y[k] - al * w[k];
+    x[k] = x[k] + al * p[k] + z[k];
+    r[k] = r[k] - al * o[k] - y[k];
+  }
   return ST_RUNNING;
 }
 
-/* p-BiCGSafe, Algorithm 4, and p-BiCGSafe-rr, Algorithm 5: one iteration i */
+/*
+ * p-BiCGSafe, Algorithm 4, and p-BiCGSafe-rr, Algorithm 5: one iteration i.
+ * The product A s_i does not depend on the reduction phase (Section 3), which
+ * is what the pipelining overlaps.  The updates are the directions and
+ * residuals of Algorithm 3, with the products A o_i and A u_i replaced by the
+ * recurrences Eq. (q) q_i = As_i + beta l_{i-1} and Eq. (w)
+ * w_i = zeta q_i + eta (g_i + beta w_{i-1}), and after A w_i the recurrences
+ * Eq. (l) l_i = q_i - A w_i, Eq. (g) g_{i+1} = zeta As_i + eta g_i - alpha A w_i
+ * and Eq. (sip1) s_{i+1} = s_i - alpha q_i - g_{i+1}.  A replacement step of
+ * Algorithm 5 forms q_i, w_i, r_{i+1}, l_i, g_{i+1}, s_{i+1} as true products
+ * instead.  f32v (precision 3): p, u, z are held as FP32 numbers.
+ */
 static int iter_pbicgsafe(const csr_t *A, const csr_t *Ares, const double *b, double **v,
                           double *S, int64_t i, int64_t maxit, double tol, int rr, int64_t m,
-                          int64_t M, double *hist, double *coef) {
+                          int64_t M, int f32v, double *hist, double *coef) {
   int64_t n = A->n;
   double *x = v[VX], *r = v[VR], *s = v[VS], *y = v[VY], *t = v[VT], *p = v[VP], *u = v[VU];
   double *z = v[VZ], *w = v[VW], *l = v[VL], *g = v[VG], *q = v[VQ], *o = v[VO];
@@ -436,32 +528,45 @@ static int iter_pbicgsafe(const csr_t *A, const csr_t *Ares, const double *b, do
   const double al = S[S_ALPHA], be = S[S_BETA], ze = S[S_ZETA], et = S[S_ETA];
   const int replace = rr && m > 0 && (i % m == 0) && i > 0 && i < M;
 
-  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - u[k]);          /* p_i */
-  for (int64_t k = 0; k < n; ++k) o[k] = s[k] + be * t[k];                   /* o_i */
-  for (int64_t k = 0; k < n; ++k) u[k] = ze * o[k] + et * (y[k] + be * u[k]); /* u_i */
+  /* directions, and unless replacing, q_i and w_i by Eqs. (q), (w) */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    o[k] = s[k] + be * t[k];
+    p[k] = held(f32v, r[k] + be * (p[k] - u[k]));
+    u[k] = held(f32v, ze * o[k] + et * (y[k] + be * u[k]));
+    if (!replace) {
+      q[k] = As[k] + be * l[k];
+      w[k] = ze * q[k] + et * (g[k] + be * w[k]);
+    }
+  }
   if (replace) {
     spmv(A, o, q, S);                                      /* q_i = A o_i */
     spmv(A, u, w, S);                                      /* w_i = A u_i */
-  } else {
-    for (int64_t k = 0; k < n; ++k) q[k] = As[k] + be * l[k];                /* q_i, Eq. (q) */
-    for (int64_t k = 0; k < n; ++k) w[k] = ze * q[k] + et * (g[k] + be * w[k]); /* w_i, Eq. (w) */
   }
-  for (int64_t k = 0; k < n; ++k) t[k] = o[k] - w[k];                        /* t_i */
-  for (int64_t k = 0; k < n; ++k) z[k] = ze * r[k] + et * z[k] - al * u[k];  /* z_i */
-  for (int64_t k = 0; k < n; ++k) y[k] = ze * s[k] + et * y[k] - al * w[k];  /* y_{i+1} */
-  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + z[k];            /* x_{i+1} */
+  /* residuals and the iterate; r_{i+1} by its recurrence unless replacing */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    t[k] = o[k] - w[k];
+    z[k] = held(f32v, ze * r[k] + et * z[k] - al * u[k]);
+    y[k] = ze * s[k] + et * y[k] - al * w[k];
+    x[k] = x[k] + al * p[k] + z[k];
+    if (!replace) r[k] = r[k] - al * o[k] - y[k];
+  }
   if (replace) {
-    spmv(Ares, x, tmp, S);                                 /* A x_{i+1} (precision 2: FP64) */
-    for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];                    /* r_{i+1} = b - A x_{i+1} */
+    spmv(Ares, x, tmp, S);                                 /* A x_{i+1} (precision 2, 3: FP64) */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+    for (int64_t k = 0; k < n; ++k) r[k] = b[k] - tmp[k];  /* r_{i+1} = b - A x_{i+1} */
     spmv(A, t, l, S);                                      /* R7: l_i = A t_i */
     spmv(A, y, g, S);                                      /* g_{i+1} = A y_{i+1} */
     spmv(A, r, s, S);                                      /* s_{i+1} = A r_{i+1} */
   } else {
-    for (int64_t k = 0; k < n; ++k) r[k] = r[k] - al * o[k] - y[k];          /* r_{i+1} */
     spmv(A, w, Aw, S);                                     /* Aw_i */
-    for (int64_t k = 0; k < n; ++k) l[k] = q[k] - Aw[k];                     /* l_i, Eq. (l) */
-    for (int64_t k = 0; k < n; ++k) g[k] = ze * As[k] + et * g[k] - al * Aw[k]; /* g_{i+1}, Eq. (g) */
-    for (int64_t k = 0; k < n; ++k) s[k] = s[k] - al * q[k] - g[k];          /* s_{i+1}, Eq. (sip1) */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+    for (int64_t k = 0; k < n; ++k) {
+      l[k] = q[k] - Aw[k];
+      g[k] = ze * As[k] + et * g[k] - al * Aw[k];
+      s[k] = s[k] - al * q[k] - g[k];
+    }
   }
   return ST_RUNNING;
 }
@@ -506,11 +611,16 @@ static int iter_pbicgstab(const csr_t *A, double **v, double *S, int64_t i, int6
   if (S[S_PENDING_BREAKDOWN] != 0.0) return ST_BREAKDOWN;
   const double al = S[S_ALPHA], be = S[S_BETA], omp = S[S_OMEGA];
 
-  for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - omp * s[k]);   /* p_i */
-  for (int64_t k = 0; k < n; ++k) s[k] = w[k] + be * (s[k] - omp * z[k]);   /* s_i = A p_i */
-  for (int64_t k = 0; k < n; ++k) z[k] = t[k] + be * (z[k] - omp * vv[k]);  /* z_i = A s_i */
-  for (int64_t k = 0; k < n; ++k) q[k] = r[k] - al * s[k];                  /* q_i */
-  for (int64_t k = 0; k < n; ++k) y[k] = w[k] - al * z[k];                  /* y_i = A q_i */
+  /* p_i and the products s_i = A p_i, z_i = A s_i by their recurrences; q_i and
+     y_i = A q_i */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    p[k] = r[k] + be * (p[k] - omp * s[k]);
+    s[k] = w[k] + be * (s[k] - omp * z[k]);
+    z[k] = t[k] + be * (z[k] - omp * vv[k]);
+    q[k] = r[k] - al * s[k];
+    y[k] = w[k] - al * z[k];
+  }
   /* phase 1: (q, y), (y, y), overlapped with v_i = A z_i */
   double qy = dot(n, q, y, S);
   double yy = dot(n, y, y, S);
@@ -519,9 +629,13 @@ static int iter_pbicgstab(const csr_t *A, double **v, double *S, int64_t i, int6
   if (!isfinite(qy) || !isfinite(yy)) return ST_NONFINITE;
   double om = (yy == 0.0) ? 0.0 : qy / yy;
   if (!isfinite(om)) return ST_BREAKDOWN;
-  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + om * q[k];     /* x_{i+1} */
-  for (int64_t k = 0; k < n; ++k) r[k] = q[k] - om * y[k];                 /* r_{i+1} */
-  for (int64_t k = 0; k < n; ++k) w[k] = y[k] - om * (t[k] - al * vv[k]);  /* w_{i+1} = A r_{i+1} */
+  /* the iterate, the residual and w_{i+1} = A r_{i+1} by its recurrence */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    x[k] = x[k] + al * p[k] + om * q[k];
+    r[k] = q[k] - om * y[k];
+    w[k] = y[k] - om * (t[k] - al * vv[k]);
+  }
   /* phase 2: (r0*, r), (r0*, w), (r0*, s), (r0*, z), (r, r), overlapped with t_{i+1} = A w_{i+1} */
   double f = dot(n, rs, r, S);
   double gw = dot(n, rs, w, S);
@@ -567,6 +681,7 @@ static int iter_bicgstab(const csr_t *A, double **v, double *S, int64_t i, int64
   int st = stop_test(rho, S, i, maxit, tol, hist);
   if (st != ST_RUNNING) return st;
   const double be = S[S_BETA], omp = S[S_OMEGA];
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
   for (int64_t k = 0; k < n; ++k) p[k] = r[k] + be * (p[k] - omp * Ap[k]);  /* p_i */
   spmv(A, p, Ap, S);                                                        /* A p_i */
   double f = dot(n, rs, r, S);
@@ -575,6 +690,7 @@ static int iter_bicgstab(const csr_t *A, double **v, double *S, int64_t i, int64
   if (!isfinite(f) || !isfinite(rsap)) return ST_NONFINITE;
   if (bad(rsap)) return ST_BREAKDOWN;
   double al = f / rsap;                                                      /* alpha_i */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
   for (int64_t k = 0; k < n; ++k) t[k] = r[k] - al * Ap[k];                  /* t_i */
   spmv(A, t, At, S);                                                        /* A t_i */
   double att = dot(n, At, t, S);
@@ -582,8 +698,11 @@ static int iter_bicgstab(const csr_t *A, double **v, double *S, int64_t i, int64
   S[S_NPHASE] += 1.0;
   if (!isfinite(att) || !isfinite(atat)) return ST_NONFINITE;
   double om = (atat == 0.0) ? 0.0 : att / atat;                             /* omega_i */
-  for (int64_t k = 0; k < n; ++k) x[k] = x[k] + al * p[k] + om * t[k];       /* x_{i+1} */
-  for (int64_t k = 0; k < n; ++k) r[k] = t[k] - om * At[k];                  /* r_{i+1} */
+#pragma omp parallel for schedule(static) if (n >= ORC_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    x[k] = x[k] + al * p[k] + om * t[k];                                     /* x_{i+1} */
+    r[k] = t[k] - om * At[k];                                                /* r_{i+1} */
+  }
   double f1 = dot(n, rs, r, S);
   S[S_NPHASE] += 1.0;
   record(coef, i, al, be, 0.0, 0.0, om, rho, f);
@@ -609,6 +728,7 @@ int orc_run(int variant, int precision, int64_t n, const int64_t *rowptr, const 
             const double *val, const double *b, double *V, double *S, int64_t i_begin,
             int64_t maxit, double tol, int64_t rr_m, int64_t rr_M, int64_t *iters, double *hist,
             double *coef, int32_t *status) {
+  if (precision == 3 && variant != V_PBICGSAFE && variant != V_PBICGSAFE_RR) return -1;
   const csr_t A64 = {n, rowptr, col, val};
   csr_t A, Ares;
   double *rounded;
@@ -630,10 +750,12 @@ int orc_run(int variant, int precision, int64_t n, const int64_t *rowptr, const 
     switch (variant) {
       case V_SSBICGSAFE2: st = iter_ssbicgsafe2(&A, v, S, i, maxit, tol, hist, coef); break;
       case V_PBICGSAFE:
-        st = iter_pbicgsafe(&A, &Ares, b, v, S, i, maxit, tol, 0, 0, 0, hist, coef);
+        st = iter_pbicgsafe(&A, &Ares, b, v, S, i, maxit, tol, 0, 0, 0, precision == 3, hist,
+                            coef);
         break;
       case V_PBICGSAFE_RR:
-        st = iter_pbicgsafe(&A, &Ares, b, v, S, i, maxit, tol, 1, rr_m, rr_M, hist, coef);
+        st = iter_pbicgsafe(&A, &Ares, b, v, S, i, maxit, tol, 1, rr_m, rr_M, precision == 3,
+                            hist, coef);
         break;
       case V_PBICGSTAB: st = iter_pbicgstab(&A, v, S, i, maxit, tol, hist, coef); break;
       case V_BICGSTAB: st = iter_bicgstab(&A, v, S, i, maxit, tol, hist, coef); break;
@@ -649,14 +771,14 @@ int orc_run(int variant, int precision, int64_t n, const int64_t *rowptr, const 
 
 /* setup + run from i = 0; x (length n) receives the final iterate. */
 int orc_solve(int variant, int precision, int64_t n, const int64_t *rowptr, const int32_t *col,
-              const double *val, const double *b, const double *x0, double tol, int64_t maxit,
-              int64_t rr_m, int64_t rr_M, int norm_ref, double *x, int64_t *iters, double *hist,
-              double *coef, int32_t *status, double *counters) {
-  if (n < 1 || variant < 0 || variant > 4 || precision < 0 || precision > 2) return -1;
+              const double *val, const double *b, const double *x0, int x0_mode, double tol,
+              int64_t maxit, int64_t rr_m, int64_t rr_M, int norm_ref, double *x, int64_t *iters,
+              double *hist, double *coef, int32_t *status, double *counters) {
+  if (n < 1 || variant < 0 || variant > 4 || precision < 0 || precision > 3) return -1;
   double *V = (double *)malloc(sizeof(double) * (size_t)NV * (size_t)n);
   double S[NS];
   if (!V) return -2;
-  int rc = orc_setup(variant, precision, n, rowptr, col, val, b, x0, norm_ref, V, S);
+  int rc = orc_setup(variant, precision, n, rowptr, col, val, b, x0, x0_mode, norm_ref, V, S);
   if (!rc)
     rc = orc_run(variant, precision, n, rowptr, col, val, b, V, S, 0, maxit, tol, rr_m, rr_M,
                  iters, hist, coef, status);
@@ -683,6 +805,12 @@ double orc_dot(int64_t n, const double *u, const double *v) {
   double S[NS];
   return dot(n, u, v, S);
 }
+
+/* OpenMP threads of later calls (n >= 1), and the number in use */
+void orc_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+}
+int orc_threads(void) { return omp_get_max_threads(); }
 
 int orc_nv(void) { return NV; }
 int orc_ns(void) { return NS; }

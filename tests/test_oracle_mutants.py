@@ -45,7 +45,7 @@ MUTANTS = {
     "no_initial_s": ("spmv(&A, r, v[VS], S);                       /* R2", "(void)0;                       /* R2"),
     "spmv_transposed": (SPMV_BODY, SPMV_TRANSPOSED),
     "spmv_drops_compensation": ("    y[i] = s + c;", "    y[i] = s;"),
-    "dot_drops_product_error": ("    xsum_add(&X, fma(u[k], v[k], -p));", "    (void)0;"),
+    "dot_drops_product_error": ("xsum_add(&T, fma(u[k], v[k], -p));", "(void)0;"),
     "dot_drops_carries": ("    X->d[i + 1] += c;", "    X->d[i + 1] += 0 * c;"),
     "dot_ties_away": ("(rem == half && (sticky || (M & 1)))", "(rem == half)"),
     "dot_ignores_sticky": ("(rem == half && (sticky || (M & 1)))", "(rem == half && (M & 1))"),
@@ -62,6 +62,20 @@ MUTANTS = {
     "prec_setup_residual_rounded": ("spmv(&Ares, x, tmp, S);", "spmv(&A, x, tmp, S);"),
     "prec_rr_residual_rounded": ("spmv(Ares, x, tmp, S);", "spmv(A, x, tmp, S);"),
     "prec_setup_s_fp64": ("spmv(&A, r, v[VS], S);", "spmv(&Ares, r, v[VS], S);"),
+    "spmv_fast_two_sum": ("const double e = (*s - (t - z)) + (v - z);", "const double e = v - z;"),
+    "dot_merge_drops_threads": ("      for (int i = 0; i < XDIG; ++i) X.d[i] += T.d[i];",
+                                "      if (omp_get_thread_num() == 0) for (int i = 0; i < XDIG; ++i) X.d[i] += T.d[i];"),
+    "x0_scale_inverted": ("const double c = num / den;", "const double c = den / num;"),
+    "x0_scale_uses_x0": ("dot(n, tmp, b, S), den", "dot(n, x, b, S), den"),
+    "x0_rule_reversed": ("if (!(rr <= bb)) {", "if (!(rr >= bb)) {"),
+    "x0_rule_keeps_r": ("      for (int64_t k = 0; k < n; ++k) r[k] = b[k]; /* b - A 0 */", "      (void)0;"),
+    "f32_z_not_held": ("z[k] = held(f32v, ze * r[k] + et * z[k] - al * u[k]);",
+                       "z[k] = ze * r[k] + et * z[k] - al * u[k];"),
+    "f32_p_not_held": ("p[k] = held(f32v, r[k] + be * (p[k] - u[k]));", "p[k] = r[k] + be * (p[k] - u[k]);"),
+    "f32_x_held": ("    x[k] = x[k] + al * p[k] + z[k];\n    if (!replace)",
+                   "    x[k] = held(f32v, x[k] + al * p[k] + z[k]);\n    if (!replace)"),
+    "f32_u_not_held": ("u[k] = held(f32v, ze * o[k] + et * (y[k] + be * u[k]));",
+                       "u[k] = ze * o[k] + et * (y[k] + be * u[k]);"),
 }
 
 

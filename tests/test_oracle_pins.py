@@ -36,6 +36,24 @@ mathematics, not against the oracle itself.
       vectors over wide exponent ranges, cancellation down to 1e-30 of the
       terms, exact and near half-way cases, a subnormal result, any order of
       the terms, and NaN for a non-finite product or a sum beyond the range.
+      P16b: the same at n = 10^6 (the threaded path), against math.fsum (a
+      correctly rounded sum) of each product split exactly by Dekker's
+      two-product in numpy -- an algorithm independent of the oracle's FMA
+      split and integer accumulator.
+  P13b rows of a sparse product with inexact products over wide exponent
+      ranges, in random order, equal the exactly rounded sum of the rounded
+      products (rational arithmetic); a Fast2Sum-style accumulator, exact only
+      when the running sum outweighs the next term, fails this.
+  P17 initial-guess modes: the least-residual factor c = (A x0, b)/(A x0, A x0)
+      recovers x* exactly from x0 = 2^j x* when A x* = b holds exactly (c =
+      2^-j), agrees with numpy's least-squares solve, never leaves a kept
+      residual above ||b||; the fallback rule gives the x0 = 0 solve bit for
+      bit for a guess worse than zero and the unmodified solve otherwise.
+  P18 precision 3 holds p, u, z as FP32 numbers: every entry of those three
+      vectors is an FP32 number after any iteration and the other vectors are
+      not rounded; with A = I and an FP32 right-hand side (where p, u, z stay
+      FP32 numbers) it equals precision 2 bit for bit; with replacement steps
+      every m = 10 iterations it reaches the FP64 system's residual.
 """
 import json
 import os
@@ -427,8 +445,187 @@ def check_p16(orc):
     return None
 
 
+def check_p13b(orc):
+    from fractions import Fraction as F
+    rng = np.random.default_rng(131)
+    n = 400
+    lengths = rng.integers(1, 60, n)
+    rowptr = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    nnz = int(rowptr[-1])
+    col = rng.integers(0, n, nnz).astype(np.int32)
+    # values and x over +-2^40 with random signs: products inexact, terms of mixed size in
+    # random order; a tenth of the rows get a cancelling pair (the row's largest product
+    # and its negation) so that the result is far below the largest term
+    val = rng.standard_normal(nnz) * 2.0 ** rng.integers(-40, 40, nnz)
+    x = rng.standard_normal(n) * 2.0 ** rng.integers(-40, 40, n)
+    for i in range(0, n, 10):
+        a, e = rowptr[i], rowptr[i + 1]
+        if e - a >= 3:
+            val[a + 1] = -val[a] * x[col[a]] / x[col[a + 1]]
+    A = W.CSR(n, rowptr, col, val, np.zeros(n))
+    y = orc.spmv(A, x)
+    u = 2.0 ** -53
+    checked = 0
+    for i in range(n):
+        prods = [val[k] * x[col[k]] for k in range(rowptr[i], rowptr[i + 1])]  # rounded products
+        ex = sum(F(p) for p in prods)
+        want = float(ex)  # rounded once (Fraction -> float rounds to nearest even)
+        # skip a row only if its exact sum lies within the compensated sum's error bound
+        # (about len^2 u^2 sum|p|) of a rounding boundary (a midpoint between doubles)
+        bound = F(4 * len(prods) ** 2) * F(u) ** 2 * sum(abs(F(p)) for p in prods)
+        lo = np.nextafter(want, -np.inf)
+        hi = np.nextafter(want, np.inf)
+        mids = [(F(want) + F(lo)) / 2, (F(want) + F(hi)) / 2]
+        if min(abs(ex - m) for m in mids) <= bound:
+            continue
+        checked += 1
+        if y[i] != want:
+            return f"P13b row {i} ({len(prods)} products): {y[i]!r} != exactly rounded {want!r}"
+    if checked < 0.95 * n:
+        return f"P13b only {checked} of {n} rows checkable"
+    return None
+
+
+def dekker_two_product(a, b):
+    """p + e = a*b exactly (Dekker/Veltkamp splitting; |a|, |b| < 2^996), elementwise in numpy."""
+    def split(v):
+        c = 134217729.0 * v  # 2^27 + 1
+        hi = c - (c - v)
+        return hi, v - hi
+    p = a * b
+    ah, al = split(a)
+    bh, bl = split(b)
+    e = ((ah * bh - p) + ah * bl + al * bh) + al * bl
+    return p, e
+
+
+def check_p16b(orc):
+    import math
+    rng = np.random.default_rng(161)
+    n = 1_000_000
+    u = rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n)
+    v = rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n)
+    q = rng.standard_normal(n)
+    z = rng.standard_normal(n)
+    w = z - (q @ z) / (q @ q) * q  # (q, w) ~ 1e-16 (q, q): near-orthogonal
+    big = rng.standard_normal(n // 2) * 1e15
+    cu = np.concatenate([big, big])
+    cv = np.concatenate([np.ones(n // 2), -np.ones(n // 2)])
+    cv[::1000] += rng.standard_normal(cv[::1000].size) * 1e-12  # cancels to ~1e-12 of the terms
+    perm = rng.permutation(n)
+    cases = [("random", u, v), ("near-orthogonal", q, w), ("cancelling", cu[perm], cv[perm])]
+    threads = orc.threads()
+    try:
+        for name, a, b in cases:
+            p, e = dekker_two_product(a, b)
+            want = math.fsum(np.concatenate([p, e]).tolist())
+            for th in (1, 4):  # the serial and the threaded sum
+                orc.set_threads(th)
+                got = orc.dot(a, b)
+                if got != want:
+                    return f"P16b {name} n={n}, {th} threads: {got!r} != {want!r}"
+    finally:
+        orc.set_threads(threads)
+    return None
+
+
+def check_p17(orc):
+    # A x* = b exactly: small integer matrix and solution, values exact in FP64
+    rng = np.random.default_rng(17)
+    n = 60
+    Ad = np.diag(rng.integers(20, 40, n).astype(float))
+    off = rng.integers(-3, 4, (n, n)).astype(float) * (rng.random((n, n)) < 0.1)
+    np.fill_diagonal(off, 0.0)
+    Ad += off
+    xs = rng.integers(-5, 6, n).astype(float)
+    A = W._from_dense(Ad, "int60", b=Ad @ xs)
+    for j in (-3, 1, 5):
+        st = orc.setup(A, x0=xs * 2.0 ** j, variant="pbicgsafe", norm_ref=1, x0_mode=2)
+        if not np.array_equal(st.vec("x"), xs):
+            return f"P17 x0 = 2^{j} x*: the scaled guess is not x* exactly"
+        if np.any(st.vec("r") != 0.0):
+            return f"P17 x0 = 2^{j} x*: r_0 != 0"
+        R = orc.solve(A, x0=xs * 2.0 ** j, tol=1e-12, maxit=50, variant="pbicgsafe", norm_ref=1,
+                      x0_mode=2)
+        if R.iters != 0 or R.status != O.CONVERGED or not np.array_equal(R.x, xs):
+            return f"P17 x0 = 2^{j} x*: the solve does not stop at x* with 0 iterations"
+    B = W.cd2d(24, 10.0)
+    M = B.to_scipy()
+    nb = np.linalg.norm(B.b)
+    for seed in range(4):
+        g = np.random.default_rng(seed)
+        x0 = 1.0 + 0.3 * g.standard_normal(B.n) + 5.0 * g.standard_normal() * np.sin(np.arange(B.n))
+        st = orc.setup(B, x0=x0, variant="pbicgsafe", x0_mode=2)
+        Ax0 = M @ x0
+        c = np.linalg.lstsq(Ax0[:, None], B.b, rcond=None)[0][0]
+        xr = st.vec("x")
+        if np.any(xr != 0.0) and rel_inf(xr, c * x0) > 1e-12:
+            return f"P17 seed {seed}: scale differs from the least-squares factor"
+        if np.linalg.norm(st.vec("r")) > nb:
+            return f"P17 seed {seed}: kept residual above ||b||"
+        if np.linalg.norm(st.vec("r") - (B.b - M @ xr)) > 1e-13 * nb:
+            return f"P17 seed {seed}: r_0 is not b - A x_0 of the scaled guess"
+    # fallback rule: a bad guess gives the x0 = 0 solve, a good one the unmodified solve
+    ref0 = orc.solve(B, tol=1e-10, maxit=500, variant="pbicgsafe")
+    bad = 50.0 * np.random.default_rng(9).standard_normal(B.n)
+    for mode in (1, 2):
+        Rb = orc.solve(B, x0=bad if mode == 1 else np.full(B.n, np.nan), tol=1e-10, maxit=500,
+                       variant="pbicgsafe", x0_mode=mode)
+        if Rb.iters != ref0.iters or not np.array_equal(Rb.x, ref0.x):
+            return f"P17 mode {mode}: a rejected guess does not give the x0 = 0 solve"
+    good = np.full(B.n, 0.9)
+    Rg = orc.solve(B, x0=good, tol=1e-10, maxit=500, variant="pbicgsafe", x0_mode=1)
+    R0 = orc.solve(B, x0=good, tol=1e-10, maxit=500, variant="pbicgsafe", x0_mode=0)
+    if Rg.iters != R0.iters or not np.array_equal(Rg.x, R0.x):
+        return "P17 mode 1: a kept guess changed the solve"
+    Rz = orc.solve(B, x0=np.zeros(B.n), tol=1e-10, maxit=500, variant="pbicgsafe", x0_mode=2)
+    if Rz.iters != ref0.iters or not np.array_equal(Rz.x, ref0.x):
+        return "P17 mode 2: x0 = 0 (no factor) does not give the x0 = 0 solve"
+    return None
+
+
+def _is_f32(v):
+    return bool(np.all(v.astype(np.float32).astype(np.float64) == v))
+
+
+def check_p18(orc):
+    A = W.cd2d(32, 10.0)
+    for v in ("pbicgsafe", "pbicgsafe_rr"):
+        for i in (1, 4, 9):
+            st, res = orc.state_at(A, i, variant=v, rr_m=4, precision=3)
+            if res.status != O.MAXIT:
+                return f"P18 {v} i={i}: status {res.status}"
+            for name in ("p", "u", "z"):
+                if not _is_f32(st.vec(name)):
+                    return f"P18 {v} i={i}: {name} is not held in FP32"
+            for name in ("x", "r", "s", "y", "w"):
+                if _is_f32(st.vec(name)):
+                    return f"P18 {v} i={i}: {name} is rounded as well"
+    Ibig = W.identity(64, seed=5)
+    I32 = W.CSR(Ibig.n, Ibig.rowptr, Ibig.col, Ibig.val, Ibig.b.astype(np.float32).astype(np.float64))
+    for v in ("pbicgsafe", "pbicgsafe_rr"):
+        R2 = orc.solve(I32, tol=1e-12, maxit=20, variant=v, precision=2)
+        R3 = orc.solve(I32, tol=1e-12, maxit=20, variant=v, precision=3)
+        if R2.iters != R3.iters or not np.array_equal(R2.x, R3.x) or not np.array_equal(R2.hist, R3.hist):
+            return f"P18 {v}: A = I differs from precision 2"
+    for B in (W.cd2d(64, 10.0), W.small_nonsym(3001, 11, density=0.003)):
+        S64 = B.to_scipy()
+        R = orc.solve(B, tol=1e-11, maxit=3000, variant="pbicgsafe_rr", rr_m=10, norm_ref=1,
+                      precision=3)
+        e = np.linalg.norm(B.b - S64 @ R.x) / np.linalg.norm(B.b)
+        if R.status != O.CONVERGED or e > 1e-10:
+            return f"P18 {B.name}: status {R.status}, FP64 residual {e:.2e}"
+    try:
+        orc.solve(A, tol=1e-8, maxit=5, variant="ssbicgsafe2", precision=3)
+        return "P18 precision 3 accepted for ssBiCGSafe2"
+    except RuntimeError:
+        pass
+    return None
+
+
 CHECKS = [check_p1, check_p2, check_p3, check_p4, check_p5, check_p6, check_p7, check_p8, check_p11,
-          check_p12, check_p13, check_p14, check_p15, check_p16]
+          check_p12, check_p13, check_p13b, check_p14, check_p15, check_p16, check_p16b, check_p17,
+          check_p18]
 
 
 # --------------------------------------------------------------------------- tests
@@ -492,3 +689,25 @@ def test_spmv_matches_scipy(orc):
         y = orc.spmv(A, x)
         ref = A.to_scipy() @ x
         assert np.allclose(y, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_thread_count_changes_nothing(orc):
+    """Rows, vector statements and exact inner products are order-free: a solve with one
+    thread and with several (the threaded paths start at 32768 rows) is bit-identical."""
+    A = W.rand_band(60_000, seed=7, band=500)
+    res = []
+    for th in (1, 4):
+        orc.set_threads(th)
+        try:
+            res.append(orc.solve(A, tol=1e-10, maxit=25, variant="pbicgsafe_rr", rr_m=10))
+        finally:
+            orc.set_threads(1)
+    a, b = res
+    assert a.iters == b.iters and np.array_equal(a.x, b.x) and np.array_equal(a.hist, b.hist)
+    x = np.random.default_rng(3).standard_normal(A.n)
+    orc.set_threads(4)
+    try:
+        y4, d4 = orc.spmv(A, x), orc.dot(x, A.b)
+    finally:
+        orc.set_threads(1)
+    assert np.array_equal(orc.spmv(A, x), y4) and orc.dot(x, A.b) == d4
