@@ -102,7 +102,7 @@ typedef struct {
                           as its own multi-inner-product pass, concurrent with A s_i.
                           1: fused inner products -- pass A and the epilogue of A w_i of
                           iteration i also form the per-block partial sums of the nine
-                          inner products of iteration i+1 (Section 4: (y,y), (y,r),
+                          inner products of iteration i+1 (Algorithms 3-5: (y,y), (y,r),
                           (r0*,r), (r0*,t), (r,r) from pass A; (s,s), (s,y), (s,r),
                           (r0*,s) from the epilogue), so that only their final sums and
                           the coefficients remain, concurrent with A s_{i+1}.  Reads
@@ -115,10 +115,17 @@ typedef struct {
                           Batches: each system's partial sums are added by a workgroup
                           of its own.  Results are bit-identical to schedule 0.  Other
                           variants: 1 and 2 are PS_EINVAL.                              */
-  int32_t x0_fallback; /* 1: if x0 is given and ||b - A x0|| > ||b|| (or is not finite),
-                          start from x0 = 0 instead (per system for a batch); a guess
-                          that is worse than zero costs nothing then.  0 (default): use
-                          x0 as given.                                                 */
+  int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).
+                          0 (default): use it as given.
+                          1: if ||b - A x0|| > ||b|| (or is not finite), start from
+                          x0 = 0 instead: a guess that is worse than zero costs nothing.
+                          2: first replace x0 by c x0, c = (A x0, b) / (A x0, A x0), the
+                          multiple with the least residual ||b - c A x0|| (<= ||b|| in
+                          exact arithmetic; x0 = 0 when c cannot be formed), then the
+                          rule of 1.  The inner products are rounded once from their
+                          exact values.  The set-up's residual statements (x0 of
+                          Algorithms 3-5) decide; r_0 = b - A x0 of the guess used.
+                          Other values: PS_EINVAL.                                     */
   int32_t precision;   /* ps_precision: the matrix values the products read.
                           PS_PREC_FP64 (default): the FP64 values.  PS_PREC_FP32_MATRIX:
                           every product reads the values rounded to the nearest FP32
@@ -188,10 +195,12 @@ typedef struct {
 
 /* classes of kernels, for ps_options.profile and ps_kernel_stats */
 enum ps_kernel {
-  PS_K_SPMV = 0,        /* sparse product with no fused work (A s_i, A z_i, ...)        */
+  PS_K_SPMV = 0,        /* sparse product with no fused work (A s_i, A z_i, and the
+                           products A o, A u, A t, A y, A r of a replacement step)       */
   PS_K_DOTS = 1,        /* multi-inner-product kernel (per-block partial sums)          */
   PS_K_UPDATE = 2,      /* fused vector-update pass                                      */
-  PS_K_SPMV_FUSED = 3,  /* sparse product with a fused update epilogue                   */
+  PS_K_SPMV_FUSED = 3,  /* sparse product with a fused update epilogue (A w_i, A u_i,
+                           and b - A x of a replacement step)                            */
   PS_K_OTHER = 4,       /* set-up, replacement and bookkeeping kernels                   */
   PS_K_DOTS_FINISH = 5, /* one-block finish: final sums, coefficients, stop test         */
   PS_K_COUNT = 6
@@ -400,6 +409,11 @@ int ps_matrix_info(ps_matrix *A, ps_info *info);
    each launch on its own stream.  Only launches of iterations before the
    stopping one are counted (later launches may be no-ops). */
 int ps_kernel_stats(ps_matrix *A, int32_t cls, double *total_ms, int64_t *launches);
+
+/* Of the launches ps_kernel_stats counts for class `cls`, how many were enqueued
+   on the library's second stream (the reduction phases that run concurrently
+   with a sparse product, Section 3; ps_options.overlap).  HOST *aux_launches. */
+int ps_kernel_streams(ps_matrix *A, int32_t cls, int64_t *aux_launches);
 
 /* Device copy dst = src of `bytes` bytes (DEVICE pointers, 16-byte aligned,
    bytes a multiple of 16) with a plain streaming kernel of the library's own;

@@ -27,6 +27,8 @@ enum Ctl : int {
 // double scalar block on the device: the public ps_scalar slots, then private ones
 enum Sc : int {
   SC_DOTS = 16,      // raw inner products of the last reduction phase (up to 9)
+  SC_SCALE = 28,     // least-residual factor c of the initial guess (x0_fallback = 2)
+  SC_SCALE_OK = 29,  // 1: c could be formed; 0: the scaled guess is zero
   SC_FALLBACK = 30,  // 1: the initial guess was worse than zero and has been replaced
   SC_COUNT = 32
 };

@@ -120,6 +120,16 @@ struct ProdFallback {
   }
 };
 
+// (A x0, b) and (A x0, A x0) of an initial guess (inputs v = {A x0, b})
+struct ProdScale {
+  static constexpr unsigned MASK = 0b11u;
+  static constexpr int ND = 2;
+  __device__ __forceinline__ static void acc(const double (&in)[5], TD (&a)[ND]) {
+    td_fma(a[0], in[0], in[1]);
+    td_fma(a[1], in[0], in[0]);
+  }
+};
+
 // (v, v): the squared norm of b for the ||b|| stop-test scale
 struct ProdNorm {
   static constexpr unsigned MASK = 0b1u;
@@ -305,6 +315,18 @@ struct FinStabSetup {
 struct FinFallback {
   __device__ static void run(const DotArgs &A, const double (&d)[2]) {
     A.sc[SC_FALLBACK] = (d[0] <= d[1]) ? 0.0 : 1.0;
+  }
+};
+
+// The multiple c x0 of an initial guess with the least residual ||b - c A x0||:
+// c = (A x0, b) / (A x0, A x0); when that cannot be formed (A x0 = 0, or a
+// non-finite value) the scaled guess is zero.
+struct FinScale {
+  __device__ static void run(const DotArgs &A, const double (&d)[2]) {
+    const double c = d[0] / d[1];
+    const bool ok = d[1] != 0.0 && isfinite(c);
+    A.sc[SC_SCALE] = ok ? c : 0.0;
+    A.sc[SC_SCALE_OK] = ok ? 1.0 : 0.0;
   }
 };
 

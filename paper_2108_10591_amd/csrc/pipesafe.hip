@@ -72,6 +72,7 @@ struct Timer {
   hipEvent_t a, b;
   int cls;
   int iter;  // iteration the launch belongs to (-1: set-up)
+  bool aux;  // enqueued on the second (reduction) stream
 };
 
 // Everything a captured batch of iterations depends on.
@@ -156,6 +157,7 @@ struct ps_matrix {
   std::vector<Timer> timers;
   double prof_ms[PS_K_COUNT] = {};
   int64_t prof_cnt[PS_K_COUNT] = {};
+  int64_t prof_aux[PS_K_COUNT] = {};     // of those, launches on the second stream
 
   double *slot(int s) const { return vec + (size_t)s * ld; }
   int *running() const { return ctl + (size_t)nsys * C_COUNT; }
@@ -236,7 +238,7 @@ int launch(ps_matrix *M, hipStream_t s, int cls, Kernel kernel, dim3 grid, size_
   hipEvent_t a = nullptr, b = nullptr;
   if (next_event(M, &a) || next_event(M, &b)) return PS_EHIP;
   hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), (uint32_t)shmem, s, a, b, 0u, args...);
-  M->timers.push_back(Timer{a, b, cls, M->cur_iter});
+  M->timers.push_back(Timer{a, b, cls, M->cur_iter, s == M->aux && s != nullptr});
   return PS_OK;
 }
 
@@ -354,6 +356,7 @@ struct Plan {
   bool fused;     // fused-dot schedule (p-BiCGSafe): schedule 1 or 2
   bool fused2;    // schedule 2: every update but w_i in the epilogue of A w_i
   bool fallback;  // replace an initial guess that is worse than zero
+  bool scale;     // first scale the guess to its least residual (x0_fallback = 2)
   bool stream_nt; // streaming (nontemporal) loads and stores in the update passes
   int precision;  // 0 FP64; 1 FP32 values in every product; 2 FP32 in the Krylov products
   bool kry32;     // the Krylov products read the FP32 values
@@ -372,6 +375,15 @@ int enqueue_setup(ps_matrix *M, const Plan &P) {
   } else {
     PS_TRY(zero_slots(M, s, {PS_V_Y, PS_V_T, PS_V_P, PS_V_U, PS_V_Z, PS_V_W, PS_V_L, PS_V_G,
                              PS_V_Q, PS_V_O, PS_V_AS, PS_V_V}));
+  }
+  if (P.scale) {
+    // c = (A x0, b) / (A x0, A x0), x0 = c x0 (a residual statement: FP64 values
+    // unless every product reads the rounded ones)
+    double *Ax = M->slot(kSlotTmp);
+    PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiStore{Ax}, -1, P.res32));
+    PS_TRY(dots<ProdScale, FinScale>(M, s, {Ax, Bv}, P.maxit, P.tol, 0, M->hist));
+    PS_TRY(launch(M, s, PS_K_OTHER, k_scale_x, elem_grid(M->n), 0, X, (const double *)M->sc,
+                  (const int *)M->chunk_sys, M->n));
   }
   PS_TRY(spmv(M, s, PS_K_OTHER, X, EpiResidual{Bv, R, RS}, -1, P.res32));
   if (P.fallback) {
@@ -526,15 +538,15 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n, next_rev(M)};
   po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_OTHER, k_pou, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_OTHER, O, EpiStore{Q}, C_DONE, P.kry32));  // q_i = A o_i
-  PS_TRY(spmv(M, A, PS_K_OTHER, U, EpiStore{W}, C_DONE, P.kry32));  // w_i = A u_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, O, EpiStore{Q}, C_DONE, P.kry32));  // q_i = A o_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, U, EpiStore{W}, C_DONE, P.kry32));  // w_i = A u_i
   TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n, next_rev(M)};
   tz.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_OTHER, k_tzyx, pair_grid(M->n), 0, tz));
-  PS_TRY(spmv(M, A, PS_K_OTHER, X, EpiResidual{Bv, R, nullptr}, C_DONE, P.res32));  // b - A x_{i+1}
-  PS_TRY(spmv(M, A, PS_K_OTHER, T, EpiStore{L}, C_DONE, P.kry32));  // l_i = A t_i
-  PS_TRY(spmv(M, A, PS_K_OTHER, Y, EpiStore{G}, C_DONE, P.kry32));  // g_{i+1} = A y_{i+1}
-  PS_TRY(spmv(M, A, PS_K_OTHER, R, EpiStore{S}, C_DONE, P.kry32));  // s_{i+1} = A r_{i+1}
+  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, X, EpiResidual{Bv, R, nullptr}, C_DONE, P.res32));  // b - A x_{i+1}
+  PS_TRY(spmv(M, A, PS_K_SPMV, T, EpiStore{L}, C_DONE, P.kry32));  // l_i = A t_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, Y, EpiStore{G}, C_DONE, P.kry32));  // g_{i+1} = A y_{i+1}
+  PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, C_DONE, P.kry32));  // s_{i+1} = A r_{i+1}
   return PS_OK;
 }
 
@@ -692,6 +704,7 @@ int collect_profile(ps_matrix *M, int stop_iter) {
   for (int c = 0; c < PS_K_COUNT; ++c) {
     M->prof_ms[c] = 0.0;
     M->prof_cnt[c] = 0;
+    M->prof_aux[c] = 0;
   }
   for (const Timer &t : M->timers) {
     if (t.iter < 0 || t.iter >= stop_iter) continue;
@@ -699,6 +712,7 @@ int collect_profile(ps_matrix *M, int stop_iter) {
     PS_HIP(hipEventElapsedTime(&ms, t.a, t.b));
     M->prof_ms[t.cls] += ms;
     M->prof_cnt[t.cls] += 1;
+    M->prof_aux[t.cls] += t.aux ? 1 : 0;
   }
   M->timers.clear();
   M->ev_used = 0;
@@ -748,6 +762,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool batch = M->nsys > 1;
   if (!o.resume && !b) return PS_EINVAL;
   if (o.norm_ref != 0 && o.norm_ref != 1) return PS_EINVAL;
+  if (o.x0_fallback < 0 || o.x0_fallback > 2) return PS_EINVAL;
   if (o.resume && (batch || o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
   const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
   if (o.schedule < -1 || o.schedule > 2 || (o.schedule >= 1 && !safe_pipelined))
@@ -785,6 +800,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.overlap = want_overlap && variant != PS_SSBICGSAFE2;
   P.B = P.overlap ? M->aux : P.A;
   P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
+  P.scale = o.x0_fallback == 2 && x0 != nullptr && !P.resume;
   const int sched = o.schedule >= 0 ? o.schedule : auto_schedule(M);
   P.fused = safe_pipelined && sched >= 1;
   P.fused2 = P.fused && sched == 2;
@@ -1524,6 +1540,12 @@ int ps_kernel_stats(ps_matrix *A, int32_t cls, double *total_ms, int64_t *launch
   if (!A || cls < 0 || cls >= PS_K_COUNT || !total_ms || !launches) return PS_EINVAL;
   *total_ms = A->prof_ms[cls];
   *launches = A->prof_cnt[cls];
+  return PS_OK;
+}
+
+int ps_kernel_streams(ps_matrix *A, int32_t cls, int64_t *aux_launches) {
+  if (!A || cls < 0 || cls >= PS_K_COUNT || !aux_launches) return PS_EINVAL;
+  *aux_launches = A->prof_aux[cls];
   return PS_OK;
 }
 

@@ -475,6 +475,16 @@ __global__ __launch_bounds__(kBlock) void k_fallback(double *__restrict__ x, dou
   }
 }
 
+// x0 = c x0 with each system's least-residual factor (FinScale), or 0
+__global__ __launch_bounds__(kBlock) void k_scale_x(double *__restrict__ x,
+                                                    const double *__restrict__ sc,
+                                                    const int *__restrict__ chunk_sys, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const double *s = sc + (size_t)system_of(chunk_sys, k) * SC_COUNT;
+  x[k] = s[SC_SCALE_OK] != 0.0 ? s[SC_SCALE] * x[k] : 0.0;
+}
+
 // control blocks of `nsys` systems, then the count of systems still running
 __global__ __launch_bounds__(kBlock) void k_init_ctl(int *ctl, int first_iter, int nsys) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;

@@ -115,6 +115,7 @@ def _lib():
         L.ps_get_scalars.argtypes = [P, P]
         L.ps_set_scalars.argtypes = [P, P]
         L.ps_kernel_stats.argtypes = [P, i32, Pf64, Pi64]
+        L.ps_kernel_streams.argtypes = [P, i32, Pi64]
         L.ps_matrix_info.argtypes = [P, ctypes.POINTER(Info)]
         L.ps_stream_copy.argtypes = [P, P, i64, P]
         L.ps_destroy.argtypes = [P]
@@ -130,7 +131,8 @@ def _lib():
         L.ps_version.restype = ctypes.c_char_p
         for name in ("ps_create", "ps_create_batch", "ps_solve_batch", "ps_solve_batch_dev",
                      "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
-                     "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats", "ps_matrix_info",
+                     "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats",
+                     "ps_kernel_streams", "ps_matrix_info",
                      "ps_stream_copy", "ps_destroy", "ps_create_ex", "ps_create_batch_ex",
                      "ps_autotune_layout", "ps_tune_options"):
             getattr(L, name).restype = ctypes.c_int
@@ -265,6 +267,9 @@ class Matrix:
         """Solve with torch CUDA tensors b, x0 (or None), x (allocated if None), float64.
 
         Work is ordered on ``stream`` (default: torch's current stream)."""
+        return self._solve_dev("ps_solve_dev", b, x0, x, tol, maxit, variant, hist, stream, opt)
+
+    def _solve_dev(self, entry, b, x0, x, tol, maxit, variant, hist, stream, opt):
         import torch
         for t in (b, x0, x):
             if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
@@ -277,12 +282,12 @@ class Matrix:
         h = np.empty(maxit + 1) if hist else None
         iters, status = ctypes.c_int32(), ctypes.c_int32()
         o = options(stream=stream, **opt)
-        _check(_lib().ps_solve_dev(self._h, ctypes.c_void_p(b.data_ptr()),
-                                   None if x0 is None else ctypes.c_void_p(x0.data_ptr()),
-                                   float(tol), int(maxit), _vid(variant), ctypes.byref(o),
-                                   ctypes.c_void_p(x.data_ptr()), ctypes.byref(iters),
-                                   None if h is None else _ptr(h), ctypes.byref(status)),
-               "ps_solve_dev")
+        _check(getattr(_lib(), entry)(self._h, ctypes.c_void_p(b.data_ptr()),
+                                      None if x0 is None else ctypes.c_void_p(x0.data_ptr()),
+                                      float(tol), int(maxit), _vid(variant), ctypes.byref(o),
+                                      ctypes.c_void_p(x.data_ptr()), ctypes.byref(iters),
+                                      None if h is None else _ptr(h), ctypes.byref(status)),
+               entry)
         it = iters.value
         return SolveResult(x, it, status.value, h[: it + 1] if h is not None else None)
 
@@ -336,6 +341,15 @@ class Matrix:
             _check(_lib().ps_kernel_stats(self._h, c, ctypes.byref(ms), ctypes.byref(cnt)),
                    "ps_kernel_stats")
             out[name] = (ms.value, cnt.value)
+        return out
+
+    def kernel_streams(self) -> dict:
+        """{class: launches on the second stream} of the last profiled solve."""
+        out = {}
+        for name, c in KERNEL_CLASSES.items():
+            cnt = ctypes.c_int64()
+            _check(_lib().ps_kernel_streams(self._h, c, ctypes.byref(cnt)), "ps_kernel_streams")
+            out[name] = cnt.value
         return out
 
 

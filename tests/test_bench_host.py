@@ -44,3 +44,27 @@ def test_more_than_one_gpu_exits_with_a_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_batch_bytes_use_the_layout_that_ran():
+    """A system's share of a batch iteration: rows padded to 512, entries at the layout's
+    bytes per slot and padding ratio (not the CSR int32 estimate)."""
+    from paper_2108_10591_amd import workloads as W
+    A = W.cd2d(40, 10.0)  # 1600 rows -> 2048 padded
+    sell = {"format": "sell", "index_bits": 16, "slots": 2 * 1000, "nnz": 1000, "gather_sort": 0}
+    got = bench.batch_bytes_per_iteration(sell, A, 2)
+    assert got == 2 * (10 * 2 * A.nnz + 4 * (2048 / 64 + 1)) + 248 * 2048
+    csr = {"format": "csr", "index_bits": 32, "slots": 1000, "nnz": 1000, "gather_sort": 1}
+    got = bench.batch_bytes_per_iteration(csr, A, 0)
+    assert got == 2 * (14 * A.nnz + 4 * (2048 + 1)) + 280 * 2048
+
+
+def test_cpu_baseline_reports_both_legs_and_the_host():
+    from paper_2108_10591_amd import workloads as W
+    A = W.cd2d(32, 10.0)
+    r = bench.cpu_baseline(A, 3, 5)
+    assert r["kind"] == "oracle" and r["unit"] == "GB/s" and r["value"] > 0
+    assert r["one_core"]["threads"] == 1 and r["one_core"]["iterations"] == 3
+    assert r["all_cores"]["iterations"] == 5 and r["cores"] == r["all_cores"]["threads"] >= 1
+    assert r["nproc"] == os.cpu_count() and "cpu_model" in r
+    assert r["bytes_per_iteration"] == 2 * (12 * A.nnz + 4 * (A.n + 1)) + 288 * A.n
