@@ -65,7 +65,8 @@ enum ps_error {
   PS_ENOMEM = -2, /* device or host allocation failed                                 */
   PS_EHIP = -3,   /* a HIP runtime call failed                                        */
   PS_EBUSY = -4,  /* the handle is in use by another thread                           */
-  PS_ENODEV = -5  /* no usable gfx950 device                                          */
+  PS_ENODEV = -5, /* no usable gfx950 device                                          */
+  PS_ETOOBIG = -6 /* the solve does not fit the static workspace (ps_solve_dev_static)   */
 };
 
 typedef struct {
@@ -353,6 +354,30 @@ int ps_solve(ps_matrix *A, const double *b, const double *x0, double tol, int32_
 int ps_solve_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol, int32_t maxit,
                  int32_t variant, const ps_options *opt, double *x_dev, int32_t *iters,
                  double *hist, int32_t *status);
+
+/*
+ * ps_solve_dev for callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid hipMalloc): same arguments and results, bit for bit,
+ * but the call allocates nothing.  The solve's scalar and control blocks,
+ * inner-product partial sums and residual history live in a static device
+ * workspace of 4 MiB (524,288 doubles) that each GPU holds for the life of the
+ * process; the handle's vectors and matrix were allocated by ps_create.
+ * Limits: it needs 32 + 32 + 27 G + 3 (5 max(ceil(n/512), P) + 4 P + 9 F) +
+ * maxit + 2 doubles (each term rounded up to a multiple of 32), where G, P, F
+ * are ps_info.dot_grid, ps_info.spmv_blocks and ceil(max(ceil(n/512), P)/256)
+ * -- about 0.11 n + maxit doubles on the sliced layout (2.1M rows with maxit =
+ * 10000 fit); beyond that PS_ETOOBIG.  PS_EINVAL also for a batch handle, for
+ * opt->resume or opt->profile set, and for a mixed precision before the handle's
+ * FP32 values exist (the first mixed-precision ps_solve* makes them).  Batches
+ * of iterations are launched directly (opt->graph is ignored).  Every call on a
+ * GPU uses that GPU's one workspace: calls that overlap in time on one GPU (from
+ * several threads, or on streams that run concurrently) race and must not be
+ * made.  ps_get_scalars after this call returns the scalars of the handle's last
+ * other solve, not this one's.
+ */
+int ps_solve_dev_static(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol,
+                        int32_t maxit, int32_t variant, const ps_options *opt, double *x_dev,
+                        int32_t *iters, double *hist, int32_t *status);
 
 /*
  * Batched systems: nsys independent systems A_k x_k = b_k given as one

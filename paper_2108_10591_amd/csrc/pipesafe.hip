@@ -32,6 +32,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "pipesafe.h"
@@ -95,6 +96,14 @@ struct GraphEntry {
 };
 
 }  // namespace
+
+// Static workspace of ps_solve_dev_static (callers that cannot allocate): the
+// scalar and control blocks, inner-product partial sums and the residual
+// history of one solve.  Each GPU the library runs on holds its own copy for
+// the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (static_workspace()).
+constexpr size_t kScratchDoubles = (size_t)1 << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 struct ps_matrix {
   int device = -1;
@@ -247,6 +256,25 @@ int launch(ps_matrix *M, hipStream_t s, int cls, Kernel kernel, dim3 grid, size_
     int rc_ = (__VA_ARGS__);        \
     if (rc_ != PS_OK) return rc_;   \
   } while (0)
+
+// The device address of `scratch` on device `dev` (which must be current),
+// looked up once per device and kept.
+constexpr int kMaxDevices = 64;
+double *g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int static_workspace(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return PS_ENODEV;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *addr = nullptr;
+    PS_HIP(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+    if (!addr) return PS_EHIP;
+    g_scratch_addr[dev] = (double *)addr;
+  }
+  *out = g_scratch_addr[dev];
+  return PS_OK;
+}
 
 dim3 pair_grid(int64_t n) { return dim3((unsigned)((n + 2 * kBlock - 1) / (2 * kBlock))); }
 dim3 elem_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); }
@@ -747,12 +775,72 @@ bool streaming(const ps_matrix *M) {
   return 2 * matrix_bytes(M) + 272 * M->n >= kStreamMinBytes;
 }
 
+// Where one solve's scalar and control blocks, inner-product partial sums and
+// history lie in a workspace of `total` doubles (ps_solve_dev_static); every
+// region starts on a 256-byte boundary.
+struct WorkspaceLayout {
+  size_t sc, ctl, partials, fpart, hist, total;
+};
+size_t round32(size_t v) { return (v + 31) / 32 * 32; }
+WorkspaceLayout workspace_layout(const ps_matrix *M, int32_t maxit) {
+  WorkspaceLayout L;
+  size_t at = 0;
+  L.sc = at;
+  at += round32((size_t)M->nsys * SC_COUNT);
+  L.ctl = at;
+  at += round32((((size_t)M->nsys + 1) * C_COUNT * sizeof(int) + sizeof(double) - 1) / sizeof(double));
+  L.partials = at;
+  at += round32(kPart * 9 * (size_t)M->dot_grid);
+  L.fpart = at;
+  at += round32(kPart * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk +
+                         9 * (size_t)M->gfold));
+  L.hist = at;
+  at += round32((size_t)maxit + 2);
+  L.total = at;
+  return L;
+}
+
+// For the duration of one solve, the handle's scalar and control blocks,
+// partial sums and history are those of a workspace (restored on return).
+struct WorkspaceSwap {
+  ps_matrix *M = nullptr;
+  double *sc = nullptr, *partials = nullptr, *fpart = nullptr, *hist = nullptr;
+  int *ctl = nullptr;
+  int64_t hist_cap = 0;
+  void apply(ps_matrix *M_, double *ws, const WorkspaceLayout &L) {
+    M = M_;
+    sc = M->sc;
+    partials = M->partials;
+    fpart = M->fpart;
+    hist = M->hist;
+    ctl = M->ctl;
+    hist_cap = M->hist_cap;
+    M->sc = ws + L.sc;
+    M->ctl = reinterpret_cast<int *>(ws + L.ctl);
+    M->partials = ws + L.partials;
+    M->fpart = ws + L.fpart;
+    M->hist = ws + L.hist;
+    M->hist_cap = (int64_t)(L.total - L.hist);
+  }
+  ~WorkspaceSwap() {
+    if (!M) return;
+    M->sc = sc;
+    M->ctl = ctl;
+    M->partials = partials;
+    M->fpart = fpart;
+    M->hist = hist;
+    M->hist_cap = hist_cap;
+  }
+};
+
 // One solve of every system of the handle.  iters, status: int32[nsys];
 // hist: NULL or double[nsys][maxit+1]; b, x0, x: double[n_orig] (the caller's
-// row order), on the device or the host.
+// row order), on the device or the host.  ws: NULL, or a device workspace laid
+// out by workspace_layout that replaces the handle's own blocks for this solve
+// (then nothing is allocated: no graphs, no profiling, no history growth).
 int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, double tol,
                int32_t maxit, int32_t variant, const ps_options *opt, double *x, int32_t *iters,
-               double *hist, int32_t *status) {
+               double *hist, int32_t *status, double *ws = nullptr) {
   if (!M) return PS_EINVAL;
   if (variant < PS_SSBICGSAFE2 || variant > PS_PBICGSTAB) return PS_EINVAL;
   if (maxit < 0 || !(tol >= 0.0) || !iters || !status || !x) return PS_EINVAL;
@@ -770,9 +858,12 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_KRYLOV ||
       (o.precision != PS_PREC_FP64 && !M->f32_ok))
     return PS_EINVAL;
+  if (ws && (batch || o.resume || o.profile || o.graph)) return PS_EINVAL;
   BusyGuard guard(M->busy);
   if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(M->device));
+  WorkspaceSwap swap;
+  if (ws) swap.apply(M, ws, workspace_layout(M, maxit));
 
   Plan P;
   P.variant = variant;
@@ -818,6 +909,9 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   PS_TRY(ensure_hist(M, M->hist_stride * M->nsys));
 
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (ws)  // a workspace holds the previous call's scalars: start from zero
+    PS_TRY(launch(M, P.A, PS_K_OTHER, k_zero, elem_grid((int64_t)M->nsys * SC_COUNT), 0, M->sc,
+                  (int64_t)0, 1, (int64_t)M->nsys * SC_COUNT));
   PS_TRY(launch(M, P.A, PS_K_OTHER, k_init_ctl, elem_grid((int64_t)M->nsys * C_COUNT + 1), 0,
                 M->ctl, P.i0, M->nsys));
   if (!P.resume) {
@@ -891,11 +985,19 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   PS_HIP(hipStreamSynchronize(P.A));
   if (P.overlap) PS_HIP(hipStreamSynchronize(P.B));
 
-  std::vector<int> c((size_t)M->nsys * C_COUNT);
-  PS_HIP(hipMemcpy(c.data(), M->ctl, c.size() * sizeof(int), hipMemcpyDeviceToHost));
+  // the control blocks (one system: on the stack, so that a solve into a
+  // workspace allocates nothing)
+  int c_one[C_COUNT];
+  std::vector<int> c_many;
+  int *c = c_one;
+  if (M->nsys > 1) {
+    c_many.resize((size_t)M->nsys * C_COUNT);
+    c = c_many.data();
+  }
+  PS_HIP(hipMemcpy(c, M->ctl, (size_t)M->nsys * C_COUNT * sizeof(int), hipMemcpyDeviceToHost));
   int it_max = 0;
   for (int k = 0; k < M->nsys; ++k) {
-    const int *ck = c.data() + (size_t)k * C_COUNT;
+    const int *ck = c + (size_t)k * C_COUNT;
     int st = ck[C_STATUS], it = ck[C_ITERS];
     if (!ck[C_DONE]) {  // cannot happen: the finish at the last iteration always stops
       st = PS_MAXIT;
@@ -1475,6 +1577,27 @@ int ps_solve_batch_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, 
   return solve_impl(A, b_dev, x0_dev, true, tol, maxit, variant, opt, x_dev, iters, hist, status);
 }
 
+int ps_solve_dev_static(ps_matrix *A, const double *b_dev, const double *x0_dev, double tol,
+                        int32_t maxit, int32_t variant, const ps_options *opt, double *x_dev,
+                        int32_t *iters, double *hist, int32_t *status) {
+  if (!A || A->nsys > 1 || maxit < 0) return PS_EINVAL;
+  ps_options o;
+  ps_default_options(&o);
+  if (opt) o = *opt;
+  if (o.resume || o.profile) return PS_EINVAL;
+  o.graph = 0;  // instantiating a graph allocates
+  // the FP32 copy of the values is made (allocated) by the first mixed-precision ps_solve*
+  if (o.precision != PS_PREC_FP64 &&
+      (A->format == PS_FMT_CSR ? A->val32 == nullptr : A->sval32 == nullptr))
+    return PS_EINVAL;
+  if (workspace_layout(A, maxit).total > kScratchDoubles) return PS_ETOOBIG;
+  PS_HIP(hipSetDevice(A->device));
+  double *ws = nullptr;
+  PS_TRY(static_workspace(A->device, &ws));
+  return solve_impl(A, b_dev, x0_dev, true, tol, maxit, variant, &o, x_dev, iters, hist, status,
+                    ws);
+}
+
 int ps_spmv_dev(ps_matrix *A, const double *x_dev, double *y_dev, void *stream) {
   if (!A || !x_dev || !y_dev || A->nsys > 1) return PS_EINVAL;
   BusyGuard guard(A->busy);
@@ -1579,6 +1702,7 @@ const char *ps_strerror(int code) {
     case PS_EHIP: return "HIP runtime error";
     case PS_EBUSY: return "handle in use by another thread";
     case PS_ENODEV: return "no usable gfx950 device";
+    case PS_ETOOBIG: return "the solve does not fit the static workspace of ps_solve_dev_static";
     default: return "unknown code";
   }
 }

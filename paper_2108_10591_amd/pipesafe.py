@@ -106,6 +106,7 @@ def _lib():
         L.ps_create.argtypes = [ctypes.POINTER(P), i64, i64, P, P, P]
         L.ps_solve.argtypes = [P, P, P, f64, i32, i32, ctypes.POINTER(Options), P, Pi32, P, Pi32]
         L.ps_solve_dev.argtypes = L.ps_solve.argtypes
+        L.ps_solve_dev_static.argtypes = L.ps_solve.argtypes
         L.ps_create_batch.argtypes = [ctypes.POINTER(P), i32, P, i64, i64, P, P, P]
         L.ps_solve_batch.argtypes = [P, P, P, f64, i32, i32, ctypes.POINTER(Options), P, P, P, P]
         L.ps_solve_batch_dev.argtypes = L.ps_solve_batch.argtypes
@@ -130,7 +131,7 @@ def _lib():
         L.ps_strerror.restype = ctypes.c_char_p
         L.ps_version.restype = ctypes.c_char_p
         for name in ("ps_create", "ps_create_batch", "ps_solve_batch", "ps_solve_batch_dev",
-                     "ps_solve", "ps_solve_dev", "ps_spmv_dev", "ps_get_state",
+                     "ps_solve", "ps_solve_dev", "ps_solve_dev_static", "ps_spmv_dev", "ps_get_state",
                      "ps_set_state", "ps_get_scalars", "ps_set_scalars", "ps_kernel_stats",
                      "ps_kernel_streams", "ps_matrix_info",
                      "ps_stream_copy", "ps_destroy", "ps_create_ex", "ps_create_batch_ex",
@@ -268,6 +269,14 @@ class Matrix:
 
         Work is ordered on ``stream`` (default: torch's current stream)."""
         return self._solve_dev("ps_solve_dev", b, x0, x, tol, maxit, variant, hist, stream, opt)
+
+    def solve_dev_static(self, b, x0=None, x=None, tol=1e-8, maxit=10_000, variant="pbicgsafe",
+                         hist=True, stream=None, **opt):
+        """solve_dev through ps_solve_dev_static: the library allocates nothing during the call
+        (its per-solve blocks live in a static device workspace; x must be given for a caller
+        that cannot allocate either)."""
+        return self._solve_dev("ps_solve_dev_static", b, x0, x, tol, maxit, variant, hist, stream,
+                               opt)
 
     def _solve_dev(self, entry, b, x0, x, tol, maxit, variant, hist, stream, opt):
         import torch

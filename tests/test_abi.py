@@ -52,7 +52,7 @@ def test_options_defaults_and_strerror(lib):
     assert ctypes.sizeof(pipesafe.Options) == 56
     assert ctypes.sizeof(pipesafe.Info) == 80
     pipesafe.library().ps_strerror.restype = ctypes.c_char_p
-    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5):
+    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
         assert pipesafe.library().ps_strerror(code)
 
 
