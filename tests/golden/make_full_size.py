@@ -1,9 +1,13 @@
 """Write the oracle's full solves of the two large workloads to full_size_oracle.json.
 
 Calls only the CPU oracle and the seeded input generators; run from the repository
-root:  python tests/golden/make_full_size.py
+root:  python tests/golden/make_full_size.py [--only-missing]
 Each record holds the iteration count, status, the whole residual history, a
-SHA-256 of the solution's bytes and a few sampled entries.
+SHA-256 of the solution's bytes and a few sampled entries.  Keys are
+"workload/variant" for FP64 solves and "workload/variant@p<precision>" for the
+mixed-precision ones (precision 1: FP32 values in every product; 2: FP32 values
+in the Krylov products, FP64 residual statements).  --only-missing keeps the
+records already in the file and adds the others.
 """
 import hashlib
 import json
@@ -26,10 +30,12 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size_oracle
 
 def solve_one(key):
     name, variant = key.split("/")
+    variant, _, prec = variant.partition("@p")
     A = workloads.workload(name)
     tol = workloads.WORKLOADS[name]["tol"]
     t = time.time()
-    R = oracle.solve(A, tol=tol, maxit=10_000, variant=variant, rr_m=100)
+    R = oracle.solve(A, tol=tol, maxit=10_000, variant=variant, rr_m=100,
+                     precision=int(prec) if prec else 0)
     print(f"{name} {variant}: {R.iters} iterations, status {R.status}, "
           f"{time.time() - t:.0f} s", flush=True)
     return key, {
@@ -42,14 +48,24 @@ def solve_one(key):
     }
 
 
+KEYS = [f"{name}/{variant}" for name in ("cd3d_128", "rand_band_1m")
+        for variant in ("pbicgsafe", "ssbicgsafe2", "pbicgsafe_rr", "pbicgstab",
+                        "pbicgsafe@p1", "pbicgsafe_rr@p2")]
+
+
 def main():
-    out = {"source": "oracle/oracle.c via oracle.solve (FP64, inner products rounded once from "
-                     "their exact value); x0 = 0, b = A*1, maxit 10000, rr_m 100",
+    out = {"source": "oracle/oracle.c via oracle.solve (FP64 arithmetic, inner products rounded "
+                     "once from their exact value; @p1/@p2: the matrix values rounded to FP32 in "
+                     "every product / in the Krylov products); x0 = 0, b = A*1, maxit 10000, "
+                     "rr_m 100",
            "runs": {}}
-    keys = [f"{name}/{variant}" for name in ("cd3d_128", "rand_band_1m")
-            for variant in ("pbicgsafe", "ssbicgsafe2", "pbicgsafe_rr", "pbicgstab")]
-    # independent solves in parallel processes (each holds one matrix)
-    with ProcessPoolExecutor(max_workers=4) as ex:
+    keys = KEYS
+    if "--only-missing" in sys.argv and os.path.exists(OUT):
+        out["runs"] = json.load(open(OUT))["runs"]
+        keys = [k for k in KEYS if k not in out["runs"]]
+    # independent solves in parallel processes (each holds one matrix; the oracle's
+    # OpenMP threads are shared among them)
+    with ProcessPoolExecutor(max_workers=2) as ex:
         for key, rec in ex.map(solve_one, keys):
             out["runs"][key] = rec
     with open(OUT, "w") as f:

@@ -45,15 +45,22 @@ def case(request):
     M.close()
 
 
-@pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue"])
+@pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue",
+                                     "pbicgsafe@p1", "pbicgsafe_rr@p2"])
 def test_full_solve_reproduces_oracle(case, golden, variant):
+    """Every method in FP64, the fused schedules of p-BiCGSafe (the same iteration), and the
+    two mixed-precision forms the benchmark times (FP32 values in every product; FP32
+    values in the Krylov products with FP64 replacement residuals every 100 iterations),
+    in the library's automatic layout and schedule."""
     name, A, M, b = case
-    # the fused schedules of p-BiCGSafe compute the same iteration
-    variant, _, sched = variant.partition("+")
-    g = golden[f"{name}/{variant}"]
-    print(f"full size {name} {variant} {sched}", flush=True)
-    res = M.solve_dev(b, tol=g["tol"], maxit=10_000, variant=variant, rr_m=100,
-                      schedule={"fused_dots": 1, "fused_epilogue": 2}.get(sched, 0))
+    key, _, sched = variant.partition("+")
+    variant, _, prec = key.partition("@p")
+    g = golden[f"{name}/{key}"]
+    print(f"full size {name} {key} {sched}", flush=True)
+    opt = dict(schedule={"fused_dots": 1, "fused_epilogue": 2}.get(sched, 0))
+    if prec:
+        opt = dict(precision=int(prec))  # automatic schedule, as the benchmark runs it
+    res = M.solve_dev(b, tol=g["tol"], maxit=10_000, variant=variant, rr_m=100, **opt)
     x = res.x.cpu().numpy()
     # the north-star bar ...
     assert res.status == g["status"]

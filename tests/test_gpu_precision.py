@@ -152,3 +152,23 @@ def test_fp32_subnormal_and_range():
     with pipesafe.Matrix.from_csr(A) as M:
         with pytest.raises(pipesafe.PipesafeError):
             M.solve(A.b, tol=1e-10, maxit=50, variant="pbicgsafe", precision=3)
+
+
+@pytest.mark.parametrize("gather_sort", [1, 0])
+def test_fp32_values_with_the_gather_ordered_csr_layout(gather_sort):
+    """FP32 values in the CSR layout whose row blocks store their entries in column order
+    (the 1M-row band's layout): a +-5000 band of 100k rows, both layouts forced, every
+    precision mode against the oracle bit for bit (FP64 values in the same layout too)."""
+    A = W.rand_band(100_000, seed=21, band=5000)
+    lay = pipesafe.layout(format="csr", gather_sort=gather_sort, spmv_shape=2)
+    with pipesafe.Matrix.from_csr(A, layout=lay) as M:
+        info = M.info()
+        assert info["format"] == "csr" and info["gather_sort"] == gather_sort
+        assert info["index_bits"] == 16
+        for variant, prec, m in (("pbicgsafe", 1, 100), ("pbicgsafe_rr", 2, 25), ("pbicgsafe", 0, 100)):
+            for sched in (0, 2):
+                say(f"gather order {gather_sort}: {variant} precision {prec} schedule {sched}")
+                ref = O.solve(A, tol=1e-10, maxit=3000, variant=variant, rr_m=m, precision=prec)
+                res = M.solve(A.b, tol=1e-10, maxit=3000, variant=variant, rr_m=m, precision=prec,
+                              schedule=sched)
+                assert_same(res, ref, (variant, prec, sched))
