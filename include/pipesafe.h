@@ -138,8 +138,9 @@ typedef struct {
                           PS_PBICGSAFE_RR the replacement steps re-anchor the iteration
                           to the FP64 system (a solve that stops before its first
                           replacement is only as accurate as the rounded matrix).
-                          Vectors, inner products, coefficients and x are FP64 in every
-                          mode.  The FP32 copy is made on the device at the first such
+                          Vectors, inner products, coefficients and x are FP64 in these
+                          modes (PS_PREC_FP32_VECTORS below also stores p, u, z in FP32).
+                          The FP32 copy is made on the device at the first such
                           solve (4 bytes per stored value) and kept; a value beyond the
                           FP32 range makes these modes PS_EINVAL.                      */
   void *stream;        /* hipStream_t on which the solve orders its work (e.g. the
@@ -151,7 +152,14 @@ typedef struct {
 enum ps_precision {
   PS_PREC_FP64 = 0,
   PS_PREC_FP32_MATRIX = 1,
-  PS_PREC_FP32_KRYLOV = 2
+  PS_PREC_FP32_KRYLOV = 2,
+  PS_PREC_FP32_VECTORS = 3 /* PS_PREC_FP32_KRYLOV, and the search directions p, u and the
+                              vector z of p-BiCGSafe(-rr) held as FP32 numbers: each rounded
+                              to the nearest FP32 number when formed and widened exactly
+                              when read (all arithmetic FP64); other variants: PS_EINVAL.
+                              Only the replacement steps bring the iterate back to the FP64
+                              system, so the replacement period bounds the accuracy.  The
+                              state functions convert p, u, z to and from FP64.          */
 };
 
 /* device layout of the matrix, chosen by ps_create (ps_info.format) */

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpipesafe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["pipesafe.hip", "wsnet.hip"]
+SOURCES = ["pipesafe.hip", "wsnet.hip", "layout.cpp"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -71,9 +71,9 @@ __device__ __forceinline__ void set_stop(int *ctl, int status, int iters) {
 // hist[i] = sqrt(rho)/sqrt(rhoref) and the stop test ||r_i|| <= tol ||r_ref||
 // (Algorithms 3-5; the test is taken before the coefficients are formed).
 // Returns true if the solve stops here.
-__device__ __forceinline__ bool stop_test(double rho, const double *sc, int *ctl, double *hist,
+__device__ __forceinline__ bool stop_test(double rho, double rhoref, int *ctl, double *hist,
                                           int i, int maxit, double tol) {
-  const double ref = sqrt(sc[PS_S_RHOREF]);
+  const double ref = sqrt(rhoref);
   const double nr = sqrt(rho);
   hist[i] = ref > 0.0 ? nr / ref : 0.0;
   if (nr <= tol * ref) {

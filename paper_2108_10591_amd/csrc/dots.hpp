@@ -159,13 +159,30 @@ __device__ __forceinline__ void load_in2(const DotArgs &A, int64_t k, double (&a
 }
 
 // ---------------------------------------------------------------- finishes
-// Run by one thread with the phase's final inner products.
+// Run by one thread with the phase's final inner products.  The scalars a
+// finish reads (left by earlier phases) are loaded by that thread at the start
+// of the kernel, before the partial sums, so the coefficient formulas do not
+// wait for a memory round trip each after the sums.
+struct FinPre {
+  int i;  // index of the iteration whose phase this is (C_ITER)
+  double rhoref, alpha, zeta, omega, f;
+};
+__device__ __forceinline__ FinPre fin_preload(const DotArgs &A) {
+  FinPre p;
+  p.i = A.ctl[C_ITER];
+  p.rhoref = A.sc[PS_S_RHOREF];
+  p.alpha = A.sc[PS_S_ALPHA];
+  p.zeta = A.sc[PS_S_ZETA];
+  p.omega = A.sc[PS_S_OMEGA];
+  p.f = A.sc[PS_S_F];
+  return p;
+}
 
 // Algorithms 3-5: stop test first, then beta, alpha, zeta, eta.
 struct FinSafe {
-  __device__ static void run(const DotArgs &A, const double (&d)[9]) {
+  __device__ static void run(const DotArgs &A, const FinPre &P, const double (&d)[9]) {
     double *sc = A.sc;
-    const int i = A.ctl[C_ITER];
+    const int i = P.i;
     const double a = d[0], b = d[1], c = d[2], dd = d[3], e = d[4], f = d[5], g = d[6], h = d[7],
                  rho = d[8];
     for (int j = 0; j < 9; ++j) sc[SC_DOTS + j] = d[j];
@@ -177,8 +194,9 @@ struct FinSafe {
       set_stop(A.ctl, PS_NONFINITE, i);
       return;
     }
+    const double rhoref = (A.flags & DF_SET_REF) ? rho : P.rhoref;
     if (A.flags & DF_SET_REF) sc[PS_S_RHOREF] = rho;
-    if (stop_test(rho, sc, A.ctl, A.hist, i, A.maxit, A.tol)) return;
+    if (stop_test(rho, rhoref, A.ctl, A.hist, i, A.maxit, A.tol)) return;
     double beta, alpha, zeta, eta;
     if (i == 0) {
       if (bad_den(g) || bad_den(a)) {
@@ -190,12 +208,12 @@ struct FinSafe {
       zeta = dd / a;
       eta = 0.0;
     } else {
-      const double den_beta = sc[PS_S_ZETA] * sc[PS_S_F];
+      const double den_beta = P.zeta * P.f;
       if (bad_den(den_beta)) {
         set_stop(A.ctl, PS_BREAKDOWN, i);
         return;
       }
-      beta = (sc[PS_S_ALPHA] * f) / den_beta;
+      beta = (P.alpha * f) / den_beta;
       const double den_alpha = g + beta * h;
       const double den_ze = a * b - c * c;
       if (bad_den(den_alpha) || bad_den(den_ze)) {
@@ -221,9 +239,9 @@ struct FinSafe {
 
 // p-BiCGStab phase 1: omega_i = (q, y)/(y, y); (y, y) = 0 gives omega = 0.
 struct FinStabOmega {
-  __device__ static void run(const DotArgs &A, const double (&d)[2]) {
+  __device__ static void run(const DotArgs &A, const FinPre &P, const double (&d)[2]) {
     double *sc = A.sc;
-    const int i = A.ctl[C_ITER];
+    const int i = P.i;
     sc[SC_DOTS + 0] = d[0];
     sc[SC_DOTS + 1] = d[1];
     if (!isfinite(d[0]) || !isfinite(d[1])) {
@@ -243,15 +261,15 @@ struct FinStabOmega {
 // test of iteration i+1 on rho_{i+1}.  A coefficient that cannot be formed is
 // a breakdown only if the solve does not stop there.
 struct FinStabBetaAlpha {
-  __device__ static void run(const DotArgs &A, const double (&d)[5]) {
+  __device__ static void run(const DotArgs &A, const FinPre &P, const double (&d)[5]) {
     double *sc = A.sc;
     const double f = d[0], gw = d[1], gs = d[2], gz = d[3], rho = d[4];
     for (int j = 0; j < 5; ++j) sc[SC_DOTS + j] = d[j];
-    const int i1 = A.ctl[C_ITER] + 1;
-    const double al = sc[PS_S_ALPHA], om = sc[PS_S_OMEGA];
+    const int i1 = P.i + 1;
+    const double al = P.alpha, om = P.omega;  // omega: this iteration's phase 1
     double beta = 0.0, alpha = 0.0;
     bool pend = false;
-    const double den_beta = om * sc[PS_S_F];
+    const double den_beta = om * P.f;
     if (bad_den(den_beta)) {
       pend = true;
     } else {
@@ -274,7 +292,7 @@ struct FinStabBetaAlpha {
       set_stop(A.ctl, PS_NONFINITE, i1);
       return;
     }
-    if (stop_test(rho, sc, A.ctl, A.hist, i1, A.maxit, A.tol)) return;
+    if (stop_test(rho, P.rhoref, A.ctl, A.hist, i1, A.maxit, A.tol)) return;
     if (pend) {
       set_stop(A.ctl, PS_BREAKDOWN, i1);
       return;
@@ -285,7 +303,7 @@ struct FinStabBetaAlpha {
 
 // p-BiCGStab set-up: alpha_0 = (r0*, r0)/(r0*, w0), then the stop test at i = 0.
 struct FinStabSetup {
-  __device__ static void run(const DotArgs &A, const double (&d)[3]) {
+  __device__ static void run(const DotArgs &A, const FinPre &P, const double (&d)[3]) {
     double *sc = A.sc;
     const double f = d[0], gw = d[1], rho = d[2];
     for (int j = 0; j < 3; ++j) sc[SC_DOTS + j] = d[j];
@@ -305,7 +323,8 @@ struct FinStabSetup {
       set_stop(A.ctl, PS_NONFINITE, 0);
       return;
     }
-    if (stop_test(rho, sc, A.ctl, A.hist, 0, A.maxit, A.tol)) return;
+    const double rhoref = (A.flags & DF_SET_REF) ? rho : P.rhoref;
+    if (stop_test(rho, rhoref, A.ctl, A.hist, 0, A.maxit, A.tol)) return;
     if (pend) set_stop(A.ctl, PS_BREAKDOWN, 0);
   }
 };
@@ -313,7 +332,7 @@ struct FinStabSetup {
 // Keep an initial guess only if ||b - A x0|| <= ||b|| (a non-finite residual
 // does not qualify); otherwise the set-up continues from x0 = 0.
 struct FinFallback {
-  __device__ static void run(const DotArgs &A, const double (&d)[2]) {
+  __device__ static void run(const DotArgs &A, const FinPre &, const double (&d)[2]) {
     A.sc[SC_FALLBACK] = (d[0] <= d[1]) ? 0.0 : 1.0;
   }
 };
@@ -322,7 +341,7 @@ struct FinFallback {
 // c = (A x0, b) / (A x0, A x0); when that cannot be formed (A x0 = 0, or a
 // non-finite value) the scaled guess is zero.
 struct FinScale {
-  __device__ static void run(const DotArgs &A, const double (&d)[2]) {
+  __device__ static void run(const DotArgs &A, const FinPre &, const double (&d)[2]) {
     const double c = d[0] / d[1];
     const bool ok = d[1] != 0.0 && isfinite(c);
     A.sc[SC_SCALE] = ok ? c : 0.0;
@@ -332,7 +351,7 @@ struct FinScale {
 
 // ||b||^2 as the stop-test reference
 struct FinNormRef {
-  __device__ static void run(const DotArgs &A, const double (&d)[1]) { A.sc[PS_S_RHOREF] = d[0]; }
+  __device__ static void run(const DotArgs &A, const FinPre &, const double (&d)[1]) { A.sc[PS_S_RHOREF] = d[0]; }
 };
 
 // ---------------------------------------------------------------- the kernel
@@ -372,6 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
   __shared__ double lds[kTdSlots * 9 * kPart];
   __shared__ double fin[9];
   if (A.ctl[C_DONE]) return;
+  FinPre pre{};
+  if (threadIdx.x == 0) pre = fin_preload(A);
   TD tot[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) tot[j] = TD{0.0, 0.0, 0.0};
@@ -387,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
     double d[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) d[j] = fin[j];
-    Fin::run(A, d);
+    Fin::run(A, pre, d);
     if (A.ctl[C_DONE]) atomicSub(A.running, 1);
   }
 }
@@ -405,6 +426,8 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_direct(DotArgs A,
   __shared__ double lds[kTdSlots * 9 * kPart];
   __shared__ double fin[9];
   if (A.ctl[C_DONE]) return;
+  FinPre pre{};
+  if (threadIdx.x == 0) pre = fin_preload(A);
   constexpr int kA[5] = {1, 4, 5, 7, 8};
   constexpr int kB[4] = {0, 2, 3, 6};
   TD tot[9];
@@ -425,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_direct(DotArgs A,
     double d[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) d[j] = fin[j];
-    Fin::run(A, d);
+    Fin::run(A, pre, d);
     if (A.ctl[C_DONE]) atomicSub(A.running, 1);
   }
 }
@@ -468,6 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const i
   Ak.sc += (size_t)k * SC_COUNT;
   Ak.hist += k * hist_stride;
   if (Ak.ctl[C_DONE]) return;
+  FinPre pre{};
+  if (threadIdx.x == 0) pre = fin_preload(Ak);
   TD tot[ND];
 #pragma unroll
   for (int j = 0; j < ND; ++j) tot[j] = TD{0.0, 0.0, 0.0};
@@ -483,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch(DotArgs A, const i
     double d[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) d[j] = fin[j];
-    Fin::run(Ak, d);
+    Fin::run(Ak, pre, d);
     if (Ak.ctl[C_DONE]) atomicSub(A.running, 1);
   }
 }
@@ -504,6 +529,8 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch_direct(
   Ak.sc += (size_t)k * SC_COUNT;
   Ak.hist += k * hist_stride;
   if (Ak.ctl[C_DONE]) return;
+  FinPre pre{};
+  if (threadIdx.x == 0) pre = fin_preload(Ak);
   constexpr int kA[5] = {1, 4, 5, 7, 8};
   constexpr int kB[4] = {0, 2, 3, 6};
   TD tot[9];
@@ -524,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish_batch_direct(
     double d[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) d[j] = fin[j];
-    Fin::run(Ak, d);
+    Fin::run(Ak, pre, d);
     if (Ak.ctl[C_DONE]) atomicSub(A.running, 1);
   }
 }

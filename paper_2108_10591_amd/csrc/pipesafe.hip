@@ -38,6 +38,7 @@
 #include "pipesafe.h"
 #include "device_common.hpp"
 #include "dots.hpp"
+#include "layout.hpp"
 #include "spmv.hpp"
 #include "updates.hpp"
 
@@ -128,6 +129,7 @@ struct ps_matrix {
   // the values rounded to FP32 (mixed-precision solves), made on first use
   float *val32 = nullptr, *sval32 = nullptr;
   bool f32_ok = true;                    // every value rounds to a finite FP32 number
+  bool pzu32 = false;                    // the p, u, z slots hold FP32 numbers (precision 3)
   size_t ld = 0;            // doubles between consecutive vector slots (256-byte multiple)
   double *vec = nullptr;    // kNumSlots * ld doubles
   double *sc = nullptr;     // SC_COUNT doubles
@@ -303,6 +305,9 @@ int spmv_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, 
                       M->template csr<double, int>(), x, epi, stop, rev);
 }
 
+// A product whose epilogue forms partial sums of inner products gives each
+// workgroup M->sell_chunks row blocks (one system only: a batch's workgroups
+// must not cross systems), so that its partial lists are short.
 template <class VT, class IT, class Epi>
 int sell_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, Stop stop,
                 int rev) {
@@ -389,6 +394,7 @@ struct Plan {
   int precision;  // 0 FP64; 1 FP32 values in every product; 2 FP32 in the Krylov products
   bool kry32;     // the Krylov products read the FP32 values
   bool res32;     // the residual statements (r = b - A x) read the FP32 values
+  bool vec32;     // p, u, z held as FP32 numbers (precision 3, p-BiCGSafe(-rr))
 };
 
 // r_0 = b - A x_0, r0* = r_0 and the zero vectors of each algorithm (x_0 and b
@@ -521,10 +527,15 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
       PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                    nullptr, nullptr};
       pa.chunk_sys = M->chunk_sys;
-      PS_TRY(P.stream_nt
-                 ? launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, true>, pair_grid(M->n), 0, pa)
-                 : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, false>, pair_grid(M->n), 0,
-                          pa));
+      const dim3 g = pair_grid(M->n);
+      if (P.vec32)
+        PS_TRY(P.stream_nt
+                   ? launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, true, float>, g, 0, pa)
+                   : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, false, float>, g, 0, pa));
+      else
+        PS_TRY(P.stream_nt
+                   ? launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, true>, g, 0, pa)
+                   : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<false, false>, g, 0, pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W, EpiPBiCGSafeB{As, L, G, S, M->sc}, C_DONE, P.kry32));
       return PS_OK;
     }
@@ -534,7 +545,17 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
       PassWArgs pw{As, L, G, W, M->sc, M->ctl, M->n, next_rev(M), M->chunk_sys};
       PS_TRY(launch(M, A, PS_K_UPDATE, k_pass_w, pair_grid(M->n), 0, pw));
       double *part = M->fpart, *RS = M->slot(PS_V_RS);
-      if (P.stream_nt)
+      if (P.vec32 && P.stream_nt)
+        PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                    EpiPBiCGSafeAll<true, float>{R, Pp, U, S, T, Y, Z, X, L, G, As, W, RS, M->sc,
+                                                 part},
+                    C_DONE, P.kry32));
+      else if (P.vec32)
+        PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
+                    EpiPBiCGSafeAll<false, float>{R, Pp, U, S, T, Y, Z, X, L, G, As, W, RS, M->sc,
+                                                  part},
+                    C_DONE, P.kry32));
+      else if (P.stream_nt)
         PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
                     EpiPBiCGSafeAll<true>{R, Pp, U, S, T, Y, Z, X, L, G, As, W, RS, M->sc, part},
                     C_DONE, P.kry32));
@@ -548,13 +569,21 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
     PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                  M->slot(PS_V_RS), pa_part};
     pa.chunk_sys = M->chunk_sys;
+    if (P.vec32)
+      PS_TRY(P.stream_nt
+                 ? launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, true, float>, pair_grid(M->n),
+                          0, pa)
+                 : launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, false, float>, pair_grid(M->n),
+                          0, pa));
     if (P.stream_nt) {
-      PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, true>, pair_grid(M->n), 0, pa));
+      if (!P.vec32)
+        PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, true>, pair_grid(M->n), 0, pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
                   EpiPBiCGSafeBDots<true>{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part},
                   C_DONE, P.kry32));
     } else {
-      PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, false>, pair_grid(M->n), 0, pa));
+      if (!P.vec32)
+        PS_TRY(launch(M, A, PS_K_UPDATE, k_passA_pbicgsafe<true, false>, pair_grid(M->n), 0, pa));
       PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, W,
                   EpiPBiCGSafeBDots<false>{As, L, G, S, Y, R, M->slot(PS_V_RS), M->sc, pb_part},
                   C_DONE, P.kry32));
@@ -563,14 +592,16 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   }
   // replacement step (Algorithm 5): true values of q, w, r, l, g, s
   PS_TRY(iter_safe_dots(M, P, A, i));
-  PouArgs po{R, S, T, Y, Pp, U, O, M->sc, M->ctl, M->n, next_rev(M)};
+  // (p, u held in FP32: u also widened into the scratch slot for the product)
+  double *Uw = P.vec32 ? M->slot(kSlotTmp) : U;
+  PouArgs po{R, S, T, Y, Pp, U, O, Uw, M->sc, M->ctl, M->n, next_rev(M)};
   po.chunk_sys = M->chunk_sys;
-  PS_TRY(launch(M, A, PS_K_OTHER, k_pou, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_SPMV, O, EpiStore{Q}, C_DONE, P.kry32));  // q_i = A o_i
-  PS_TRY(spmv(M, A, PS_K_SPMV, U, EpiStore{W}, C_DONE, P.kry32));  // w_i = A u_i
+  PS_TRY(launch(M, A, PS_K_OTHER, P.vec32 ? k_pou32 : k_pou, pair_grid(M->n), 0, po));
+  PS_TRY(spmv(M, A, PS_K_SPMV, O, EpiStore{Q}, C_DONE, P.kry32));   // q_i = A o_i
+  PS_TRY(spmv(M, A, PS_K_SPMV, Uw, EpiStore{W}, C_DONE, P.kry32));  // w_i = A u_i
   TzyxArgs tz{O, W, R, U, S, Pp, T, Z, Y, X, M->sc, M->ctl, M->n, next_rev(M)};
   tz.chunk_sys = M->chunk_sys;
-  PS_TRY(launch(M, A, PS_K_OTHER, k_tzyx, pair_grid(M->n), 0, tz));
+  PS_TRY(launch(M, A, PS_K_OTHER, P.vec32 ? k_tzyx32 : k_tzyx, pair_grid(M->n), 0, tz));
   PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, X, EpiResidual{Bv, R, nullptr}, C_DONE, P.res32));  // b - A x_{i+1}
   PS_TRY(spmv(M, A, PS_K_SPMV, T, EpiStore{L}, C_DONE, P.kry32));  // l_i = A t_i
   PS_TRY(spmv(M, A, PS_K_SPMV, Y, EpiStore{G}, C_DONE, P.kry32));  // g_{i+1} = A y_{i+1}
@@ -584,7 +615,7 @@ int iter_ssbicgsafe2(ps_matrix *M, const Plan &P, int i) {
          *T = M->slot(PS_V_T), *Pp = M->slot(PS_V_P), *U = M->slot(PS_V_U), *Z = M->slot(PS_V_Z);
   PS_TRY(spmv(M, A, PS_K_SPMV, R, EpiStore{S}, C_DONE, P.kry32));  // s_i = A r_i
   PS_TRY(iter_safe_dots(M, P, A, i));
-  PouArgs po{R, S, T, Y, Pp, U, nullptr, M->sc, M->ctl, M->n, next_rev(M)};
+  PouArgs po{R, S, T, Y, Pp, U, nullptr, nullptr, M->sc, M->ctl, M->n, next_rev(M)};
   po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_pu, pair_grid(M->n), 0, po));
   PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, C_DONE,
@@ -775,6 +806,27 @@ bool streaming(const ps_matrix *M) {
   return 2 * matrix_bytes(M) + 272 * M->n >= kStreamMinBytes;
 }
 
+// Put p, u, z in FP32 (to32) or FP64 storage, converting the slots that hold the
+// other one (through the scratch slot).
+int convert_pzu(ps_matrix *M, hipStream_t s, bool to32) {
+  if (M->pzu32 == to32) return PS_OK;
+  double *tmp = M->slot(kSlotTmp);
+  for (int v : {PS_V_P, PS_V_U, PS_V_Z}) {
+    double *x = M->slot(v);
+    if (to32) {
+      PS_TRY(launch(M, s, PS_K_OTHER, k_copy, elem_grid(M->n), 0, tmp, (const double *)x, M->n));
+      PS_TRY(launch(M, s, PS_K_OTHER, k_narrow, elem_grid(M->n), 0, reinterpret_cast<float *>(x),
+                    (const double *)tmp, M->n));
+    } else {
+      PS_TRY(launch(M, s, PS_K_OTHER, k_widen, elem_grid(M->n), 0, tmp,
+                    reinterpret_cast<const float *>(x), M->n));
+      PS_TRY(launch(M, s, PS_K_OTHER, k_copy, elem_grid(M->n), 0, x, (const double *)tmp, M->n));
+    }
+  }
+  M->pzu32 = to32;
+  return PS_OK;
+}
+
 // Where one solve's scalar and control blocks, inner-product partial sums and
 // history lie in a workspace of `total` doubles (ps_solve_dev_static); every
 // region starts on a 256-byte boundary.
@@ -855,8 +907,9 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
   if (o.schedule < -1 || o.schedule > 2 || (o.schedule >= 1 && !safe_pipelined))
     return PS_EINVAL;
-  if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_KRYLOV ||
-      (o.precision != PS_PREC_FP64 && !M->f32_ok))
+  if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_VECTORS ||
+      (o.precision != PS_PREC_FP64 && !M->f32_ok) ||
+      (o.precision == PS_PREC_FP32_VECTORS && !safe_pipelined))
     return PS_EINVAL;
   if (ws && (batch || o.resume || o.profile || o.graph)) return PS_EINVAL;
   BusyGuard guard(M->busy);
@@ -899,12 +952,17 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;
   P.res32 = o.precision == PS_PREC_FP32_MATRIX;
-  if (P.kry32) PS_TRY(ensure_f32(M, P.A));
+  P.vec32 = o.precision == PS_PREC_FP32_VECTORS;
   M->prof_mask = o.profile;
   M->cur_iter = -1;
   M->sweep = 0;
   M->timers.clear();
   M->ev_used = 0;
+  if (P.kry32) PS_TRY(ensure_f32(M, P.A));
+  // the storage of p, u, z: a resumed solve converts the loaded state; a fresh
+  // set-up zeroes them (zero bits are zero in either type)
+  if (P.resume) PS_TRY(convert_pzu(M, P.A, P.vec32));
+  M->pzu32 = P.vec32;
   M->hist_stride = (int64_t)maxit + 2;
   PS_TRY(ensure_hist(M, M->hist_stride * M->nsys));
 
@@ -1074,42 +1132,12 @@ void free_matrix(ps_matrix *M) {
   delete M;
 }
 
-// Cut rows into blocks of <= kBlock rows whose nonzeros fit `budget`; a row
-// longer than the budget forms a block of its own.  No block crosses one of
-// the ascending row indices in `cuts` (the systems of a batch).
-std::vector<int> row_blocks(int64_t n, const int64_t *rowptr, int budget,
-                            const std::vector<int64_t> &cuts) {
-  std::vector<int> blk;
-  blk.push_back(0);
-  int64_t r = 0;
-  size_t c = 0;
-  while (r < n) {
-    const int64_t start = r;
-    while (c < cuts.size() && cuts[c] <= start) ++c;
-    const int64_t limit = c < cuts.size() ? std::min<int64_t>(n, cuts[c]) : n;
-    int64_t nz = 0;
-    while (r < limit && r - start < kBlock) {
-      const int64_t len = rowptr[r + 1] - rowptr[r];
-      if (nz + len > budget) break;
-      nz += len;
-      ++r;
-    }
-    if (r == start) ++r;
-    blk.push_back((int)r);
-  }
-  return blk;
-}
-
-// Host-side description of a batch: the systems' padded starts and the maps
-// built from them (see ps_create_batch).
-struct BatchLayout {
-  int nsys = 1;
-  int64_t n_orig = 0;
-  std::vector<int64_t> pstart;   // [nsys+1] first padded row of each system
-  std::vector<int> row_map;      // [n_orig] padded row of each caller row
-  std::vector<int> chunk_sys;    // [n_pad/256]
-  std::vector<int> first_blk;    // [nsys+1] first 512-row workgroup of each system
-};
+// Host description of a batch: the systems padded to 512-row multiples
+// (layout.hpp).
+using BatchLayout = psl::BatchPadding;
+static_assert(psl::kRowsPerBlock == kBlock && psl::kSliceRows == kWave &&
+                  psl::kPad16 == kSellPad16 && psl::kBatchAlign == 2 * kBlock,
+              "host layouts and kernels must agree");
 
 // CSR checks shared by the create entry points
 bool valid_csr(int64_t n, int64_t nnz, const int64_t *rowptr, const int32_t *col,
@@ -1213,31 +1241,8 @@ int create_batch_impl(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, int
   if (nsys == 1) return create_impl(out, n, nnz, rowptr, col, val, nullptr, lay);
   // pad each system to a multiple of 512 rows with empty rows
   BatchLayout bl;
-  bl.nsys = nsys;
-  bl.n_orig = n;
-  bl.pstart.resize((size_t)nsys + 1, 0);
-  for (int32_t k = 0; k < nsys; ++k)
-    bl.pstart[k + 1] = bl.pstart[k] + (sys_ptr[k + 1] - sys_ptr[k] + 511) / 512 * 512;
-  const int64_t np = bl.pstart[nsys];
-  if (np >= INT32_MAX - 1) return PS_EINVAL;
-  std::vector<int64_t> prow((size_t)np + 1, 0);
-  std::vector<int32_t> pcol((size_t)std::max<int64_t>(nnz, 1));
-  bl.row_map.resize((size_t)n);
-  bl.chunk_sys.resize((size_t)(np / 256));
-  bl.first_blk.resize((size_t)nsys + 1);
-  for (int32_t k = 0; k < nsys; ++k) {
-    const int64_t shift = bl.pstart[k] - sys_ptr[k];
-    for (int64_t r = sys_ptr[k]; r < sys_ptr[k + 1]; ++r) {
-      bl.row_map[r] = (int)(r + shift);
-      prow[r + shift + 1] = rowptr[r + 1] - rowptr[r];
-      for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) pcol[e] = (int32_t)(col[e] + shift);
-    }
-    for (int64_t c = bl.pstart[k] / 256; c < bl.pstart[k + 1] / 256; ++c) bl.chunk_sys[c] = k;
-    bl.first_blk[k] = (int)(bl.pstart[k] / 512);
-  }
-  bl.first_blk[nsys] = (int)(np / 512);
-  for (int64_t r = 0; r < np; ++r) prow[r + 1] += prow[r];
-  return create_impl(out, np, nnz, prow.data(), pcol.data(), val, &bl, lay);
+  if (!psl::pad_batch(nsys, sys_ptr, n, rowptr, col, bl)) return PS_EINVAL;
+  return create_impl(out, bl.n_pad, nnz, bl.rowptr.data(), bl.col.data(), val, &bl, lay);
 }
 
 int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
@@ -1276,14 +1281,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   }
   if (lay && lay->sell_rows_per_lane > 0) M->sell_rpl = lay->sell_rows_per_lane;
   const int64_t SH = (int64_t)kWave * M->sell_rpl;  // rows per slice
-  const int64_t nslice = (n + SH - 1) / SH;
-  int64_t slots = 0;
-  for (int64_t sl = 0; sl < nslice; ++sl) {
-    int64_t w = 0;
-    for (int64_t r = sl * SH; r < std::min<int64_t>(n, (sl + 1) * SH); ++r)
-      w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
-    slots += w * SH;
-  }
+  const int64_t slots = psl::sell_slots(n, rowptr, M->sell_rpl);
   M->format = (double)slots <= kSellMaxPadding * (double)nnz + SH ? PS_FMT_SELL : PS_FMT_CSR;
   if (const char *e = std::getenv("PIPESAFE_FORMAT")) {  // tuning override
     const int v = std::atoi(e);
@@ -1291,24 +1289,18 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   }
   if (lay && lay->format >= 0) M->format = lay->format;
   if (slots >= INT32_MAX) M->format = PS_FMT_CSR;
-  std::vector<int> blk, rp32;
-  std::vector<unsigned char> rord;
-  std::vector<short> col16;
-  std::vector<unsigned short> gpos;   // CSR gather order (empty: row order)
-  std::vector<int> gcol;              // the columns and values in that order
-  std::vector<double> gval;
-  const int32_t *ccol = col;          // the CSR arrays as uploaded
-  const double *cval = val;
-  std::vector<int> scol, soff;
-  std::vector<short> scol16;
-  std::vector<double> sval;
+  // 16-bit column offsets where every entry fits (unless 32-bit columns are asked for)
+  bool want16 = true;
+  if (const char *e = std::getenv("PIPESAFE_INDEX")) {  // tuning override: 32
+    if (std::atoi(e) == 32) want16 = false;
+  }
+  if (lay && lay->index_bits == 32) want16 = false;
+  psl::CsrLayout C;   // the layout's host arrays (layout.hpp)
+  psl::SellLayout SL;
   if (M->format == PS_FMT_CSR) {
-    blk = row_blocks(n, rowptr, kIpt[M->shape] * kBlock,
-                     bl ? std::vector<int64_t>(bl->pstart.begin() + 1, bl->pstart.end())
-                        : std::vector<int64_t>());
-    M->nblk = (int)blk.size() - 1;
-    rp32.resize(n + 1);
-    for (int64_t i = 0; i <= n; ++i) rp32[i] = (int)rowptr[i];
+    const int budget = kIpt[M->shape] * kBlock;
+    const std::vector<int64_t> cuts =
+        bl ? std::vector<int64_t>(bl->pstart.begin() + 1, bl->pstart.end()) : std::vector<int64_t>();
     // multi-lane shapes sum each block's rows longest first (stable) when the
     // rows are uneven (longest above twice the mean): power-law band rows
     // 7-13% faster per product, uniform rows 3% slower (the extra index load)
@@ -1316,119 +1308,33 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     for (int64_t i = 0; i < n; ++i) maxlen = std::max<int64_t>(maxlen, rowptr[i + 1] - rowptr[i]);
     bool order = M->shape >= 2 && (double)maxlen > 2.0 * mean;
     if (const char *e = std::getenv("PIPESAFE_CSR_ORDER")) order = order && std::atoi(e) != 0;
-    if (order) {
-      rord.resize((size_t)n);
-      std::vector<int> loc;
-      for (int b = 0; b < M->nblk; ++b) {
-        loc.resize((size_t)(blk[b + 1] - blk[b]));
-        for (size_t i = 0; i < loc.size(); ++i) loc[i] = (int)i;
-        const int64_t r0 = blk[b];
-        std::stable_sort(loc.begin(), loc.end(), [&](int a, int c) {
-          return rowptr[r0 + a + 1] - rowptr[r0 + a] > rowptr[r0 + c + 1] - rowptr[r0 + c];
-        });
-        for (size_t i = 0; i < loc.size(); ++i) rord[(size_t)r0 + i] = (unsigned char)loc[i];
-      }
-    }
     // gather order: each short-row block's entries sorted by column (stable),
     // when a typical block's columns span more than the L1 holds of x (4096
     // doubles): a wave's gathers then touch a few cache lines instead of up to 64
     // (1M-row band, +-5000: product 120 -> 100 us; a +-250 band, whose gathers
     // already hit L1, 87 -> 97 us, hence the condition)
-    std::vector<int64_t> spans;
-    for (int b = 0; b < M->nblk; ++b) {
-      const int64_t k0 = rowptr[blk[b]], k1 = rowptr[blk[b + 1]];
-      if (k1 <= k0 || k1 - k0 > (int64_t)kIpt[M->shape] * kBlock) continue;
-      int cmin = col[k0], cmax = col[k0];
-      for (int64_t k = k0; k < k1; ++k) {
-        cmin = std::min(cmin, col[k]);
-        cmax = std::max(cmax, col[k]);
-      }
-      spans.push_back((int64_t)cmax - cmin + 1);
-    }
-    bool gsort = false;
-    if (!spans.empty()) {
-      std::nth_element(spans.begin(), spans.begin() + spans.size() / 2, spans.end());
-      gsort = spans[spans.size() / 2] > 4096;
-    }
+    bool gsort = psl::csr_wide_blocks(psl::row_blocks(n, rowptr, budget, cuts), rowptr, col,
+                                      budget, 4096);
     if (const char *e = std::getenv("PIPESAFE_CSR_SORT")) gsort = std::atoi(e) != 0;
     if (lay && lay->gather_sort >= 0) gsort = lay->gather_sort != 0;
+    psl::build_csr(n, rowptr, col, val, budget, cuts, order, gsort, want16, C);
+    M->nblk = (int)C.blk.size() - 1;
     M->gather_sort = gsort;
-    if (gsort) {
-      gpos.resize((size_t)std::max<int64_t>(nnz, 1));
-      gcol.assign(col, col + nnz);
-      gval.assign(val, val + nnz);
-      std::vector<int> loc;
-      for (int b = 0; b < M->nblk; ++b) {
-        const int64_t k0 = rowptr[blk[b]], k1 = rowptr[blk[b + 1]];
-        loc.resize((size_t)(k1 - k0));
-        for (size_t i = 0; i < loc.size(); ++i) loc[i] = (int)i;
-        if (k1 - k0 <= (int64_t)kIpt[M->shape] * kBlock)  // long rows keep row order
-          std::stable_sort(loc.begin(), loc.end(),
-                           [&](int a, int c) { return col[k0 + a] < col[k0 + c]; });
-        for (size_t i = 0; i < loc.size(); ++i) {
-          gpos[(size_t)k0 + i] = (unsigned short)loc[i];
-          gcol[(size_t)k0 + i] = col[k0 + loc[i]];
-          gval[(size_t)k0 + i] = val[k0 + loc[i]];
-        }
-      }
-      ccol = gcol.data();
-      cval = gval.data();
-    }
-    // 16-bit column offsets from each row block's first row when they all fit
-    bool fits16 = true;
-    for (int b = 0; b < M->nblk && fits16; ++b)
-      for (int64_t k = rowptr[blk[b]]; k < rowptr[blk[b + 1]]; ++k)
-        if (ccol[k] - blk[b] > 32767 || blk[b] - ccol[k] > 32767) {
-          fits16 = false;
-          break;
-        }
-    M->index_bits = fits16 ? 16 : 32;
-    if (const char *e = std::getenv("PIPESAFE_INDEX")) {  // tuning override: 32
-      if (std::atoi(e) == 32) M->index_bits = 32;
-    }
-    if (lay && lay->index_bits == 32) M->index_bits = 32;
-    if (M->index_bits == 16) {
-      col16.resize((size_t)nnz);
-      for (int b = 0; b < M->nblk; ++b)
-        for (int64_t k = rowptr[blk[b]]; k < rowptr[blk[b + 1]]; ++k)
-          col16[(size_t)k] = (short)(ccol[k] - blk[b]);
-    }
+    M->index_bits = C.index_bits;
   } else {
-    M->nslice = (int)nslice;
-    M->slots = slots;
+    psl::build_sell(n, rowptr, col, val, M->sell_rpl, want16, SL);
+    M->nslice = (int)SL.nslice;
+    M->slots = SL.slots;
     M->nblk = (int)((n + kBlock * M->sell_rpl - 1) / (kBlock * M->sell_rpl));
-    // 16-bit column offsets when every entry lies within 32767 of its diagonal
-    bool fits16 = true;
-    for (int64_t r = 0; r < n && fits16; ++r)
-      for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
-        if (col[k] - r > 32767 || r - col[k] > 32767) {
-          fits16 = false;
-          break;
-        }
-    M->index_bits = fits16 ? 16 : 32;
-    if (const char *e = std::getenv("PIPESAFE_INDEX")) {  // tuning override: 32
-      if (std::atoi(e) == 32) M->index_bits = 32;
-    }
-    if (lay && lay->index_bits == 32) M->index_bits = 32;
-    if (M->index_bits == 16) scol16.assign((size_t)slots, kSellPad16);
-    else scol.assign((size_t)slots, -1);
-    sval.assign((size_t)slots, 0.0);
-    soff.assign((size_t)nslice + 1, 0);
-    for (int64_t sl = 0; sl < nslice; ++sl) {
-      int64_t w = 0;
-      for (int64_t r = sl * SH; r < std::min<int64_t>(n, (sl + 1) * SH); ++r)
-        w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
-      soff[sl + 1] = (int)(soff[sl] + w * SH);
-    }
-    for (int64_t r = 0; r < n; ++r) {
-      const int64_t base = soff[r / SH] + r % SH;
-      for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
-        if (M->index_bits == 16) scol16[base + (k - rowptr[r]) * SH] = (short)(col[k] - r);
-        else scol[base + (k - rowptr[r]) * SH] = col[k];
-        sval[base + (k - rowptr[r]) * SH] = val[k];
-      }
-    }
+    M->index_bits = SL.index_bits;
   }
+  const std::vector<int> &blk = C.blk, &rp32 = C.rowptr, &scol = SL.col, &soff = SL.off;
+  const std::vector<unsigned char> &rord = C.rord;
+  const std::vector<unsigned short> &gpos = C.pos;
+  const std::vector<short> &col16 = C.col16, &scol16 = SL.col16;
+  const std::vector<double> &sval = SL.val;
+  const int32_t *ccol = C.col;  // the CSR arrays as uploaded
+  const double *cval = C.val;
   M->ld = ((size_t)n + 31) / 32 * 32;
   // batches: each system's first sparse-product workgroup (blocks never cross
   // systems: the sliced layout's 256*RPL rows divide the 512-row padding, and
@@ -1611,16 +1517,38 @@ int ps_spmv_dev(ps_matrix *A, const double *x_dev, double *y_dev, void *stream) 
   return PS_OK;
 }
 
+// the state vectors are FP64 at the interface; p, u, z of a precision-3 solve
+// are converted (exactly) on the way in and out
+bool pzu_slot(int which) { return which == PS_V_P || which == PS_V_U || which == PS_V_Z; }
+
 int ps_get_state(ps_matrix *A, int32_t which, double *host_out) {
   if (!A || !host_out || which < 0 || which >= PS_V_COUNT || A->nsys > 1) return PS_EINVAL;
+  BusyGuard guard(A->busy);
+  if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(A->device));
-  PS_HIP(hipMemcpy(host_out, A->slot(which), A->n * sizeof(double), hipMemcpyDeviceToHost));
+  const double *src = A->slot(which);
+  if (A->pzu32 && pzu_slot(which)) {
+    double *tmp = A->slot(kSlotTmp);
+    hipLaunchKernelGGL(k_widen, elem_grid(A->n), dim3(kBlock), 0, A->own, tmp,
+                       reinterpret_cast<const float *>(src), A->n);
+    PS_HIP(hipGetLastError());
+    PS_HIP(hipStreamSynchronize(A->own));
+    src = tmp;
+  }
+  PS_HIP(hipMemcpy(host_out, src, A->n * sizeof(double), hipMemcpyDeviceToHost));
   return PS_OK;
 }
 
 int ps_set_state(ps_matrix *A, int32_t which, const double *host_in) {
   if (!A || !host_in || which < 0 || which >= PS_V_COUNT || A->nsys > 1) return PS_EINVAL;
+  BusyGuard guard(A->busy);
+  if (!guard.ok) return PS_EBUSY;
   PS_HIP(hipSetDevice(A->device));
+  if (A->pzu32 && pzu_slot(which)) {
+    // the other two of p, u, z back to FP64 first: the slots share one storage state
+    PS_TRY(convert_pzu(A, A->own, false));
+    PS_HIP(hipStreamSynchronize(A->own));
+  }
   PS_HIP(hipMemcpy(A->slot(which), host_in, A->n * sizeof(double), hipMemcpyHostToDevice));
   return PS_OK;
 }

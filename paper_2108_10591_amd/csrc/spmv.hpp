@@ -95,12 +95,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
     re = A.rowptr[r + 1];
     ein = epi.load(r);
   }
-  // LPR > 1: lane j of each group finishes the group's row of round j (the group
-  // sum leaves the row's value in every lane), so it loads that row's epilogue
-  // operands here, before the products, instead of after the sum
+  // LPR > 1: the row sums are staged in LDS and thread k finishes row r0 + k, so
+  // the epilogue's loads (issued here, before the products) and stores are
+  // coalesced whatever order the rows are summed in
   if constexpr (LPR > 1) {
-    const int li = (threadIdx.x % LPR) * (kBlock / LPR) + threadIdx.x / LPR;
-    if (r0 + li < r1) ein = epi.load(r0 + (A.rord ? (int)A.rord[r0 + li] : li));
+    if (r < r1) ein = epi.load(r);
   }
   const int k0 = A.rowptr[r0], k1 = A.rowptr[r1];
   const int nz = k1 - k0;
@@ -189,8 +188,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
         put(r, acc.hi + acc.lo, ein);
       }
     } else {
+      // a block's <= kBlock rows take at most LPR rounds of kBlock / LPR groups;
+      // lane j of a group keeps the sum of its round-j row
       constexpr int kGroups = kBlock / LPR;
+      static_assert(kGroups * LPR == kBlock, "rounds of groups cover a block");
       const int g = threadIdx.x / LPR, j = threadIdx.x % LPR;
+      double mine = 0.0;
+      int mine_at = -1;
       for (int t = 0, base = 0; base < r1 - r0; ++t, base += kGroups) {  // same trip count
         const int li = base + g;
         const int rr = li < r1 - r0 ? r0 + (A.rord ? (int)A.rord[r0 + li] : li) : r1;
@@ -200,14 +204,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
           for (int k = a + j; k < e; k += LPR) sum_acc(acc, prod[k]);
         }
         group_sum_dd<LPR>(acc);
-        if (rr < r1) {
-          if (t < LPR) {
-            if (j == t) put(rr, acc.hi + acc.lo, ein);
-          } else if (j == 0) {
-            put(rr, acc.hi + acc.lo, epi.load(rr));
-          }
+        if (rr < r1 && j == t) {
+          mine = acc.hi + acc.lo;
+          mine_at = rr - r0;
         }
       }
+      __syncthreads();  // every product has been read: the row sums go where they were
+      if (mine_at >= 0) prod[mine_at] = mine;
+      __syncthreads();
+      if (r < r1) put(r, prod[threadIdx.x], ein);
     }
   }
   if constexpr (ND > 0) {
@@ -240,7 +245,7 @@ struct SellDev {
   const VT *val;      // VT[slots] (double, or float: see CsrDev)
   const int *off;     // int32[nslice+1] first slot of each slice
   int n;
-  int nblk;           // ceil(n / (kBlock * RPL)) workgroups
+  int nblk;           // ceil(n / (kBlock * RPL)) row blocks of kWavesPerBlock slices
 };
 
 // Slots per row loaded ahead of their gathers per step.
@@ -515,21 +520,44 @@ struct EpiPBiCGSafeBDots {
 };
 
 // p-BiCGSafe, fused-epilogue schedule: with w_i already formed for every row
-// (k_pass_w), the epilogue of A w_i makes all the other updates of iteration i
-// in the algorithm's order -- p_i, o_i, u_i, q_i, t_i, z_i, y_{i+1}, x_{i+1},
-// r_{i+1} (Algorithm 4; Eqs. (q), (w)), then l_i, g_{i+1}, s_{i+1} (Eqs. (l),
-// (g), (sip1)) -- and the partial sums of all nine inner products of iteration
-// i+1, written as [5][nblk] triples of (b, e, f, h, rho) followed by [4][nblk]
-// triples of (a, c, d, g): the layout k_fold_partials takes.  NT: p, u, t, z, x,
-// y, r (next read by the next such epilogue) and As (dead here) stream past the
-// cache; l, g, w and s, read by the next w pass and product, do not.
-template <bool NT>
+// (k_pass_w, Eqs. (q), (w)), the epilogue of A w_i makes all the other updates
+// of iteration i (Algorithm 4): the search directions p_i, u_i and q_i (Eq. (q),
+// formed again from the operands pass w read), the residual updates t_i, z_i,
+// y_{i+1}, x_{i+1}, r_{i+1}, then the recurrences Eqs. (l), (g), (sip1) with A w_i
+// -- and the partial sums of all nine inner products of iteration i+1, written
+// as [5][nblk] triples of (b, e, f, h, rho) followed by [4][nblk] triples of
+// (a, c, d, g): the layout k_fold_partials takes.  NT: p, u, t, z, x, y, r (next
+// read by the next such epilogue) and As (dead here) stream past the cache; l,
+// g, w and s, read by the next w pass and product, do not.  ZT: the stored type
+// of p, u, z (float: precision 3).
+template <bool NT, class ZT = double>
 struct EpiPBiCGSafeAll {
   static constexpr int kDots = 9;
   __device__ __forceinline__ EpiPBiCGSafeAll at(int sys) const {
     EpiPBiCGSafeAll e = *this;
     e.sc += (size_t)sys * SC_COUNT;
     return e;
+  }
+  // p, u, z of stored type ZT (float: held as FP32 numbers, widened on load,
+  // rounded to nearest when formed)
+  __device__ __forceinline__ static double ldz(const double *a, int k) {
+    if constexpr (sizeof(ZT) == 8) return ld(a, k);
+    const float *f = reinterpret_cast<const float *>(a);
+    if constexpr (NT) return (double)__builtin_nontemporal_load(f + k);
+    else return (double)f[k];
+  }
+  __device__ __forceinline__ static void stz(double *a, int k, double v) {
+    if constexpr (sizeof(ZT) == 8) {
+      st(a, k, v);
+    } else {
+      float *f = reinterpret_cast<float *>(a);
+      if constexpr (NT) __builtin_nontemporal_store((float)v, f + k);
+      else f[k] = (float)v;
+    }
+  }
+  __device__ __forceinline__ static double held(double v) {
+    if constexpr (sizeof(ZT) == 8) return v;
+    else return (double)(float)v;
   }
   double *r, *p, *u, *s, *t, *y, *z, *x, *l, *g;
   const double *As, *w, *rs;
@@ -547,27 +575,27 @@ struct EpiPBiCGSafeAll {
     else a[k] = v;
   }
   __device__ __forceinline__ In load(int k) const {
-    return In{ld(r, k), ld(p, k), ld(u, k), s[k], ld(t, k), ld(y, k), ld(As, k),
-              l[k],     g[k],     ld(z, k), ld(x, k), rs[k], w[k]};
+    return In{ld(r, k), ldz(p, k), ldz(u, k), s[k], ld(t, k), ld(y, k), ld(As, k),
+              l[k],     g[k],      ldz(z, k), ld(x, k), rs[k], w[k]};
   }
   __device__ __forceinline__ void store(int k, double aw, const In &in, TD (&acc)[9]) const {
     const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
-    const double pn = in.r + be * (in.p - in.u);
     const double o = in.s + be * in.t;
-    const double un = ze * o + et * (in.y + be * in.u);
+    const double pn = held(in.r + be * (in.p - in.u));
+    const double un = held(ze * o + et * (in.y + be * in.u));
     const double q = in.As + be * in.l;
     const double tn = o - in.w;
-    const double zn = ze * in.r + et * in.z - al * un;
+    const double zn = held(ze * in.r + et * in.z - al * un);
     const double yn = ze * in.s + et * in.y - al * in.w;
     const double xn = in.x + al * pn + zn;
     const double rn = in.r - al * o - yn;
     const double ln = q - aw;
     const double gn = ze * in.As + et * in.g - al * aw;
     const double sn = in.s - al * q - gn;
-    st(p, k, pn);
-    st(u, k, un);
+    stz(p, k, pn);
+    stz(u, k, un);
     st(t, k, tn);
-    st(z, k, zn);
+    stz(z, k, zn);
     st(y, k, yn);
     st(x, k, xn);
     st(r, k, rn);

@@ -59,6 +59,53 @@ __device__ __forceinline__ void stv_s(double *__restrict__ p, int64_t k, const d
   }
 }
 
+// Vectors held as FP32 numbers (precision 3: p, u, z): loaded and widened
+// exactly, rounded to the nearest FP32 number (ties to even) when stored.  ZT is
+// the stored type, double or float; the arithmetic is FP64 either way.
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+template <int W, bool NT, class ZT>
+__device__ __forceinline__ void ldz(const double *__restrict__ p, int64_t k, double (&o)[W]) {
+  if constexpr (sizeof(ZT) == 8) {
+    ldv_s<W, NT>(p, k, o);
+  } else {
+    const float *q = reinterpret_cast<const float *>(p);
+    if constexpr (W == 2) {
+      const f2v v = NT ? __builtin_nontemporal_load(reinterpret_cast<const f2v *>(q + k))
+                       : *reinterpret_cast<const f2v *>(q + k);
+      o[0] = (double)v.x;
+      o[1] = (double)v.y;
+    } else {
+      o[0] = (double)(NT ? __builtin_nontemporal_load(q + k) : q[k]);
+    }
+  }
+}
+
+template <int W, bool NT, class ZT>
+__device__ __forceinline__ void stz(double *__restrict__ p, int64_t k, const double (&o)[W]) {
+  if constexpr (sizeof(ZT) == 8) {
+    stv_s<W, NT>(p, k, o);
+  } else {
+    float *q = reinterpret_cast<float *>(p);
+    if constexpr (W == 2) {
+      const f2v v = {(float)o[0], (float)o[1]};
+      if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<f2v *>(q + k));
+      else *reinterpret_cast<f2v *>(q + k) = v;
+    } else {
+      if constexpr (NT) __builtin_nontemporal_store((float)o[0], q + k);
+      else q[k] = (float)o[0];
+    }
+  }
+}
+
+// the value a vector of stored type ZT holds for v: v itself, or the FP32 number
+// nearest to it
+template <class ZT>
+__device__ __forceinline__ double held(double v) {
+  if constexpr (sizeof(ZT) == 8) return v;
+  else return (double)(float)v;
+}
+
 // A kernel that follows a reduction phase: if that phase stopped the solve
 // (of the workgroup's system), note it in C_HALT (read by the sparse products
 // of later iterations, which may run concurrently with a finish and so must
@@ -127,14 +174,14 @@ struct PassAArgs {
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
-template <int W, bool DOTS, bool NT>
+template <int W, bool DOTS, bool NT, class ZT>
 __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, TD (&acc)[5]) {
   const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA],
                et = P.sc[PS_S_ETA];
   double r[W], p[W], u[W], s[W], t[W], y[W], As[W], l[W], g[W], w[W], z[W], x[W], q[W];
   ldv<W>(P.r, k, r);
-  ldv_s<W, NT>(P.p, k, p);
-  ldv_s<W, NT>(P.u, k, u);
+  ldz<W, NT, ZT>(P.p, k, p);
+  ldz<W, NT, ZT>(P.u, k, u);
   ldv<W>(P.s, k, s);
   ldv_s<W, NT>(P.t, k, t);
   ldv<W>(P.y, k, y);
@@ -142,17 +189,18 @@ __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, TD (&a
   ldv<W>(P.l, k, l);
   ldv<W>(P.g, k, g);
   ldv<W>(P.w, k, w);
-  ldv_s<W, NT>(P.z, k, z);
+  ldz<W, NT, ZT>(P.z, k, z);
   ldv_s<W, NT>(P.x, k, x);
 #pragma unroll
   for (int j = 0; j < W; ++j) {
-    p[j] = r[j] + be * (p[j] - u[j]);
+    // directions and Eqs. (q), (w); then the residuals and the iterate
     const double o = s[j] + be * t[j];
-    u[j] = ze * o + et * (y[j] + be * u[j]);
+    p[j] = held<ZT>(r[j] + be * (p[j] - u[j]));
+    u[j] = held<ZT>(ze * o + et * (y[j] + be * u[j]));
     q[j] = As[j] + be * l[j];
     w[j] = ze * q[j] + et * (g[j] + be * w[j]);
     t[j] = o - w[j];
-    z[j] = ze * r[j] + et * z[j] - al * u[j];
+    z[j] = held<ZT>(ze * r[j] + et * z[j] - al * u[j]);
     y[j] = ze * s[j] + et * y[j] - al * w[j];
     x[j] = x[j] + al * p[j] + z[j];
     r[j] = r[j] - al * o - y[j];
@@ -169,19 +217,19 @@ __device__ __forceinline__ void passA_body(const PassAArgs &P, int64_t k, TD (&a
       td_fma(acc[4], r[j], r[j]);
     }
   }
-  stv_s<W, NT>(P.p, k, p);
-  stv_s<W, NT>(P.u, k, u);
+  stz<W, NT, ZT>(P.p, k, p);
+  stz<W, NT, ZT>(P.u, k, u);
   stv<W>(P.w, k, w);
   stv_s<W, NT>(P.t, k, t);
-  stv_s<W, NT>(P.z, k, z);
+  stz<W, NT, ZT>(P.z, k, z);
   stv<W>(P.y, k, y);
   stv_s<W, NT>(P.x, k, x);
   stv<W>(P.r, k, r);
 }
 
 // NT: p, u, t, z, x (read and written here, next read by the next pass A)
-// stream past the cache.
-template <bool DOTS, bool NT>
+// stream past the cache.  ZT: the stored type of p, u, z.
+template <bool DOTS, bool NT, class ZT = double>
 __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   const PassAArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
@@ -190,8 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   for (int j = 0; j < 5; ++j) acc[j] = TD{0.0, 0.0, 0.0};
   const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
-  if (k + 1 < P.n) passA_body<2, DOTS, NT>(P, k, acc);
-  else if (k < P.n) passA_body<1, DOTS, NT>(P, k, acc);
+  if (k + 1 < P.n) passA_body<2, DOTS, NT, ZT>(P, k, acc);
+  else if (k < P.n) passA_body<1, DOTS, NT, ZT>(P, k, acc);
   if constexpr (DOTS) {
     __shared__ double red[kTdSlots * 5 * kPart];
     const TD t = block_sum_td<5>(acc, red);
@@ -248,6 +296,7 @@ struct PouArgs {
   const double *r, *s, *t, *y;
   double *p, *u;
   double *o;  // stored only when a later kernel needs A o_i (replacement step)
+  double *u_wide;  // p, u held in FP32 (k_pou<float>): u widened, for the product A u_i
   const double *sc;
   int *ctl;
   int64_t n;
@@ -255,25 +304,26 @@ struct PouArgs {
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
-template <int W, bool STORE_O>
+template <int W, bool STORE_O, class ZT = double>
 __device__ __forceinline__ void pou_body(const PouArgs &P, int64_t k) {
   const double be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA], et = P.sc[PS_S_ETA];
   double r[W], p[W], u[W], s[W], t[W], y[W], o[W];
   ldv<W>(P.r, k, r);
-  ldv<W>(P.p, k, p);
-  ldv<W>(P.u, k, u);
+  ldz<W, false, ZT>(P.p, k, p);
+  ldz<W, false, ZT>(P.u, k, u);
   ldv<W>(P.s, k, s);
   ldv<W>(P.t, k, t);
   ldv<W>(P.y, k, y);
 #pragma unroll
   for (int j = 0; j < W; ++j) {
-    p[j] = r[j] + be * (p[j] - u[j]);
     o[j] = s[j] + be * t[j];
-    u[j] = ze * o[j] + et * (y[j] + be * u[j]);
+    p[j] = held<ZT>(r[j] + be * (p[j] - u[j]));
+    u[j] = held<ZT>(ze * o[j] + et * (y[j] + be * u[j]));
   }
-  stv<W>(P.p, k, p);
-  stv<W>(P.u, k, u);
+  stz<W, false, ZT>(P.p, k, p);
+  stz<W, false, ZT>(P.u, k, u);
   if (STORE_O) stv<W>(P.o, k, o);
+  if constexpr (sizeof(ZT) == 4) stv<W>(P.u_wide, k, u);
 }
 
 template <int W>
@@ -283,6 +333,10 @@ __device__ __forceinline__ void pou_body_noo(const PouArgs &P, int64_t k) {
 template <int W>
 __device__ __forceinline__ void pou_body_o(const PouArgs &P, int64_t k) {
   pou_body<W, true>(P, k);
+}
+template <int W>
+__device__ __forceinline__ void pou_body_o32(const PouArgs &P, int64_t k) {
+  pou_body<W, true, float>(P, k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pu(PouArgs P_) {
@@ -295,6 +349,13 @@ __global__ __launch_bounds__(kBlock) void k_pou(PouArgs P_) {
   const PouArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   PS_DISPATCH_PAIRS(P.n, pou_body_o);
+}
+
+// k_pou with p, u held in FP32 (and u also written widened to P.u_wide)
+__global__ __launch_bounds__(kBlock) void k_pou32(PouArgs P_) {
+  const PouArgs P = bind_system(P_);
+  if (halted_after_finish(P.ctl)) return;
+  PS_DISPATCH_PAIRS(P.n, pou_body_o32);
 }
 
 // replacement step of Algorithm 5, after q_i = A o_i and w_i = A u_i:
@@ -310,36 +371,60 @@ struct TzyxArgs {
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
-template <int W>
+template <int W, class ZT = double>
 __device__ __forceinline__ void tzyx_body(const TzyxArgs &P, int64_t k) {
   const double al = P.sc[PS_S_ALPHA], ze = P.sc[PS_S_ZETA], et = P.sc[PS_S_ETA];
   double o[W], w[W], r[W], u[W], s[W], p[W], t[W], z[W], y[W], x[W];
   ldv<W>(P.o, k, o);
   ldv<W>(P.w, k, w);
   ldv<W>(P.r, k, r);
-  ldv<W>(P.u, k, u);
+  ldz<W, false, ZT>(P.u, k, u);
   ldv<W>(P.s, k, s);
-  ldv<W>(P.p, k, p);
-  ldv<W>(P.z, k, z);
+  ldz<W, false, ZT>(P.p, k, p);
+  ldz<W, false, ZT>(P.z, k, z);
   ldv<W>(P.y, k, y);
   ldv<W>(P.x, k, x);
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     t[j] = o[j] - w[j];
-    z[j] = ze * r[j] + et * z[j] - al * u[j];
+    z[j] = held<ZT>(ze * r[j] + et * z[j] - al * u[j]);
     y[j] = ze * s[j] + et * y[j] - al * w[j];
     x[j] = x[j] + al * p[j] + z[j];
   }
   stv<W>(P.t, k, t);
-  stv<W>(P.z, k, z);
+  stz<W, false, ZT>(P.z, k, z);
   stv<W>(P.y, k, y);
   stv<W>(P.x, k, x);
+}
+template <int W>
+__device__ __forceinline__ void tzyx_body32(const TzyxArgs &P, int64_t k) {
+  tzyx_body<W, float>(P, k);
 }
 
 __global__ __launch_bounds__(kBlock) void k_tzyx(TzyxArgs P_) {
   const TzyxArgs P = bind_system(P_);
   if (P.ctl[C_DONE]) return;
   PS_DISPATCH_PAIRS(P.n, tzyx_body);
+}
+
+// k_tzyx with u, p, z held in FP32
+__global__ __launch_bounds__(kBlock) void k_tzyx32(TzyxArgs P_) {
+  const TzyxArgs P = bind_system(P_);
+  if (P.ctl[C_DONE]) return;
+  PS_DISPATCH_PAIRS(P.n, tzyx_body32);
+}
+
+// conversions of a vector slot between FP64 and FP32 storage (through a scratch
+// slot: the FP32 numbers occupy the first half of the slot's bytes)
+__global__ __launch_bounds__(kBlock) void k_narrow(float *__restrict__ dst,
+                                                   const double *__restrict__ src, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) dst[k] = (float)src[k];
+}
+__global__ __launch_bounds__(kBlock) void k_widen(double *__restrict__ dst,
+                                                  const float *__restrict__ src, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) dst[k] = (double)src[k];
 }
 
 // --------------------------------------------------- pipelined BiCGStab

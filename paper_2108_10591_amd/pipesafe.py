@@ -20,7 +20,7 @@ VARIANTS = {"ssbicgsafe2": 0, "pbicgsafe": 1, "pbicgsafe_rr": 2, "pbicgstab": 3}
 CONVERGED, MAXIT, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 STATUS_NAMES = {0: "converged", 1: "maxit", 2: "breakdown", 3: "nonfinite"}
 # ps_options.precision: the matrix values the products read (include/pipesafe.h)
-PRECISIONS = {"fp64": 0, "fp32_matrix": 1, "fp32_krylov": 2}
+PRECISIONS = {"fp64": 0, "fp32_matrix": 1, "fp32_krylov": 2, "fp32_vectors": 3}
 VEC = ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o", "As", "v", "b"]
 SCAL = ["alpha", "beta", "zeta", "eta", "omega", "f", "rhoref", "rho", "pending", "gs", "gw", "gz"]
 KERNEL_CLASSES = {"spmv": 0, "dots": 1, "update": 2, "spmv_fused": 3, "other": 4, "dots_finish": 5}
