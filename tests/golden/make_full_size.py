@@ -6,7 +6,8 @@ Each record holds the iteration count, status, the whole residual history, a
 SHA-256 of the solution's bytes and a few sampled entries.  Keys are
 "workload/variant" for FP64 solves and "workload/variant@p<precision>" for the
 mixed-precision ones (precision 1: FP32 values in every product; 2: FP32 values
-in the Krylov products, FP64 residual statements).  --only-missing keeps the
+in the Krylov products, FP64 residual statements; 3: as 2, with p, u, z held as
+FP32 numbers).  --only-missing keeps the
 records already in the file and adds the others.
 """
 import hashlib
@@ -50,14 +51,14 @@ def solve_one(key):
 
 KEYS = [f"{name}/{variant}" for name in ("cd3d_128", "rand_band_1m")
         for variant in ("pbicgsafe", "ssbicgsafe2", "pbicgsafe_rr", "pbicgstab",
-                        "pbicgsafe@p1", "pbicgsafe_rr@p2")]
+                        "pbicgsafe@p1", "pbicgsafe_rr@p2", "pbicgsafe_rr@p3")]
 
 
 def main():
     out = {"source": "oracle/oracle.c via oracle.solve (FP64 arithmetic, inner products rounded "
                      "once from their exact value; @p1/@p2: the matrix values rounded to FP32 in "
-                     "every product / in the Krylov products); x0 = 0, b = A*1, maxit 10000, "
-                     "rr_m 100",
+                     "every product / in the Krylov products / and p, u, z held in FP32); x0 = 0, b = A*1, "
+                     "maxit 10000, rr_m 100",
            "runs": {}}
     keys = KEYS
     if "--only-missing" in sys.argv and os.path.exists(OUT):

@@ -46,12 +46,12 @@ def case(request):
 
 
 @pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue",
-                                     "pbicgsafe@p1", "pbicgsafe_rr@p2"])
+                                     "pbicgsafe@p1", "pbicgsafe_rr@p2", "pbicgsafe_rr@p3"])
 def test_full_solve_reproduces_oracle(case, golden, variant):
     """Every method in FP64, the fused schedules of p-BiCGSafe (the same iteration), and the
-    two mixed-precision forms the benchmark times (FP32 values in every product; FP32
-    values in the Krylov products with FP64 replacement residuals every 100 iterations),
-    in the library's automatic layout and schedule."""
+    three mixed-precision forms the benchmark times (FP32 values in every product; FP32
+    values in the Krylov products with FP64 replacement residuals every 100 iterations;
+    the same with p, u, z held in FP32), in the library's automatic layout and schedule."""
     name, A, M, b = case
     key, _, sched = variant.partition("+")
     variant, _, prec = key.partition("@p")

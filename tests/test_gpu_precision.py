@@ -145,13 +145,14 @@ def test_fp32_subnormal_and_range():
     val2[off[0]] = 1e39  # finite in FP64, beyond FP32
     B = W.CSR(A.n, A.rowptr, A.col, val2, A.b, name="f32_overflow_300")
     with pipesafe.Matrix.from_csr(B) as M:
-        for pname in PREC:
+        for pname in list(PREC) + ["fp32_vectors"]:
             with pytest.raises(pipesafe.PipesafeError):
                 M.solve(B.b, tol=1e-10, maxit=50, variant="pbicgsafe", precision=pname)
         assert M.solve(B.b, tol=1e-10, maxit=50, variant="pbicgsafe").iters >= 0
     with pipesafe.Matrix.from_csr(A) as M:
-        with pytest.raises(pipesafe.PipesafeError):
-            M.solve(A.b, tol=1e-10, maxit=50, variant="pbicgsafe", precision=3)
+        for bad in (4, -1):
+            with pytest.raises(pipesafe.PipesafeError):
+                M.solve(A.b, tol=1e-10, maxit=50, variant="pbicgsafe", precision=bad)
 
 
 @pytest.mark.parametrize("gather_sort", [1, 0])
@@ -172,3 +173,54 @@ def test_fp32_values_with_the_gather_ordered_csr_layout(gather_sort):
                 res = M.solve(A.b, tol=1e-10, maxit=3000, variant=variant, rr_m=m, precision=prec,
                               schedule=sched)
                 assert_same(res, ref, (variant, prec, sched))
+
+
+@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp32_vectors_bit_identical_to_oracle(case, fmt):
+    """Precision 3: the Krylov products read FP32 values and p, u, z are held as FP32
+    numbers (rounded when formed, widened when read), in every schedule of p-BiCGSafe and
+    in p-BiCGSafe-rr's replacement steps; the oracle's precision 3 bit for bit."""
+    A = CASES[case]()
+    x0 = np.random.default_rng(6).standard_normal(A.n) * 0.1
+    with device_format(fmt), pipesafe.Matrix.from_csr(A) as M:
+        for variant in ("pbicgsafe", "pbicgsafe_rr"):
+            for sched in (0, 1, 2):
+                for kw in (dict(), dict(x0=x0, norm_ref=1)):
+                    say(f"fp32 vectors {case} {fmt} {variant} schedule {sched} {sorted(kw)}")
+                    ref = O.solve(A, tol=1e-10, maxit=1500, variant=variant, rr_m=10, precision=3,
+                                  **kw)
+                    res = M.solve(A.b, tol=1e-10, maxit=1500, variant=variant, rr_m=10, precision=3,
+                                  schedule=sched, **kw)
+                    assert_same(res, ref, (case, fmt, variant, sched, sorted(kw)))
+        for variant in ("ssbicgsafe2", "pbicgstab"):
+            with pytest.raises(pipesafe.PipesafeError):
+                M.solve(A.b, tol=1e-10, maxit=10, variant=variant, precision=3)
+
+
+def test_fp32_vectors_state_round_trip():
+    """The state interface is FP64: the oracle's precision-3 state at iteration k, loaded
+    into the GPU and advanced one iteration (a replacement step among them), equals the
+    oracle's state at k + 1 in every vector; p, u, z read back are FP32 numbers."""
+    A = W.cd2d(32, 10.0)
+    with pipesafe.Matrix.from_csr(A) as M:
+        for k in (3, 4):
+            st, _ = O.state_at(A, k, variant="pbicgsafe_rr", rr_m=4, precision=3)
+            st1, _ = O.state_at(A, k + 1, variant="pbicgsafe_rr", rr_m=4, precision=3)
+            for v in ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o"]:
+                M.set_state(v, st.vec(v))
+            M.set_state("b", A.b)
+            M.set_scalars({n: st.scal(n) for n in ["alpha", "beta", "zeta", "eta", "f", "rhoref"]})
+            res = M.solve(A.b, tol=0.0, maxit=k + 1, variant="pbicgsafe_rr", rr_m=4, precision=3,
+                          resume=1, resume_iter=k, schedule=0)
+            assert res.status == O.MAXIT and res.iters == k + 1
+            for v in ["x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g"]:
+                got = M.get_state(v)
+                assert np.array_equal(got, st1.vec(v)), (k, v)
+            for v in ("p", "u", "z"):
+                got = M.get_state(v)
+                assert np.array_equal(got.astype(np.float32).astype(np.float64), got), v
+        # a later FP64 solve from the same handle is unaffected by the FP32 storage
+        ref = O.solve(A, tol=1e-10, maxit=500, variant="pbicgsafe")
+        res = M.solve(A.b, tol=1e-10, maxit=500, variant="pbicgsafe")
+        assert_same(res, ref, "fp64 after fp32 vectors")
