@@ -100,7 +100,8 @@ def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 160 * n, "spmv_fused": M + 64 * n}[cls]
 
 
-SOLVER_SOURCES = ["device_common.hpp", "dots.hpp", "pipesafe.hip", "spmv.hpp", "updates.hpp"]
+SOLVER_SOURCES = ["device_common.hpp", "dots.hpp", "layout.cpp", "layout.hpp", "pipesafe.hip", "spmv.hpp",
+                  "updates.hpp"]
 
 
 def source_digest():
@@ -274,10 +275,10 @@ def bench_batch(name, reps=3):
 def bench_mixed(name, rr_ms, reps=3):
     """Mixed precision on one system: time to the workload's tolerance from x0 = 0 in FP64
     (p-BiCGSafe, and p-BiCGSafe-rr at each replacement period m), with the matrix values
-    rounded to FP32 in every product (p-BiCGSafe), and with them rounded in the Krylov
-    products only (p-BiCGSafe-rr, FP64 replacement residual).  Each result states its true
-    FP64 residual ||b - A x|| / ||b|| (FP64 product on the GPU) and its distance from the
-    FP64 p-BiCGSafe solution."""
+    rounded to FP32 in every product (p-BiCGSafe), with them rounded in the Krylov
+    products only (p-BiCGSafe-rr, FP64 replacement residual), and with p, u, z also held
+    in FP32 (p-BiCGSafe-rr).  Each result states its true FP64 residual ||b - A x|| / ||b||
+    (FP64 product on the GPU) and its distance from the FP64 p-BiCGSafe solution."""
     import torch
 
     from paper_2108_10591_amd import pipesafe, workloads
@@ -288,7 +289,8 @@ def bench_mixed(name, rr_ms, reps=3):
     x = torch.empty_like(b)
     runs = [("fp64", "pbicgsafe", 0, 100), ("fp32_matrix", "pbicgsafe", 1, 100)]
     for m in rr_ms:
-        runs += [(f"fp64_rr_m{m}", "pbicgsafe_rr", 0, m), (f"fp32_krylov_rr_m{m}", "pbicgsafe_rr", 2, m)]
+        runs += [(f"fp64_rr_m{m}", "pbicgsafe_rr", 0, m), (f"fp32_krylov_rr_m{m}", "pbicgsafe_rr", 2, m),
+                 (f"fp32_vectors_rr_m{m}", "pbicgsafe_rr", 3, m)]
     out = {"workload": name, "n": A.n, "nnz": A.nnz, "tol": tol, "x0": "zero",
            "stop": "||r_i|| <= tol ||r_0|| (recursive residual)"}
     with pipesafe.Matrix.from_csr(A) as M:
@@ -387,8 +389,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--no-warmstart", action="store_true", help="skip the learned-initial-guess leg")
-    ap.add_argument("--warmstart-count", type=int, default=4096,
-                    help="training problems of the learned-initial-guess leg (20000 for the full run)")
+    ap.add_argument("--warmstart-count", type=int, default=20000,
+                    help="training problems of the learned-initial-guess leg")
     ap.add_argument("--warmstart-epochs", type=int, default=20)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--mixed-rr-m", default="100",
