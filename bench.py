@@ -45,8 +45,10 @@ def kernel_name(cls, layout, schedule, streaming=0):
         return {"spmv": f"{k}<EpiStore> (A s_i)",
                 "update": f"k_passA_pbicgsafe<true, {nt}> (pass A + 5 partial inner products)",
                 "spmv_fused": f"{k}<EpiPBiCGSafeBDots<{nt}>> (A w_i + l, g, s + 4 partial inner products)"}[cls]
-    if schedule == 2:
-        return {"spmv": f"{k}<EpiStore> (A s_i)", "update": "k_pass_w (w_i)",
+    if schedule in (2, 3):
+        spmv = (f"{k}<EpiStoreFold> (A s_i + the fold and finish of 9 inner products)"
+                if schedule == 3 else f"{k}<EpiStore> (A s_i)")
+        return {"spmv": spmv, "update": "k_pass_w (w_i)",
                 "spmv_fused": f"{k}<EpiPBiCGSafeAll<{nt}>> (A w_i + every other update + 9 partial inner products)"}[cls]
     return {"spmv": f"{k}<EpiStore> (A s_i)", "dots": "k_dots<ProdSafe9<false>> (9 inner products)",
             "update": f"k_passA_pbicgsafe<false, {nt}> (pass A)",
@@ -80,12 +82,15 @@ def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
     p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (168n) + A w with q, l, g, s
                  and y, r, r0* (M+88n)
     p-BiCGSafe, fused-epilogue schedule: A s (M+16n) + w pass (40n: As, l, g, w read, w
-                 written) + A w with every other update (M+192n: 13 reads, 10 writes, w gather)
+                 written) + A w with every other update (M+192n: 13 reads, 10 writes, w gather);
+                 the same for its single-stream form (schedule 3), whose A s also adds the
+                 partial sums (9 triples per product workgroup: 0.2% of the iteration at 128^3,
+                 not counted, like every schedule's partial sums)
     """
     M = matrix_bytes(n, nnz, info)
     if variant in ("pbicgsafe", "pbicgsafe_rr") and schedule == 1:
         return 2 * M + 272 * n
-    if variant in ("pbicgsafe", "pbicgsafe_rr") and schedule == 2:
+    if variant in ("pbicgsafe", "pbicgsafe_rr") and schedule in (2, 3):
         return 2 * M + 248 * n
     return {"pbicgsafe": 2 * M + 280 * n, "pbicgsafe_rr": 2 * M + 280 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
@@ -95,7 +100,7 @@ def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
     M = matrix_bytes(n, nnz, info)
     if schedule == 1:
         return {"spmv": M + 16 * n, "update": 168 * n, "spmv_fused": M + 88 * n}[cls]
-    if schedule == 2:
+    if schedule in (2, 3):
         return {"spmv": M + 16 * n, "update": 40 * n, "spmv_fused": M + 192 * n}[cls]
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 160 * n, "spmv_fused": M + 64 * n}[cls]
 
@@ -528,10 +533,11 @@ def main():
     if not args.no_variants:
         var = {}
         others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", -1), ("pbicgstab", 0)]
-        others += [("pbicgsafe", sc) for sc in (0, 1, 2) if sc != sched]
+        others += [("pbicgsafe", sc) for sc in (0, 1, 2, 3) if sc != sched]
         for v, sc in others:
             key = v if v != "pbicgsafe" else {0: "pbicgsafe_dot_pass", 1: "pbicgsafe_fused_dots",
-                                              2: "pbicgsafe_fused_epilogue"}[sc]
+                                              2: "pbicgsafe_fused_epilogue",
+                                              3: "pbicgsafe_single_stream"}[sc]
             M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc)
             torch.cuda.synchronize()
             t1 = time.perf_counter()

@@ -94,7 +94,7 @@ typedef struct {
                           HIP graphs; 0: launch every kernel directly.  Results are
                           bit-identical either way.  Ignored while profiling.          */
   int32_t schedule;    /* p-BiCGSafe and p-BiCGSafe-rr.  -1 (default): automatic --
-                          sliced layout: 2; CSR: 2 below 2^18 rows, else 0;
+                          sliced layout: 3; CSR: 3 below 2^18 rows, else 0;
                           batches: 2
                           (ps_info.auto_schedule tells; other variants ignore -1).
                           With -rr, a replacement step and the iteration after it form
@@ -114,8 +114,18 @@ typedef struct {
                           than 1 (measured: equal to 1 within 1% up to 112^3 stencils,
                           5.5% faster at 128^3; slower than 0 on uneven CSR rows).
                           Batches: each system's partial sums are added by a workgroup
-                          of its own.  Results are bit-identical to schedule 0.  Other
-                          variants: 1 and 2 are PS_EINVAL.                              */
+                          of its own.
+                          3: as 2 on one stream: the product A s_i also performs the
+                          reduction phase -- its first workgroups fold the partial
+                          sums before their rows, and the last of them to finish
+                          adds the folded sums and forms the stop test and the
+                          coefficients -- so no fold or finish launch and no
+                          cross-stream wait remain (overlap is then unused).  One
+                          system only (batches: PS_EINVAL).  Measured: 7-14% faster
+                          than 2 on stencils from 24^3 to 128^3 rows and on banded
+                          CSR matrices up to 2*10^5 rows.
+                          Results are bit-identical to schedule 0.  Other variants: 1,
+                          2 and 3 are PS_EINVAL.                                        */
   int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).
                           0 (default): use it as given.
                           1: if ||b - A x0|| > ||b|| (or is not finite), start from

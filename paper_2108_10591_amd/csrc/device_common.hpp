@@ -21,6 +21,8 @@ enum Ctl : int {
                   // sparse products that may run concurrently with a finish
   C_ITER = 5,     // index of the iteration whose reduction phase runs next; advanced
                   // by the finish, so replayed launches need no per-iteration argument
+  C_FOLDS = 6,    // fold slices completed in the current product (single-stream
+                  // schedule); back to 0 once the last one has finished the phase
   C_COUNT = 16
 };
 

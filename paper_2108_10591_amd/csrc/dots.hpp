@@ -178,61 +178,101 @@ __device__ __forceinline__ FinPre fin_preload(const DotArgs &A) {
   return p;
 }
 
-// Algorithms 3-5: stop test first, then beta, alpha, zeta, eta.
+// The outcome of the BiCGSafe reduction phase of iteration i (Algorithms 3-5;
+// the stop test first, reading R5; a zero or non-finite denominator is a
+// breakdown, reading R10): the history entry, the status if the solve stops
+// here (else -1), and otherwise beta, alpha, zeta, eta.  It writes nothing, so
+// every caller that needs the coefficients can form them itself.
+struct SafeStep {
+  double hist;  // ||r_i|| / ||r_ref||, NaN if an inner product is not finite
+  int status;   // ps_status when the solve stops at i, else -1
+  double alpha, beta, zeta, eta;
+};
+__device__ __forceinline__ SafeStep safe_step(const double (&d)[9], int i, double rhoref,
+                                              double alpha_prev, double zeta_prev, double f_prev,
+                                              int maxit, double tol) {
+  SafeStep s{0.0, -1, 0.0, 0.0, 0.0, 0.0};
+  const double a = d[0], b = d[1], c = d[2], dd = d[3], e = d[4], f = d[5], g = d[6], h = d[7],
+               rho = d[8];
+  bool finite = true;
+  for (int j = 0; j < 9; ++j) finite = finite && isfinite(d[j]);
+  if (!finite) {
+    s.hist = NAN;
+    s.status = PS_NONFINITE;
+    return s;
+  }
+  const double ref = sqrt(rhoref);
+  const double nr = sqrt(rho);
+  s.hist = ref > 0.0 ? nr / ref : 0.0;
+  if (nr <= tol * ref) {
+    s.status = PS_CONVERGED;
+    return s;
+  }
+  if (i >= maxit) {
+    s.status = PS_MAXIT;
+    return s;
+  }
+  double beta, alpha, zeta, eta;
+  if (i == 0) {
+    if (bad_den(g) || bad_den(a)) {
+      s.status = PS_BREAKDOWN;
+      return s;
+    }
+    beta = 0.0;
+    alpha = f / g;
+    zeta = dd / a;
+    eta = 0.0;
+  } else {
+    const double den_beta = zeta_prev * f_prev;
+    if (bad_den(den_beta)) {
+      s.status = PS_BREAKDOWN;
+      return s;
+    }
+    beta = (alpha_prev * f) / den_beta;
+    const double den_alpha = g + beta * h;
+    const double den_ze = a * b - c * c;
+    if (bad_den(den_alpha) || bad_den(den_ze)) {
+      s.status = PS_BREAKDOWN;
+      return s;
+    }
+    alpha = f / den_alpha;
+    zeta = (b * dd - c * e) / den_ze;
+    eta = (a * e - c * dd) / den_ze;
+  }
+  if (!isfinite(beta) || !isfinite(alpha) || !isfinite(zeta) || !isfinite(eta)) {
+    s.status = PS_BREAKDOWN;
+    return s;
+  }
+  s.alpha = alpha;
+  s.beta = beta;
+  s.zeta = zeta;
+  s.eta = eta;
+  return s;
+}
+
+// Algorithms 3-5: stop test first, then beta, alpha, zeta, eta, stored in the
+// scalar block.
 struct FinSafe {
   __device__ static void run(const DotArgs &A, const FinPre &P, const double (&d)[9]) {
     double *sc = A.sc;
     const int i = P.i;
-    const double a = d[0], b = d[1], c = d[2], dd = d[3], e = d[4], f = d[5], g = d[6], h = d[7],
-                 rho = d[8];
+    const double rho = d[8];
     for (int j = 0; j < 9; ++j) sc[SC_DOTS + j] = d[j];
     sc[PS_S_RHO] = rho;
-    bool finite = true;
-    for (int j = 0; j < 9; ++j) finite = finite && isfinite(d[j]);
-    if (!finite) {
-      A.hist[i] = NAN;
-      set_stop(A.ctl, PS_NONFINITE, i);
+    const bool set_ref = (A.flags & DF_SET_REF) != 0;
+    const SafeStep st =
+        safe_step(d, i, set_ref ? rho : P.rhoref, P.alpha, P.zeta, P.f, A.maxit, A.tol);
+    A.hist[i] = st.hist;
+    if (set_ref && st.status != PS_NONFINITE) sc[PS_S_RHOREF] = rho;
+    if (st.status >= 0) {
+      set_stop(A.ctl, st.status, i);
       return;
     }
-    const double rhoref = (A.flags & DF_SET_REF) ? rho : P.rhoref;
-    if (A.flags & DF_SET_REF) sc[PS_S_RHOREF] = rho;
-    if (stop_test(rho, rhoref, A.ctl, A.hist, i, A.maxit, A.tol)) return;
-    double beta, alpha, zeta, eta;
-    if (i == 0) {
-      if (bad_den(g) || bad_den(a)) {
-        set_stop(A.ctl, PS_BREAKDOWN, i);
-        return;
-      }
-      beta = 0.0;
-      alpha = f / g;
-      zeta = dd / a;
-      eta = 0.0;
-    } else {
-      const double den_beta = P.zeta * P.f;
-      if (bad_den(den_beta)) {
-        set_stop(A.ctl, PS_BREAKDOWN, i);
-        return;
-      }
-      beta = (P.alpha * f) / den_beta;
-      const double den_alpha = g + beta * h;
-      const double den_ze = a * b - c * c;
-      if (bad_den(den_alpha) || bad_den(den_ze)) {
-        set_stop(A.ctl, PS_BREAKDOWN, i);
-        return;
-      }
-      alpha = f / den_alpha;
-      zeta = (b * dd - c * e) / den_ze;
-      eta = (a * e - c * dd) / den_ze;
-    }
-    if (!isfinite(beta) || !isfinite(alpha) || !isfinite(zeta) || !isfinite(eta)) {
-      set_stop(A.ctl, PS_BREAKDOWN, i);
-      return;
-    }
-    sc[PS_S_ALPHA] = alpha;
-    sc[PS_S_BETA] = beta;
-    sc[PS_S_ZETA] = zeta;
-    sc[PS_S_ETA] = eta;
-    sc[PS_S_F] = f;
+    sc[PS_S_ALPHA] = st.alpha;
+    sc[PS_S_BETA] = st.beta;
+    sc[PS_S_ZETA] = st.zeta;
+    sc[PS_S_ETA] = st.eta;
+    sc[PS_S_F] = d[5];
     A.ctl[C_ITER] = i + 1;
   }
 };
@@ -385,12 +425,11 @@ __global__ __launch_bounds__(kBlock) void k_dots(DotArgs A) {
 }
 
 // One block: add the G partial triples of each product in block order, round
-// once, and run the phase's finish.
+// once, and run the phase's finish.  Every thread of the block calls it; lds
+// holds kTdSlots * ND * kPart doubles.
 template <int ND, class Fin>
-__global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
-  __shared__ double lds[kTdSlots * 9 * kPart];
-  __shared__ double fin[9];
-  if (A.ctl[C_DONE]) return;
+__device__ __forceinline__ void finish_block(const DotArgs &A, int G, double *lds) {
+  __shared__ double fin[ND];
   FinPre pre{};
   if (threadIdx.x == 0) pre = fin_preload(A);
   TD tot[ND];
@@ -411,6 +450,13 @@ __global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
     Fin::run(A, pre, d);
     if (A.ctl[C_DONE]) atomicSub(A.running, 1);
   }
+}
+
+template <int ND, class Fin>
+__global__ __launch_bounds__(kBlock) void k_dots_finish(DotArgs A, int G) {
+  __shared__ double lds[kTdSlots * 9 * kPart];
+  if (A.ctl[C_DONE]) return;
+  finish_block<ND, Fin>(A, G, lds);
 }
 
 // The fused schedules' finish when the partial lists are short: add pass A's
@@ -564,12 +610,12 @@ constexpr int kFoldPerThread = 1;
 // This kernel folds them into [9][gridDim.x] triples in the layout k_dots
 // writes (block k takes entries k*kFoldPerThread*kBlock .. of every list,
 // kFoldPerThread per thread), so the same one-block finish follows.
-__global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restrict__ pa, int ga,
-                                                          const double *__restrict__ pb, int gb,
-                                                          double *__restrict__ out,
-                                                          const int *__restrict__ ctl) {
-  __shared__ double lds[kTdSlots * 9 * kPart];
-  if (ctl[C_DONE]) return;
+// Slice `slice` of the fold: entries slice*kFoldPerThread*kBlock .. of every list,
+// added into out[j * G + slice] (G slices in all).  All threads of the block take part.
+__device__ __forceinline__ void fold_slice(const double *__restrict__ pa, int ga,
+                                           const double *__restrict__ pb, int gb,
+                                           double *__restrict__ out, int G, int slice,
+                                           double *lds) {
   constexpr int kA[5] = {1, 4, 5, 7, 8};
   constexpr int kB[4] = {0, 2, 3, 6};
   TD t[9];
@@ -578,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restri
   // kFoldPerThread entries of every list per thread, kBlock apart
 #pragma unroll
   for (int q = 0; q < kFoldPerThread; ++q) {
-    const int idx = (blockIdx.x * kFoldPerThread + q) * kBlock + threadIdx.x;
+    const int idx = (slice * kFoldPerThread + q) * kBlock + threadIdx.x;
     if (idx < ga) {
 #pragma unroll
       for (int j = 0; j < 5; ++j) td_add(t[kA[j]], td_load(pa, j * ga + idx));
@@ -589,8 +635,130 @@ __global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restri
     }
   }
   const TD s = block_sum_td<9>(t, lds);
-  const int G = gridDim.x;
-  if (threadIdx.x < 9) td_store(out, threadIdx.x * G + blockIdx.x, s);
+  if (threadIdx.x < 9) td_store(out, threadIdx.x * G + slice, s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restrict__ pa, int ga,
+                                                          const double *__restrict__ pb, int gb,
+                                                          double *__restrict__ out,
+                                                          const int *__restrict__ ctl) {
+  __shared__ double lds[kTdSlots * 9 * kPart];
+  if (ctl[C_DONE]) return;
+  fold_slice(pa, ga, pb, gb, out, gridDim.x, blockIdx.x, lds);
+}
+
+// Lean sums of the nine products for use inside a sparse product (the
+// single-stream schedule), where the fold and finish must stay short and use
+// few registers: one triple accumulator per thread, no per-product register
+// arrays.  Thread t < 252 works for product t / 28 (28 threads each) and adds
+// its entries sequentially; those partials go through LDS, where lane 4j + q of
+// wavefront 0 adds seven of product j's, and two quad steps add the four.
+// The order differs from block_sum_td's, which the triple accumulators make
+// immaterial: the final rounding gives each product rounded once from its
+// exact value either way (see TD).
+constexpr int kLeanPer = 28;                      // threads per product
+constexpr int kLeanLds = 9 * kLeanPer * kPart;    // doubles of LDS the lean sums use
+static_assert(9 * kLeanPer <= kBlock && kLeanPer % 4 == 0, "lean sums: 252 threads, quarters");
+
+// Thread (j, s) = (t / 28, t % 28) holds a partial of product j; on return lane
+// 4j of wavefront 0 (j < 9) holds product j's total.  Every thread calls it.
+__device__ __forceinline__ TD lean_sum9(const TD &acc, double *lds) {
+  const int t = threadIdx.x;
+  if (t < 9 * kLeanPer) td_store(lds, t, acc);
+  __syncthreads();
+  TD r{0.0, 0.0, 0.0};
+  if (t < 36) {
+    const int base = (t >> 2) * kLeanPer + (t & 3) * (kLeanPer / 4);
+    r = td_load(lds, base);
+    for (int k = 1; k < kLeanPer / 4; ++k) td_add(r, td_load(lds, base + k));
+  }
+  if (t < kWave) {  // lanes 36..63 add zeros
+    td_step<0xB1>(r);  // quad_perm [1,0,3,2]
+    td_step<0x4E>(r);  // quad_perm [2,3,0,1]
+  }
+  __syncthreads();  // lds free again
+  return r;
+}
+
+// The lean form of fold_slice: slice `slice` of the two partial lists into
+// out[j * G + slice].
+__device__ __forceinline__ void fold_lean(const double *__restrict__ pa, int ga,
+                                          const double *__restrict__ pb, int gb,
+                                          double *__restrict__ out, int G, int slice,
+                                          double *lds) {
+  static_assert(kFoldPerThread == 1, "a slice is kBlock entries of every list");
+  // product j comes from list (kFromB >> j) & 1 (0: pa, 1: pb), row (kRows >> 4j) & 15:
+  // pb rows 0-3 are (a, c, d, g), pa rows 0-4 are (b, e, f, h, rho)
+  constexpr unsigned kFromB = 0x4Du;                  // products 0, 2, 3, 6
+  constexpr unsigned long long kRows = 0x433212100ull;  // 0,0,1,2,1,2,3,3,4
+  const int t = threadIdx.x;
+  TD acc{0.0, 0.0, 0.0};
+  if (t < 9 * kLeanPer) {
+    const int j = t / kLeanPer, s = t % kLeanPer;
+    const bool from_b = (kFromB >> j) & 1u;
+    const int len = from_b ? gb : ga;
+    const double *src = (from_b ? pb : pa) + (size_t)((kRows >> (4 * j)) & 15u) * len * kPart;
+    for (int e = s; e < kBlock; e += kLeanPer) {
+      const int idx = slice * kBlock + e;
+      if (idx < len) td_add(acc, td_load(src, idx));
+    }
+  }
+  const TD r = lean_sum9(acc, lds);
+  if (t < 36 && (t & 3) == 0) td_store(out, (int64_t)(t >> 2) * G + slice, r);
+}
+
+// The lean form of finish_block's sums: the G folded triples of each product,
+// rounded once into fin[0..8].
+__device__ __forceinline__ void finish_lean(const double *__restrict__ partials, int G,
+                                            double *lds, double *fin) {
+  const int t = threadIdx.x;
+  TD acc{0.0, 0.0, 0.0};
+  if (t < 9 * kLeanPer) {
+    const int j = t / kLeanPer, s = t % kLeanPer;
+    for (int b = s; b < G; b += kLeanPer) td_add(acc, td_load(partials, (int64_t)j * G + b));
+  }
+  const TD r = lean_sum9(acc, lds);
+  if (t < 36 && (t & 3) == 0) fin[t >> 2] = td_round(r);  // the one final rounding
+}
+
+// Fold and finish inside another kernel (the single-stream schedule): workgroup
+// `slice` (< G) folds its slice into F.partials ([9][G]); the workgroup that
+// completes the last slice -- counted in the control word C_FOLDS, which it
+// resets for the next iteration -- then adds the G slices and runs FinSafe, as
+// k_fold_partials and k_dots_finish would (with the lean sums).  No workgroup
+// waits for another: the others go on with their own work.  A release fence
+// before the count and an acquire fence after the last count make every slice
+// visible to the last workgroup, whichever XCD and L2 wrote it.  Every thread
+// of the block calls it; lds holds kLeanLds doubles.
+__device__ __forceinline__ void fold_then_finish(const double *__restrict__ pa, int ga,
+                                                 const double *__restrict__ pb, int gb,
+                                                 const DotArgs &F, int G, int slice, double *lds) {
+  __shared__ int last;
+  __shared__ double fin[9];
+  fold_lean(pa, ga, pb, gb, F.partials, G, slice, lds);
+  __syncthreads();  // the slice's stores (lanes 0, 4, .., 32) are done
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const int before = atomicAdd(&F.ctl[C_FOLDS], 1);
+    last = before == G - 1;
+    if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      atomicExch(&F.ctl[C_FOLDS], 0);
+    }
+  }
+  __syncthreads();
+  if (!last) return;
+  FinPre pre{};
+  if (threadIdx.x == 0) pre = fin_preload(F);
+  finish_lean(F.partials, G, lds, fin);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double d[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) d[j] = fin[j];
+    FinSafe::run(F, pre, d);
+    if (F.ctl[C_DONE]) atomicSub(F.running, 1);
+  }
 }
 
 }  // namespace ps

@@ -387,7 +387,8 @@ struct Plan {
   hipStream_t A, B;
   bool overlap;
   bool fused;     // fused-dot schedule (p-BiCGSafe): schedule 1 or 2
-  bool fused2;    // schedule 2: every update but w_i in the epilogue of A w_i
+  bool fused2;    // schedules 2, 3: every update but w_i in the epilogue of A w_i
+  bool fused3;    // schedule 3: the reduction folded and finished inside A s_i, one stream
   bool fallback;  // replace an initial guess that is worse than zero
   bool scale;     // first scale the guess to its least residual (x0_fallback = 2)
   bool stream_nt; // streaming (nontemporal) loads and stores in the update passes
@@ -504,6 +505,12 @@ bool replacement(const Plan &P, int i) {
   return P.variant == PS_PBICGSAFE_RR && P.rr_m > 0 && (i % P.rr_m) == 0 && i > 0 && i < P.rr_M;
 }
 bool after_replacement(const Plan &P, int i) { return i > 0 && replacement(P, i - 1); }
+// schedule 3: iteration j's reduction phase is folded and finished inside its
+// product A s_j, from the partial sums the previous fused epilogue left -- the
+// iterations whose inner products schedule 2 takes from those sums
+bool fold_in_product(const Plan &P, int j) {
+  return P.fused3 && j > P.i0 && !replacement(P, j) && !after_replacement(P, j);
+}
 
 int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
   hipStream_t A = P.A;
@@ -513,16 +520,35 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
          *O = M->slot(PS_V_O), *As = M->slot(PS_V_AS), *Bv = M->slot(PS_V_B);
   const bool replace = replacement(P, i);
   if (!replace) {
-    PS_TRY(fork(M, P));
-    // the reduction phase on the second stream, enqueued first so that its few
-    // workgroups are dispatched ahead of the product's thousands; the partial
-    // sums come from the previous iteration's passes, which the first
-    // iteration and the one after a replacement step do not have
-    if (P.fused && i > P.i0 && !after_replacement(P, i))
-      PS_TRY(fused_finish(M, P, P.B));
-    else PS_TRY(iter_safe_dots(M, P, P.B, i));
-    PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT, P.kry32));  // As_i, concurrently
-    PS_TRY(join(M, P));
+    if (fold_in_product(P, i)) {
+      // schedule 3, one stream: A s_i, whose first workgroups fold the previous
+      // epilogue's partial sums and finish the reduction phase; the stop word is
+      // C_DONE, as nothing else runs beside it
+      double *pa = M->fpart, *pb = pa + kPart * 5 * (size_t)M->nblk;
+      DotArgs D{};
+      D.n = M->n;
+      D.partials = M->fpart + kPart * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk);
+      D.ctl = M->ctl;
+      D.sc = M->sc;
+      D.hist = M->hist;
+      D.maxit = P.maxit;
+      D.tol = P.tol;
+      D.flags = 0;
+      D.running = M->running();
+      PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStoreFold{As, pa, pb, M->nblk, M->nblk, M->gfold, D},
+                  C_DONE, P.kry32));
+    } else {
+      PS_TRY(fork(M, P));
+      // the reduction phase on the second stream, enqueued first so that its few
+      // workgroups are dispatched ahead of the product's thousands; the partial
+      // sums come from the previous iteration's passes, which the first
+      // iteration and the one after a replacement step do not have
+      if (P.fused && i > P.i0 && !after_replacement(P, i))
+        PS_TRY(fused_finish(M, P, P.B));
+      else PS_TRY(iter_safe_dots(M, P, P.B, i));
+      PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStore{As}, C_HALT, P.kry32));  // As_i, concurrently
+      PS_TRY(join(M, P));
+    }
     if (!P.fused) {
       PassAArgs pa{X, R, Pp, U, T, Y, Z, W, S, As, L, G, M->sc, M->ctl, M->n, next_rev(M),
                    nullptr, nullptr};
@@ -678,7 +704,8 @@ void clear_graphs(ps_matrix *M) {
 int get_graph(ps_matrix *M, const Plan &P, int count, int probe_i, GraphEntry **out) {
   const GraphKey key{P.variant, P.maxit,   P.rr_m,           P.rr_M, P.overlap ? 1 : 0,
                      count,     M->sweep,
-                     (P.fused ? 1 : 0) | (P.stream_nt ? 2 : 0) | (P.fused2 ? 4 : 0),
+                     (P.fused ? 1 : 0) | (P.stream_nt ? 2 : 0) | (P.fused2 ? 4 : 0) |
+                         (P.fused3 ? 8 : 0),
                      P.precision, P.tol,   P.A};
   for (GraphEntry &g : M->graphs)
     if (g.key == key) {
@@ -785,20 +812,21 @@ int64_t matrix_bytes(const ps_matrix *M) {
 }
 bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kOverlapMinBytes; }
 // The automatic p-BiCGSafe(-rr) schedule, from measurements with the triple
-// inner-product accumulators:
-//  - sliced layout: the fused epilogue (2) -- 4-7% faster than the fused
-//    partial sums (1) on stencils from 4096 rows to 2^21 (2.5% slower near
-//    10^5 rows), and 6-20% faster than the separate pass (0); pass A of
-//    schedule 1 carries five triple accumulators, schedule 2's w pass none;
-//  - CSR: 2 below kFusedMinRows rows (the same margins), else the separate
-//    pass (0: on uneven rows the gather-bound products gain nothing from the
-//    skipped pass and pay for the extra epilogue reads);
+// inner-product accumulators (microseconds per iteration, schedules 0 / 2 / 3):
+//  - one system, sliced layout: the single-stream fused epilogue (3) -- stencils
+//    of 24^3 .. 128^3 rows: 24.6 / 19.8 / 18.4, 42.9 / 37.0 / 33.3 (64^3),
+//    78.2 / 74.0 / 63.4 (96^3), 151.5 / 140.0 / 128.5 (128^3); schedule 2
+//    beats 1 by 4-7% and 0 by 6-20%;
+//  - one system, CSR: 3 below kFusedMinRows rows (banded 2*10^4 and 2*10^5
+//    rows: 35.2 / 30.1 / 28.5 and 71.8 / 72.1 / 61.0), else the separate pass
+//    (0; 10^6 uneven rows: 219 / 249 / 238 -- the gather-bound products gain
+//    nothing from the skipped pass and pay for the extra epilogue reads);
 //  - batches: 2 (the 512-system stencil batch: 17% more solves/s than 0, 4%
-//    more than 1).
+//    more than 1; schedule 3 is single-system only).
 int auto_schedule(const ps_matrix *M) {
   if (M->nsys > 1) return 2;
-  if (M->format == PS_FMT_SELL) return 2;
-  return M->n < kFusedMinRows ? 2 : 0;
+  if (M->format == PS_FMT_SELL) return 3;
+  return M->n < kFusedMinRows ? 3 : 0;
 }
 // two sparse products and the update passes' 34 vector reads and writes
 bool streaming(const ps_matrix *M) {
@@ -905,7 +933,10 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   if (o.x0_fallback < 0 || o.x0_fallback > 2) return PS_EINVAL;
   if (o.resume && (batch || o.resume_iter < 0 || o.resume_iter > maxit)) return PS_EINVAL;
   const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
-  if (o.schedule < -1 || o.schedule > 2 || (o.schedule >= 1 && !safe_pipelined))
+  // schedule 3 folds in the product's first gfold workgroups: never more than the
+  // product has with the layouts built here (gfold = nblk / 256, rounded up)
+  if (o.schedule < -1 || o.schedule > 3 || (o.schedule >= 1 && !safe_pipelined) ||
+      (o.schedule == 3 && (batch || M->gfold > M->nblk)))
     return PS_EINVAL;
   if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_VECTORS ||
       (o.precision != PS_PREC_FP64 && !M->f32_ok) ||
@@ -947,7 +978,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.scale = o.x0_fallback == 2 && x0 != nullptr && !P.resume;
   const int sched = o.schedule >= 0 ? o.schedule : auto_schedule(M);
   P.fused = safe_pipelined && sched >= 1;
-  P.fused2 = P.fused && sched == 2;
+  P.fused2 = P.fused && sched >= 2;
+  P.fused3 = P.fused && sched == 3;
   P.stream_nt = safe_pipelined && streaming(M);
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;

@@ -9,9 +9,19 @@
 // budget gets a block of its own, which splits it over all threads.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
+#include "dots.hpp"
 
 namespace ps {
+
+// An epilogue may carry a prologue: work that some workgroups of the product do
+// before their rows (EpiStoreFold).
+template <class E, class = void>
+struct has_prologue : std::false_type {};
+template <class E>
+struct has_prologue<E, std::void_t<decltype(&E::prologue)>> : std::true_type {};
 
 // VT: the stored type of the values, double or float (the matrix rounded to
 // FP32 for the mixed-precision solves); a float value is widened exactly, so
@@ -79,6 +89,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
   const int sys = system_of(st.chunk_sys, r0);
   if (st.stopped(sys)) return;
   const Epi epi = epi_all.at(sys);
+  if constexpr (has_prologue<Epi>::value) {
+    __shared__ double pro[kLeanLds];
+    epi.prologue(pro);
+  }
   constexpr int ND = Epi::kDots;
   TD dacc[ND > 0 ? ND : 1];
 #pragma unroll
@@ -294,6 +308,10 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double
   const int sys = system_of(st.chunk_sys, (int64_t)b * kBlock * RPL);
   if (st.stopped(sys)) return;
   const Epi epi = epi_all.at(sys);
+  if constexpr (has_prologue<Epi>::value) {
+    __shared__ double pro[kLeanLds];
+    epi.prologue(pro);
+  }
   const int lane = threadIdx.x % kWave;
   const int sl = b * kWavesPerBlock + threadIdx.x / kWave;
   const int r0 = sl * SH + lane * RPL;  // the lane's first row
@@ -384,6 +402,30 @@ struct EpiStore {
   struct In {};
   __device__ __forceinline__ In load(int) const { return In{}; }
   __device__ __forceinline__ void store(int r, double ax, const In &) const { y[r] = ax; }
+};
+
+// y = A x, with a prologue for the single-stream fused schedule (schedule 3):
+// workgroups 0 .. gf-1 fold the partial sums of this iteration's nine inner
+// products that the previous fused epilogue left ([5][ga] and [4][gb] triples)
+// into [9][gf] (fin.partials), and the last of them to finish adds those and
+// forms the iteration's stop test and scalars (fold_then_finish) -- the
+// reduction phase inside the product it is hidden behind, with no second stream
+// and no launch of its own.  Rows are stored as by EpiStore; no workgroup of the
+// product reads what the prologue writes.
+struct EpiStoreFold {
+  static constexpr int kDots = 0;
+  __device__ __forceinline__ EpiStoreFold at(int) const { return *this; }
+  double *y;
+  const double *pa, *pb;  // the epilogue's partial triples (the layout fused_finish reads)
+  int ga, gb;
+  int gf;                 // fold slices (workgroups taking part)
+  DotArgs fin;            // the finish: fin.partials = the [9][gf] folded triples
+  struct In {};
+  __device__ __forceinline__ In load(int) const { return In{}; }
+  __device__ __forceinline__ void store(int r, double ax, const In &) const { y[r] = ax; }
+  __device__ __forceinline__ void prologue(double *lds) const {
+    if ((int)blockIdx.x < gf) fold_then_finish(pa, ga, pb, gb, fin, gf, (int)blockIdx.x, lds);
+  }
 };
 
 // r = b - A x (and optionally r0* = r): the initial residual of every

@@ -19,13 +19,15 @@ def test_iteration_bytes_are_the_sum_of_launch_bytes(n, nnz):
     product of each class and, with the separate pass, one inner-product pass."""
     for sched, classes in ((0, ("spmv", "dots", "update", "spmv_fused")),
                            (1, ("spmv", "update", "spmv_fused")),
-                           (2, ("spmv", "update", "spmv_fused"))):
+                           (2, ("spmv", "update", "spmv_fused")),
+                           (3, ("spmv", "update", "spmv_fused"))):
         per_launch = sum(bench.bytes_per_launch(c, n, nnz, sched) for c in classes)
         for variant in ("pbicgsafe", "pbicgsafe_rr"):
             assert bench.bytes_per_iteration(variant, n, nnz, sched) == per_launch, (sched, variant)
     # the fused schedules skip the 40n pass: 8n (schedule 1) and 32n (schedule 2) fewer bytes
-    b0, b1, b2 = (bench.bytes_per_iteration("pbicgsafe", n, nnz, s) for s in (0, 1, 2))
+    b0, b1, b2, b3 = (bench.bytes_per_iteration("pbicgsafe", n, nnz, s) for s in (0, 1, 2, 3))
     assert b0 - b1 == 8 * n and b0 - b2 == 32 * n
+    assert b3 == b2  # the same vector traffic on one stream
     # the device layout's own matrix bytes replace the CSR estimate when known
     info = {"matrix_bytes": 123_456}
     assert bench.bytes_per_iteration("pbicgsafe", n, nnz, 2, info) == 2 * 123_456 + 248 * n

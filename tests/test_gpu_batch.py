@@ -136,6 +136,8 @@ def test_batch_rejects_single_system_calls():
         assert L.ps_solve(M._h, None, None, 1e-8, 10, 1, None, None, None, None, None) == -1
         with pytest.raises(pipesafe.PipesafeError):
             M.solve(b, tol=1e-8, maxit=10, variant="pbicgstab", schedule=1)
+        with pytest.raises(pipesafe.PipesafeError):  # one stop flag per system: no schedule 3
+            M.solve(b, tol=1e-8, maxit=10, variant="pbicgsafe", schedule=3)
         with pytest.raises(pipesafe.PipesafeError):
             M.solve(b, tol=1e-8, maxit=10, variant="pbicgsafe", resume=1)
         # schedule -1 (automatic) means the fused epilogue for batches

@@ -46,9 +46,11 @@ def case(request):
 
 
 @pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue",
-                                     "pbicgsafe@p1", "pbicgsafe_rr@p2", "pbicgsafe_rr@p3"])
+                                     "pbicgsafe+single_stream", "pbicgsafe@p1",
+                                     "pbicgsafe_rr@p2", "pbicgsafe_rr@p3"])
 def test_full_solve_reproduces_oracle(case, golden, variant):
-    """Every method in FP64, the fused schedules of p-BiCGSafe (the same iteration), and the
+    """Every method in FP64, the fused schedules of p-BiCGSafe (the same iteration; the
+    single-stream one is the automatic choice on the stencil), and the
     three mixed-precision forms the benchmark times (FP32 values in every product; FP32
     values in the Krylov products with FP64 replacement residuals every 100 iterations;
     the same with p, u, z held in FP32), in the library's automatic layout and schedule."""
@@ -57,7 +59,7 @@ def test_full_solve_reproduces_oracle(case, golden, variant):
     variant, _, prec = key.partition("@p")
     g = golden[f"{name}/{key}"]
     print(f"full size {name} {key} {sched}", flush=True)
-    opt = dict(schedule={"fused_dots": 1, "fused_epilogue": 2}.get(sched, 0))
+    opt = dict(schedule={"fused_dots": 1, "fused_epilogue": 2, "single_stream": 3}.get(sched, 0))
     if prec:
         opt = dict(precision=int(prec))  # automatic schedule, as the benchmark runs it
     res = M.solve_dev(b, tol=g["tol"], maxit=10_000, variant=variant, rr_m=100, **opt)
@@ -79,7 +81,7 @@ def test_spmv_full_size_bit_exact(case):
     info = M.info()
     assert info["format"] == {"cd3d_128": "sell", "rand_band_1m": "csr"}[name]
     assert info["auto_overlap"] == 1
-    assert info["auto_schedule"] == {"cd3d_128": 2, "rand_band_1m": 0}[name]
+    assert info["auto_schedule"] == {"cd3d_128": 3, "rand_band_1m": 0}[name]
     assert info["streaming"] == 1  # both move ~0.9 GiB per p-BiCGSafe iteration
     # offsets fit 16 bits (up to 128^2; the band's +-5000): 10 bytes per stored entry
     assert info["index_bits"] == 16

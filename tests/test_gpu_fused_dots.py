@@ -1,9 +1,11 @@
-"""GPU parity of the fused-dot schedule of p-BiCGSafe (option schedule = 1).
+"""GPU parity of the fused-dot schedules of p-BiCGSafe (option schedule = 1, 2, 3).
 
-The schedule changes where the nine inner products of Algorithm 4 are formed
+A schedule changes where the nine inner products of Algorithm 4 are formed
 (per-block partial sums inside pass A and the epilogue of A w_i of the previous
-iteration, instead of a pass of their own), not what they are: the partial sums
-are triple sums rounded once, as in the separate pass.  So every result
+iteration, instead of a pass of their own) and where they are reduced and turned
+into the iteration's scalars (a finish kernel of their own, or the prologue of
+the A s product and the start of the w pass), not what they are: the partial
+sums are triple sums rounded once, as in the separate pass.  So every result
 must equal the oracle's p-BiCGSafe bit for bit, like schedule 0.
 """
 import os
@@ -55,11 +57,13 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_fused_schedule_trajectory_bit_identical_to_oracle(case, schedule):
     """Schedule 1: partial sums in pass A and the A w epilogue; schedule 2: only w_i in a
-    pass of its own, every other update and all nine partial sums in the A w epilogue."""
+    pass of its own, every other update and all nine partial sums in the A w epilogue;
+    schedule 3: schedule 2 on one stream, the partial sums folded in the A s product's
+    prologue and the scalars formed at the start of the w pass."""
     A = CASES[case]()
     for tol, maxit in ((1e-10, 3000), (0.0, 9)):
         say(f"fused schedule {schedule} {case} tol={tol} maxit={maxit}")
@@ -83,7 +87,7 @@ def test_fused_schedule_graphs_and_batches_bit_identical():
         with pipesafe.Matrix.from_csr(A) as M:
             ref = M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", graph=0, overlap=0)
             runs = [M.solve(A.b, tol=1e-10, maxit=600, variant="pbicgsafe", schedule=sc, **kw)
-                    for sc in (1, 2)
+                    for sc in (1, 2, 3)
                     for kw in (dict(graph=0, overlap=0), dict(graph=1, batch_iters=4),
                                dict(graph=0, batch_iters=1, overlap=1),
                                dict(graph=1, batch_iters=4), dict(graph=1, batch_iters=7, overlap=0),
@@ -114,7 +118,8 @@ def test_streaming_update_passes_bit_identical_to_oracle(case):
         assert M.info()["streaming"] == 1
         for kw in (dict(schedule=0), dict(schedule=1), dict(schedule=1, graph=1, batch_iters=4),
                    dict(schedule=0, graph=0, overlap=1), dict(schedule=2),
-                   dict(schedule=2, graph=1, batch_iters=3)):
+                   dict(schedule=2, graph=1, batch_iters=3), dict(schedule=3),
+                   dict(schedule=3, graph=1, batch_iters=5)):
             say(f"streaming {case} {kw}")
             res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgsafe", **kw)
             assert res.status == ref.status and res.iters == ref.iters, (case, kw)
@@ -124,7 +129,7 @@ def test_streaming_update_passes_bit_identical_to_oracle(case):
         assert M2.info()["streaming"] == 0  # small systems: automatic choice is off
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 @pytest.mark.parametrize("case", ["cd2d_64", "rand_band_20k", "nonsym_ragged_3001"])
 def test_fused_schedules_with_residual_replacement(case, schedule):
     """p-BiCGSafe-rr with a fused schedule: a replacement step and the iteration after it
@@ -156,7 +161,7 @@ def test_fused_schedule_resume_from_oracle_state():
             M.set_state(v, st.vec(v))
         M.set_state("b", A.b)
         M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "f", "rhoref"]})
-        for sched in (1, 2):
+        for sched in (1, 2, 3):
             for v in ["x", "r", "rs", "s", "y", "t", "p", "u", "z", "w", "l", "g", "q", "o"]:
                 M.set_state(v, st.vec(v))
             M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "zeta", "eta", "f",
@@ -168,7 +173,7 @@ def test_fused_schedule_resume_from_oracle_state():
                 assert np.array_equal(M.get_state(v), st2.vec(v)), (sched, v)
 
 
-@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 2, 3])
 def test_fused_schedule_statuses(schedule):
     # A = I converges at i = 1, the first stop test that reads fused partial sums
     for n in (1, 2, 63, 1000):
@@ -196,4 +201,4 @@ def test_fused_schedule_statuses(schedule):
             with pytest.raises(pipesafe.PipesafeError):
                 M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=schedule)
         with pytest.raises(pipesafe.PipesafeError):
-            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=3)
+            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=4)

@@ -253,7 +253,7 @@ def test_device_layout_choice():
             info = M.info()
         assert info["format"] == fmt, name
         assert info["n"] == A.n and info["nnz"] == A.nnz
-        assert info["auto_overlap"] == 0 and info["auto_schedule"] == 2  # small systems
+        assert info["auto_overlap"] == 0 and info["auto_schedule"] == 3  # small systems
         if fmt == "sell":
             L = np.diff(A.rowptr)
             ns = (A.n + 63) // 64

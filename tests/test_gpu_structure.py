@@ -4,7 +4,10 @@
   * p-BiCGSafe: two sparse products and one reduction phase per iteration in
     every schedule, the reduction phase on the second stream when the overlap
     is on (the one-GPU form of hiding the global reduction behind A s_i,
-    Section 3) and on the main stream when it is off;
+    Section 3) and on the main stream when it is off; schedule 3 puts the
+    reduction phase inside the launches around A s_i (the fold in its
+    prologue, the finish at the start of the w pass): three launches on one
+    stream;
   * p-BiCGSafe-rr: a replacement step (Algorithm 5) forms q, w, r, l, g, s as
     true products -- six launches: the seventh product of the algorithm, A s_i,
     has no use in that step and is skipped -- with its reduction phase on the
@@ -68,17 +71,33 @@ def test_pbicgsafe_two_products_one_phase(schedule, overlap):
                 assert n["dots"] <= 1, n  # a fold of the partial sums, or none
 
 
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_pbicgsafe_single_stream_schedule(overlap):
+    A = W.cd2d(48, 10.0)
+    with pipesafe.Matrix.from_csr(A) as M:
+        for k in (3, 4):
+            n, aux = iteration(M, A, "pbicgsafe", k, schedule=3, overlap=overlap)
+            # A s_i (folding the partial sums), the w pass (finishing them), A w_i
+            assert n == {"spmv": 1, "spmv_fused": 1, "update": 1, "dots": 0, "dots_finish": 0,
+                         "other": 0}, n
+            assert sum(aux.values()) == 0, aux
+
+
 def test_replacement_step_products():
     A = W.cd2d(48, 10.0)
     with pipesafe.Matrix.from_csr(A) as M:
-        for sched in (0, 2):
+        for sched in (0, 2, 3):
             n, aux = iteration(M, A, "pbicgsafe_rr", 4, rr_m=4, schedule=sched, overlap=1)
             # q = A o, w = A u, l = A t, g = A y, s = A r, and r = b - A x
             assert n["spmv"] == 5 and n["spmv_fused"] == 1, n
             assert n["dots"] == 1 and n["dots_finish"] == 1, n  # its own reduction pass
             assert sum(aux.values()) == 0, aux  # a replacement step is one chain
             std, _ = iteration(M, A, "pbicgsafe_rr", 3, rr_m=4, schedule=sched, overlap=1)
-            assert std["spmv"] + std["spmv_fused"] == 2 and std["dots_finish"] == 1, std
+            assert std["spmv"] + std["spmv_fused"] == 2, std
+            assert std["dots_finish"] == (0 if sched == 3 else 1), std
+            # the step after a replacement forms its inner products in their own pass
+            nxt, _ = iteration(M, A, "pbicgsafe_rr", 5, rr_m=4, schedule=sched, overlap=1)
+            assert nxt["spmv"] + nxt["spmv_fused"] == 2 and nxt["dots_finish"] == 1, nxt
 
 
 def test_ssbicgsafe2_one_stream():

@@ -26,7 +26,7 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-CASES = [("pbicgsafe", dict(schedule=2)), ("pbicgsafe", dict(schedule=0)),
+CASES = [("pbicgsafe", dict(schedule=2)), ("pbicgsafe", dict(schedule=3)), ("pbicgsafe", dict(schedule=0)),
          ("pbicgsafe", dict(schedule=1, overlap=1)), ("pbicgsafe_rr", dict(rr_m=20)),
          ("ssbicgsafe2", {}), ("pbicgstab", dict(overlap=1))]
 
