@@ -77,7 +77,8 @@ def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
                  registers) + A w with q, l, g, s (M+64n)
     ssBiCGSafe2: A r (M+16n) + 9 dots (40n) + p, u (64n) + A u with t, z, y, x, r (M+104n)
     p-BiCGStab:  pass 1 (96n) + A z (M+16n) + 2 dots (16n) + pass 2 (72n) + A w (M+16n)
-                 + 5 dots (40n)
+                 + 5 dots (40n); single-stream schedule (3): the passes also read r0*
+                 (104n, 80n) and form the partial sums, no dot passes: 2M + 216n
     (p-BiCGSafe-rr is counted as p-BiCGSafe; its replacement steps add ~1% at m = 100.)
     p-BiCGSafe, fused-dot schedule: A s (M+16n) + pass A with r0* (168n) + A w with q, l, g, s
                  and y, r, r0* (M+88n)
@@ -92,6 +93,8 @@ def bytes_per_iteration(variant, n, nnz, schedule=0, info=None):
         return 2 * M + 272 * n
     if variant in ("pbicgsafe", "pbicgsafe_rr") and schedule in (2, 3):
         return 2 * M + 248 * n
+    if variant == "pbicgstab" and schedule == 3:
+        return 2 * M + 216 * n
     return {"pbicgsafe": 2 * M + 280 * n, "pbicgsafe_rr": 2 * M + 280 * n,
             "ssbicgsafe2": 2 * M + 224 * n, "pbicgstab": 2 * M + 256 * n}[variant]
 
@@ -457,10 +460,12 @@ def main():
     variant = args.variant
 
     # one profiled solve to find the dominant kernel class
-    if variant != "pbicgsafe":
-        sched = 0
-    else:
+    if variant in ("pbicgsafe", "pbicgsafe_rr"):
         sched = info["auto_schedule"] if args.schedule < 0 else args.schedule
+    elif variant == "pbicgstab":  # the single-stream schedule unless asked for the passes
+        sched = 0 if args.schedule == 0 else 3
+    else:
+        sched = 0
     res = M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=variant, overlap=args.overlap,
                       schedule=sched, profile=CLASSES[:4], hist=False)
     stats = M.kernel_stats()
@@ -532,12 +537,12 @@ def main():
 
     if not args.no_variants:
         var = {}
-        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", -1), ("pbicgstab", 0)]
+        others = [("ssbicgsafe2", 0), ("pbicgsafe_rr", -1), ("pbicgstab", -1), ("pbicgstab", 0)]
         others += [("pbicgsafe", sc) for sc in (0, 1, 2, 3) if sc != sched]
         for v, sc in others:
-            key = v if v != "pbicgsafe" else {0: "pbicgsafe_dot_pass", 1: "pbicgsafe_fused_dots",
-                                              2: "pbicgsafe_fused_epilogue",
-                                              3: "pbicgsafe_single_stream"}[sc]
+            key = {"pbicgsafe": {0: "pbicgsafe_dot_pass", 1: "pbicgsafe_fused_dots",
+                                 2: "pbicgsafe_fused_epilogue", 3: "pbicgsafe_single_stream"},
+                   "pbicgstab": {-1: "pbicgstab", 0: "pbicgstab_dot_passes"}}.get(v, {}).get(sc, v)
             M.solve_dev(b, None, x, tol=tol, maxit=maxit, variant=v, schedule=sc)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -547,6 +552,8 @@ def main():
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t1) / reps
             sc_run = info["auto_schedule"] if sc < 0 else sc  # what the library chose
+            if v == "pbicgstab":  # its own rule: 3 for one system unless asked for 0
+                sc_run = 0 if sc == 0 else 3
             gbps = bytes_per_iteration(v, A.n, A.nnz, sc_run, info) * rv.iters / (ms * 1e-3) / 1e9
             v = key
             var[v] = {"iterations": rv.iters, "status": rv.status_name, "time_to_tol_ms": round(ms, 3),

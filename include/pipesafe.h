@@ -93,10 +93,11 @@ typedef struct {
   int32_t graph;       /* 1 (default): replay batches of identical iterations as cached
                           HIP graphs; 0: launch every kernel directly.  Results are
                           bit-identical either way.  Ignored while profiling.          */
-  int32_t schedule;    /* p-BiCGSafe and p-BiCGSafe-rr.  -1 (default): automatic --
+  int32_t schedule;    /* Where the reduction phases run: p-BiCGSafe, p-BiCGSafe-rr and
+                          (0 and 3 only) p-BiCGStab.  -1 (default): automatic --
                           sliced layout: 3; CSR: 3 below 2^18 rows, else 0;
-                          batches: 2
-                          (ps_info.auto_schedule tells; other variants ignore -1).
+                          batches: 2 (ps_info.auto_schedule tells); p-BiCGStab: 3
+                          for one system, 0 for batches; ssBiCGSafe2 ignores -1.
                           With -rr, a replacement step and the iteration after it form
                           their inner products in their own pass.
                           0: the reduction phase of Algorithm 4
@@ -124,8 +125,14 @@ typedef struct {
                           system only (batches: PS_EINVAL).  Measured: 7-14% faster
                           than 2 on stencils from 24^3 to 128^3 rows and on banded
                           CSR matrices up to 2*10^5 rows.
-                          Results are bit-identical to schedule 0.  Other variants: 1,
-                          2 and 3 are PS_EINVAL.                                        */
+                          p-BiCGStab, 3: pass 1 also forms the partial sums of
+                          (q,y), (y,y), (r0*,s), (r0*,z) and pass 2 those of
+                          (r0*,r), (r0*,w), (r,r); the products A z_i and A w_{i+1}
+                          fold and finish the two reduction phases the same way:
+                          four launches per iteration on one stream, 40n bytes fewer
+                          than the separate passes (0).
+                          Results are bit-identical to schedule 0.  ssBiCGSafe2: 1, 2
+                          and 3 are PS_EINVAL; p-BiCGStab: 1 and 2.                     */
   int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).
                           0 (default): use it as given.
                           1: if ||b - A x0|| > ||b|| (or is not finite), start from

@@ -647,32 +647,37 @@ __global__ __launch_bounds__(kBlock) void k_fold_partials(const double *__restri
   fold_slice(pa, ga, pb, gb, out, gridDim.x, blockIdx.x, lds);
 }
 
-// Lean sums of the nine products for use inside a sparse product (the
-// single-stream schedule), where the fold and finish must stay short and use
-// few registers: one triple accumulator per thread, no per-product register
-// arrays.  Thread t < 252 works for product t / 28 (28 threads each) and adds
-// its entries sequentially; those partials go through LDS, where lane 4j + q of
-// wavefront 0 adds seven of product j's, and two quad steps add the four.
-// The order differs from block_sum_td's, which the triple accumulators make
-// immaterial: the final rounding gives each product rounded once from its
-// exact value either way (see TD).
-constexpr int kLeanPer = 28;                      // threads per product
-constexpr int kLeanLds = 9 * kLeanPer * kPart;    // doubles of LDS the lean sums use
-static_assert(9 * kLeanPer <= kBlock && kLeanPer % 4 == 0, "lean sums: 252 threads, quarters");
+// Lean sums of a reduction phase's ND products for use inside a sparse product
+// (the single-stream schedule), where the fold and finish must stay short and
+// use few registers: one triple accumulator per thread, no per-product register
+// arrays.  kPer threads work for each product (thread t for product t / kPer)
+// and add their entries sequentially; those partials go through LDS, where lane
+// 4j + q of wavefront 0 adds a quarter of product j's, and two quad steps add
+// the four quarters.  The order differs from block_sum_td's, which the triple
+// accumulators make immaterial: the final rounding gives each product rounded
+// once from its exact value either way (see TD).
+template <int ND>
+struct Lean {
+  static_assert(ND >= 1 && 4 * ND <= kWave, "the quarters of every product in one wavefront");
+  static constexpr int kPer = ((kBlock / ND) & ~3) < 64 ? ((kBlock / ND) & ~3) : 64;
+};
+constexpr int kLeanLds = kBlock * kPart;  // doubles of LDS the lean sums use (ND * kPer <= kBlock)
 
-// Thread (j, s) = (t / 28, t % 28) holds a partial of product j; on return lane
-// 4j of wavefront 0 (j < 9) holds product j's total.  Every thread calls it.
-__device__ __forceinline__ TD lean_sum9(const TD &acc, double *lds) {
+// Thread (j, s) = (t / kPer, t % kPer) holds a partial of product j; on return
+// lane 4j of wavefront 0 (j < ND) holds product j's total.  Every thread calls it.
+template <int ND>
+__device__ __forceinline__ TD lean_sum(const TD &acc, double *lds) {
+  constexpr int P = Lean<ND>::kPer;
   const int t = threadIdx.x;
-  if (t < 9 * kLeanPer) td_store(lds, t, acc);
+  if (t < ND * P) td_store(lds, t, acc);
   __syncthreads();
   TD r{0.0, 0.0, 0.0};
-  if (t < 36) {
-    const int base = (t >> 2) * kLeanPer + (t & 3) * (kLeanPer / 4);
+  if (t < 4 * ND) {
+    const int base = (t >> 2) * P + (t & 3) * (P / 4);
     r = td_load(lds, base);
-    for (int k = 1; k < kLeanPer / 4; ++k) td_add(r, td_load(lds, base + k));
+    for (int k = 1; k < P / 4; ++k) td_add(r, td_load(lds, base + k));
   }
-  if (t < kWave) {  // lanes 36..63 add zeros
+  if (t < kWave) {  // the lanes past 4 ND add zeros
     td_step<0xB1>(r);  // quad_perm [1,0,3,2]
     td_step<0x4E>(r);  // quad_perm [2,3,0,1]
   }
@@ -680,63 +685,70 @@ __device__ __forceinline__ TD lean_sum9(const TD &acc, double *lds) {
   return r;
 }
 
-// The lean form of fold_slice: slice `slice` of the two partial lists into
-// out[j * G + slice].
-__device__ __forceinline__ void fold_lean(const double *__restrict__ pa, int ga,
-                                          const double *__restrict__ pb, int gb,
-                                          double *__restrict__ out, int G, int slice,
-                                          double *lds) {
+// The partial lists a fold reads: product j comes from list pb if bit j of
+// from_b is set, else from pa, at row (rows >> 4j) & 15 of that list; each row
+// of pa holds ga triples, each of pb gb.
+struct FoldLists {
+  const double *pa, *pb;
+  int ga, gb;
+  unsigned from_b;
+  unsigned long long rows;
+};
+
+// Slice `slice` of the fold (kBlock entries of every list) into out[j * G + slice].
+template <int ND>
+__device__ __forceinline__ void fold_lean(const FoldLists &L, double *__restrict__ out, int G,
+                                          int slice, double *lds) {
   static_assert(kFoldPerThread == 1, "a slice is kBlock entries of every list");
-  // product j comes from list (kFromB >> j) & 1 (0: pa, 1: pb), row (kRows >> 4j) & 15:
-  // pb rows 0-3 are (a, c, d, g), pa rows 0-4 are (b, e, f, h, rho)
-  constexpr unsigned kFromB = 0x4Du;                  // products 0, 2, 3, 6
-  constexpr unsigned long long kRows = 0x433212100ull;  // 0,0,1,2,1,2,3,3,4
+  constexpr int P = Lean<ND>::kPer;
   const int t = threadIdx.x;
   TD acc{0.0, 0.0, 0.0};
-  if (t < 9 * kLeanPer) {
-    const int j = t / kLeanPer, s = t % kLeanPer;
-    const bool from_b = (kFromB >> j) & 1u;
-    const int len = from_b ? gb : ga;
-    const double *src = (from_b ? pb : pa) + (size_t)((kRows >> (4 * j)) & 15u) * len * kPart;
-    for (int e = s; e < kBlock; e += kLeanPer) {
+  if (t < ND * P) {
+    const int j = t / P, s = t % P;
+    const bool from_b = (L.from_b >> j) & 1u;
+    const int len = from_b ? L.gb : L.ga;
+    const double *src = (from_b ? L.pb : L.pa) + (size_t)((L.rows >> (4 * j)) & 15u) * len * kPart;
+    for (int e = s; e < kBlock; e += P) {
       const int idx = slice * kBlock + e;
       if (idx < len) td_add(acc, td_load(src, idx));
     }
   }
-  const TD r = lean_sum9(acc, lds);
-  if (t < 36 && (t & 3) == 0) td_store(out, (int64_t)(t >> 2) * G + slice, r);
+  const TD r = lean_sum<ND>(acc, lds);
+  if (t < 4 * ND && (t & 3) == 0) td_store(out, (int64_t)(t >> 2) * G + slice, r);
 }
 
-// The lean form of finish_block's sums: the G folded triples of each product,
-// rounded once into fin[0..8].
+// The G folded triples of each product, rounded once into fin[0 .. ND-1].
+template <int ND>
 __device__ __forceinline__ void finish_lean(const double *__restrict__ partials, int G,
                                             double *lds, double *fin) {
+  constexpr int P = Lean<ND>::kPer;
   const int t = threadIdx.x;
   TD acc{0.0, 0.0, 0.0};
-  if (t < 9 * kLeanPer) {
-    const int j = t / kLeanPer, s = t % kLeanPer;
-    for (int b = s; b < G; b += kLeanPer) td_add(acc, td_load(partials, (int64_t)j * G + b));
+  if (t < ND * P) {
+    const int j = t / P, s = t % P;
+    for (int b = s; b < G; b += P) td_add(acc, td_load(partials, (int64_t)j * G + b));
   }
-  const TD r = lean_sum9(acc, lds);
-  if (t < 36 && (t & 3) == 0) fin[t >> 2] = td_round(r);  // the one final rounding
+  const TD r = lean_sum<ND>(acc, lds);
+  if (t < 4 * ND && (t & 3) == 0) fin[t >> 2] = td_round(r);  // the one final rounding
 }
 
 // Fold and finish inside another kernel (the single-stream schedule): workgroup
-// `slice` (< G) folds its slice into F.partials ([9][G]); the workgroup that
-// completes the last slice -- counted in the control word C_FOLDS, which it
-// resets for the next iteration -- then adds the G slices and runs FinSafe, as
-// k_fold_partials and k_dots_finish would (with the lean sums).  No workgroup
-// waits for another: the others go on with their own work.  A release fence
-// before the count and an acquire fence after the last count make every slice
-// visible to the last workgroup, whichever XCD and L2 wrote it.  Every thread
-// of the block calls it; lds holds kLeanLds doubles.
-__device__ __forceinline__ void fold_then_finish(const double *__restrict__ pa, int ga,
-                                                 const double *__restrict__ pb, int gb,
-                                                 const DotArgs &F, int G, int slice, double *lds) {
+// `slice` (< G) folds its slice of the lists into F.partials ([ND][G]); the
+// workgroup that completes the last slice -- counted in the control word
+// C_FOLDS, which it resets for the next phase -- then adds the G slices and
+// runs Fin, as k_fold_partials and k_dots_finish would (with the lean sums).
+// No workgroup waits for another: the others go on with their own work.  A
+// release fence before the count and an acquire fence after the last count
+// make every slice visible to the last workgroup, whichever XCD and L2 wrote
+// it.  Every thread of the block calls it; lds holds kLeanLds doubles.
+template <int ND, class Fin>
+__device__ __forceinline__ void fold_then_finish(const FoldLists &L, const DotArgs &F, int G,
+                                                 int slice, double *lds) {
   __shared__ int last;
-  __shared__ double fin[9];
-  fold_lean(pa, ga, pb, gb, F.partials, G, slice, lds);
-  __syncthreads();  // the slice's stores (lanes 0, 4, .., 32) are done
+  __shared__ double fin[ND];
+  if (F.ctl[C_DONE]) return;  // the same answer in every fold workgroup (nothing else runs)
+  fold_lean<ND>(L, F.partials, G, slice, lds);
+  __syncthreads();  // the slice's stores (lanes 0, 4, ..) are done
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const int before = atomicAdd(&F.ctl[C_FOLDS], 1);
@@ -750,15 +762,20 @@ __device__ __forceinline__ void fold_then_finish(const double *__restrict__ pa, 
   if (!last) return;
   FinPre pre{};
   if (threadIdx.x == 0) pre = fin_preload(F);
-  finish_lean(F.partials, G, lds, fin);
+  finish_lean<ND>(F.partials, G, lds, fin);
   __syncthreads();
   if (threadIdx.x == 0) {
-    double d[9];
+    double d[ND];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) d[j] = fin[j];
-    FinSafe::run(F, pre, d);
+    for (int j = 0; j < ND; ++j) d[j] = fin[j];
+    Fin::run(F, pre, d);
     if (F.ctl[C_DONE]) atomicSub(F.running, 1);
   }
 }
+
+// The lists of the BiCGSafe schedules: the fused epilogue's [5][ga] triples of
+// (b, e, f, h, rho) and [4][gb] of (a, c, d, g), in the order of ProdSafe9
+constexpr unsigned kSafeFromB = 0x4Du;                   // products 0, 2, 3, 6 from pb
+constexpr unsigned long long kSafeRows = 0x433212100ull;  // rows 0,0,1,2,1,2,3,3,4
 
 }  // namespace ps

@@ -535,8 +535,9 @@ int iter_pbicgsafe(ps_matrix *M, const Plan &P, int i) {
       D.tol = P.tol;
       D.flags = 0;
       D.running = M->running();
-      PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStoreFold{As, pa, pb, M->nblk, M->nblk, M->gfold, D},
-                  C_DONE, P.kry32));
+      const FoldLists lists{pa, pb, M->nblk, M->nblk, kSafeFromB, kSafeRows};
+      PS_TRY(spmv(M, A, PS_K_SPMV, S, EpiStoreFold<9, FinSafe>{As, lists, M->gfold, D}, C_DONE,
+                  P.kry32));
     } else {
       PS_TRY(fork(M, P));
       // the reduction phase on the second stream, enqueued first so that its few
@@ -656,7 +657,44 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
          *Z = M->slot(PS_V_Z), *W = M->slot(PS_V_W), *Q = M->slot(PS_V_Q), *V = M->slot(PS_V_V);
   Stab1Args s1{R, W, T, V, Pp, S, Z, Q, Y, M->sc, M->ctl, M->n, next_rev(M)};
   s1.chunk_sys = M->chunk_sys;
-  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1, pair_grid(M->n), 0, s1));
+  if (P.fused3) {
+    // one stream: each pass also forms the partial sums of the inner products of
+    // the vectors it writes, and the product after it folds them and runs the
+    // phase's finish (omega after pass 1; beta, alpha and the stop test after
+    // pass 2).  The products keep their C_HALT stop word, so that a product whose
+    // own prologue stops the solve still completes its rows, as before.
+    double *p1 = M->fpart, *p2 = p1 + kPart * 4 * (size_t)M->ga;  // [4][ga], [3][ga]
+    double *pf = M->fpart + kPart * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk);
+    const int gf = (M->ga + kBlock - 1) / kBlock;
+    DotArgs D{};
+    D.n = M->n;
+    D.ctl = M->ctl;
+    D.sc = M->sc;
+    D.hist = M->hist;
+    D.maxit = P.maxit;
+    D.tol = P.tol;
+    D.flags = 0;
+    D.running = M->running();
+    s1.rs = RS;
+    s1.part = p1;
+    PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1<true>, pair_grid(M->n), 0, s1));
+    D.partials = pf;  // [2][gf]: (q, y), (y, y), rows 0 and 1 of pass 1's list
+    const FoldLists l1{p1, p1, M->ga, M->ga, 0u, 0x10ull};
+    PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStoreFold<2, FinStabOmega>{V, l1, gf, D}, C_HALT,
+                P.kry32));  // v_i = A z_i
+    Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
+    s2.rs = RS;
+    s2.part = p2;
+    PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2<true>, pair_grid(M->n), 0, s2));
+    // [5][gf] in FinStabBetaAlpha's order: (r0*, r), (r0*, w) from pass 2's rows 0, 1;
+    // (r0*, s), (r0*, z) from pass 1's rows 2, 3; (r, r) from pass 2's row 2
+    D.partials = pf + kPart * 2 * (size_t)gf;
+    const FoldLists l2{p2, p1, M->ga, M->ga, 0xCu, 0x23210ull};
+    PS_TRY(spmv(M, A, PS_K_SPMV, W, EpiStoreFold<5, FinStabBetaAlpha>{T, l2, gf, D}, C_HALT,
+                P.kry32));  // t_{i+1} = A w_{i+1}
+    return PS_OK;
+  }
+  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1<false>, pair_grid(M->n), 0, s1));
   PS_TRY(fork(M, P));
   // each reduction phase enqueued ahead of the product it overlaps
   PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, P.maxit, P.tol, 0, M->hist));
@@ -664,7 +702,7 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
   PS_TRY(join(M, P));
   Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
   s2.chunk_sys = M->chunk_sys;
-  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2, pair_grid(M->n), 0, s2));
+  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2<false>, pair_grid(M->n), 0, s2));
   PS_TRY(fork(M, P));
   PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, P.maxit, P.tol, 0,
                                            M->hist));
@@ -935,7 +973,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
   // schedule 3 folds in the product's first gfold workgroups: never more than the
   // product has with the layouts built here (gfold = nblk / 256, rounded up)
-  if (o.schedule < -1 || o.schedule > 3 || (o.schedule >= 1 && !safe_pipelined) ||
+  if (o.schedule < -1 || o.schedule > 3 ||
+      (o.schedule >= 1 && !safe_pipelined && !(o.schedule == 3 && variant == PS_PBICGSTAB)) ||
       (o.schedule == 3 && (batch || M->gfold > M->nblk)))
     return PS_EINVAL;
   if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_VECTORS ||
@@ -979,7 +1018,11 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const int sched = o.schedule >= 0 ? o.schedule : auto_schedule(M);
   P.fused = safe_pipelined && sched >= 1;
   P.fused2 = P.fused && sched >= 2;
-  P.fused3 = P.fused && sched == 3;
+  // p-BiCGStab: schedule 3 or the separate passes; automatically 3 for one system
+  // (microseconds per iteration, 0 / 3: 128^3 stencil 166.7 / 148.9, 96^3 77.8 /
+  // 61.7, 2*10^5-row band 74.7 / 59.8, 10^6-row band 243.8 / 229.2)
+  const bool stab3 = o.schedule == 3 || (o.schedule < 0 && !batch);
+  P.fused3 = variant == PS_PBICGSTAB ? stab3 : sched == 3 && safe_pipelined;
   P.stream_nt = safe_pipelined && streaming(M);
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;

@@ -404,27 +404,27 @@ struct EpiStore {
   __device__ __forceinline__ void store(int r, double ax, const In &) const { y[r] = ax; }
 };
 
-// y = A x, with a prologue for the single-stream fused schedule (schedule 3):
-// workgroups 0 .. gf-1 fold the partial sums of this iteration's nine inner
-// products that the previous fused epilogue left ([5][ga] and [4][gb] triples)
-// into [9][gf] (fin.partials), and the last of them to finish adds those and
-// forms the iteration's stop test and scalars (fold_then_finish) -- the
-// reduction phase inside the product it is hidden behind, with no second stream
-// and no launch of its own.  Rows are stored as by EpiStore; no workgroup of the
-// product reads what the prologue writes.
+// y = A x, with a prologue for the single-stream schedule (schedule 3): the
+// product's first gf workgroups fold the partial sums of a reduction phase's ND
+// inner products that earlier kernels left (lists) into [ND][gf]
+// (fin.partials), and the last of them to finish adds those and runs the
+// phase's finish Fin (fold_then_finish) -- the reduction phase inside the
+// product it is hidden behind, with no second stream and no launch of its own.
+// Rows are stored as by EpiStore; no workgroup of the product reads what the
+// prologue writes.
+template <int ND, class Fin>
 struct EpiStoreFold {
   static constexpr int kDots = 0;
   __device__ __forceinline__ EpiStoreFold at(int) const { return *this; }
   double *y;
-  const double *pa, *pb;  // the epilogue's partial triples (the layout fused_finish reads)
-  int ga, gb;
-  int gf;                 // fold slices (workgroups taking part)
-  DotArgs fin;            // the finish: fin.partials = the [9][gf] folded triples
+  FoldLists lists;
+  int gf;      // fold slices (workgroups taking part)
+  DotArgs fin; // the finish: fin.partials = the [ND][gf] folded triples
   struct In {};
   __device__ __forceinline__ In load(int) const { return In{}; }
   __device__ __forceinline__ void store(int r, double ax, const In &) const { y[r] = ax; }
   __device__ __forceinline__ void prologue(double *lds) const {
-    if ((int)blockIdx.x < gf) fold_then_finish(pa, ga, pb, gb, fin, gf, (int)blockIdx.x, lds);
+    if ((int)blockIdx.x < gf) fold_then_finish<ND, Fin>(lists, fin, gf, (int)blockIdx.x, lds);
   }
 };
 

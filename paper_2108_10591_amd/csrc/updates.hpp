@@ -431,6 +431,10 @@ __global__ __launch_bounds__(kBlock) void k_widen(double *__restrict__ dst,
 // pass 1 of iteration i (after the stop test on rho_i):
 //   p_i = r_i + beta (p - omega s),  s_i = w_i + beta (s - omega z),
 //   z_i = t_i + beta (z - omega v),  q_i = r_i - alpha s_i,  y_i = w_i - alpha z_i
+// With DOTS (the single-stream schedule) it also forms the block partial sums
+// of the inner products whose vectors it has just written: [4][gridDim.x]
+// triples of (q, y), (y, y) -- phase 1 -- and (r0*, s), (r0*, z) -- two of
+// phase 2's, whose s and z nothing changes before that phase.
 struct Stab1Args {
   const double *r, *w, *t, *v;
   double *p, *s, *z, *q, *y;
@@ -439,10 +443,12 @@ struct Stab1Args {
   int64_t n;
   int rev;  // sweep direction
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
+  const double *rs;      // r0* (DOTS)
+  double *part;          // partial sums (DOTS)
 };
 
-template <int W>
-__device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k) {
+template <int W, bool DOTS>
+__device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k, TD (&acc)[4]) {
   const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], om = P.sc[PS_S_OMEGA];
   double r[W], w[W], t[W], v[W], p[W], s[W], z[W], q[W], y[W];
   ldv<W>(P.r, k, r);
@@ -460,6 +466,17 @@ __device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k) {
     q[j] = r[j] - al * s[j];
     y[j] = w[j] - al * z[j];
   }
+  if constexpr (DOTS) {
+    double rs[W];
+    ldv<W>(P.rs, k, rs);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      td_fma(acc[0], q[j], y[j]);
+      td_fma(acc[1], y[j], y[j]);
+      td_fma(acc[2], rs[j], s[j]);
+      td_fma(acc[3], rs[j], z[j]);
+    }
+  }
   stv<W>(P.p, k, p);
   stv<W>(P.s, k, s);
   stv<W>(P.z, k, z);
@@ -467,15 +484,34 @@ __device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k) {
   stv<W>(P.y, k, y);
 }
 
+// The partial sums of a pass's block: [ND][gridDim.x] triples, block b's at
+// column b.
+template <int ND>
+__device__ __forceinline__ void store_pass_partials(TD (&acc)[ND], double *part, int b) {
+  __shared__ double red[kTdSlots * ND * kPart];
+  const TD t = block_sum_td<ND>(acc, red);
+  if (threadIdx.x < ND) td_store(part, (int64_t)threadIdx.x * gridDim.x + b, t);
+}
+
+template <bool DOTS>
 __global__ __launch_bounds__(kBlock) void k_stab_pass1(Stab1Args P_) {
   const Stab1Args P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
-  PS_DISPATCH_PAIRS(P.n, stab1_body);
+  TD acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = TD{0.0, 0.0, 0.0};
+  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
+  if (k + 1 < P.n) stab1_body<2, DOTS>(P, k, acc);
+  else if (k < P.n) stab1_body<1, DOTS>(P, k, acc);
+  if constexpr (DOTS) store_pass_partials<4>(acc, P.part, b);
 }
 
 // pass 2 of iteration i (after omega_i):
 //   x_{i+1} = x_i + alpha p_i + omega q_i,  r_{i+1} = q_i - omega y_i,
 //   w_{i+1} = y_i - omega (t_i - alpha v_i)
+// With DOTS also [3][gridDim.x] partial triples of (r0*, r), (r0*, w), (r, r)
+// of the new r and w (the rest of phase 2).
 struct Stab2Args {
   const double *p, *q, *y, *t, *v;
   double *x, *r, *w;
@@ -484,10 +520,12 @@ struct Stab2Args {
   int64_t n;
   int rev;  // sweep direction
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
+  const double *rs;      // r0* (DOTS)
+  double *part;          // partial sums (DOTS)
 };
 
-template <int W>
-__device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k) {
+template <int W, bool DOTS>
+__device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k, TD (&acc)[3]) {
   const double al = P.sc[PS_S_ALPHA], om = P.sc[PS_S_OMEGA];
   double p[W], q[W], y[W], t[W], v[W], x[W], r[W], w[W];
   ldv<W>(P.p, k, p);
@@ -502,15 +540,33 @@ __device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k) {
     r[j] = q[j] - om * y[j];
     w[j] = y[j] - om * (t[j] - al * v[j]);
   }
+  if constexpr (DOTS) {
+    double rs[W];
+    ldv<W>(P.rs, k, rs);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      td_fma(acc[0], rs[j], r[j]);
+      td_fma(acc[1], rs[j], w[j]);
+      td_fma(acc[2], r[j], r[j]);
+    }
+  }
   stv<W>(P.x, k, x);
   stv<W>(P.r, k, r);
   stv<W>(P.w, k, w);
 }
 
+template <bool DOTS>
 __global__ __launch_bounds__(kBlock) void k_stab_pass2(Stab2Args P_) {
   const Stab2Args P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
-  PS_DISPATCH_PAIRS(P.n, stab2_body);
+  TD acc[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) acc[j] = TD{0.0, 0.0, 0.0};
+  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
+  if (k + 1 < P.n) stab2_body<2, DOTS>(P, k, acc);
+  else if (k < P.n) stab2_body<1, DOTS>(P, k, acc);
+  if constexpr (DOTS) store_pass_partials<3>(acc, P.part, b);
 }
 
 // ------------------------------------------------------------ bookkeeping

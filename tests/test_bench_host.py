@@ -28,6 +28,9 @@ def test_iteration_bytes_are_the_sum_of_launch_bytes(n, nnz):
     b0, b1, b2, b3 = (bench.bytes_per_iteration("pbicgsafe", n, nnz, s) for s in (0, 1, 2, 3))
     assert b0 - b1 == 8 * n and b0 - b2 == 32 * n
     assert b3 == b2  # the same vector traffic on one stream
+    # p-BiCGStab on one stream: the dot passes' 56n gone, r0* read by both passes (16n)
+    assert bench.bytes_per_iteration("pbicgstab", n, nnz, 0) - \
+        bench.bytes_per_iteration("pbicgstab", n, nnz, 3) == 40 * n
     # the device layout's own matrix bytes replace the CSR estimate when known
     info = {"matrix_bytes": 123_456}
     assert bench.bytes_per_iteration("pbicgsafe", n, nnz, 2, info) == 2 * 123_456 + 248 * n

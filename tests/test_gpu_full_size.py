@@ -46,11 +46,13 @@ def case(request):
 
 
 @pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue",
-                                     "pbicgsafe+single_stream", "pbicgsafe@p1",
+                                     "pbicgsafe+single_stream", "pbicgstab+single_stream",
+                                     "pbicgsafe@p1",
                                      "pbicgsafe_rr@p2", "pbicgsafe_rr@p3"])
 def test_full_solve_reproduces_oracle(case, golden, variant):
     """Every method in FP64, the fused schedules of p-BiCGSafe (the same iteration; the
-    single-stream one is the automatic choice on the stencil), and the
+    single-stream one is the automatic choice on the stencil) and p-BiCGStab's
+    single-stream schedule, and the
     three mixed-precision forms the benchmark times (FP32 values in every product; FP32
     values in the Krylov products with FP64 replacement residuals every 100 iterations;
     the same with p, u, z held in FP32), in the library's automatic layout and schedule."""

@@ -196,9 +196,73 @@ def test_fused_schedule_statuses(schedule):
         r3 = M.solve(B.b, tol=1e-30, maxit=3, variant="pbicgsafe", schedule=schedule)
         o3 = O.solve(B, tol=1e-30, maxit=3, variant="pbicgsafe")
         assert r3.iters == 3 and np.array_equal(r3.x, o3.x)
-        # the schedules exist for p-BiCGSafe and p-BiCGSafe-rr only
-        for v in ("ssbicgsafe2", "pbicgstab"):
+        # the schedules exist for p-BiCGSafe and p-BiCGSafe-rr (and 3 for p-BiCGStab)
+        for v in ("ssbicgsafe2", "pbicgstab") if schedule < 3 else ("ssbicgsafe2",):
             with pytest.raises(pipesafe.PipesafeError):
                 M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=schedule)
         with pytest.raises(pipesafe.PipesafeError):
             M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=4)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_pbicgstab_single_stream_bit_identical_to_oracle(case):
+    """p-BiCGStab, schedule 3: the passes form the partial sums of both reduction phases
+    and the products fold and finish them -- the same inner products, so the oracle's
+    bits, with graphs or without, and the same bits as the separate passes (0)."""
+    A = CASES[case]()
+    for tol, maxit in ((1e-10, 3000), (0.0, 9)):
+        ref = O.solve(A, tol=tol, maxit=maxit, variant="pbicgstab")
+        with pipesafe.Matrix.from_csr(A) as M:
+            for kw in (dict(schedule=3), dict(schedule=3, graph=0),
+                       dict(schedule=3, graph=1, batch_iters=3), dict(schedule=0, overlap=1)):
+                say(f"pbicgstab {case} tol={tol} maxit={maxit} {kw}")
+                res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgstab", **kw)
+                assert res.status == ref.status and res.iters == ref.iters, (case, kw)
+                assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, kw)
+                assert np.array_equal(res.x, ref.x, equal_nan=True), (case, kw)
+
+
+def test_pbicgstab_single_stream_statuses_and_resume():
+    # A = I converges at the first stop test (the set-up's); a NaN in b is caught there too
+    for n in (1, 63, 1000):
+        E = W.identity(n, seed=n)
+        with pipesafe.Matrix.from_csr(E) as M:
+            res = M.solve(E.b, tol=1e-12, maxit=50, variant="pbicgstab", schedule=3)
+            ref = O.solve(E, tol=1e-12, maxit=50, variant="pbicgstab")
+        assert res.status == ref.status and res.iters == ref.iters and np.array_equal(res.x, ref.x)
+    B = W.small_nonsym(40, 0)
+    with pipesafe.Matrix.from_csr(B) as M:
+        b = B.b.copy()
+        b[7] = np.nan
+        assert M.solve(b, tol=1e-10, maxit=100, variant="pbicgstab", schedule=3).status == \
+            O.NONFINITE
+        for maxit in (0, 1, 3):
+            r = M.solve(B.b, tol=1e-30, maxit=maxit, variant="pbicgstab", schedule=3)
+            o = O.solve(B, tol=1e-30, maxit=maxit, variant="pbicgstab")
+            assert r.status == o.status and r.iters == o.iters and np.array_equal(r.x, o.x)
+        for sched in (1, 2):  # p-BiCGStab has the separate passes and schedule 3 only
+            with pytest.raises(pipesafe.PipesafeError):
+                M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgstab", schedule=sched)
+    S = W.skew_blocks(64, seed=1)  # breakdowns: the same status and step as the oracle
+    with pipesafe.Matrix.from_csr(S) as M:
+        res = M.solve(S.b, tol=1e-10, maxit=100, variant="pbicgstab", schedule=3)
+    ref = O.solve(S, tol=1e-10, maxit=100, variant="pbicgstab")
+    assert res.status == ref.status and res.iters == ref.iters
+    # resume from the oracle's state: every later iteration is the oracle's
+    A = W.workload("cd2d_64")
+    k, extra = 5, 4
+    st, _ = O.state_at(A, k, variant="pbicgstab")
+    st2, _ = O.state_at(A, k + extra, variant="pbicgstab")
+    names = ["x", "r", "rs", "s", "y", "t", "p", "z", "w", "q", "v"]
+    with pipesafe.Matrix.from_csr(A) as M:
+        for v in names:
+            M.set_state(v, st.vec(v))
+        M.set_state("b", A.b)
+        M.set_scalars({k_: st.scal(k_) for k_ in ["alpha", "beta", "omega", "f", "rhoref", "rho",
+                                                   "gs", "gw", "gz"]}
+                      | {"pending": st.scal("pending_breakdown")})
+        res = M.solve(A.b, tol=0.0, maxit=k + extra, variant="pbicgstab", resume=1, resume_iter=k,
+                      schedule=3, graph=1, batch_iters=2)
+        assert res.status == O.MAXIT and res.iters == k + extra
+        for v in ["x", "r", "p", "s", "z", "w", "t", "v", "q", "y"]:
+            assert np.array_equal(M.get_state(v), st2.vec(v)), v

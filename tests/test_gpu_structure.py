@@ -15,7 +15,8 @@
   * ssBiCGSafe2: two products and one reduction phase, all on one stream (its
     inner products need s_i = A r_i);
   * p-BiCGStab: two products and two reduction phases, each on the second
-    stream beside one product.
+    stream beside one product (schedule 0), or inside the product (schedule 3:
+    two passes and two products on one stream).
 Counts are per iteration: a solve stopped (tol = 0) at k + 1 minus one stopped
 at k."""
 import sys
@@ -113,8 +114,14 @@ def test_ssbicgsafe2_one_stream():
 def test_pbicgstab_two_products_two_phases(overlap):
     A = W.cd2d(48, 10.0)
     with pipesafe.Matrix.from_csr(A) as M:
-        n, aux = iteration(M, A, "pbicgstab", 3, overlap=overlap)
+        n, aux = iteration(M, A, "pbicgstab", 3, overlap=overlap, schedule=0)
         assert n["spmv"] == 2 and n["spmv_fused"] == 0, n
         assert n["dots"] == 2 and n["dots_finish"] == 2 and n["update"] == 2, n
         assert aux == {"spmv": 0, "dots": 2 * overlap, "update": 0, "spmv_fused": 0, "other": 0,
                        "dots_finish": 2 * overlap}, aux
+        # schedule 3: both phases inside the products, one stream
+        for k in (0, 3):
+            n, aux = iteration(M, A, "pbicgstab", k, overlap=overlap, schedule=3)
+            assert n == {"spmv": 2, "spmv_fused": 0, "update": 2, "dots": 0, "dots_finish": 0,
+                         "other": 0}, n
+            assert sum(aux.values()) == 0, aux
