@@ -63,6 +63,9 @@ constexpr int64_t kFusedMinRows = 1 << 18;
 // above the 256 MiB last-level cache; below it the cache still holds part of
 // the previous iteration's vectors and the hint costs a little).
 constexpr int64_t kStreamMinBytes = 512ll << 20;
+// p-BiCGStab's passes stream from a larger iteration: the hints cost 2-3% at
+// 112^3 (iteration ~550 MiB by the same count) and save 18% at 128^3 (~825 MiB)
+constexpr int64_t kStabStreamMinBytes = 640ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 constexpr int kSellRowsPerLane = 1;       // 64-row slices
 constexpr double kTuneMaxPadding = 1.5;   // the autotuner tries the sliced layout up to this
@@ -677,7 +680,9 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
     D.running = M->running();
     s1.rs = RS;
     s1.part = p1;
-    PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1<true>, pair_grid(M->n), 0, s1));
+    PS_TRY(P.stream_nt ? launch(M, A, PS_K_UPDATE, k_stab_pass1<true, true>, pair_grid(M->n), 0, s1)
+                       : launch(M, A, PS_K_UPDATE, k_stab_pass1<true, false>, pair_grid(M->n), 0,
+                                s1));
     D.partials = pf;  // [2][gf]: (q, y), (y, y), rows 0 and 1 of pass 1's list
     const FoldLists l1{p1, p1, M->ga, M->ga, 0u, 0x10ull};
     PS_TRY(spmv(M, A, PS_K_SPMV, Z, EpiStoreFold<2, FinStabOmega>{V, l1, gf, D}, C_HALT,
@@ -685,7 +690,9 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
     Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
     s2.rs = RS;
     s2.part = p2;
-    PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2<true>, pair_grid(M->n), 0, s2));
+    PS_TRY(P.stream_nt ? launch(M, A, PS_K_UPDATE, k_stab_pass2<true, true>, pair_grid(M->n), 0, s2)
+                       : launch(M, A, PS_K_UPDATE, k_stab_pass2<true, false>, pair_grid(M->n), 0,
+                                s2));
     // [5][gf] in FinStabBetaAlpha's order: (r0*, r), (r0*, w) from pass 2's rows 0, 1;
     // (r0*, s), (r0*, z) from pass 1's rows 2, 3; (r, r) from pass 2's row 2
     D.partials = pf + kPart * 2 * (size_t)gf;
@@ -694,7 +701,8 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
                 P.kry32));  // t_{i+1} = A w_{i+1}
     return PS_OK;
   }
-  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass1<false>, pair_grid(M->n), 0, s1));
+  PS_TRY(P.stream_nt ? launch(M, A, PS_K_UPDATE, k_stab_pass1<false, true>, pair_grid(M->n), 0, s1)
+                     : launch(M, A, PS_K_UPDATE, k_stab_pass1<false, false>, pair_grid(M->n), 0, s1));
   PS_TRY(fork(M, P));
   // each reduction phase enqueued ahead of the product it overlaps
   PS_TRY(dots<ProdStab2, FinStabOmega>(M, P.B, {Q, Y}, P.maxit, P.tol, 0, M->hist));
@@ -702,7 +710,8 @@ int iter_pbicgstab(ps_matrix *M, const Plan &P, int /*i*/) {
   PS_TRY(join(M, P));
   Stab2Args s2{Pp, Q, Y, T, V, X, R, W, M->sc, M->ctl, M->n, next_rev(M)};
   s2.chunk_sys = M->chunk_sys;
-  PS_TRY(launch(M, A, PS_K_UPDATE, k_stab_pass2<false>, pair_grid(M->n), 0, s2));
+  PS_TRY(P.stream_nt ? launch(M, A, PS_K_UPDATE, k_stab_pass2<false, true>, pair_grid(M->n), 0, s2)
+                     : launch(M, A, PS_K_UPDATE, k_stab_pass2<false, false>, pair_grid(M->n), 0, s2));
   PS_TRY(fork(M, P));
   PS_TRY(dots<ProdStab5, FinStabBetaAlpha>(M, P.B, {RS, R, W, S, Z}, P.maxit, P.tol, 0,
                                            M->hist));
@@ -867,9 +876,10 @@ int auto_schedule(const ps_matrix *M) {
   return M->n < kFusedMinRows ? 3 : 0;
 }
 // two sparse products and the update passes' 34 vector reads and writes
-bool streaming(const ps_matrix *M) {
+bool streaming(const ps_matrix *M, int32_t variant = PS_PBICGSAFE) {
   if (M->stream_override >= 0) return M->stream_override != 0;
-  return 2 * matrix_bytes(M) + 272 * M->n >= kStreamMinBytes;
+  return 2 * matrix_bytes(M) + 272 * M->n >=
+         (variant == PS_PBICGSTAB ? kStabStreamMinBytes : kStreamMinBytes);
 }
 
 // Put p, u, z in FP32 (to32) or FP64 storage, converting the slots that hold the
@@ -1023,7 +1033,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   // 61.7, 2*10^5-row band 74.7 / 59.8, 10^6-row band 243.8 / 229.2)
   const bool stab3 = o.schedule == 3 || (o.schedule < 0 && !batch);
   P.fused3 = variant == PS_PBICGSTAB ? stab3 : sched == 3 && safe_pipelined;
-  P.stream_nt = safe_pipelined && streaming(M);
+  P.stream_nt = (safe_pipelined || variant == PS_PBICGSTAB) && streaming(M, variant);
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;
   P.res32 = o.precision == PS_PREC_FP32_MATRIX;

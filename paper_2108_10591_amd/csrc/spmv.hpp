@@ -46,18 +46,6 @@ struct CsrDev {
   int nblk;
 };
 
-// Row-block index for workgroup `b`: consecutive workgroups are dispatched
-// round-robin over the 8 XCDs, so give each XCD a contiguous range of row
-// blocks; its L2 then holds the x entries its rows gather.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-  constexpr int kXcd = 8;
-  const int q = nb / kXcd, rem = nb % kXcd;
-  const int xcd = b % kXcd, k = b / kXcd;
-  // XCD x owns q (+1 if x < rem) consecutive blocks
-  const int start = xcd * q + (xcd < rem ? xcd : rem);
-  return start + k;
-}
-
 // IPT: nonzeros per thread of a short-row block (the block's LDS budget is
 // IPT * kBlock products).  Every load a thread needs for the products -- and,
 // with one lane per row, its row bounds and the epilogue's operands -- is

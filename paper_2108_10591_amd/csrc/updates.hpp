@@ -122,10 +122,16 @@ __device__ __forceinline__ bool halted_after_finish(int *ctl) {
 // The arguments with the scalar and control blocks of the system that the
 // workgroup's 512 rows belong to (batched solves; chunk_sys = nullptr: one
 // system).
+// The pair block (512 rows) this workgroup of a streaming pass takes: the
+// products' XCD-aware order (xcd_block), walked in the sweep direction.
+__device__ __forceinline__ int pass_block(int rev) {
+  return sweep_block(xcd_block((int)blockIdx.x, (int)gridDim.x), (int)gridDim.x, rev);
+}
+
 template <class Args>
 __device__ __forceinline__ Args bind_system(Args P) {
   if (P.chunk_sys) {
-    const int sys = P.chunk_sys[2 * sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev)];
+    const int sys = P.chunk_sys[2 * pass_block(P.rev)];
     P.sc += (size_t)sys * SC_COUNT;
     P.ctl += (size_t)sys * C_COUNT;
   }
@@ -135,7 +141,7 @@ __device__ __forceinline__ Args bind_system(Args P) {
 // Entry index of this thread (two entries per thread), blocks taken in the
 // sweep direction `rev`.
 __device__ __forceinline__ int64_t pair_index(int rev) {
-  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, rev);
+  const int b = pass_block(rev);
   return 2 * ((int64_t)b * kBlock + threadIdx.x);
 }
 
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_passA_pbicgsafe(PassAArgs P_) {
   TD acc[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) acc[j] = TD{0.0, 0.0, 0.0};
-  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int b = pass_block(P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
   if (k + 1 < P.n) passA_body<2, DOTS, NT, ZT>(P, k, acc);
   else if (k < P.n) passA_body<1, DOTS, NT, ZT>(P, k, acc);
@@ -284,7 +290,7 @@ __device__ __forceinline__ void passW_body(const PassWArgs &P, int64_t k) {
 __global__ __launch_bounds__(kBlock) void k_pass_w(PassWArgs P_) {
   const PassWArgs P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
-  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int b = pass_block(P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
   if (k + 1 < P.n) passW_body<2>(P, k);
   else if (k < P.n) passW_body<1>(P, k);
@@ -435,6 +441,10 @@ __global__ __launch_bounds__(kBlock) void k_widen(double *__restrict__ dst,
 // of the inner products whose vectors it has just written: [4][gridDim.x]
 // triples of (q, y), (y, y) -- phase 1 -- and (r0*, s), (r0*, z) -- two of
 // phase 2's, whose s and z nothing changes before that phase.
+// NT: p, s, q, y (next read by pass 2 or the next pass 1) stream past the
+// cache, so that it keeps the matrix, which both products read, and z, w, v, t,
+// r (cd3d 128^3: 144.0 -> 117.7 us per iteration with the single-stream
+// schedule); pass 2 streams p, q, y and x.
 struct Stab1Args {
   const double *r, *w, *t, *v;
   double *p, *s, *z, *q, *y;
@@ -447,7 +457,7 @@ struct Stab1Args {
   double *part;          // partial sums (DOTS)
 };
 
-template <int W, bool DOTS>
+template <int W, bool DOTS, bool NT>
 __device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k, TD (&acc)[4]) {
   const double al = P.sc[PS_S_ALPHA], be = P.sc[PS_S_BETA], om = P.sc[PS_S_OMEGA];
   double r[W], w[W], t[W], v[W], p[W], s[W], z[W], q[W], y[W];
@@ -455,8 +465,8 @@ __device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k, TD (&a
   ldv<W>(P.w, k, w);
   ldv<W>(P.t, k, t);
   ldv<W>(P.v, k, v);
-  ldv<W>(P.p, k, p);
-  ldv<W>(P.s, k, s);
+  ldv_s<W, NT>(P.p, k, p);
+  ldv_s<W, NT>(P.s, k, s);
   ldv<W>(P.z, k, z);
 #pragma unroll
   for (int j = 0; j < W; ++j) {
@@ -477,11 +487,11 @@ __device__ __forceinline__ void stab1_body(const Stab1Args &P, int64_t k, TD (&a
       td_fma(acc[3], rs[j], z[j]);
     }
   }
-  stv<W>(P.p, k, p);
-  stv<W>(P.s, k, s);
+  stv_s<W, NT>(P.p, k, p);
+  stv_s<W, NT>(P.s, k, s);
   stv<W>(P.z, k, z);
-  stv<W>(P.q, k, q);
-  stv<W>(P.y, k, y);
+  stv_s<W, NT>(P.q, k, q);
+  stv_s<W, NT>(P.y, k, y);
 }
 
 // The partial sums of a pass's block: [ND][gridDim.x] triples, block b's at
@@ -493,17 +503,17 @@ __device__ __forceinline__ void store_pass_partials(TD (&acc)[ND], double *part,
   if (threadIdx.x < ND) td_store(part, (int64_t)threadIdx.x * gridDim.x + b, t);
 }
 
-template <bool DOTS>
+template <bool DOTS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_stab_pass1(Stab1Args P_) {
   const Stab1Args P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   TD acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = TD{0.0, 0.0, 0.0};
-  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int b = pass_block(P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
-  if (k + 1 < P.n) stab1_body<2, DOTS>(P, k, acc);
-  else if (k < P.n) stab1_body<1, DOTS>(P, k, acc);
+  if (k + 1 < P.n) stab1_body<2, DOTS, NT>(P, k, acc);
+  else if (k < P.n) stab1_body<1, DOTS, NT>(P, k, acc);
   if constexpr (DOTS) store_pass_partials<4>(acc, P.part, b);
 }
 
@@ -524,16 +534,16 @@ struct Stab2Args {
   double *part;          // partial sums (DOTS)
 };
 
-template <int W, bool DOTS>
+template <int W, bool DOTS, bool NT>
 __device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k, TD (&acc)[3]) {
   const double al = P.sc[PS_S_ALPHA], om = P.sc[PS_S_OMEGA];
   double p[W], q[W], y[W], t[W], v[W], x[W], r[W], w[W];
-  ldv<W>(P.p, k, p);
-  ldv<W>(P.q, k, q);
-  ldv<W>(P.y, k, y);
+  ldv_s<W, NT>(P.p, k, p);
+  ldv_s<W, NT>(P.q, k, q);
+  ldv_s<W, NT>(P.y, k, y);
   ldv<W>(P.t, k, t);
   ldv<W>(P.v, k, v);
-  ldv<W>(P.x, k, x);
+  ldv_s<W, NT>(P.x, k, x);
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     x[j] = x[j] + al * p[j] + om * q[j];
@@ -550,22 +560,22 @@ __device__ __forceinline__ void stab2_body(const Stab2Args &P, int64_t k, TD (&a
       td_fma(acc[2], r[j], r[j]);
     }
   }
-  stv<W>(P.x, k, x);
+  stv_s<W, NT>(P.x, k, x);
   stv<W>(P.r, k, r);
   stv<W>(P.w, k, w);
 }
 
-template <bool DOTS>
+template <bool DOTS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_stab_pass2(Stab2Args P_) {
   const Stab2Args P = bind_system(P_);
   if (halted_after_finish(P.ctl)) return;
   TD acc[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) acc[j] = TD{0.0, 0.0, 0.0};
-  const int b = sweep_block((int)blockIdx.x, (int)gridDim.x, P.rev);
+  const int b = pass_block(P.rev);
   const int64_t k = 2 * ((int64_t)b * kBlock + threadIdx.x);
-  if (k + 1 < P.n) stab2_body<2, DOTS>(P, k, acc);
-  else if (k < P.n) stab2_body<1, DOTS>(P, k, acc);
+  if (k + 1 < P.n) stab2_body<2, DOTS, NT>(P, k, acc);
+  else if (k < P.n) stab2_body<1, DOTS, NT>(P, k, acc);
   if constexpr (DOTS) store_pass_partials<3>(acc, P.part, b);
 }
 

@@ -99,10 +99,10 @@ def test_fused_schedule_graphs_and_batches_bit_identical():
 
 @pytest.mark.parametrize("case", ["cd2d_64", "nonsym_ragged_3001", "long_rows_600"])
 def test_streaming_update_passes_bit_identical_to_oracle(case):
-    """PIPESAFE_STREAM=1 forces the streaming (nontemporal) loads and stores of p-BiCGSafe's
-    update passes, which the library picks by itself only for systems far above the
-    last-level cache: a cache hint, so both schedules keep the oracle's bits (odd n: the
-    one-entry tail of each pass)."""
+    """PIPESAFE_STREAM=1 forces the streaming (nontemporal) loads and stores of the update
+    passes (p-BiCGSafe's and p-BiCGStab's), which the library picks by itself only for
+    systems far above the last-level cache: a cache hint, so every schedule keeps the
+    oracle's bits (odd n: the one-entry tail of each pass)."""
     A = CASES[case]()
     ref = O.solve(A, tol=1e-10, maxit=3000, variant="pbicgsafe")
     old = os.environ.get("PIPESAFE_STREAM")
@@ -122,6 +122,14 @@ def test_streaming_update_passes_bit_identical_to_oracle(case):
                    dict(schedule=3, graph=1, batch_iters=5)):
             say(f"streaming {case} {kw}")
             res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgsafe", **kw)
+            assert res.status == ref.status and res.iters == ref.iters, (case, kw)
+            assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, kw)
+            assert np.array_equal(res.x, ref.x, equal_nan=True), (case, kw)
+        # p-BiCGStab's passes stream p, s, q, y, x under the same switch
+        ref = O.solve(A, tol=1e-10, maxit=3000, variant="pbicgstab")
+        for kw in (dict(schedule=0), dict(schedule=3), dict(schedule=3, graph=1, batch_iters=3)):
+            say(f"streaming {case} pbicgstab {kw}")
+            res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgstab", **kw)
             assert res.status == ref.status and res.iters == ref.iters, (case, kw)
             assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, kw)
             assert np.array_equal(res.x, ref.x, equal_nan=True), (case, kw)
