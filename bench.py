@@ -262,6 +262,27 @@ def bench_batch(name, reps=3):
     best = next(row for row in lrows if row["best"])
     log(f"  autotuned ({t_tune:.1f} s of tuning): layout {best}, options {topts}: "
         f"{1e3 * t_tuned:.1f} ms, {B.nsys / t_tuned:.0f} solves/s")
+    # what the small systems cost the batch: the same solve without them, and theirs alone
+    # (a bound on any separate path for them, such as one workgroup per system)
+    split = {}
+    side = [int(round(np.sqrt(A.n))) for A in B.systems]
+    for tag, keep in (("side_gt_64", lambda q: q > 64), ("side_le_64", lambda q: q <= 64)):
+        sub = [A for A, q in zip(B.systems, side) if keep(q)]
+        Bs = workloads.Batch(sub, f"{name}_{tag}")
+        bsub = torch.from_numpy(Bs.concat().b).cuda()
+        xsub = torch.empty_like(bsub)
+        with pipesafe.BatchMatrix.from_batch(Bs) as Ms:
+            Ms.solve_dev(bsub, None, xsub, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rs = Ms.solve_dev(bsub, None, xsub, tol=tol, maxit=10_000, variant="pbicgsafe",
+                                  hist=False)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t0) / reps
+        split[tag] = {"systems": len(sub), "time_ms": round(1e3 * ts, 2),
+                      "iterations_max": int(np.max(rs.iters))}
+    log(f"  split by grid side: {split}")
     return {"workload": name, "systems": B.nsys, "rows": C.n, "nnz": C.nnz, "tol": tol,
             "variant": "pbicgsafe", "layout": info["format"], "schedule": sched,
             "iterations_min_mean_max": [int(r.iters.min()), round(float(r.iters.mean()), 1),
@@ -277,7 +298,8 @@ def bench_batch(name, reps=3):
                           "layouts_timed_us": [round(row["us"], 2) for row in lrows],
                           "time_ms": round(1e3 * t_tuned, 2),
                           "solves_per_s": round(B.nsys / t_tuned, 1),
-                          "same_format_as_automatic": tinfo["format"] == info["format"]}}
+                          "same_format_as_automatic": tinfo["format"] == info["format"]},
+            "split": split}
 
 
 def bench_mixed(name, rr_ms, reps=3):
