@@ -209,8 +209,8 @@ typedef struct {
                             (nontemporal) hints -- when an iteration moves at least
                             512 MiB (two products plus 272 bytes per row), or as
                             PIPESAFE_STREAM=0|1 sets; the results are the same.
-                            p-BiCGStab's passes do the same from 640 MiB by that count
-                            (not reported here).                                       */
+                            p-BiCGStab's passes and ssBiCGSafe2's epilogue do the same
+                            from 640 MiB by that count (not reported here).            */
   int64_t n_padded;      /* rows on the device: n, or for a batch the systems padded to
                             multiples of 512 rows                                      */
   int32_t index_bits;    /* stored column index: 32, or 16 when every entry fits --

@@ -63,9 +63,10 @@ constexpr int64_t kFusedMinRows = 1 << 18;
 // above the 256 MiB last-level cache; below it the cache still holds part of
 // the previous iteration's vectors and the hint costs a little).
 constexpr int64_t kStreamMinBytes = 512ll << 20;
-// p-BiCGStab's passes stream from a larger iteration: the hints cost 2-3% at
-// 112^3 (iteration ~550 MiB by the same count) and save 18% at 128^3 (~825 MiB)
-constexpr int64_t kStabStreamMinBytes = 640ll << 20;
+// p-BiCGStab's passes and ssBiCGSafe2's epilogue stream from a larger
+// iteration: the hints cost 2-3% at 112^3 (~550 MiB by the same count) and save
+// 18% (p-BiCGStab) and 4.6% (ssBiCGSafe2) at 128^3 (~825 MiB)
+constexpr int64_t kOtherStreamMinBytes = 640ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
 constexpr int kSellRowsPerLane = 1;       // 64-row slices
 constexpr double kTuneMaxPadding = 1.5;   // the autotuner tries the sliced layout up to this
@@ -648,8 +649,12 @@ int iter_ssbicgsafe2(ps_matrix *M, const Plan &P, int i) {
   PouArgs po{R, S, T, Y, Pp, U, nullptr, nullptr, M->sc, M->ctl, M->n, next_rev(M)};
   po.chunk_sys = M->chunk_sys;
   PS_TRY(launch(M, A, PS_K_UPDATE, k_pu, pair_grid(M->n), 0, po));
-  PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B{S, U, Pp, T, Z, Y, X, R, M->sc}, C_DONE,
-              P.kry32));
+  if (P.stream_nt)
+    PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B<true>{S, U, Pp, T, Z, Y, X, R, M->sc},
+                C_DONE, P.kry32));
+  else
+    PS_TRY(spmv(M, A, PS_K_SPMV_FUSED, U, EpiSsBiCGSafe2B<false>{S, U, Pp, T, Z, Y, X, R, M->sc},
+                C_DONE, P.kry32));
   return PS_OK;
 }
 
@@ -878,8 +883,8 @@ int auto_schedule(const ps_matrix *M) {
 // two sparse products and the update passes' 34 vector reads and writes
 bool streaming(const ps_matrix *M, int32_t variant = PS_PBICGSAFE) {
   if (M->stream_override >= 0) return M->stream_override != 0;
-  return 2 * matrix_bytes(M) + 272 * M->n >=
-         (variant == PS_PBICGSTAB ? kStabStreamMinBytes : kStreamMinBytes);
+  const bool safe = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
+  return 2 * matrix_bytes(M) + 272 * M->n >= (safe ? kStreamMinBytes : kOtherStreamMinBytes);
 }
 
 // Put p, u, z in FP32 (to32) or FP64 storage, converting the slots that hold the
@@ -1033,7 +1038,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   // 61.7, 2*10^5-row band 74.7 / 59.8, 10^6-row band 243.8 / 229.2)
   const bool stab3 = o.schedule == 3 || (o.schedule < 0 && !batch);
   P.fused3 = variant == PS_PBICGSTAB ? stab3 : sched == 3 && safe_pipelined;
-  P.stream_nt = (safe_pipelined || variant == PS_PBICGSTAB) && streaming(M, variant);
+  P.stream_nt = streaming(M, variant);
   P.precision = o.precision;
   P.kry32 = o.precision != PS_PREC_FP64;
   P.res32 = o.precision == PS_PREC_FP32_MATRIX;

@@ -469,6 +469,9 @@ struct EpiPBiCGSafeB {
 // o_i = s_i + beta t_{i-1} (recomputed, not stored), t_i = o_i - w_i,
 // z_i = zeta r_i + eta z_{i-1} - alpha u_i, y_{i+1} = zeta s_i + eta y_i - alpha w_i,
 // x_{i+1} = x_i + alpha p_i + z_i, r_{i+1} = r_i - alpha o_i - y_{i+1}.
+// NT: x and z, which no other kernel of the iteration touches, stream past the
+// cache (cd3d 128^3: 141.3 -> 134.8 us per iteration).
+template <bool NT>
 struct EpiSsBiCGSafe2B {
   static constexpr int kDots = 0;
   // the scalars of system `sys`
@@ -483,18 +486,26 @@ struct EpiSsBiCGSafe2B {
   struct In {
     double s, t, r, z, u, y, x, p;
   };
+  __device__ __forceinline__ static double ld(const double *a, int k) {
+    if constexpr (NT) return __builtin_nontemporal_load(a + k);
+    else return a[k];
+  }
+  __device__ __forceinline__ static void st(double *a, int k, double v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, a + k);
+    else a[k] = v;
+  }
   __device__ __forceinline__ In load(int row) const {
-    return In{s[row], t[row], r[row], z[row], u[row], y[row], x[row], p[row]};
+    return In{s[row], t[row], r[row], ld(z, row), u[row], y[row], ld(x, row), p[row]};
   }
   __device__ __forceinline__ void store(int row, double wv, const In &in) const {
     const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
     const double o = in.s + be * in.t;
     t[row] = o - wv;
     const double zn = ze * in.r + et * in.z - al * in.u;
-    z[row] = zn;
+    st(z, row, zn);
     const double yn = ze * in.s + et * in.y - al * wv;
     y[row] = yn;
-    x[row] = in.x + al * in.p + zn;
+    st(x, row, in.x + al * in.p + zn);
     r[row] = in.r - al * o - yn;
   }
 };

@@ -100,7 +100,7 @@ def test_fused_schedule_graphs_and_batches_bit_identical():
 @pytest.mark.parametrize("case", ["cd2d_64", "nonsym_ragged_3001", "long_rows_600"])
 def test_streaming_update_passes_bit_identical_to_oracle(case):
     """PIPESAFE_STREAM=1 forces the streaming (nontemporal) loads and stores of the update
-    passes (p-BiCGSafe's and p-BiCGStab's), which the library picks by itself only for
+    passes and epilogues (every method), which the library picks by itself only for
     systems far above the last-level cache: a cache hint, so every schedule keeps the
     oracle's bits (odd n: the one-entry tail of each pass)."""
     A = CASES[case]()
@@ -125,14 +125,18 @@ def test_streaming_update_passes_bit_identical_to_oracle(case):
             assert res.status == ref.status and res.iters == ref.iters, (case, kw)
             assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, kw)
             assert np.array_equal(res.x, ref.x, equal_nan=True), (case, kw)
-        # p-BiCGStab's passes stream p, s, q, y, x under the same switch
-        ref = O.solve(A, tol=1e-10, maxit=3000, variant="pbicgstab")
-        for kw in (dict(schedule=0), dict(schedule=3), dict(schedule=3, graph=1, batch_iters=3)):
-            say(f"streaming {case} pbicgstab {kw}")
-            res = M.solve(A.b, tol=1e-10, maxit=3000, variant="pbicgstab", **kw)
-            assert res.status == ref.status and res.iters == ref.iters, (case, kw)
-            assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, kw)
-            assert np.array_equal(res.x, ref.x, equal_nan=True), (case, kw)
+        # p-BiCGStab's passes stream p, s, q, y, x and ssBiCGSafe2's epilogue x, z under the
+        # same switch
+        for v, kws in (("pbicgstab", (dict(schedule=0), dict(schedule=3),
+                                      dict(schedule=3, graph=1, batch_iters=3))),
+                       ("ssbicgsafe2", (dict(), dict(graph=0)))):
+            ref = O.solve(A, tol=1e-10, maxit=3000, variant=v)
+            for kw in kws:
+                say(f"streaming {case} {v} {kw}")
+                res = M.solve(A.b, tol=1e-10, maxit=3000, variant=v, **kw)
+                assert res.status == ref.status and res.iters == ref.iters, (case, v, kw)
+                assert np.array_equal(res.hist, ref.hist, equal_nan=True), (case, v, kw)
+                assert np.array_equal(res.x, ref.x, equal_nan=True), (case, v, kw)
     with pipesafe.Matrix.from_csr(A) as M2:
         assert M2.info()["streaming"] == 0  # small systems: automatic choice is off
 
