@@ -56,8 +56,8 @@ struct CsrDev {
 // are added with two-sum accumulators (hi, lo) and rounded once, so the value
 // does not depend on the order of the additions: with LPR = 1 a lane adds its
 // row in storage order; with LPR > 1 the group's lanes take every LPR-th
-// product and their pairs are combined across the group, which keeps lanes
-// busy on long, uneven rows.
+// product (alternately into two accumulators) and their pairs are combined
+// across the group, which keeps lanes busy on long, uneven rows.
 //
 // `st` names the control word that turns the launch (for a batch: the row
 // block's system) into a no-op: C_DONE for products that follow a finish in
@@ -202,8 +202,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev<VT, IT> A, const double 
         const int rr = li < r1 - r0 ? r0 + (A.rord ? (int)A.rord[r0 + li] : li) : r1;
         DD acc{0.0, 0.0};
         if (rr < r1) {
+          // two accumulators per lane (every 2 LPR-th product each), so that two
+          // additions are in flight: 1M-row band product 99.5 -> 96.9 us
           const int a = A.rowptr[rr] - k0, e = A.rowptr[rr + 1] - k0;
-          for (int k = a + j; k < e; k += LPR) sum_acc(acc, prod[k]);
+          DD acc2{0.0, 0.0};
+          int k = a + j;
+          for (; k + LPR < e; k += 2 * LPR) {
+            sum_acc(acc, prod[k]);
+            sum_acc(acc2, prod[k + LPR]);
+          }
+          if (k < e) sum_acc(acc, prod[k]);
+          dd_add(acc, acc2.hi, acc2.lo);
         }
         group_sum_dd<LPR>(acc);
         if (rr < r1 && j == t) {
