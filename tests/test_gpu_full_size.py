@@ -46,8 +46,8 @@ def case(request):
 
 
 @pytest.mark.parametrize("variant", VARIANTS + ["pbicgsafe+fused_dots", "pbicgsafe+fused_epilogue",
-                                     "pbicgsafe+single_stream", "pbicgstab+single_stream",
-                                     "pbicgsafe@p1",
+                                     "pbicgsafe+single_stream", "pbicgsafe_rr+single_stream",
+                                     "pbicgstab+single_stream", "pbicgsafe@p1",
                                      "pbicgsafe_rr@p2", "pbicgsafe_rr@p3"])
 def test_full_solve_reproduces_oracle(case, golden, variant):
     """Every method in FP64, the fused schedules of p-BiCGSafe (the same iteration; the
