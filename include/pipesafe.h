@@ -389,7 +389,7 @@ int ps_solve_dev(ps_matrix *A, const double *b_dev, const double *x0_dev, double
  * inner-product partial sums and residual history live in a static device
  * workspace of 4 MiB (524,288 doubles) that each GPU holds for the life of the
  * process; the handle's vectors and matrix were allocated by ps_create.
- * Limits: it needs 32 + 32 + 27 G + 3 (5 max(ceil(n/512), P) + 4 P + 9 F) +
+ * Limits: it needs 32 + 32 + 27 (G + ceil(G/256)) + 3 (5 max(ceil(n/512), P) + 4 P + 9 F) +
  * maxit + 2 doubles (each term rounded up to a multiple of 32), where G, P, F
  * are ps_info.dot_grid, ps_info.spmv_blocks and ceil(max(ceil(n/512), P)/256)
  * -- about 0.11 n + maxit doubles on the sliced layout (2.1M rows with maxit =

@@ -773,6 +773,18 @@ __device__ __forceinline__ void fold_then_finish(const FoldLists &L, const DotAr
   }
 }
 
+// The fold and finish as a kernel of their own, over G = gridDim.x slices: the
+// finish of the separate inner-product pass (its [ND][dot grid] triples, G =
+// the dot grid / kBlock rounded up), where the lean sums of a few workgroups
+// take less time than k_dots_finish's one-workgroup sum (ssBiCGSafe2, whose
+// reduction phase is on the main stream: 128^3 134.7 -> 132.7 us per
+// iteration, 96^3 70.4 -> 68.4).
+template <int ND, class Fin>
+__global__ __launch_bounds__(kBlock) void k_fold_finish(FoldLists L, DotArgs F) {
+  __shared__ double lds[kLeanLds];
+  fold_then_finish<ND, Fin>(L, F, (int)gridDim.x, (int)blockIdx.x, lds);
+}
+
 // The lists of the BiCGSafe schedules: the fused epilogue's [5][ga] triples of
 // (b, e, f, h, rho) and [4][gb] of (a, c, d, g), in the order of ProdSafe9
 constexpr unsigned kSafeFromB = 0x4Du;                   // products 0, 2, 3, 6 from pb

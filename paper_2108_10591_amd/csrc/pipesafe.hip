@@ -287,6 +287,9 @@ dim3 elem_grid(int64_t n) { return dim3((unsigned)((n + kBlock - 1) / kBlock)); 
 
 // Direction of the next full sweep over the rows: consecutive sweeps alternate
 // (see sweep_block).
+// fold slices of the separate inner-product pass's partial lists
+int dot_slices(const ps_matrix *M) { return (M->dot_grid + kBlock - 1) / kBlock; }
+
 int next_rev(ps_matrix *M) {
   const int r = M->sweep;
   M->sweep ^= 1;
@@ -368,7 +371,12 @@ int dots(ps_matrix *M, hipStream_t s, std::initializer_list<const double *> in, 
                   (const int *)M->first_blk, M->nblk512(), M->hist_stride);
   }
   PS_TRY(launch(M, s, PS_K_DOTS, k_dots<Prod>, dim3(M->dot_grid), 0, A));
-  return launch(M, s, PS_K_DOTS_FINISH, k_dots_finish<Prod::ND, Fin>, dim3(1), 0, A, M->dot_grid);
+  // the [ND][dot_grid] partials folded by a few workgroups, the last of which
+  // finishes; the folded slices go after the partials
+  const FoldLists lists{M->partials, M->partials, M->dot_grid, M->dot_grid, 0u, 0x876543210ull};
+  A.partials = M->partials + kPart * 9 * (size_t)M->dot_grid;
+  return launch(M, s, PS_K_DOTS_FINISH, k_fold_finish<Prod::ND, Fin>, dim3(dot_slices(M)), 0,
+                lists, A);
 }
 
 // ------------------------------------------------------------------ set-up
@@ -923,7 +931,7 @@ WorkspaceLayout workspace_layout(const ps_matrix *M, int32_t maxit) {
   L.ctl = at;
   at += round32((((size_t)M->nsys + 1) * C_COUNT * sizeof(int) + sizeof(double) - 1) / sizeof(double));
   L.partials = at;
-  at += round32(kPart * 9 * (size_t)M->dot_grid);
+  at += round32(kPart * 9 * ((size_t)M->dot_grid + dot_slices(M)));
   L.fpart = at;
   at += round32(kPart * (5 * (size_t)std::max(M->ga, M->nblk) + 4 * (size_t)M->nblk +
                          9 * (size_t)M->gfold));
@@ -1492,7 +1500,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     PS_CREATE_HIP(hipMalloc(&M->stage, (size_t)bl->n_orig * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->bpart, kPart * 9 * (size_t)(n / 512) * sizeof(double)));
   }
-  PS_CREATE_HIP(hipMalloc(&M->partials, kPart * 9 * (size_t)M->dot_grid * sizeof(double)));
+  PS_CREATE_HIP(hipMalloc(&M->partials,
+                          kPart * 9 * ((size_t)M->dot_grid + dot_slices(M)) * sizeof(double)));
   M->ga = (int)pair_grid(n).x;
   M->gfold = (std::max(M->ga, M->nblk) + kFoldPerThread * kBlock - 1) / (kFoldPerThread * kBlock);
   PS_CREATE_HIP(hipMalloc(&M->fpart, kPart * (5 * (size_t)std::max(M->ga, M->nblk) +
