@@ -388,6 +388,28 @@ def bench_small(name, reps=5):
             out[v] = {"iterations": r.iters, "status": r.status_name,
                       "time_to_tol_ms": round(1e3 * t, 3),
                       "us_per_iter": round(1e6 * t / max(r.iters, 1), 2)}
+    # a tiny system (16^2 rows of the same problem family): the automatic choice, the whole
+    # solve in one workgroup (schedule 4), against the single-stream launches (3)
+    T = workloads.cd2d(16)
+    bt = torch.from_numpy(T.b).cuda()
+    xt = torch.empty_like(bt)
+    tiny = {"workload": "cd2d_16", "n": T.n, "tol": tol}
+    with pipesafe.Matrix.from_csr(T) as M:
+        tiny["auto_schedule"] = M.info()["auto_schedule"]
+        for tag, sched in (("automatic", -1), ("schedule_3", 3)):
+            r = M.solve_dev(bt, None, xt, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False,
+                            schedule=sched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(4 * reps):
+                r = M.solve_dev(bt, None, xt, tol=tol, maxit=10_000, variant="pbicgsafe",
+                                hist=False, schedule=sched)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / (4 * reps)
+            tiny[tag] = {"iterations": r.iters, "status": r.status_name,
+                         "time_to_tol_ms": round(1e3 * t, 4),
+                         "us_per_iter": round(1e6 * t / max(r.iters, 1), 2)}
+    out["tiny_system"] = tiny
     log(f"small system {name}: {out}")
     return out
 

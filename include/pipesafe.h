@@ -95,7 +95,8 @@ typedef struct {
                           bit-identical either way.  Ignored while profiling.          */
   int32_t schedule;    /* Where the reduction phases run: p-BiCGSafe, p-BiCGSafe-rr and
                           (0 and 3 only) p-BiCGStab.  -1 (default): automatic --
-                          sliced layout: 3; CSR: 3 below 2^18 rows, else 0;
+                          sliced layout: 4 up to 896 rows (p-BiCGSafe in FP64 from
+                          x0; otherwise 3), else 3; CSR: 3 below 2^18 rows, else 0;
                           batches: 2 (ps_info.auto_schedule tells); p-BiCGStab: 3
                           for one system, 0 for batches; ssBiCGSafe2 ignores -1.
                           With -rr, a replacement step and the iteration after it form
@@ -131,8 +132,17 @@ typedef struct {
                           fold and finish the two reduction phases the same way:
                           four launches per iteration on one stream, 40n bytes fewer
                           than the separate passes (0).
-                          Results are bit-identical to schedule 0.  ssBiCGSafe2: 1, 2
-                          and 3 are PS_EINVAL; p-BiCGStab: 1 and 2.                     */
+                          4: the whole solve in one workgroup of 512 threads per
+                          system (Algorithm 4 with schedule 3's reduction phase; one
+                          launch per solve, barriers between the phases that gather):
+                          p-BiCGSafe only, FP64, sliced layout with one row per lane,
+                          no resume or profiling, at most 2^20 rows per system, one
+                          system or a batch; otherwise PS_EINVAL.  Measured: faster
+                          than 3 below about 1000 rows (256 rows: 10.5 against 16.1
+                          us per iteration), far slower above (4096 rows: 43.3
+                          against 17.9), where one CU's bandwidth bounds it.
+                          Results are bit-identical to schedule 0.  ssBiCGSafe2: 1, 2,
+                          3 and 4 are PS_EINVAL; p-BiCGStab: 1, 2 and 4.               */
   int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).
                           0 (default): use it as given.
                           1: if ||b - A x0|| > ||b|| (or is not finite), start from
@@ -202,7 +212,8 @@ typedef struct {
                             CSR (8 + index_bits/8 + 2 gather_sort) nnz + 4 (n+1);
                             SELL (8 + index_bits/8) slots + 4 (slices+1)               */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
-  int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe(-rr) */
+  int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe (4 is
+                            3 for p-BiCGSafe-rr and for options schedule 4 excludes) */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
   int32_t streaming;     /* 1: p-BiCGSafe(-rr)'s update passes load and store the vectors that
                             no kernel reads before the next iteration with streaming
@@ -349,9 +360,11 @@ int ps_autotune_layout(ps_matrix **out, int32_t nsys, const int64_t *sys_ptr, in
 
 /* Time `iters` iterations of `variant` from b_dev (DEVICE, the caller's row
    order, as ps_solve_batch_dev; x0 = 0, tol = 0) for every combination of
-   schedule (p-BiCGSafe(-rr): 0, 1, 2), overlap (0, 1; ssBiCGSafe2: 0),
-   streaming update passes (p-BiCGSafe(-rr): off, on) and graph batch (8, 16, 32
-   iterations), each run once to capture its graphs and once timed (host
+   schedule (p-BiCGSafe(-rr): 0, 1, 2, and 3 for one system; p-BiCGStab: 0,
+   and 3 for one system; 4 where the options allow it), overlap (0, 1;
+   ssBiCGSafe2, schedules 3 and 4: 0), streaming update passes (p-BiCGSafe(-rr):
+   off, on; schedule 4: as the handle has it) and graph batch (8, 16, 32
+   iterations; schedule 4: one launch), each run once to capture its graphs and once timed (host
    clock around the call), and write the fastest into opt->schedule,
    opt->overlap and opt->batch_iters (the other fields of *opt are the base
    of every run and stay as given).  The streaming choice is stored in the

@@ -39,6 +39,7 @@
 #include "device_common.hpp"
 #include "dots.hpp"
 #include "layout.hpp"
+#include "solve_one.hpp"
 #include "spmv.hpp"
 #include "updates.hpp"
 
@@ -58,6 +59,13 @@ constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 // skipped pass and pays for the extra reads in its epilogue.
 constexpr int64_t kOverlapMinBytes = 128ll << 20;
 constexpr int64_t kFusedMinRows = 1 << 18;
+// schedule 4 (the whole solve in one workgroup per system): its threads (1024
+// threads leave 128 registers per lane, and the epilogue's accumulators then
+// spill: 58.4 against 43.3 us per iteration on 4096 rows), and the rows per
+// system it accepts at all
+constexpr int kOneGroupThreads = 512;
+constexpr int64_t kOneGroupMaxRows = 1 << 20;
+constexpr int64_t kOneGroupAutoRows = 896;  // the automatic schedule's choice (auto_schedule)
 // p-BiCGSafe's update passes stream the vectors they do not hand to the next
 // kernel past the cache once an iteration moves at least kStreamMinBytes (well
 // above the 256 MiB last-level cache; below it the cache still holds part of
@@ -149,6 +157,7 @@ struct ps_matrix {
   // row per system, inner-product partials per 512-row workgroup
   int nsys = 1;
   int64_t n_orig = 0;            // rows of the caller's concatenation (= n for one system)
+  int64_t max_sys_rows = 0;      // padded rows of the largest system (= n for one system)
   int *chunk_sys = nullptr;      // device: system of each 256-row chunk (nullptr: one system)
   int *first_blk = nullptr;      // device: first 512-row workgroup of each system, [nsys+1]
   int *first_pblk = nullptr;     // device: first sparse-product workgroup of each system
@@ -401,6 +410,7 @@ struct Plan {
   bool fused;     // fused-dot schedule (p-BiCGSafe): schedule 1 or 2
   bool fused2;    // schedules 2, 3: every update but w_i in the epilogue of A w_i
   bool fused3;    // schedule 3: the reduction folded and finished inside A s_i, one stream
+  bool one;       // schedule 4: the whole solve in one workgroup (k_solve_one)
   bool fallback;  // replace an initial guess that is worse than zero
   bool scale;     // first scale the guess to its least residual (x0_fallback = 2)
   bool stream_nt; // streaming (nontemporal) loads and stores in the update passes
@@ -882,10 +892,16 @@ bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kO
 //    (0; 10^6 uneven rows: 219 / 249 / 238 -- the gather-bound products gain
 //    nothing from the skipped pass and pay for the extra epilogue reads);
 //  - batches: 2 (the 512-system stencil batch: 17% more solves/s than 0, 4%
-//    more than 1; schedule 3 is single-system only).
+//    more than 1; schedule 3 is single-system only);
+//  - one sliced system of at most kOneGroupAutoRows rows: the whole solve in
+//    one workgroup (4; 3 / 4: 36 rows 15.5 / 10.4, 256 rows 16.1 / 10.5, 576
+//    rows 17.4 / 13.9, 784 rows 18.1 / 16.9, 1024 rows 17.5 / 17.5, 4096 rows
+//    17.9 / 43.3 -- a single CU's bandwidth caps it beyond a few hundred rows).
+//    p-BiCGSafe only: the other methods fall back to 3.
 int auto_schedule(const ps_matrix *M) {
   if (M->nsys > 1) return 2;
-  if (M->format == PS_FMT_SELL) return 3;
+  if (M->format == PS_FMT_SELL)
+    return M->n <= kOneGroupAutoRows && M->sell_rpl == 1 ? 4 : 3;
   return M->n < kFusedMinRows ? 3 : 0;
 }
 // two sparse products and the update passes' 34 vector reads and writes
@@ -979,6 +995,15 @@ struct WorkspaceSwap {
 // row order), on the device or the host.  ws: NULL, or a device workspace laid
 // out by workspace_layout that replaces the handle's own blocks for this solve
 // (then nothing is allocated: no graphs, no profiling, no history growth).
+// schedule 4 runs p-BiCGSafe in FP64 on the sliced layout (one row per lane),
+// from x_0 (no resume), without profiling, on systems of at most
+// kOneGroupMaxRows rows each
+bool one_group_ok(const ps_matrix *M, int32_t variant, const ps_options &o) {
+  return variant == PS_PBICGSAFE && M->format == PS_FMT_SELL && M->sell_rpl == 1 &&
+         o.precision == PS_PREC_FP64 && !o.resume && !o.profile &&
+         M->max_sys_rows <= kOneGroupMaxRows;
+}
+
 int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, double tol,
                int32_t maxit, int32_t variant, const ps_options *opt, double *x, int32_t *iters,
                double *hist, int32_t *status, double *ws = nullptr) {
@@ -996,9 +1021,10 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
   // schedule 3 folds in the product's first gfold workgroups: never more than the
   // product has with the layouts built here (gfold = nblk / 256, rounded up)
-  if (o.schedule < -1 || o.schedule > 3 ||
+  if (o.schedule < -1 || o.schedule > 4 ||
       (o.schedule >= 1 && !safe_pipelined && !(o.schedule == 3 && variant == PS_PBICGSTAB)) ||
-      (o.schedule == 3 && (batch || M->gfold > M->nblk)))
+      (o.schedule == 3 && (batch || M->gfold > M->nblk)) ||
+      (o.schedule == 4 && !one_group_ok(M, variant, o)))
     return PS_EINVAL;
   if (o.precision < PS_PREC_FP64 || o.precision > PS_PREC_FP32_VECTORS ||
       (o.precision != PS_PREC_FP64 && !M->f32_ok) ||
@@ -1038,7 +1064,9 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.B = P.overlap ? M->aux : P.A;
   P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
   P.scale = o.x0_fallback == 2 && x0 != nullptr && !P.resume;
-  const int sched = o.schedule >= 0 ? o.schedule : auto_schedule(M);
+  int sched = o.schedule >= 0 ? o.schedule : auto_schedule(M);
+  if (sched == 4 && !one_group_ok(M, variant, o)) sched = 3;  // automatic, not p-BiCGSafe
+  P.one = sched == 4;
   P.fused = safe_pipelined && sched >= 1;
   P.fused2 = P.fused && sched >= 2;
   // p-BiCGStab: schedule 3 or the separate passes; automatically 3 for one system
@@ -1104,6 +1132,24 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   const int K = o.batch_iters > 0 ? o.batch_iters : auto_batch(M);
   int nbatch = 0;
   bool stopped = false;
+  if (P.one) {
+    // one workgroup per system
+    OneArgs a{M->slot(PS_V_X), M->slot(PS_V_R), M->slot(PS_V_S), M->slot(PS_V_Y),
+              M->slot(PS_V_T), M->slot(PS_V_P), M->slot(PS_V_U), M->slot(PS_V_Z),
+              M->slot(PS_V_W), M->slot(PS_V_L), M->slot(PS_V_G), M->slot(PS_V_AS),
+              M->slot(PS_V_RS), M->sc, M->ctl, M->hist, M->hist_stride, M->running(),
+              M->nsys > 1 ? M->first_blk : nullptr, (int)M->n, P.maxit, P.tol,
+              P.norm_ref == 0 ? DF_SET_REF : 0};
+    // (never profiled, so launched directly, with its own block size)
+    if (M->index_bits == 16)
+      hipLaunchKernelGGL((k_solve_one<short, kOneGroupThreads>), dim3(M->nsys),
+                         dim3(kOneGroupThreads), 0, P.A, M->template sell<double, short>(), a);
+    else
+      hipLaunchKernelGGL((k_solve_one<int, kOneGroupThreads>), dim3(M->nsys),
+                         dim3(kOneGroupThreads), 0, P.A, M->template sell<double, int>(), a);
+    PS_HIP(hipGetLastError());
+    stopped = true;  // the loop below has nothing left to launch
+  }
   for (int i = P.i0; i <= last && !stopped;) {
     const int end = std::min(last, i + K - 1);
     bool launched = false;
@@ -1490,6 +1536,13 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   const int nsys = bl ? bl->nsys : 1;
   M->nsys = nsys;
   M->n_orig = bl ? bl->n_orig : n;
+  M->max_sys_rows = n;
+  if (bl) {
+    M->max_sys_rows = 0;
+    for (int k = 0; k < nsys; ++k)
+      M->max_sys_rows =
+          std::max<int64_t>(M->max_sys_rows, 512 * (int64_t)(bl->first_blk[k + 1] - bl->first_blk[k]));
+  }
   PS_CREATE_HIP(hipMalloc(&M->sc, (size_t)nsys * SC_COUNT * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->ctl, ((size_t)nsys + 1) * C_COUNT * sizeof(int)));
   if (bl) {
@@ -1859,6 +1912,14 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
   std::vector<int> scheds = {0}, overlaps = {0, 1}, streams = {-1}, batches = {8, 16, 32};
   const bool safe_pipelined = variant == PS_PBICGSAFE || variant == PS_PBICGSAFE_RR;
   if (safe_pipelined) scheds = {0, 1, 2};
+  // one stream (3): one system, p-BiCGSafe(-rr) or p-BiCGStab; one workgroup per
+  // system (4): where the base options allow it
+  if (A->nsys == 1 && (safe_pipelined || variant == PS_PBICGSTAB) && A->gfold <= A->nblk)
+    scheds.push_back(3);
+  ps_options one = base;
+  one.resume = 0;
+  one.profile = 0;
+  if (one_group_ok(A, variant, one)) scheds.push_back(4);
   if (variant == PS_SSBICGSAFE2) overlaps = {0};  // a single stream either way
   if (safe_pipelined) streams = {0, 1};
   double *x = nullptr;
@@ -1874,10 +1935,13 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
   double best_us = -1.0;
   ps_options best = base;
   int best_stream = saved_stream;
+  const std::vector<int> one_ov = {0}, one_sm = {-1}, one_bi = {8};
   for (int sc : scheds)
-    for (int ov : overlaps)
-      for (int sm : streams)
-        for (int bi : batches) {
+    // schedules 3 and 4 use one stream; 4 launches once per solve, so that the
+    // streaming and graph-batch choices do nothing there
+    for (int ov : sc >= 3 ? one_ov : overlaps)
+      for (int sm : sc == 4 ? one_sm : streams)
+        for (int bi : sc == 4 ? one_bi : batches) {
           ps_options o = base;
           o.schedule = sc;
           o.overlap = ov;
@@ -1917,7 +1981,7 @@ int ps_tune_options(ps_matrix *A, const double *b_dev, int32_t variant, int32_t 
     A->stream_override = saved_stream;
     return rc;
   }
-  opt->schedule = safe_pipelined ? best.schedule : base.schedule;
+  opt->schedule = variant != PS_SSBICGSAFE2 ? best.schedule : base.schedule;
   opt->overlap = best.overlap;
   opt->batch_iters = best.batch_iters;
   A->stream_override = best_stream;

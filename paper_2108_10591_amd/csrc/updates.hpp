@@ -271,6 +271,13 @@ struct PassWArgs {
   const int *chunk_sys;  // system of each 256-row chunk (batched solves), or nullptr
 };
 
+// w_i from A s_i, l_{i-1}, g_{i-1}, w_{i-1} (Eqs. (q), (w): q_i = A s_i + beta l_{i-1})
+__device__ __forceinline__ double w_next(double As, double l, double g, double w, double be,
+                                         double ze, double et) {
+  const double q = As + be * l;
+  return ze * q + et * (g + be * w);
+}
+
 template <int W>
 __device__ __forceinline__ void passW_body(const PassWArgs &P, int64_t k) {
   const double be = P.sc[PS_S_BETA], ze = P.sc[PS_S_ZETA], et = P.sc[PS_S_ETA];
@@ -280,10 +287,7 @@ __device__ __forceinline__ void passW_body(const PassWArgs &P, int64_t k) {
   ldv<W>(P.g, k, g);
   ldv<W>(P.w, k, w);
 #pragma unroll
-  for (int j = 0; j < W; ++j) {
-    const double q = As[j] + be * l[j];
-    w[j] = ze * q + et * (g[j] + be * w[j]);
-  }
+  for (int j = 0; j < W; ++j) w[j] = w_next(As[j], l[j], g[j], w[j], be, ze, et);
   stv<W>(P.w, k, w);
 }
 

@@ -213,7 +213,7 @@ def test_fused_schedule_statuses(schedule):
             with pytest.raises(pipesafe.PipesafeError):
                 M.solve(B.b, tol=1e-10, maxit=10, variant=v, schedule=schedule)
         with pytest.raises(pipesafe.PipesafeError):
-            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=4)
+            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=5)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))

@@ -1,0 +1,136 @@
+"""GPU parity of schedule 4: the whole p-BiCGSafe solve in one workgroup.
+
+For small systems on the sliced layout, one workgroup runs every iteration of
+Algorithm 4 -- the reduction phase from the nine inner products, A s_i, w_i,
+A w_i and every other update -- with barriers between the phases that gather.
+The row sums are the sliced product's (slots in order, compensated, rounded
+once), the updates the separate passes' expressions and the inner products
+exact sums rounded once, so every result equals the oracle's p-BiCGSafe bit
+for bit, like the multi-kernel schedules.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2108_10591_amd import pipesafe, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SELL16 = pipesafe.layout("sell", 1, -1, 16)
+SELL32 = pipesafe.layout("sell", 1, -1, 32)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    pipesafe.library()
+
+
+CASES = {
+    "cd2d_64": lambda: W.workload("cd2d_64"),
+    "cd2d_37": lambda: W.cd2d(37),  # 1369 rows: a ragged last slice
+    "cd3d_16": lambda: W.cd3d(16, 20.0, seed=1),
+    "nonsym_ragged_3001": lambda: W.small_nonsym(3001, 11, density=0.003),
+    "rand_band_20k": lambda: W.rand_band(20_000, seed=3, band=500),
+}
+
+
+@pytest.mark.parametrize("lay", ["sell16", "sell32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_one_group_trajectory_bit_identical_to_oracle(case, lay):
+    A = CASES[case]()
+    L = SELL16 if lay == "sell16" else SELL32
+    with pipesafe.Matrix.from_csr(A, L) as M:
+        if lay == "sell16" and M.info()["index_bits"] != 16:
+            pytest.skip("columns too far from the diagonal for 16-bit offsets")
+        for tol, maxit in ((1e-10, 3000), (0.0, 9), (0.0, 1)):
+            say(f"one group {case} {lay} tol={tol} maxit={maxit}")
+            ref = O.solve(A, tol=tol, maxit=maxit, variant="pbicgsafe")
+            res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=4)
+            assert res.status == ref.status and res.iters == ref.iters, \
+                (case, res.status, ref.status, res.iters, ref.iters)
+            assert np.array_equal(res.hist, ref.hist, equal_nan=True), case
+            assert np.array_equal(res.x, ref.x, equal_nan=True), case
+            # and the same bits as the multi-kernel schedule, twice in a row
+            r3 = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=3)
+            r4 = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=4)
+            assert np.array_equal(r3.x, r4.x) and np.array_equal(r3.hist, r4.hist), case
+
+
+def test_one_group_statuses_and_options():
+    # A = I converges at i = 1
+    for n in (1, 2, 63, 1000):
+        E = W.identity(n, seed=n)
+        with pipesafe.Matrix.from_csr(E, SELL32) as M:
+            res = M.solve(E.b, tol=1e-12, maxit=50, variant="pbicgsafe", schedule=4)
+        assert res.status == O.CONVERGED and res.iters == 1 and np.array_equal(res.x, E.b)
+    S = W.skew_blocks(64, seed=1)
+    with pipesafe.Matrix.from_csr(S, SELL32) as M:
+        res = M.solve(S.b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=4)
+    ref = O.solve(S, tol=1e-10, maxit=100, variant="pbicgsafe")
+    assert res.status == O.BREAKDOWN == ref.status and res.iters == ref.iters == 0
+    B = W.small_nonsym(40, 0)
+    with pipesafe.Matrix.from_csr(B, SELL32) as M:
+        b = B.b.copy()
+        b[7] = np.nan
+        assert M.solve(b, tol=1e-10, maxit=100, variant="pbicgsafe", schedule=4).status == \
+            O.NONFINITE
+        r0 = M.solve(B.b, tol=1e-10, maxit=0, variant="pbicgsafe", schedule=4)
+        assert r0.status == O.MAXIT and r0.iters == 0
+        x1, x2 = np.linspace(-1.0, 1.0, B.n), np.full(B.n, 0.5)
+        for kw, okw in ((dict(x0=x1), dict(x0=x1)), (dict(norm_ref=1), dict(norm_ref=1)),
+                        (dict(x0=x2, x0_fallback=2), dict(x0=x2, x0_mode=2))):
+            ref = O.solve(B, tol=1e-12, maxit=200, variant="pbicgsafe", **okw)
+            res = M.solve(B.b, tol=1e-12, maxit=200, variant="pbicgsafe", schedule=4, **kw)
+            assert res.status == ref.status and res.iters == ref.iters, kw
+            assert np.array_equal(res.x, ref.x) and np.array_equal(res.hist, ref.hist), kw
+        # schedule 4 is p-BiCGSafe in FP64 from x_0 only
+        for kw in (dict(variant="pbicgsafe_rr"), dict(variant="pbicgstab"),
+                   dict(variant="ssbicgsafe2"), dict(variant="pbicgsafe", precision=1),
+                   dict(variant="pbicgsafe", schedule=5)):
+            kw = dict(dict(schedule=4), **kw)
+            with pytest.raises(pipesafe.PipesafeError):
+                M.solve(B.b, tol=1e-10, maxit=10, **kw)
+    with pipesafe.Matrix.from_csr(B, pipesafe.layout("csr")) as M:  # the sliced layout only
+        with pytest.raises(pipesafe.PipesafeError):
+            M.solve(B.b, tol=1e-10, maxit=10, variant="pbicgsafe", schedule=4)
+
+
+def test_one_group_batch_equals_each_system_alone():
+    """Batches: one workgroup per system, each over its own padded rows, scalar and
+    control blocks and history; systems that stop early (identity, breakdown, NaN) leave
+    the others running."""
+    import test_gpu_batch as TB
+    B, C, b = TB.mixed_batch()
+    for tol, maxit in ((1e-10, 2000), (0.0, 7)):
+        refs = TB.oracle_each(B, b, tol, maxit, "pbicgsafe")
+        for L in (SELL16, SELL32):
+            with pipesafe.BatchMatrix.from_batch(B, L) as M:
+                say(f"one group batch tol={tol} index_bits={M.info()['index_bits']}")
+                for _ in range(2):
+                    res = M.solve(b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=4)
+                    TB.check_same(res, refs, B, ("one group", tol))
+
+
+def test_one_group_automatic_choice():
+    """The automatic schedule runs sliced p-BiCGSafe systems of at most 896 rows in one
+    workgroup (ps_info.auto_schedule = 4); p-BiCGSafe-rr and larger systems take 3."""
+    for N, want in ((16, 4), (29, 4), (30, 3)):
+        A = W.cd2d(N)
+        with pipesafe.Matrix.from_csr(A, SELL16) as M:
+            assert M.info()["auto_schedule"] == want, N
+            for v in ("pbicgsafe", "pbicgsafe_rr"):
+                say(f"automatic schedule cd2d_{N} {v}")
+                ref = O.solve(A, tol=1e-10, maxit=2000, variant=v, rr_m=13)
+                res = M.solve(A.b, tol=1e-10, maxit=2000, variant=v, rr_m=13)
+                assert res.status == ref.status and res.iters == ref.iters, (N, v)
+                assert np.array_equal(res.x, ref.x) and np.array_equal(res.hist, ref.hist), (N, v)

@@ -29,7 +29,7 @@ def _gpu():
 CASES = [("pbicgsafe", dict(schedule=2)), ("pbicgsafe", dict(schedule=3)), ("pbicgsafe", dict(schedule=0)),
          ("pbicgsafe", dict(schedule=1, overlap=1)), ("pbicgsafe_rr", dict(rr_m=20)),
          ("ssbicgsafe2", {}), ("pbicgstab", dict(overlap=1, schedule=0)),
-         ("pbicgstab", dict(schedule=3))]
+         ("pbicgstab", dict(schedule=3)), ("pbicgsafe", dict(schedule=4))]
 
 
 def _same(a, b):
