@@ -108,8 +108,8 @@ def bytes_per_launch(cls, n, nnz, schedule=0, info=None):
     return {"spmv": M + 16 * n, "dots": 40 * n, "update": 160 * n, "spmv_fused": M + 64 * n}[cls]
 
 
-SOLVER_SOURCES = ["device_common.hpp", "dots.hpp", "layout.cpp", "layout.hpp", "pipesafe.hip", "spmv.hpp",
-                  "updates.hpp"]
+SOLVER_SOURCES = ["device_common.hpp", "dots.hpp", "layout.cpp", "layout.hpp", "pipesafe.hip",
+                  "solve_one.hpp", "spmv.hpp", "updates.hpp"]
 
 
 def source_digest():

@@ -43,6 +43,10 @@ def test_recorded_traffic_is_refused_when_it_does_not_apply():
     assert bench.load_traffic("no_such_class", t.get("workload"), t.get("schedule")) is None
     # the digest covers the solver's sources: it is a stable function of them
     assert bench.source_digest() == bench.source_digest() and len(bench.source_digest()) == 16
+    # every solver source (all of csrc but the warm-start network's) is in the digest
+    csrc = os.path.join(os.path.dirname(bench.__file__), "paper_2108_10591_amd", "csrc")
+    assert sorted(bench.SOLVER_SOURCES) == sorted(f for f in os.listdir(csrc)
+                                                  if not f.startswith("wsnet"))
 
 
 def test_more_than_one_gpu_exits_with_a_message():
