@@ -134,3 +134,21 @@ def test_one_group_automatic_choice():
                 res = M.solve(A.b, tol=1e-10, maxit=2000, variant=v, rr_m=13)
                 assert res.status == ref.status and res.iters == ref.iters, (N, v)
                 assert np.array_equal(res.x, ref.x) and np.array_equal(res.hist, ref.hist), (N, v)
+
+
+@pytest.mark.parametrize("case", ["empty_and_single", "long_rows", "one_row", "single_empty_row",
+                                  "unsorted_dups"])
+def test_one_group_edge_matrices(case):
+    """Empty rows, rows of up to 20000 entries beside short ones (a slice as wide as its
+    longest row), one-row systems, unsorted and duplicated entries: whatever the oracle
+    does in 40 iterations (converge, break down, overflow), the same bits."""
+    import test_gpu_parity as TP
+    A = TP._spmv_matrix(case)
+    ref = O.solve(A, tol=1e-10, maxit=40, variant="pbicgsafe")
+    with pipesafe.Matrix.from_csr(A, SELL32) as M:
+        assert M.info()["format"] == "sell"
+        say(f"one group edge case {case}")
+        res = M.solve(A.b, tol=1e-10, maxit=40, variant="pbicgsafe", schedule=4)
+    assert res.status == ref.status and res.iters == ref.iters, (case, res.status, ref.status)
+    assert np.array_equal(res.hist, ref.hist, equal_nan=True), case
+    assert np.array_equal(res.x, ref.x, equal_nan=True), case
