@@ -189,7 +189,8 @@ def batch_bytes_per_iteration(info, A, schedule):
         M = slot_bytes * slots + 4 * (npad / 64 + 1)
     else:
         M = slot_bytes * A.nnz + 4 * (npad + 1)
-    per_row = {0: 280, 1: 272, 2: 248}[schedule]
+    # schedules 3 and 4 make schedule 2's passes (4: inside one workgroup per system)
+    per_row = {0: 280, 1: 272, 2: 248, 3: 248, 4: 248}[schedule]
     return 2 * M + per_row * npad
 
 

@@ -97,8 +97,10 @@ typedef struct {
                           (0 and 3 only) p-BiCGStab.  -1 (default): automatic --
                           sliced layout: 4 up to 896 rows (p-BiCGSafe in FP64 from
                           x0; otherwise 3), else 3; CSR: 3 below 2^18 rows, else 0;
-                          batches: 2 (ps_info.auto_schedule tells); p-BiCGStab: 3
-                          for one system, 0 for batches; ssBiCGSafe2 ignores -1.
+                          batches: 4 on the sliced layout when no system has more
+                          than 1600 rows (same conditions; otherwise 2), else 2
+                          (ps_info.auto_schedule tells); p-BiCGStab: 3 for one
+                          system, 0 for batches; ssBiCGSafe2 ignores -1.
                           With -rr, a replacement step and the iteration after it form
                           their inner products in their own pass.
                           0: the reduction phase of Algorithm 4
@@ -140,7 +142,8 @@ typedef struct {
                           system or a batch; otherwise PS_EINVAL.  Measured: faster
                           than 3 below about 1000 rows (256 rows: 10.5 against 16.1
                           us per iteration), far slower above (4096 rows: 43.3
-                          against 17.9), where one CU's bandwidth bounds it.
+                          against 17.9), where one CU's bandwidth bounds it; batches
+                          of systems up to 40^2 rows: 1.0-2.1x the solves/s of 2.
                           Results are bit-identical to schedule 0.  ssBiCGSafe2: 1, 2,
                           3 and 4 are PS_EINVAL; p-BiCGStab: 1, 2 and 4.               */
   int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).
@@ -213,7 +216,8 @@ typedef struct {
                             SELL (8 + index_bits/8) slots + 4 (slices+1)               */
   int32_t auto_overlap;  /* what ps_options.overlap = -1 resolves to on this matrix     */
   int32_t auto_schedule; /* what ps_options.schedule = -1 resolves to for p-BiCGSafe (4 is
-                            3 for p-BiCGSafe-rr and for options schedule 4 excludes) */
+                            3, for batches 2, with p-BiCGSafe-rr and with the options
+                            schedule 4 excludes) */
   int32_t nsys;          /* systems (1 unless created by ps_create_batch)              */
   int32_t streaming;     /* 1: p-BiCGSafe(-rr)'s update passes load and store the vectors that
                             no kernel reads before the next iteration with streaming

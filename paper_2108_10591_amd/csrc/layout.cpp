@@ -180,6 +180,7 @@ bool pad_batch(int32_t nsys, const int64_t *sys_ptr, int64_t n, const int64_t *r
   out.row_map.resize((size_t)n);
   out.chunk_sys.resize((size_t)(np / 256));
   out.first_blk.resize((size_t)nsys + 1);
+  out.sys_end.resize((size_t)nsys);
   for (int32_t k = 0; k < nsys; ++k) {
     const int64_t shift = out.pstart[(size_t)k] - sys_ptr[k];
     for (int64_t r = sys_ptr[k]; r < sys_ptr[k + 1]; ++r) {
@@ -191,6 +192,7 @@ bool pad_batch(int32_t nsys, const int64_t *sys_ptr, int64_t n, const int64_t *r
     for (int64_t c = out.pstart[(size_t)k] / 256; c < out.pstart[(size_t)k + 1] / 256; ++c)
       out.chunk_sys[(size_t)c] = k;
     out.first_blk[(size_t)k] = (int)(out.pstart[(size_t)k] / kBatchAlign);
+    out.sys_end[(size_t)k] = (int)(out.pstart[(size_t)k] + sys_ptr[k + 1] - sys_ptr[k]);
   }
   out.first_blk[(size_t)nsys] = (int)(np / kBatchAlign);
   for (int64_t r = 0; r < np; ++r) out.rowptr[(size_t)r + 1] += out.rowptr[(size_t)r];

@@ -87,6 +87,7 @@ struct BatchPadding {
   std::vector<int> row_map;          // [n_orig] padded row of each caller row
   std::vector<int> chunk_sys;        // [n_pad/256] system of each 256-row chunk
   std::vector<int> first_blk;        // [nsys+1] first 512-row chunk of each system
+  std::vector<int> sys_end;          // [nsys] end of each system's own rows (before its padding)
   std::vector<int64_t> rowptr;       // [n_pad+1] the padded matrix
   std::vector<int32_t> col;          // [nnz] its columns (values keep the caller's order)
 };

@@ -65,7 +65,8 @@ constexpr int64_t kFusedMinRows = 1 << 18;
 // system it accepts at all
 constexpr int kOneGroupThreads = 512;
 constexpr int64_t kOneGroupMaxRows = 1 << 20;
-constexpr int64_t kOneGroupAutoRows = 896;  // the automatic schedule's choice (auto_schedule)
+// the automatic schedule's choice (auto_schedule): one system, a batch's largest
+constexpr int64_t kOneGroupAutoRows = 896, kOneGroupBatchAutoRows = 1600;
 // p-BiCGSafe's update passes stream the vectors they do not hand to the next
 // kernel past the cache once an iteration moves at least kStreamMinBytes (well
 // above the 256 MiB last-level cache; below it the cache still holds part of
@@ -157,10 +158,11 @@ struct ps_matrix {
   // row per system, inner-product partials per 512-row workgroup
   int nsys = 1;
   int64_t n_orig = 0;            // rows of the caller's concatenation (= n for one system)
-  int64_t max_sys_rows = 0;      // padded rows of the largest system (= n for one system)
+  int64_t max_sys_rows = 0;      // rows of the largest system (= n for one system)
   int *chunk_sys = nullptr;      // device: system of each 256-row chunk (nullptr: one system)
   int *first_blk = nullptr;      // device: first 512-row workgroup of each system, [nsys+1]
   int *first_pblk = nullptr;     // device: first sparse-product workgroup of each system
+  int *sys_end = nullptr;        // device: end of each system's own rows, [nsys]
   int *row_map = nullptr;        // device: padded row of each caller row
   double *stage = nullptr;       // device: n_orig doubles for host input/output
   double *bpart = nullptr;       // device: [9][n/512] partial triples
@@ -892,14 +894,22 @@ bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kO
 //    (0; 10^6 uneven rows: 219 / 249 / 238 -- the gather-bound products gain
 //    nothing from the skipped pass and pay for the extra epilogue reads);
 //  - batches: 2 (the 512-system stencil batch: 17% more solves/s than 0, 4%
-//    more than 1; schedule 3 is single-system only);
+//    more than 1; schedule 3 is single-system only), or 4 (one workgroup per
+//    system) on the sliced layout when no system has more than
+//    kOneGroupBatchAutoRows rows (stencil batches, ms for 2 / 4: 512 systems
+//    of 8^2..16^2 rows 1.58 / 0.96, 2048 of them 3.00 / 2.79, 4096 5.15 /
+//    5.14; 512 of 24^2..32^2 4.09 / 3.23; 512 of 30^2..40^2 5.99 / 5.23;
+//    512 of 40^2..64^2 15.7 / 17.7);
 //  - one sliced system of at most kOneGroupAutoRows rows: the whole solve in
 //    one workgroup (4; 3 / 4: 36 rows 15.5 / 10.4, 256 rows 16.1 / 10.5, 576
 //    rows 17.4 / 13.9, 784 rows 18.1 / 16.9, 1024 rows 17.5 / 17.5, 4096 rows
 //    17.9 / 43.3 -- a single CU's bandwidth caps it beyond a few hundred rows).
 //    p-BiCGSafe only: the other methods fall back to 3.
 int auto_schedule(const ps_matrix *M) {
-  if (M->nsys > 1) return 2;
+  if (M->nsys > 1)
+    return M->format == PS_FMT_SELL && M->sell_rpl == 1 && M->max_sys_rows <= kOneGroupBatchAutoRows
+               ? 4
+               : 2;
   if (M->format == PS_FMT_SELL)
     return M->n <= kOneGroupAutoRows && M->sell_rpl == 1 ? 4 : 3;
   return M->n < kFusedMinRows ? 3 : 0;
@@ -1065,7 +1075,7 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
   P.fallback = o.x0_fallback != 0 && x0 != nullptr && !P.resume;
   P.scale = o.x0_fallback == 2 && x0 != nullptr && !P.resume;
   int sched = o.schedule >= 0 ? o.schedule : auto_schedule(M);
-  if (sched == 4 && !one_group_ok(M, variant, o)) sched = 3;  // automatic, not p-BiCGSafe
+  if (sched == 4 && !one_group_ok(M, variant, o)) sched = batch ? 2 : 3;  // automatic
   P.one = sched == 4;
   P.fused = safe_pipelined && sched >= 1;
   P.fused2 = P.fused && sched >= 2;
@@ -1138,8 +1148,8 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
               M->slot(PS_V_T), M->slot(PS_V_P), M->slot(PS_V_U), M->slot(PS_V_Z),
               M->slot(PS_V_W), M->slot(PS_V_L), M->slot(PS_V_G), M->slot(PS_V_AS),
               M->slot(PS_V_RS), M->sc, M->ctl, M->hist, M->hist_stride, M->running(),
-              M->nsys > 1 ? M->first_blk : nullptr, (int)M->n, P.maxit, P.tol,
-              P.norm_ref == 0 ? DF_SET_REF : 0};
+              M->nsys > 1 ? M->first_blk : nullptr, M->nsys > 1 ? M->sys_end : nullptr,
+              (int)M->n, P.maxit, P.tol, P.norm_ref == 0 ? DF_SET_REF : 0};
     // (never profiled, so launched directly, with its own block size)
     if (M->index_bits == 16)
       hipLaunchKernelGGL((k_solve_one<short, kOneGroupThreads>), dim3(M->nsys),
@@ -1261,6 +1271,7 @@ void free_matrix(ps_matrix *M) {
   (void)hipFree(M->chunk_sys);
   (void)hipFree(M->first_blk);
   (void)hipFree(M->first_pblk);
+  (void)hipFree(M->sys_end);
   (void)hipFree(M->row_map);
   (void)hipFree(M->stage);
   (void)hipFree(M->bpart);
@@ -1540,8 +1551,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   if (bl) {
     M->max_sys_rows = 0;
     for (int k = 0; k < nsys; ++k)
-      M->max_sys_rows =
-          std::max<int64_t>(M->max_sys_rows, 512 * (int64_t)(bl->first_blk[k + 1] - bl->first_blk[k]));
+      M->max_sys_rows = std::max<int64_t>(M->max_sys_rows,
+                                          bl->sys_end[k] - 512 * (int64_t)bl->first_blk[k]);
   }
   PS_CREATE_HIP(hipMalloc(&M->sc, (size_t)nsys * SC_COUNT * sizeof(double)));
   PS_CREATE_HIP(hipMalloc(&M->ctl, ((size_t)nsys + 1) * C_COUNT * sizeof(int)));
@@ -1549,6 +1560,7 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
     PS_CREATE_HIP(hipMalloc(&M->chunk_sys, bl->chunk_sys.size() * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->first_blk, bl->first_blk.size() * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->first_pblk, pfirst.size() * sizeof(int)));
+    PS_CREATE_HIP(hipMalloc(&M->sys_end, bl->sys_end.size() * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->row_map, bl->row_map.size() * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->stage, (size_t)bl->n_orig * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->bpart, kPart * 9 * (size_t)(n / 512) * sizeof(double)));
@@ -1590,6 +1602,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
       (bl && !chk(hipMemcpy(M->first_blk, bl->first_blk.data(), bl->first_blk.size() * sizeof(int),
                             hipMemcpyHostToDevice))) ||
       (bl && !chk(hipMemcpy(M->first_pblk, pfirst.data(), pfirst.size() * sizeof(int),
+                            hipMemcpyHostToDevice))) ||
+      (bl && !chk(hipMemcpy(M->sys_end, bl->sys_end.data(), bl->sys_end.size() * sizeof(int),
                             hipMemcpyHostToDevice))) ||
       (bl && !chk(hipMemcpy(M->row_map, bl->row_map.data(), bl->row_map.size() * sizeof(int),
                             hipMemcpyHostToDevice))) ||

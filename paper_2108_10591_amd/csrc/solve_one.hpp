@@ -3,12 +3,13 @@
 // microseconds of launch and drain with almost no work (schedule 4).
 //
 // The workgroup's NT threads own the rows r0 + t, r0 + t + NT, ... of their
-// system in every phase, so A s_i and w_i, which are row-local once the row's
-// sum is known, need no barrier between them; a barrier separates the phases
-// that gather (A s_i reads every s, A w_i every w).  Each iteration is the
-// single-stream fused schedule's: the reduction phase from the nine inner
-// products that the previous iteration's epilogue accumulated (the first from
-// the vectors themselves), A s_i with w_i, and A w_i with every other update.
+// system (a batch's padding rows excluded) in every phase, so A s_i and w_i,
+// which are row-local once the row's sum is known, need no barrier between
+// them; a barrier separates the phases that gather (A s_i reads every s, A w_i
+// every w).  Each iteration is the single-stream fused schedule's: the
+// reduction phase from the nine inner products that the previous iteration's
+// epilogue accumulated (the first from the vectors themselves), A s_i with
+// w_i, and A w_i with every other update.
 // Every per-row expression is the one the separate kernels use (sell_row adds
 // a row's slots in slot order, as k_sell does; w_next and EpiPBiCGSafeAll are
 // the pass's and the epilogue's), and the inner products are exact sums
@@ -106,7 +107,10 @@ struct OneArgs {
   double *hist;  // residual histories, hist_stride entries per system
   int64_t hist_stride;
   int *running;
-  const int *first_blk;  // batches: first 512-row block of each system, [systems + 1]; else nullptr
+  // batches: first 512-row block of each system, [systems + 1], and the end of its own
+  // rows, [systems] (its padding rows are empty and stay zero in every vector, so they
+  // are skipped); one system: nullptr
+  const int *first_blk, *sys_end;
   int n, maxit;
   double tol;
   int first_flags;  // DotFlags of the first reduction phase (DF_SET_REF: rho_0 is the reference)
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(NT) void k_solve_one(SellDev<double, IT> S, OneArgs
   __shared__ int cl[C_COUNT];       // and its control block
   const int sys = blockIdx.x;
   const int r0 = O.first_blk ? O.first_blk[sys] * 512 : 0;
-  const int r1 = O.first_blk ? O.first_blk[sys + 1] * 512 : O.n;
+  const int r1 = O.first_blk ? O.sys_end[sys] : O.n;
   double *gsc = O.sc + (size_t)sys * SC_COUNT;
   int *gctl = O.ctl + (size_t)sys * C_COUNT;
   if (threadIdx.x < SC_COUNT) scl[threadIdx.x] = gsc[threadIdx.x];

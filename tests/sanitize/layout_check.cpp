@@ -199,6 +199,7 @@ void check_batch(const std::vector<int64_t> &sizes, const std::string &name) {
     if (p0 % psl::kBatchAlign || p1 - p0 < sizes[(size_t)k] || p1 - p0 >= sizes[(size_t)k] + psl::kBatchAlign)
       fail(name + ": system padding");
     if (P.first_blk[(size_t)k] * (int64_t)psl::kBatchAlign != p0) fail(name + ": first 512-row chunk");
+    if (P.sys_end[(size_t)k] != p0 + sizes[(size_t)k]) fail(name + ": end of the system's own rows");
     for (int64_t c = p0 / 256; c < p1 / 256; ++c)
       if (P.chunk_sys[(size_t)c] != k) fail(name + ": chunk owner");
     const int64_t shift = p0 - sys_ptr[(size_t)k];

@@ -152,3 +152,20 @@ def test_one_group_edge_matrices(case):
     assert res.status == ref.status and res.iters == ref.iters, (case, res.status, ref.status)
     assert np.array_equal(res.hist, ref.hist, equal_nan=True), case
     assert np.array_equal(res.x, ref.x, equal_nan=True), case
+
+
+def test_one_group_automatic_for_batches_of_small_systems():
+    """Batches whose systems have at most 1600 rows (sliced layout) run one workgroup per
+    system by default; p-BiCGSafe-rr and larger systems keep the shared launches (2)."""
+    small = W.cd2d_batch(nsys=48, seed=7, nmin=6, nmax=40)
+    large = W.cd2d_batch(nsys=6, seed=7, nmin=36, nmax=48)
+    for B, want in ((small, 4), (large, 2)):
+        C = B.concat()
+        with pipesafe.BatchMatrix.from_batch(B, SELL16) as M:
+            assert M.info()["auto_schedule"] == want, B.name
+            for v in ("pbicgsafe", "pbicgsafe_rr"):
+                say(f"automatic batch schedule {B.name} max side {max(int(round(A.n ** 0.5)) for A in B.systems)} {v}")
+                import test_gpu_batch as TB
+                refs = TB.oracle_each(B, C.b, 1e-10, 2000, v, rr_m=11)
+                res = M.solve(C.b, tol=1e-10, maxit=2000, variant=v, rr_m=11)
+                TB.check_same(res, refs, B, (B.name, v))
