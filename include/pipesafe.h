@@ -134,16 +134,17 @@ typedef struct {
                           fold and finish the two reduction phases the same way:
                           four launches per iteration on one stream, 40n bytes fewer
                           than the separate passes (0).
-                          4: the whole solve in one workgroup of 512 threads per
-                          system (Algorithm 4 with schedule 3's reduction phase; one
-                          launch per solve, barriers between the phases that gather):
+                          4: the whole solve in one workgroup per system (64-512
+                          threads, by the rows per system and how many systems run;
+                          Algorithm 4 with schedule 3's reduction phase; one launch
+                          per solve, barriers between the phases that gather):
                           p-BiCGSafe only, FP64, sliced layout with one row per lane,
                           no resume or profiling, at most 2^20 rows per system, one
                           system or a batch; otherwise PS_EINVAL.  Measured: faster
-                          than 3 below about 1000 rows (256 rows: 10.5 against 16.1
+                          than 3 below about 1000 rows (256 rows: 7.8 against 15.9
                           us per iteration), far slower above (4096 rows: 43.3
                           against 17.9), where one CU's bandwidth bounds it; batches
-                          of systems up to 40^2 rows: 1.0-2.1x the solves/s of 2.
+                          of systems up to 40^2 rows: 1.4-3.1x the solves/s of 2.
                           Results are bit-identical to schedule 0.  ssBiCGSafe2: 1, 2,
                           3 and 4 are PS_EINVAL; p-BiCGStab: 1, 2 and 4.               */
   int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).

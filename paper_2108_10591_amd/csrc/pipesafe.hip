@@ -59,11 +59,14 @@ constexpr int kMaxDotGrid = 512;  // partial-sum blocks: two per CU
 // skipped pass and pays for the extra reads in its epilogue.
 constexpr int64_t kOverlapMinBytes = 128ll << 20;
 constexpr int64_t kFusedMinRows = 1 << 18;
-// schedule 4 (the whole solve in one workgroup per system): its threads (1024
-// threads leave 128 registers per lane, and the epilogue's accumulators then
-// spill: 58.4 against 43.3 us per iteration on 4096 rows), and the rows per
-// system it accepts at all
+// schedule 4 (the whole solve in one workgroup per system): its largest
+// workgroup (1024 threads leave 128 registers per lane, and the epilogue's
+// accumulators then spill: 58.4 against 43.3 us per iteration on 4096 rows),
+// the threads the chip holds at once (two 64-lane waves per SIMD at the
+// kernel's 176 registers: 8 waves on each of 256 CUs), and the rows per system
+// it accepts at all
 constexpr int kOneGroupThreads = 512;
+constexpr int64_t kOneGroupResident = 256 * 8 * 64;
 constexpr int64_t kOneGroupMaxRows = 1 << 20;
 // the automatic schedule's choice (auto_schedule): one system, a batch's largest
 constexpr int64_t kOneGroupAutoRows = 896, kOneGroupBatchAutoRows = 1600;
@@ -897,12 +900,12 @@ bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kO
 //    more than 1; schedule 3 is single-system only), or 4 (one workgroup per
 //    system) on the sliced layout when no system has more than
 //    kOneGroupBatchAutoRows rows (stencil batches, ms for 2 / 4: 512 systems
-//    of 8^2..16^2 rows 1.58 / 0.96, 2048 of them 3.00 / 2.79, 4096 5.15 /
-//    5.14; 512 of 24^2..32^2 4.09 / 3.23; 512 of 30^2..40^2 5.99 / 5.23;
-//    512 of 40^2..64^2 15.7 / 17.7);
+//    of 8^2..16^2 rows 1.58 / 0.57, 4096 of them 5.16 / 1.66; 512 of
+//    24^2..32^2 4.11 / 2.25, 2048 10.37 / 7.52; 512 of 30^2..40^2 5.95 / 4.24;
+//    of 40^2..64^2: 512 15.6 / 14.7, 1024 29.1 / 34.9, 2048 56.9 / 71.5);
 //  - one sliced system of at most kOneGroupAutoRows rows: the whole solve in
-//    one workgroup (4; 3 / 4: 36 rows 15.5 / 10.4, 256 rows 16.1 / 10.5, 576
-//    rows 17.4 / 13.9, 784 rows 18.1 / 16.9, 1024 rows 17.5 / 17.5, 4096 rows
+//    one workgroup (4; 3 / 4: 36 rows 15.3 / 6.4, 256 rows 15.9 / 7.8, 576
+//    rows 17.5 / 13.7, 784 rows 17.3 / 16.9, 1024 rows 17.7 / 17.4, 4096 rows
 //    17.9 / 43.3 -- a single CU's bandwidth caps it beyond a few hundred rows).
 //    p-BiCGSafe only: the other methods fall back to 3.
 int auto_schedule(const ps_matrix *M) {
@@ -1005,6 +1008,28 @@ struct WorkspaceSwap {
 // row order), on the device or the host.  ws: NULL, or a device workspace laid
 // out by workspace_layout that replaces the handle's own blocks for this solve
 // (then nothing is allocated: no graphs, no profiling, no history growth).
+// k_solve_one, one workgroup of nt threads (64, 128, 256 or 512) per system
+template <int NT>
+int launch_one_nt(ps_matrix *M, hipStream_t s, const OneArgs &a) {
+  if (M->index_bits == 16)
+    hipLaunchKernelGGL((k_solve_one<short, NT>), dim3(M->nsys), dim3(NT), 0, s,
+                       M->template sell<double, short>(), a);
+  else
+    hipLaunchKernelGGL((k_solve_one<int, NT>), dim3(M->nsys), dim3(NT), 0, s,
+                       M->template sell<double, int>(), a);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+int launch_one(ps_matrix *M, hipStream_t s, int nt, const OneArgs &a) {
+  switch (nt) {
+    case 64: return launch_one_nt<64>(M, s, a);
+    case 128: return launch_one_nt<128>(M, s, a);
+    case 256: return launch_one_nt<256>(M, s, a);
+    case 512: return launch_one_nt<512>(M, s, a);
+  }
+  return PS_EINVAL;
+}
+
 // schedule 4 runs p-BiCGSafe in FP64 on the sliced layout (one row per lane),
 // from x_0 (no resume), without profiling, on systems of at most
 // kOneGroupMaxRows rows each
@@ -1150,14 +1175,14 @@ int solve_impl(ps_matrix *M, const double *b, const double *x0, bool on_device, 
               M->slot(PS_V_RS), M->sc, M->ctl, M->hist, M->hist_stride, M->running(),
               M->nsys > 1 ? M->first_blk : nullptr, M->nsys > 1 ? M->sys_end : nullptr,
               (int)M->n, P.maxit, P.tol, P.norm_ref == 0 ? DF_SET_REF : 0};
-    // (never profiled, so launched directly, with its own block size)
-    if (M->index_bits == 16)
-      hipLaunchKernelGGL((k_solve_one<short, kOneGroupThreads>), dim3(M->nsys),
-                         dim3(kOneGroupThreads), 0, P.A, M->template sell<double, short>(), a);
-    else
-      hipLaunchKernelGGL((k_solve_one<int, kOneGroupThreads>), dim3(M->nsys),
-                         dim3(kOneGroupThreads), 0, P.A, M->template sell<double, int>(), a);
-    PS_HIP(hipGetLastError());
+    // (never profiled, so launched directly, with its own block size).  The
+    // workgroup: 512 threads, fewer when the systems have fewer rows or when so
+    // many systems run that smaller workgroups let more of them be resident at
+    // once; 64 at the least
+    int nt = kOneGroupThreads;
+    while (nt > 64 && (nt / 2 >= M->max_sys_rows || (int64_t)M->nsys * nt > kOneGroupResident))
+      nt /= 2;
+    PS_TRY(launch_one(M, P.A, nt, a));
     stopped = true;  // the loop below has nothing left to launch
   }
   for (int i = P.i0; i <= last && !stopped;) {

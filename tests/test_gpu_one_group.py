@@ -169,3 +169,20 @@ def test_one_group_automatic_for_batches_of_small_systems():
                 refs = TB.oracle_each(B, C.b, 1e-10, 2000, v, rr_m=11)
                 res = M.solve(C.b, tol=1e-10, maxit=2000, variant=v, rr_m=11)
                 TB.check_same(res, refs, B, (B.name, v))
+
+
+def test_one_group_many_tiny_systems():
+    """600 systems of 36..144 rows: workgroups of 128 threads (so that more systems are
+    resident at once), some threads owning two rows; the oracle's bits for every system,
+    and the shared launches' (schedule 2)."""
+    import test_gpu_batch as TB
+    B = W.cd2d_batch(nsys=600, seed=11, nmin=6, nmax=12)
+    C = B.concat()
+    refs = TB.oracle_each(B, C.b, 1e-10, 500, "pbicgsafe")
+    with pipesafe.BatchMatrix.from_batch(B, SELL16) as M:
+        assert M.info()["auto_schedule"] == 4
+        say("one group: 600 tiny systems")
+        res = M.solve(C.b, tol=1e-10, maxit=500, variant="pbicgsafe")
+        TB.check_same(res, refs, B, "600 tiny systems")
+        r2 = M.solve(C.b, tol=1e-10, maxit=500, variant="pbicgsafe", schedule=2)
+        assert np.array_equal(r2.x, res.x) and np.array_equal(r2.iters, res.iters)
