@@ -284,6 +284,27 @@ def bench_batch(name, reps=3):
         split[tag] = {"systems": len(sub), "time_ms": round(1e3 * ts, 2),
                       "iterations_max": int(np.max(rs.iters))}
     log(f"  split by grid side: {split}")
+    # a batch of many small systems (4096 stencils of 8^2..16^2 rows, the same family):
+    # the automatic schedule (one workgroup per system) against the shared launches
+    Bt = workloads.cd2d_batch(nsys=4096, seed=5, nmin=8, nmax=16)
+    bt = torch.from_numpy(Bt.concat().b).cuda()
+    xt = torch.empty_like(bt)
+    small = {"systems": Bt.nsys, "grid_sides": [8, 16], "tol": tol}
+    with pipesafe.BatchMatrix.from_batch(Bt) as Mt2:
+        small["auto_schedule"] = Mt2.info()["auto_schedule"]
+        for tag, sched in (("automatic", -1), ("schedule_2", 2)):
+            Mt2.solve_dev(bt, None, xt, tol=tol, maxit=10_000, variant="pbicgsafe", hist=False,
+                          schedule=sched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                rt2 = Mt2.solve_dev(bt, None, xt, tol=tol, maxit=10_000, variant="pbicgsafe",
+                                    hist=False, schedule=sched)
+            torch.cuda.synchronize()
+            ts = (time.perf_counter() - t0) / reps
+            small[tag] = {"time_ms": round(1e3 * ts, 3), "solves_per_s": round(Bt.nsys / ts, 1),
+                          "iterations_max": int(np.max(rt2.iters))}
+    log(f"  small systems: {small}")
     return {"workload": name, "systems": B.nsys, "rows": C.n, "nnz": C.nnz, "tol": tol,
             "variant": "pbicgsafe", "layout": info["format"], "schedule": sched,
             "iterations_min_mean_max": [int(r.iters.min()), round(float(r.iters.mean()), 1),
@@ -300,7 +321,7 @@ def bench_batch(name, reps=3):
                           "time_ms": round(1e3 * t_tuned, 2),
                           "solves_per_s": round(B.nsys / t_tuned, 1),
                           "same_format_as_automatic": tinfo["format"] == info["format"]},
-            "split": split}
+            "split": split, "small_systems": small}
 
 
 def bench_mixed(name, rr_ms, reps=3):
