@@ -95,7 +95,7 @@ typedef struct {
                           bit-identical either way.  Ignored while profiling.          */
   int32_t schedule;    /* Where the reduction phases run: p-BiCGSafe, p-BiCGSafe-rr and
                           (0 and 3 only) p-BiCGStab.  -1 (default): automatic --
-                          sliced layout: 4 up to 896 rows (p-BiCGSafe in FP64 from
+                          sliced layout: 4 up to 1024 rows (p-BiCGSafe in FP64 from
                           x0; otherwise 3), else 3; CSR: 3 below 2^18 rows, else 0;
                           batches: 4 on the sliced layout when no system has more
                           than 1600 rows (same conditions; otherwise 2), else 2
@@ -140,11 +140,14 @@ typedef struct {
                           per solve, barriers between the phases that gather):
                           p-BiCGSafe only, FP64, sliced layout with one row per lane,
                           no resume or profiling, at most 2^20 rows per system, one
-                          system or a batch; otherwise PS_EINVAL.  Measured: faster
-                          than 3 below about 1000 rows (256 rows: 7.8 against 15.9
-                          us per iteration), far slower above (4096 rows: 43.3
-                          against 17.9), where one CU's bandwidth bounds it; batches
-                          of systems up to 40^2 rows: 1.4-3.1x the solves/s of 2.
+                          system or a batch; otherwise PS_EINVAL.  Systems of at
+                          most two rows per thread and at most 8 entries per row keep
+                          their rows in registers and s, w in LDS.  Measured: faster
+                          than 3 up to about 1000 rows (256 rows: 5.7 against 16.1
+                          us per iteration; 1024: 11.5 against 17.6), far slower
+                          above (4096 rows: 43.3 against 17.9), where one CU's
+                          bandwidth bounds it; batches of systems up to 40^2 rows:
+                          1.4-3.5x the solves/s of 2.
                           Results are bit-identical to schedule 0.  ssBiCGSafe2: 1, 2,
                           3 and 4 are PS_EINVAL; p-BiCGStab: 1, 2 and 4.               */
   int32_t x0_fallback; /* What to do with a given x0 (per system for a batch).

@@ -69,7 +69,7 @@ constexpr int kOneGroupThreads = 512;
 constexpr int64_t kOneGroupResident = 256 * 8 * 64;
 constexpr int64_t kOneGroupMaxRows = 1 << 20;
 // the automatic schedule's choice (auto_schedule): one system, a batch's largest
-constexpr int64_t kOneGroupAutoRows = 896, kOneGroupBatchAutoRows = 1600;
+constexpr int64_t kOneGroupAutoRows = 1024, kOneGroupBatchAutoRows = 1600;
 // p-BiCGSafe's update passes stream the vectors they do not hand to the next
 // kernel past the cache once an iteration moves at least kStreamMinBytes (well
 // above the 256 MiB last-level cache; below it the cache still holds part of
@@ -141,6 +141,7 @@ struct ps_matrix {
   int64_t slots = 0;
   int nslice = 0;
   int sell_rpl = 1;                      // rows per lane of the sliced layout (1 or 2)
+  int sell_width = 0;                    // the sliced layout's widest slice (entries per row)
   int stream_override = -1;              // streaming update passes: -1 automatic, 0, 1
   // the values rounded to FP32 (mixed-precision solves), made on first use
   float *val32 = nullptr, *sval32 = nullptr;
@@ -904,9 +905,11 @@ bool auto_overlap(const ps_matrix *M) { return matrix_bytes(M) + 16 * M->n >= kO
 //    24^2..32^2 4.11 / 2.25, 2048 10.37 / 7.52; 512 of 30^2..40^2 5.95 / 4.24;
 //    of 40^2..64^2: 512 15.6 / 14.7, 1024 29.1 / 34.9, 2048 56.9 / 71.5);
 //  - one sliced system of at most kOneGroupAutoRows rows: the whole solve in
-//    one workgroup (4; 3 / 4: 36 rows 15.3 / 6.4, 256 rows 15.9 / 7.8, 576
-//    rows 17.5 / 13.7, 784 rows 17.3 / 16.9, 1024 rows 17.7 / 17.4, 4096 rows
-//    17.9 / 43.3 -- a single CU's bandwidth caps it beyond a few hundred rows).
+//    one workgroup (4; 3 / 4, stencils, whose rows the workgroup keeps in
+//    registers: 36 rows 15.3 / 5.1, 256 rows 16.1 / 5.7, 576 rows 17.6 / 10.0,
+//    1024 rows 17.6 / 11.5; wider rows, read from memory every iteration: 1024
+//    rows 17.7 / 17.4; 1296 rows 17.9 / 21.0, 4096 rows 17.9 / 43.3 -- a
+//    single CU's bandwidth caps it beyond about a thousand rows).
 //    p-BiCGSafe only: the other methods fall back to 3.
 int auto_schedule(const ps_matrix *M) {
   if (M->nsys > 1)
@@ -1008,15 +1011,24 @@ struct WorkspaceSwap {
 // row order), on the device or the host.  ws: NULL, or a device workspace laid
 // out by workspace_layout that replaces the handle's own blocks for this solve
 // (then nothing is allocated: no graphs, no profiling, no history growth).
-// k_solve_one, one workgroup of nt threads (64, 128, 256 or 512) per system
+// k_solve_one, one workgroup of nt threads (64, 128, 256 or 512) per system;
+// k_solve_tiny when every system has at most 2 nt rows and no slice more than
+// kTinySlots entries per row
+template <class IT, int NT>
+void launch_one_it(ps_matrix *M, hipStream_t s, const OneArgs &a) {
+  const SellDev<double, IT> S = M->template sell<double, IT>();
+  const bool tiny = M->sell_width <= kTinySlots;
+  if (tiny && M->max_sys_rows <= NT)
+    hipLaunchKernelGGL((k_solve_tiny<IT, NT, 1>), dim3(M->nsys), dim3(NT), 0, s, S, a);
+  else if (tiny && M->max_sys_rows <= 2 * NT)
+    hipLaunchKernelGGL((k_solve_tiny<IT, NT, 2>), dim3(M->nsys), dim3(NT), 0, s, S, a);
+  else
+    hipLaunchKernelGGL((k_solve_one<IT, NT>), dim3(M->nsys), dim3(NT), 0, s, S, a);
+}
 template <int NT>
 int launch_one_nt(ps_matrix *M, hipStream_t s, const OneArgs &a) {
-  if (M->index_bits == 16)
-    hipLaunchKernelGGL((k_solve_one<short, NT>), dim3(M->nsys), dim3(NT), 0, s,
-                       M->template sell<double, short>(), a);
-  else
-    hipLaunchKernelGGL((k_solve_one<int, NT>), dim3(M->nsys), dim3(NT), 0, s,
-                       M->template sell<double, int>(), a);
+  if (M->index_bits == 16) launch_one_it<short, NT>(M, s, a);
+  else launch_one_it<int, NT>(M, s, a);
   PS_HIP(hipGetLastError());
   return PS_OK;
 }
@@ -1567,6 +1579,8 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
       PS_CREATE_HIP(hipMalloc(&M->scol, std::max<int64_t>(slots, 1) * sizeof(int)));
     PS_CREATE_HIP(hipMalloc(&M->sval, std::max<int64_t>(slots, 1) * sizeof(double)));
     PS_CREATE_HIP(hipMalloc(&M->soff, soff.size() * sizeof(int)));
+    for (size_t q = 0; q + 1 < soff.size(); ++q)
+      M->sell_width = std::max(M->sell_width, (soff[q + 1] - soff[q]) / (kWave * M->sell_rpl));
   }
   PS_CREATE_HIP(hipMalloc(&M->vec, (size_t)kNumSlots * M->ld * sizeof(double)));
   const int nsys = bl ? bl->nsys : 1;

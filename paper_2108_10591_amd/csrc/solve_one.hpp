@@ -202,4 +202,168 @@ __global__ __launch_bounds__(NT) void k_solve_one(SellDev<double, IT> S, OneArgs
   if (threadIdx.x < C_COUNT) gctl[threadIdx.x] = cl[threadIdx.x];
 }
 
+// The same solve when every system has at most R * NT rows (R = 1 or 2) and the
+// layout's slices at most kTinySlots entries per row: thread t owns rows
+// r0 + t + q NT (q < R) for the whole solve and keeps those rows' entries and
+// their vector entries in registers; s and w, the vectors the products gather,
+// also live in LDS (sv, wv), so an iteration touches global memory only for the
+// history.  The arithmetic is k_solve_one's (each row's slots summed in slot
+// order, w_next, the epilogue's next() and dots()), so are the results.  The
+// vectors are written back when the system stops.
+constexpr int kTinySlots = 8;
+
+template <class IT, int NT, int R>
+__global__ __launch_bounds__(NT) void k_solve_tiny(SellDev<double, IT> S, OneArgs O) {
+  using E = EpiPBiCGSafeAll<false>;
+  __shared__ double lds[9 * (NT / 16) * kPart];
+  __shared__ double d9[9];
+  __shared__ double scl[SC_COUNT];
+  __shared__ int cl[C_COUNT];
+  __shared__ double sv[R * NT], wv[R * NT];  // s and w of the system's rows
+  const int sys = blockIdx.x;
+  const int r0 = O.first_blk ? O.first_blk[sys] * 512 : 0;
+  const int r1 = O.first_blk ? O.sys_end[sys] : O.n;
+  double *gsc = O.sc + (size_t)sys * SC_COUNT;
+  int *gctl = O.ctl + (size_t)sys * C_COUNT;
+  if (threadIdx.x < SC_COUNT) scl[threadIdx.x] = gsc[threadIdx.x];
+  if (threadIdx.x < C_COUNT) cl[threadIdx.x] = gctl[threadIdx.x];
+  __syncthreads();
+  if (cl[C_DONE]) return;  // stopped in the set-up
+  DotArgs D{};
+  D.ctl = cl;
+  D.sc = scl;
+  D.hist = O.hist + (size_t)sys * O.hist_stride;
+  D.maxit = O.maxit;
+  D.tol = O.tol;
+  D.flags = O.first_flags;
+  D.running = O.running;
+  // the rows' entries in slot order: columns as indices into sv / wv (-1: padding)
+  int cc[R][kTinySlots];
+  double vv[R][kTinySlots];
+  E::In st[R];
+  bool mine[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = r0 + threadIdx.x + q * NT;
+    mine[q] = k < r1;
+    st[q] = E::In{};
+#pragma unroll
+    for (int j = 0; j < kTinySlots; ++j) {
+      cc[q][j] = -1;
+      vv[q][j] = 0.0;
+    }
+    if (mine[q]) {
+      const int sl = k / kWave;
+      const int beg = S.off[sl] + k % kWave, end = S.off[sl + 1];
+#pragma unroll
+      for (int j = 0; j < kTinySlots; ++j) {
+        const int kk = beg + j * kWave;
+        if (kk < end) {
+          const IT d = S.col[kk];
+          vv[q][j] = S.val[kk];
+          if constexpr (sizeof(IT) == 4) cc[q][j] = d < 0 ? -1 : (int)d - r0;
+          else cc[q][j] = d == kSellPad16 ? -1 : k + (int)d - r0;
+        }
+      }
+      st[q] = E::In{O.r[k], O.p[k], O.u[k], O.s[k], O.t[k], O.y[k], O.As[k],
+                    O.l[k], O.g[k], O.z[k], O.x[k], O.rs[k], O.w[k]};
+    }
+    sv[threadIdx.x + q * NT] = st[q].s;
+  }
+  // the first reduction phase from the vectors (y_0 = t_{-1} = 0), in ProdSafe9's order
+  bool first = true;
+  TD acc[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) acc[j] = TD{0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+    if (mine[q]) {
+      const double a[5] = {st[q].s, st[q].y, st[q].r, st[q].rs, st[q].t};
+      ProdSafe9<true>::acc(a, acc);
+    }
+  for (;;) {
+    const TD tot = block_sum_td_rows<9, NT>(acc, lds);  // (its barriers also publish sv)
+    if (threadIdx.x < 9) d9[threadIdx.x] = td_round(tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const FinPre pre = fin_preload(D);
+      double d[9];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const int row = (int)((kSafeRows >> (4 * j)) & 15u);
+        d[j] = d9[first ? j : ((kSafeFromB >> j) & 1u) ? 5 + row : row];
+      }
+      FinSafe::run(D, pre, d);
+      if (cl[C_DONE]) atomicSub(D.running, 1);
+    }
+    D.flags = 0;
+    first = false;
+    __syncthreads();
+    if (cl[C_DONE]) break;
+    const double al = scl[PS_S_ALPHA], be = scl[PS_S_BETA], ze = scl[PS_S_ZETA],
+                 et = scl[PS_S_ETA];
+    // A s_i and w_i (Eqs. (q), (w))
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (mine[q]) {
+        DD a{0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < kTinySlots; ++j)
+          if (cc[q][j] >= 0) sum_acc(a, vv[q][j] * sv[cc[q][j]]);
+        st[q].As = a.hi + a.lo;
+        st[q].w = w_next(st[q].As, st[q].l, st[q].g, st[q].w, be, ze, et);
+      }
+      wv[threadIdx.x + q * NT] = st[q].w;
+    }
+    __syncthreads();  // every w_i before A w_i
+    // A w_i with every other update, and the next iteration's inner products
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] = TD{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (mine[q]) {
+        DD a{0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < kTinySlots; ++j)
+          if (cc[q][j] >= 0) sum_acc(a, vv[q][j] * wv[cc[q][j]]);
+        const E::Out o = E::next(st[q], a.hi + a.lo, al, be, ze, et);
+        st[q].p = o.p;
+        st[q].u = o.u;
+        st[q].t = o.t;
+        st[q].z = o.z;
+        st[q].y = o.y;
+        st[q].x = o.x;
+        st[q].r = o.r;
+        st[q].l = o.l;
+        st[q].g = o.g;
+        st[q].s = o.s;
+        E::dots(o, st[q].rs, acc);
+      }
+      // (this iteration's reads of sv all came before the barrier above)
+      sv[threadIdx.x + q * NT] = st[q].s;
+    }
+    __syncthreads();  // every s_{i+1} before the next A s
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = r0 + threadIdx.x + q * NT;
+    if (mine[q]) {
+      O.r[k] = st[q].r;
+      O.p[k] = st[q].p;
+      O.u[k] = st[q].u;
+      O.s[k] = st[q].s;
+      O.t[k] = st[q].t;
+      O.y[k] = st[q].y;
+      O.As[k] = st[q].As;
+      O.l[k] = st[q].l;
+      O.g[k] = st[q].g;
+      O.z[k] = st[q].z;
+      O.x[k] = st[q].x;
+      O.w[k] = st[q].w;
+    }
+  }
+  if (threadIdx.x < SC_COUNT) gsc[threadIdx.x] = scl[threadIdx.x];
+  if (threadIdx.x < C_COUNT) gctl[threadIdx.x] = cl[threadIdx.x];
+}
+
 }  // namespace ps

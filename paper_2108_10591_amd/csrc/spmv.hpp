@@ -628,8 +628,12 @@ struct EpiPBiCGSafeAll {
     return In{ld(r, k), ldz(p, k), ldz(u, k), s[k], ld(t, k), ld(y, k), ld(As, k),
               l[k],     g[k],      ldz(z, k), ld(x, k), rs[k], w[k]};
   }
-  __device__ __forceinline__ void store(int k, double aw, const In &in, TD (&acc)[9]) const {
-    const double al = sc[PS_S_ALPHA], be = sc[PS_S_BETA], ze = sc[PS_S_ZETA], et = sc[PS_S_ETA];
+  // the row's new entries, from its operands and A w_i (aw)
+  struct Out {
+    double p, u, t, z, y, x, r, l, g, s;
+  };
+  __device__ __forceinline__ static Out next(const In &in, double aw, double al, double be,
+                                             double ze, double et) {
     const double o = in.s + be * in.t;
     const double pn = held(in.r + be * (in.p - in.u));
     const double un = held(ze * o + et * (in.y + be * in.u));
@@ -642,25 +646,33 @@ struct EpiPBiCGSafeAll {
     const double ln = q - aw;
     const double gn = ze * in.As + et * in.g - al * aw;
     const double sn = in.s - al * q - gn;
-    stz(p, k, pn);
-    stz(u, k, un);
-    st(t, k, tn);
-    stz(z, k, zn);
-    st(y, k, yn);
-    st(x, k, xn);
-    st(r, k, rn);
-    l[k] = ln;
-    g[k] = gn;
-    s[k] = sn;
-    td_fma(acc[0], yn, yn);
-    td_fma(acc[1], yn, rn);
-    td_fma(acc[2], in.rs, rn);
-    td_fma(acc[3], in.rs, tn);
-    td_fma(acc[4], rn, rn);
-    td_fma(acc[5], sn, sn);
-    td_fma(acc[6], sn, yn);
-    td_fma(acc[7], sn, rn);
-    td_fma(acc[8], in.rs, sn);
+    return Out{pn, un, tn, zn, yn, xn, rn, ln, gn, sn};
+  }
+  // the row's terms of the nine inner products of iteration i+1
+  __device__ __forceinline__ static void dots(const Out &o, double rs, TD (&acc)[9]) {
+    td_fma(acc[0], o.y, o.y);
+    td_fma(acc[1], o.y, o.r);
+    td_fma(acc[2], rs, o.r);
+    td_fma(acc[3], rs, o.t);
+    td_fma(acc[4], o.r, o.r);
+    td_fma(acc[5], o.s, o.s);
+    td_fma(acc[6], o.s, o.y);
+    td_fma(acc[7], o.s, o.r);
+    td_fma(acc[8], rs, o.s);
+  }
+  __device__ __forceinline__ void store(int k, double aw, const In &in, TD (&acc)[9]) const {
+    const Out o = next(in, aw, sc[PS_S_ALPHA], sc[PS_S_BETA], sc[PS_S_ZETA], sc[PS_S_ETA]);
+    stz(p, k, o.p);
+    stz(u, k, o.u);
+    st(t, k, o.t);
+    stz(z, k, o.z);
+    st(y, k, o.y);
+    st(x, k, o.x);
+    st(r, k, o.r);
+    l[k] = o.l;
+    g[k] = o.g;
+    s[k] = o.s;
+    dots(o, in.rs, acc);
   }
 };
 

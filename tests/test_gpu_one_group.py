@@ -122,9 +122,9 @@ def test_one_group_batch_equals_each_system_alone():
 
 
 def test_one_group_automatic_choice():
-    """The automatic schedule runs sliced p-BiCGSafe systems of at most 896 rows in one
+    """The automatic schedule runs sliced p-BiCGSafe systems of at most 1024 rows in one
     workgroup (ps_info.auto_schedule = 4); p-BiCGSafe-rr and larger systems take 3."""
-    for N, want in ((16, 4), (29, 4), (30, 3)):
+    for N, want in ((16, 4), (32, 4), (33, 3)):
         A = W.cd2d(N)
         with pipesafe.Matrix.from_csr(A, SELL16) as M:
             assert M.info()["auto_schedule"] == want, N
@@ -186,3 +186,76 @@ def test_one_group_many_tiny_systems():
         TB.check_same(res, refs, B, "600 tiny systems")
         r2 = M.solve(C.b, tol=1e-10, maxit=500, variant="pbicgsafe", schedule=2)
         assert np.array_equal(r2.x, res.x) and np.array_equal(r2.iters, res.iters)
+
+
+@pytest.mark.parametrize("case", ["cd2d_8", "cd2d_16", "cd2d_22", "cd3d_6", "cd3d_8",
+                                  "band_300", "nonsym_500"])
+def test_one_group_register_resident(case):
+    """Systems of at most 512 rows whose slices hold at most 8 entries per row keep every
+    vector entry of their row, and the row's entries, in registers (s and w in LDS): the
+    oracle's bits, and schedule 3's, with 16- and 32-bit columns."""
+    A = {"cd2d_8": lambda: W.cd2d(8), "cd2d_16": lambda: W.cd2d(16), "cd2d_22": lambda: W.cd2d(22),
+         "cd3d_6": lambda: W.cd3d(6, 20.0, seed=2), "cd3d_8": lambda: W.cd3d(8, 20.0, seed=3),
+         "band_300": lambda: W.rand_band(300, seed=4, lmin=3, lmax=8, band=40),
+         "nonsym_500": lambda: W.random_csr(500, 6, lengths=np.random.default_rng(6).integers(
+             1, 8, 500))}[case]()
+    if case == "nonsym_500":  # diagonally dominant, so that the solve converges
+        S = A.to_scipy().tolil()
+        S.setdiag(1.5 * np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)
+        S = S.tocsr()
+        S.sort_indices()
+        rp = S.indptr.astype(np.int64)
+        A = W.CSR(n=500, rowptr=rp, col=S.indices.astype(np.int32), val=S.data.astype(np.float64),
+                  b=W.rhs_ones(rp, S.data.astype(np.float64)), name="nonsym_500")
+    for L in (SELL16, SELL32):
+        with pipesafe.Matrix.from_csr(A, L) as M:
+            for tol, maxit in ((1e-10, 2000), (0.0, 7)):
+                say(f"register-resident {case} tol={tol} index_bits={M.info()['index_bits']}")
+                ref = O.solve(A, tol=tol, maxit=maxit, variant="pbicgsafe")
+                res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=4)
+                assert res.status == ref.status and res.iters == ref.iters, case
+                assert np.array_equal(res.hist, ref.hist) and np.array_equal(res.x, ref.x), case
+                r3 = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=3)
+                assert np.array_equal(r3.x, res.x), case
+            # the state the solve leaves is the multi-kernel solve's too
+            M.solve(A.b, tol=0.0, maxit=5, variant="pbicgsafe", schedule=4)
+            st4 = {v: M.get_state(v) for v in ("x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g")}
+            M.solve(A.b, tol=0.0, maxit=5, variant="pbicgsafe", schedule=3)
+            for v, a in st4.items():
+                assert np.array_equal(a, M.get_state(v)), (case, v)
+
+
+def test_one_group_register_resident_batch():
+    """A batch of 200 systems of 36..256 rows (one row per thread in 256-thread
+    workgroups), some of them stopping early: each system's bits as the oracle's."""
+    import test_gpu_batch as TB
+    B = W.cd2d_batch(nsys=200, seed=13, nmin=6, nmax=16)
+    C = B.concat()
+    b = C.b.copy()
+    p = B.sys_ptr()
+    b[p[3]:p[4]] = 0.0  # converges at i = 0
+    for tol, maxit in ((1e-10, 500), (0.0, 6)):
+        refs = TB.oracle_each(B, b, tol, maxit, "pbicgsafe")
+        with pipesafe.BatchMatrix.from_batch(B, SELL16) as M:
+            say(f"register-resident batch tol={tol}")
+            res = M.solve(b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=4)
+            TB.check_same(res, refs, B, ("register-resident batch", tol))
+
+
+@pytest.mark.parametrize("case", ["cd2d_24", "cd2d_31", "cd3d_10"])
+def test_one_group_register_resident_two_rows(case):
+    """513..1024 rows: two rows per thread of a 512-thread workgroup, in registers."""
+    A = {"cd2d_24": lambda: W.cd2d(24), "cd2d_31": lambda: W.cd2d(31),
+         "cd3d_10": lambda: W.cd3d(10, 20.0, seed=4)}[case]()
+    for L in (SELL16, SELL32):
+        with pipesafe.Matrix.from_csr(A, L) as M:
+            for tol, maxit in ((1e-10, 2000), (0.0, 5)):
+                say(f"register-resident, two rows per thread: {case} tol={tol}")
+                ref = O.solve(A, tol=tol, maxit=maxit, variant="pbicgsafe")
+                res = M.solve(A.b, tol=tol, maxit=maxit, variant="pbicgsafe", schedule=4)
+                assert res.status == ref.status and res.iters == ref.iters, case
+                assert np.array_equal(res.hist, ref.hist) and np.array_equal(res.x, ref.x), case
+            st4 = {v: M.get_state(v) for v in ("x", "r", "s", "y", "t", "p", "u", "z", "w", "l", "g")}
+            M.solve(A.b, tol=0.0, maxit=5, variant="pbicgsafe", schedule=3)
+            for v, a in st4.items():
+                assert np.array_equal(a, M.get_state(v)), (case, v)
