@@ -80,6 +80,11 @@ constexpr int64_t kStreamMinBytes = 512ll << 20;
 // 18% (p-BiCGStab) and 4.6% (ssBiCGSafe2) at 128^3 (~825 MiB)
 constexpr int64_t kOtherStreamMinBytes = 640ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
+// ... or <= 1.5 nnz for systems the automatic schedule solves in one workgroup
+// each (schedule 4 needs the sliced layout; it reads a row's entries once, or
+// from cache, so their padding costs it little): a batch of 4096 systems of
+// 8^2..16^2 rows has 1.25 slots per entry
+constexpr double kSellMaxPaddingSmall = 1.5;
 constexpr int kSellRowsPerLane = 1;       // 64-row slices
 constexpr double kTuneMaxPadding = 1.5;   // the autotuner tries the sliced layout up to this
 // fused schedules: the finish adds the partial lists itself (no fold kernel)
@@ -1474,7 +1479,15 @@ int create_impl(ps_matrix **out, int64_t n, int64_t nnz, const int64_t *rowptr,
   if (lay && lay->sell_rows_per_lane > 0) M->sell_rpl = lay->sell_rows_per_lane;
   const int64_t SH = (int64_t)kWave * M->sell_rpl;  // rows per slice
   const int64_t slots = psl::sell_slots(n, rowptr, M->sell_rpl);
-  M->format = (double)slots <= kSellMaxPadding * (double)nnz + SH ? PS_FMT_SELL : PS_FMT_CSR;
+  int64_t sys_rows = n;  // rows of the largest system
+  if (bl) {
+    sys_rows = 0;
+    for (int k = 0; k < bl->nsys; ++k)
+      sys_rows = std::max<int64_t>(sys_rows, bl->sys_end[k] - bl->pstart[k]);
+  }
+  const bool one_group = M->sell_rpl == 1 && sys_rows <= (bl ? kOneGroupBatchAutoRows : kOneGroupAutoRows);
+  const double max_pad = one_group ? kSellMaxPaddingSmall : kSellMaxPadding;
+  M->format = (double)slots <= max_pad * (double)nnz + SH ? PS_FMT_SELL : PS_FMT_CSR;
   if (const char *e = std::getenv("PIPESAFE_FORMAT")) {  // tuning override
     const int v = std::atoi(e);
     if (v == PS_FMT_CSR || v == PS_FMT_SELL) M->format = v;
