@@ -109,3 +109,20 @@ def test_autotuned_batch_reproduces_oracle():
         assert res.iters[k] == ref.iters and res.status[k] == ref.status, k
         assert np.array_equal(res.x[off:off + S.n], ref.x), k
         off += S.n
+
+
+def test_tuned_options_on_a_small_sliced_system():
+    """A 400-row stencil: the tuner also times the single-stream schedule (3) and the
+    one-workgroup solve (4, one run: it has no stream, streaming or graph choice), and
+    whatever it picks reproduces the oracle bit for bit."""
+    A = W.cd2d(20, 10.0)
+    b = torch.from_numpy(A.b).cuda()
+    with pipesafe.Matrix.from_csr(A) as M:
+        assert M.info()["format"] == "sell"
+        opts, rows = M.tune_options(b, variant="pbicgsafe", iters=20)
+        say(f"tune_options small sliced: {opts}")
+        assert sum(r["schedule"] == 4 for r in rows) == 1
+        assert sum(r["schedule"] == 3 for r in rows) == 2 * 3  # streaming x graph batch
+        assert len(rows) == 3 * 2 * 2 * 3 + 2 * 3 + 1 and sum(r["best"] for r in rows) == 1
+        ref = O.solve(A, tol=1e-10, maxit=2000, variant="pbicgsafe")
+        same(M.solve(A.b, tol=1e-10, maxit=2000, variant="pbicgsafe", **opts), ref, "small")
