@@ -259,8 +259,10 @@ struct SellDev {
   int nblk;           // ceil(n / (kBlock * RPL)) row blocks of kWavesPerBlock slices
 };
 
-// Slots per row loaded ahead of their gathers per step.
+// Slots per row loaded ahead of their gathers per step: 8, or 5 for batches of
+// five-point stencils (kSellUnrollNarrow; see sell_launch).
 constexpr int kSellUnroll = 8;
+constexpr int kSellUnrollNarrow = 5;
 
 template <int RPL, class VT, class IT>
 __device__ __forceinline__ void sell_load(const SellDev<VT, IT> &S, int kk, IT (&c)[RPL],
@@ -293,7 +295,7 @@ __device__ __forceinline__ void sell_load(const SellDev<VT, IT> &S, int kk, IT (
   }
 }
 
-template <int RPL, class VT, class IT, class Epi>
+template <int RPL, class VT, class IT, class Epi, int SU = kSellUnroll>
 __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double *__restrict__ x,
                                                  Epi epi_all, Stop st, int rev) {
   constexpr int ND = Epi::kDots;
@@ -321,13 +323,13 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double
     DD acc[RPL];
 #pragma unroll
     for (int u = 0; u < RPL; ++u) acc[u] = DD{0.0, 0.0};
-    for (int k = S.off[sl] + lane * RPL; k < end; k += kSellUnroll * SH) {
-      int c[kSellUnroll][RPL];
-      VT v[kSellUnroll][RPL];  // widened at the product: a conversion next to its load
+    for (int k = S.off[sl] + lane * RPL; k < end; k += SU * SH) {
+      int c[SU][RPL];
+      VT v[SU][RPL];  // widened at the product: a conversion next to its load
                                // would make each load wait for itself
       if constexpr (sizeof(IT) == 4) {
 #pragma unroll
-        for (int t = 0; t < kSellUnroll; ++t) {
+        for (int t = 0; t < SU; ++t) {
           const int kk = k + t * SH;
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
@@ -340,9 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double
         // 16-bit offsets: loads from a clamped slot (this step's first, which is in
         // range) instead of a guarded branch, columns formed after all loads are
         // issued, so that no load waits for itself
-        IT d[kSellUnroll][RPL];
+        IT d[SU][RPL];
 #pragma unroll
-        for (int t = 0; t < kSellUnroll; ++t) {
+        for (int t = 0; t < SU; ++t) {
           const int kk = k + t * SH < end ? k + t * SH : k;
           sell_load<RPL, VT, IT>(S, kk, d[t], v[t]);
         }
@@ -350,22 +352,22 @@ __global__ __launch_bounds__(kBlock) void k_sell(SellDev<VT, IT> S, const double
         // before the column arithmetic, which would otherwise be interleaved with
         // them and make later loads wait for earlier ones (128^3: 143.7 -> 140.3 us
         // per iteration)
-        __builtin_amdgcn_sched_group_barrier(0x020, 2 * kSellUnroll * RPL, 0);  // VMEM reads
+        __builtin_amdgcn_sched_group_barrier(0x020, 2 * SU * RPL, 0);  // VMEM reads
         __builtin_amdgcn_sched_group_barrier(0x002, 64, 0);                     // then VALU
 #pragma unroll
-        for (int t = 0; t < kSellUnroll; ++t)
+        for (int t = 0; t < SU; ++t)
 #pragma unroll
           for (int u = 0; u < RPL; ++u)
             c[t][u] = (k + t * SH < end && d[t][u] != kSellPad16) ? r0 + u + (int)d[t][u] : -1;
       }
       // unconditional gathers (padding reads x[0]): all of them in flight at once
-      double xv[kSellUnroll][RPL];
+      double xv[SU][RPL];
 #pragma unroll
-      for (int t = 0; t < kSellUnroll; ++t)
+      for (int t = 0; t < SU; ++t)
 #pragma unroll
         for (int u = 0; u < RPL; ++u) xv[t][u] = x[c[t][u] < 0 ? 0 : c[t][u]];
 #pragma unroll
-      for (int t = 0; t < kSellUnroll; ++t)
+      for (int t = 0; t < SU; ++t)
 #pragma unroll
         for (int u = 0; u < RPL; ++u)
           if (c[t][u] >= 0) sum_acc(acc[u], (double)v[t][u] * xv[t][u]);
