@@ -260,9 +260,10 @@ struct SellDev {
 };
 
 // Slots per row loaded ahead of their gathers per step: 8, or 5 for batches of
-// five-point stencils (kSellUnrollNarrow; see sell_launch).
+// five-point stencils, 7 for seven-point ones (see sell_launch).
 constexpr int kSellUnroll = 8;
 constexpr int kSellUnrollNarrow = 5;
+constexpr int kSellUnroll7 = 7;
 
 template <int RPL, class VT, class IT>
 __device__ __forceinline__ void sell_load(const SellDev<VT, IT> &S, int kk, IT (&c)[RPL],
