@@ -80,6 +80,7 @@ constexpr int64_t kStreamMinBytes = 512ll << 20;
 // 18% (p-BiCGStab) and 4.6% (ssBiCGSafe2) at 128^3 (~825 MiB)
 constexpr int64_t kOtherStreamMinBytes = 640ll << 20;
 constexpr double kSellMaxPadding = 1.10;  // sliced ELLPACK if its slots <= 1.10 nnz
+constexpr int64_t kSellUnroll7MinRows = 1 << 20;  // seven slots per step from here (sell_launch)
 // ... or <= 1.5 nnz for systems the automatic schedule solves in one workgroup
 // each (schedule 4 needs the sliced layout; it reads a row's entries once, or
 // from cache, so their padding costs it little): a batch of 4096 systems of
@@ -347,10 +348,11 @@ int sell_launch(ps_matrix *M, hipStream_t s, int cls, const double *x, Epi epi, 
   // single systems keep eight)
   if (M->nsys > 1 && M->sell_width <= kSellUnrollNarrow)
     return launch(M, s, cls, k_sell<1, VT, IT, Epi, kSellUnrollNarrow>, g, 0, S, x, epi, stop, rev);
-  // slices of exactly seven entries per row (seven-point stencils): seven slots
-  // per step, none loaded in vain (128^3 system: 128.0 -> 126.8-127.1 us per
-  // iteration)
-  if (M->sell_width == kSellUnroll7)
+  // large systems whose slices hold exactly seven entries per row (seven-point
+  // stencils): seven slots per step, none loaded in vain.  Measured on one box,
+  // schedule 3, us per iteration with eight / seven: 128^3 127.3 / 126.2, 112^3
+  // 90.3 / 90.0, but 96^3 62.8 / 64.6, 64^3 32.8 / 33.3, 32^3 19.9 / 20.1
+  if (M->sell_width == kSellUnroll7 && M->n >= kSellUnroll7MinRows)
     return launch(M, s, cls, k_sell<1, VT, IT, Epi, kSellUnroll7>, g, 0, S, x, epi, stop, rev);
   return launch(M, s, cls, k_sell<1, VT, IT, Epi>, g, 0, S, x, epi, stop, rev);
 }

@@ -260,7 +260,7 @@ struct SellDev {
 };
 
 // Slots per row loaded ahead of their gathers per step: 8, or 5 for batches of
-// five-point stencils, 7 for seven-point ones (see sell_launch).
+// five-point stencils, 7 for large seven-point ones (see sell_launch).
 constexpr int kSellUnroll = 8;
 constexpr int kSellUnrollNarrow = 5;
 constexpr int kSellUnroll7 = 7;
